@@ -1,0 +1,173 @@
+"""Seeded synthetic inputs for the H^1-regularised Gauss-Newton linear solve.
+
+This module only draws numbers: grids, sensitivity rows J_i, right-hand sides b
+and the paper-form data (m - m_ref, g - g_obs). It contains none of the
+solver's arithmetic and is imported by both the CPU oracle and the GPU path's
+tests and benchmark, so that both sides see bit-identical inputs.
+
+The paper's experiments (ERT on unstructured meshes, Section 4) need meshes
+and data that are not available; the workloads below are synthetic stand-ins
+with the shapes the linear solve of Algorithm 3 sees: a dense M x N
+sensitivity matrix (Section 2.3, the matrix J_m) whose rows are smooth,
+localised fields, and an N-vector right-hand side.
+
+Seeding: every array is drawn from numpy's PCG64 seeded with
+SeedSequence([workload_id, stream, row]); stream 0 = rows of J (noise),
+1 = right-hand side b, 2 = bump parameters of the rows of J, 3 = paper-form
+data d and res. Per-row seeds let a large J be regenerated in row chunks.
+"""
+from __future__ import annotations
+
+import dataclasses
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+__all__ = [
+    "Workload", "WORKLOADS", "workload", "grid_shape", "num_nodes", "axis_coords",
+    "j_rows", "rhs_b", "paper_data", "rng_for",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One synthetic GN-system workload.
+
+    shape   nodes per axis, x fastest (len 2 or 3); unit square / cube
+    beta    mass weight of the H^1 Gram operator A = K + beta*M
+    alpha   regularisation weight in (alpha*A + J^T J) x = b
+    m       rows of J
+    j_kind  "gauss" (iid N(0,1)/sqrt(N) entries) or "bumps" (sum of Gaussian
+            bumps of width `width` with N(0,1) amplitudes plus `noise` white noise)
+    wid     integer workload id used in the seed
+    """
+    name: str
+    wid: int
+    shape: tuple
+    beta: float
+    alpha: float
+    m: int
+    j_kind: str
+    nbumps: int = 4
+    width: float = 0.05
+    noise: float = 1e-3
+
+    @property
+    def dim(self) -> int:
+        return len(self.shape)
+
+    @property
+    def N(self) -> int:
+        return num_nodes(self.shape)
+
+    def with_(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+WORKLOADS = {
+    # 2D unit square, 33x33 nodes, J iid Gaussian rows.
+    "square33": Workload("square33", 1, (33, 33), 1e-2, 1e-3, 16, "gauss"),
+    # 3D unit cube, 129^3 nodes, 512 bump rows.
+    "cube129": Workload("cube129", 2, (129, 129, 129), 1e-2, 1e-4, 512, "bumps"),
+    # 3D unit cube, 257^3 nodes, 1024 bump rows.
+    "cube257": Workload("cube257", 4, (257, 257, 257), 1e-2, 1e-5, 1024, "bumps"),
+    # Reduced 3D cases used by parity tests (same recipe as cube129).
+    "cube17": Workload("cube17", 12, (17, 17, 17), 1e-2, 1e-4, 24, "bumps"),
+    "cube33": Workload("cube33", 13, (33, 33, 33), 1e-2, 1e-4, 64, "bumps"),
+    "cube65": Workload("cube65", 14, (65, 65, 65), 1e-2, 1e-4, 128, "bumps"),
+    # 2D square with bump rows (shape of one instance of the batched workload).
+    "square129": Workload("square129", 15, (129, 129), 1e-2, 1e-4, 64, "bumps"),
+}
+
+
+def workload(name: str) -> Workload:
+    return WORKLOADS[name]
+
+
+def grid_shape(wl: Workload) -> tuple:
+    return tuple(wl.shape)
+
+
+def num_nodes(shape) -> int:
+    return int(np.prod(shape))
+
+
+def axis_coords(n: int) -> np.ndarray:
+    """Node coordinates on [0, 1] for n vertex-centred nodes."""
+    return np.arange(n, dtype=np.float64) / (n - 1)
+
+
+def rng_for(wid: int, stream: int, row: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([wid, stream, row])))
+
+
+def _one_row(wl: Workload, i: int) -> np.ndarray:
+    N = wl.N
+    if wl.j_kind == "gauss":
+        return rng_for(wl.wid, 0, i).standard_normal(N) / np.sqrt(N)
+    if wl.j_kind != "bumps":
+        raise ValueError(f"unknown j_kind {wl.j_kind!r}")
+    prm = rng_for(wl.wid, 2, i)
+    centres = prm.random((wl.nbumps, wl.dim))
+    amps = prm.standard_normal(wl.nbumps)
+    row = wl.noise * rng_for(wl.wid, 0, i).standard_normal(N)
+    # reshape to (nz, ny, nx) / (ny, nx): x fastest in memory
+    grid = row.reshape(tuple(reversed(wl.shape)))
+    s2 = 2.0 * wl.width ** 2
+    for k in range(wl.nbumps):
+        # separable Gaussian: prod_d exp(-(x_d - c_d)^2 / (2 w^2))
+        f = None
+        for ax in reversed(range(wl.dim)):   # slowest axis first
+            g = np.exp(-(axis_coords(wl.shape[ax]) - centres[k, ax]) ** 2 / s2)
+            f = g if f is None else np.multiply.outer(f, g)
+        grid += amps[k] * f
+    return row
+
+
+def j_rows(wl: Workload, i0: int = 0, i1: int | None = None, dtype=np.float64,
+           threads: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
+    """Rows i0..i1-1 of J as a C-contiguous (i1-i0, N) array (row i = sensitivity i)."""
+    i1 = wl.m if i1 is None else i1
+    if not (0 <= i0 <= i1 <= wl.m):
+        raise ValueError("row range out of bounds")
+    if out is None:
+        out = np.empty((i1 - i0, wl.N), dtype=dtype)
+    threads = threads or min(16, os.cpu_count() or 1)
+
+    def fill(i):
+        out[i - i0] = _one_row(wl, i)
+
+    if threads > 1 and i1 - i0 > 1:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(fill, range(i0, i1)))
+    else:
+        for i in range(i0, i1):
+            fill(i)
+    return out
+
+
+def rhs_b(wl: Workload, k: int = 1) -> np.ndarray:
+    """k right-hand sides b ~ N(0,1), shape (k, N) (k=1 -> shape (N,))."""
+    b = np.stack([rng_for(wl.wid, 1, j).standard_normal(wl.N) for j in range(k)])
+    return b[0] if k == 1 else b
+
+
+def paper_data(wl: Workload) -> tuple:
+    """(d, res): d = m - m_ref (smooth N-vector), res = g - g_obs (M-vector).
+
+    Used to form the paper's Gauss-Newton right-hand side; d is a low-frequency
+    cosine field plus noise so that the regularisation term is O(1).
+    """
+    g = rng_for(wl.wid, 3, 0)
+    amps = g.standard_normal(3)
+    d = 0.0
+    for k, a in enumerate(amps):
+        f = None
+        for ax in reversed(range(wl.dim)):
+            c = np.cos((k + 1) * np.pi * axis_coords(wl.shape[ax]))
+            f = c if f is None else np.multiply.outer(f, c)
+        d = d + a * f
+    d = np.ascontiguousarray(d).reshape(-1) + 0.1 * g.standard_normal(wl.N)
+    res = g.standard_normal(wl.m)
+    return d, res

@@ -1,0 +1,98 @@
+"""Pins for the oracle's GN solves, the paper's update and the Woodbury
+preconditioner (CPU only)."""
+import numpy as np
+import pytest
+
+import h1w_inputs as H
+from oracle import gn, multigrid, operator as op, poisson
+
+
+def _small(shape, m, alpha=1e-3, beta=1e-2, seed=0):
+    rng = np.random.default_rng(seed)
+    N = int(np.prod(shape))
+    J = rng.standard_normal((m, N)) / np.sqrt(N)
+    b = rng.standard_normal(N)
+    return J, b, alpha, beta
+
+
+def test_three_routes_agree_square33():
+    wl = H.workload("square33")
+    J, b = H.j_rows(wl), H.rhs_b(wl)
+    s, be, al = wl.shape, wl.beta, wl.alpha
+    xs = [gn.solve_dense(s, be, J, al, b), gn.solve_augmented(s, be, J, al, b),
+          gn.solve_woodbury(s, be, J, al, b)]
+    for x in xs:
+        assert gn.true_relres(s, be, J, al, b, x) < 1e-12
+    for x in xs[1:]:
+        assert np.linalg.norm(x - xs[0]) <= 1e-12 * np.linalg.norm(xs[0])
+
+
+@pytest.mark.parametrize("name", ["cube17"])
+def test_three_routes_agree_3d(name):
+    wl = H.workload(name).with_(m=12)
+    J, b = H.j_rows(wl), H.rhs_b(wl)
+    s, be, al = wl.shape, wl.beta, wl.alpha
+    x1 = gn.solve_dense(s, be, J, al, b)
+    x2 = gn.solve_augmented(s, be, J, al, b)
+    x3 = gn.solve_woodbury(s, be, J, al, b)
+    for x in (x2, x3):
+        assert np.linalg.norm(x - x1) <= 1e-10 * np.linalg.norm(x1)
+    assert gn.true_relres(s, be, J, al, b, x3) < 1e-12
+
+
+def test_no_rows_reduces_to_scaled_poisson():
+    shape = (17, 9)
+    J, b, al, be = _small(shape, 0)
+    x = gn.solve_woodbury(shape, be, J, al, b)
+    assert np.allclose(x, poisson.lu_solve(shape, be, b) / al, rtol=1e-12, atol=0)
+    x2 = gn.solve_dense(shape, be, J, al, b)
+    # dense Cholesky forward error ~ cond(alpha*A) * eps ~ 2e5 * 1e-16
+    assert np.linalg.norm(x - x2) <= 1e-10 * np.linalg.norm(x2)
+
+
+def test_one_row_sherman_morrison():
+    shape = (9, 9, 5)
+    J, b, al, be = _small(shape, 1, alpha=1e-4)
+    A = op.gram_operator(shape, be).toarray()
+    j = J[0]
+    Ai = np.linalg.inv(al * A)
+    ref = Ai @ b - (Ai @ j) * (j @ Ai @ b) / (1.0 + j @ Ai @ j)
+    x = gn.solve_woodbury(shape, be, J, al, b)
+    assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_paper_update_solves_paper_rhs():
+    wl = H.workload("square33")
+    J = H.j_rows(wl)
+    d, res = H.paper_data(wl)
+    s, be, al = wl.shape, wl.beta, wl.alpha
+    dm = gn.paper_update(s, be, J, al, d, res)
+    b = gn.paper_rhs(s, be, J, al, d, res)
+    ref = gn.solve_dense(s, be, J, al, b)
+    assert np.linalg.norm(dm - ref) <= 1e-10 * np.linalg.norm(ref)
+    # b written out from eq. (block_primal) times alpha with the assembled matrix
+    A = op.gram_operator(s, be).toarray()
+    assert np.allclose(b, -al * A @ d - J.T @ res, rtol=1e-13, atol=1e-12)
+
+
+def test_woodbury_precond_with_exact_inverse_is_G_inverse():
+    shape = (17, 17)
+    J, b, al, be = _small(shape, 5, alpha=1e-4)
+    B = lambda F: poisson.lu_solve(shape, be, F)
+    R = np.random.default_rng(3).standard_normal((2, int(np.prod(shape))))
+    Z = gn.woodbury_precond(B, J, al, R)
+    G = gn.gn_dense(shape, be, J, al)
+    ref = np.linalg.solve(G, R.T).T
+    assert np.linalg.norm(Z - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_woodbury_precond_identity_with_vcycle():
+    # alpha z + B J^T J z = B r  for z = (alpha B^{-1} + J^T J)^{-1} r
+    shape = (33, 33)
+    J, b, al, be = _small(shape, 7, alpha=1e-3)
+    V = multigrid.VCycle(shape, be, coarse_max=9)
+    r = np.random.default_rng(4).standard_normal(int(np.prod(shape)))
+    z = gn.woodbury_precond(V.apply, J, al, r)
+    lhs = al * z + V.apply(J.T @ (J @ z))
+    rhs = V.apply(r)
+    assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs)
