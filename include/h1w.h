@@ -1,0 +1,208 @@
+/*
+ * h1w.h -- C ABI of the MI355X library for the Gauss-Newton linear systems of
+ * H^1-regularised parameter identification (Blechta & Ernst, arXiv 2209.02815).
+ *
+ * Problem (Section 2.2, eq. (block_primal), multiplied by the regularisation
+ * parameter, which is called alpha here):
+ *
+ *     G x = b,    G = alpha*A + J^T J,
+ *
+ * where A = K + beta*W is the discrete H^1 Gram operator on a structured
+ * vertex-centred grid of the unit square/cube with natural (Neumann) boundary
+ * conditions, and J is the dense m x N sensitivity matrix (Section 2.3, the
+ * matrix J_m). On an n_x x n_y (x n_z) grid with h_d = 1/(n_d - 1):
+ *
+ *     A = sum_d W1 (x) .. K1^(d) .. (x) W1 + beta * (W1 (x) .. (x) W1),
+ *     K1 = h^-2 tridiag(-1, 2, -1) with first/last diagonal entries 1,
+ *     W1 = diag(1/2, 1, .., 1, 1/2);
+ * interior rows are the 5-/7-point -Laplacian + beta.
+ *
+ * Method (Section 3.2, Algorithm 3, rebuilt for the symmetric positive
+ * definite primal system): conjugate gradients preconditioned by the Woodbury
+ * formula around B ~ A^{-1}, one symmetric geometric-multigrid V-cycle:
+ *     Z = B J^T (m batched Poisson solves), S = alpha*I + J Z (capacitance),
+ *     P^{-1} r = (1/alpha) (B r - Z S^{-1} J B r)  = (alpha B^{-1} + J^T J)^{-1} r.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller, 8-byte aligned,
+ *    stored row-major: a batch of k grid vectors is k rows of N = n_x n_y n_z
+ *    values each (x fastest), row i starting at ptr + i*ld with ld >= N.
+ *    J is m x N row-major with leading dimension ldj >= N.
+ *  - All work is enqueued on the stream given to h1w_setup. Calls that read
+ *    convergence scalars (h1w_gn_solve, H1W_MG_SOLVE) block the host until
+ *    they return; the others return once their work is enqueued, except where
+ *    stated.
+ *  - Every call returns an h1w_status and never aborts; on failure
+ *    h1w_last_error(ctx) describes the cause. Arguments are validated on the
+ *    host before any kernel is launched.
+ *  - One host thread per context. Contexts are independent.
+ *  - The library owns the context, its workspace (allocated in h1w_setup and
+ *    grown in h1w_capacitance_build / h1w_gn_solve) and the current
+ *    capacitance factor. Nothing is allocated inside the CG iteration.
+ */
+#ifndef H1W_H
+#define H1W_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h1w_ctx h1w_ctx;
+
+typedef enum {
+    H1W_OK = 0,
+    H1W_EINVAL = -1,   /* invalid argument (null pointer, bad size, ld < N, ...) */
+    H1W_ENOMEM = -2,   /* device allocation failed */
+    H1W_EHIP = -3,     /* HIP runtime error (message in h1w_last_error) */
+    H1W_ENOTSPD = -4,  /* Cholesky met a non-positive pivot (info->failed_pivot) */
+    H1W_ENOCONV = -5,  /* maxit reached; outputs hold the last iterate */
+    H1W_ENUMERIC = -6, /* NaN or Inf in a residual or pivot */
+    H1W_ENOTIMPL = -7, /* entry point not built in this version */
+    H1W_ESTATE = -8    /* call order violated (e.g. precond before capacitance) */
+} h1w_status;
+
+typedef enum { H1W_FP64 = 0, H1W_MIXED = 1 } h1w_precision;
+typedef enum { H1W_DT_F64 = 0, H1W_DT_F32 = 1 } h1w_dtype;
+typedef enum { H1W_VCYCLE_ONCE = 0, H1W_MG_SOLVE = 1 } h1w_poisson_mode;
+typedef enum { H1W_Z_AUTO = 0, H1W_Z_STORED = 1, H1W_Z_RECOMPUTE = 2 } h1w_zmode;
+typedef enum { H1W_FACTOR_AUTO = 0, H1W_FACTOR_CHOL = 1, H1W_FACTOR_LU = 2 } h1w_factor;
+
+/* Grid and multigrid description (h1w_setup). Zero fields take defaults. */
+typedef struct {
+    int dim;             /* 2 or 3 */
+    int n[3];            /* nodes per axis (x, y, z), each >= 2; n[2] ignored for dim 2 */
+    double beta;         /* mass weight in A = K + beta*W, > 0 */
+    int precision;       /* h1w_precision: V-cycles and stored Z in FP64 (H1W_FP64)
+                            or FP32 (H1W_MIXED); J, S, its factor and CG are FP64 */
+    int nu;              /* smoothing steps per side = Chebyshev degree (0 -> 2) */
+    double cheb_lo;      /* Chebyshev interval for eig(D^-1 A): [lo, hi] */
+    double cheb_hi;      /* (0, 0) -> [0.3, 2.0] */
+    int64_t coarse_max;  /* coarsest level: first level with <= coarse_max nodes
+                            (or that cannot be halved); 0 -> 729 (3D) / 289 (2D) */
+    int rhs_chunk;       /* right-hand sides per batched V-cycle launch (0 -> auto) */
+    unsigned flags;      /* reserved, must be 0 */
+} h1w_grid_desc;
+
+/* Krylov options (h1w_gn_solve). A zeroed struct selects the defaults. */
+typedef struct {
+    double rtol;         /* stop when ||b - G x||_2 <= rtol ||b||_2, recomputed
+                            in FP64 from x (0 -> 1e-10) */
+    int maxit;           /* 0 -> 500 */
+    int zmode;           /* h1w_zmode: how the preconditioner applies Z w:
+                            STORED reads Z, RECOMPUTE runs a second V-cycle
+                            B (J^T w); AUTO = RECOMPUTE for FP64, STORED for MIXED
+                            (MIXED requires STORED) */
+    int factor;          /* h1w_factor: AUTO = Cholesky for FP64 (LU if it fails),
+                            LU for MIXED */
+    int check_every;     /* reserved (0) */
+    unsigned flags;      /* reserved, must be 0 */
+} h1w_solve_opts;
+
+/* Diagnostics filled by the calls that take an h1w_info* (may be NULL). */
+typedef struct {
+    int iters;               /* Krylov iterations */
+    int factor_used;         /* h1w_factor actually used */
+    int zmode_used;          /* h1w_zmode actually used */
+    int failed_pivot;        /* first non-positive Cholesky pivot, -1 if none */
+    int nlevels;             /* multigrid levels */
+    int restarts;            /* CG restarts after a failed true-residual check */
+    double relres_true;      /* ||b - G x|| / ||b|| recomputed from x in FP64 */
+    double relres_rec;       /* recursive residual estimate at exit */
+    double t_zbuild_ms;      /* batched V-cycles for Z */
+    double t_gemm_ms;        /* capacitance GEMM */
+    double t_factor_ms;      /* factorisation and inverse of S */
+    double t_cg_ms;          /* Krylov loop including the final true residual */
+    double t_total_ms;       /* whole call */
+    double asym_S_over_alpha;/* max |S - S^T| / alpha (full GEMM only, else 0) */
+} h1w_info;
+
+/* Create a context for one grid: builds the multigrid hierarchy, the dense
+ * inverse of the coarsest operator and the V-cycle workspace.
+ * hip_stream: a hipStream_t (NULL = default stream). */
+h1w_status h1w_setup(const h1w_grid_desc* desc, void* hip_stream, h1w_ctx** out);
+
+/* Free the context and all device memory it owns. NULL is ignored. */
+void h1w_destroy(h1w_ctx* ctx);
+
+/* Message for the last failed call on ctx (valid until the next call). */
+const char* h1w_last_error(const h1w_ctx* ctx);
+
+/* Static description of a status code. */
+const char* h1w_status_string(h1w_status s);
+
+/* Number of grid nodes N and multigrid levels of a context. */
+h1w_status h1w_get_sizes(const h1w_ctx* ctx, int64_t* N, int* nlevels);
+
+/* Y = A X for k grid vectors (the regularisation operator of eq.
+ * (block_primal) with the mass term). dtype selects double or float arrays.
+ * X and Y must not overlap. */
+h1w_status h1w_operator_apply(h1w_ctx* ctx, int k, const void* X, int64_t ldx,
+                              void* Y, int64_t ldy, int dtype);
+
+/* Batched Poisson solves with A (the Laplace solve inside the preconditioner,
+ * Section 3.2 and Algorithm 3, first step).
+ * mode H1W_VCYCLE_ONCE: X = B F, one symmetric V-cycle from a zero initial
+ *   guess in the context's V-cycle precision; dtype must be H1W_DT_F64 for an
+ *   FP64 context and H1W_DT_F32 for a MIXED one. rtol and maxit are ignored.
+ * mode H1W_MG_SOLVE: X ~ A^{-1} F by FP64 conjugate gradients preconditioned
+ *   by B (flexible when B is FP32) until ||F_i - A X_i|| <= rtol ||F_i|| for
+ *   every row i, at most maxit iterations (ENOCONV otherwise); dtype must be
+ *   H1W_DT_F64. Blocks the host.
+ * F and X must not overlap. info->iters = the largest iteration count. */
+h1w_status h1w_poisson_solve_batched(h1w_ctx* ctx, int k, const void* F, int64_t ldf,
+                                     void* X, int64_t ldx, int dtype, int mode,
+                                     double rtol, int maxit, h1w_info* info);
+
+/* Capacitance build (Algorithm 3, first three steps): Z = B J^T (kept in the
+ * context, FP64 or FP32 by the context precision), S = alpha*I + J Z^T
+ * (FP64 accumulation) and its factorisation (Cholesky, or LU with partial
+ * pivoting for a MIXED context or when Cholesky fails; factor selects it).
+ * J (m x N, FP64) is NOT copied: it must stay valid and unchanged until the
+ * next h1w_capacitance_build or h1w_gn_solve on this context.
+ * S_out (optional, m x m row-major FP64, leading dimension lds >= m) receives S.
+ * Z_out (optional, m x N, leading dimension ldz >= N, dtype of the context's
+ * V-cycle precision) receives Z.
+ * Returns ENOTSPD if factor = CHOL was forced and a pivot is not positive. */
+h1w_status h1w_capacitance_build(h1w_ctx* ctx, int m, const double* J, int64_t ldj,
+                                 double alpha, int factor, double* S_out, int64_t lds,
+                                 void* Z_out, int64_t ldz, h1w_info* info);
+
+/* Woodbury preconditioner apply for k vectors using the context's current
+ * capacitance (Algorithm 3, preconditioner formula):
+ *   Zout_i = (1/alpha)(B R_i - Z S^{-1} J B R_i)   (zmode STORED), or
+ *   Zout_i = (1/alpha) B (R_i - J^T S^{-1} J B R_i) (zmode RECOMPUTE).
+ * FP64 arrays. ESTATE if no capacitance has been built. */
+h1w_status h1w_precond_apply(h1w_ctx* ctx, int k, const double* R, int64_t ldr,
+                             double* Zout, int64_t ldz, int zmode);
+
+/* Full Gauss-Newton linear solve: capacitance build + preconditioned CG
+ * from x0 = 0 (Algorithm 3 with MINRES replaced by CG on the SPD primal form).
+ * b (N, FP64) is the right-hand side; if b is NULL, the paper's right-hand
+ * side b = -alpha*A d - J^T res is formed from d = m - m_ref (N) and
+ * res = g - g_obs (m) (eq. (block_primal) times alpha); then dm = x.
+ * x (N, FP64) receives the solution. J must stay valid during the call.
+ * Returns ENOCONV (x = last iterate, info->relres_true filled) when maxit is
+ * reached, ENUMERIC on NaN/Inf. Blocks the host. */
+h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha,
+                        const double* b, const double* d, const double* res, double* x,
+                        const h1w_solve_opts* opts, h1w_info* info);
+
+/* y = G x = alpha*A x + J^T (J x) for one vector (FP64); used for true
+ * residuals. J is m x N. */
+h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha,
+                        const double* x, double* y);
+
+/* ERT sensitivities (Section 4: forward model, adjoint derivative of the
+ * pole-pole voltages). Not built in this version: always returns
+ * H1W_ENOTIMPL without touching its arguments. */
+h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double* logsig, int n_src,
+                                 const int* src_node, int n_meas, const int* pair,
+                                 const double* kgeo, double* g_out, double* J_out,
+                                 int64_t ldj, const h1w_solve_opts* opts, h1w_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H1W_H */

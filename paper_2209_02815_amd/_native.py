@@ -1,0 +1,222 @@
+"""ctypes binding of libh1w.so (include/h1w.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and takes torch
+tensors already resident on the GPU; all arithmetic happens in the HIP
+library. Import fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libh1w.so")
+
+H1W_OK, H1W_EINVAL, H1W_ENOMEM, H1W_EHIP, H1W_ENOTSPD, H1W_ENOCONV, H1W_ENUMERIC, H1W_ENOTIMPL, H1W_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+H1W_FP64, H1W_MIXED = 0, 1
+H1W_DT_F64, H1W_DT_F32 = 0, 1
+H1W_VCYCLE_ONCE, H1W_MG_SOLVE = 0, 1
+H1W_Z_AUTO, H1W_Z_STORED, H1W_Z_RECOMPUTE = 0, 1, 2
+H1W_FACTOR_AUTO, H1W_FACTOR_CHOL, H1W_FACTOR_LU = 0, 1, 2
+
+EXPORTED = [
+    "h1w_setup", "h1w_destroy", "h1w_last_error", "h1w_status_string", "h1w_get_sizes",
+    "h1w_operator_apply", "h1w_poisson_solve_batched", "h1w_capacitance_build",
+    "h1w_precond_apply", "h1w_gn_solve", "h1w_gn_apply", "h1w_ert_sensitivities",
+]
+
+
+class h1w_grid_desc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("beta", C.c_double), ("precision", C.c_int),
+                ("nu", C.c_int), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
+                ("coarse_max", C.c_int64), ("rhs_chunk", C.c_int), ("flags", C.c_uint)]
+
+
+class h1w_solve_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int), ("zmode", C.c_int), ("factor", C.c_int),
+                ("check_every", C.c_int), ("flags", C.c_uint)]
+
+
+class h1w_info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("factor_used", C.c_int), ("zmode_used", C.c_int),
+                ("failed_pivot", C.c_int), ("nlevels", C.c_int), ("restarts", C.c_int),
+                ("relres_true", C.c_double), ("relres_rec", C.c_double),
+                ("t_zbuild_ms", C.c_double), ("t_gemm_ms", C.c_double), ("t_factor_ms", C.c_double),
+                ("t_cg_ms", C.c_double), ("t_total_ms", C.c_double), ("asym_S_over_alpha", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class H1WError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+def _load():
+    # torch's HIP libraries need the unversioned libamdhip64.so; loading torch
+    # first makes libh1w.so (which needs libamdhip64.so.7) bind to that same
+    # runtime instead of pulling a second HIP runtime into the process.
+    import torch  # noqa: F401
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with paper_2209_02815_amd.build.build()")
+    lib = C.CDLL(_LIB_PATH)
+    P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "h1w_setup": (I, [C.POINTER(h1w_grid_desc), P, C.POINTER(P)]),
+        "h1w_destroy": (None, [P]),
+        "h1w_last_error": (C.c_char_p, [P]),
+        "h1w_status_string": (C.c_char_p, [I]),
+        "h1w_get_sizes": (I, [P, C.POINTER(I64), C.POINTER(I)]),
+        "h1w_operator_apply": (I, [P, I, P, I64, P, I64, I]),
+        "h1w_poisson_solve_batched": (I, [P, I, P, I64, P, I64, I, I, D, I, C.POINTER(h1w_info)]),
+        "h1w_capacitance_build": (I, [P, I, P, I64, D, I, P, I64, P, I64, C.POINTER(h1w_info)]),
+        "h1w_precond_apply": (I, [P, I, P, I64, P, I64, I]),
+        "h1w_gn_solve": (I, [P, I, P, I64, D, P, P, P, P, C.POINTER(h1w_solve_opts), C.POINTER(h1w_info)]),
+        "h1w_gn_apply": (I, [P, I, P, I64, D, P, P]),
+        "h1w_ert_sensitivities": (I, [P, P, I, P, I, P, P, P, P, I64, C.POINTER(h1w_solve_opts),
+                                      C.POINTER(h1w_info)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(ctx, st: int):
+    if st != H1W_OK:
+        msg = lib.h1w_last_error(ctx)
+        raise H1WError(st, (msg or b"").decode() or lib.h1w_status_string(st).decode())
+
+
+# ------------------------------------------------------------------ tensor helpers
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _rows(t, N: int, what: str):
+    """(k, ld) of a 1-D (one row) or 2-D row-major CUDA tensor with N columns."""
+    if t is None:
+        return 0, N
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if t.dim() == 1:
+        if t.shape[0] != N or t.stride(0) != 1:
+            raise ValueError(f"{what} must have {N} contiguous entries")
+        return 1, N
+    if t.dim() != 2 or t.shape[1] != N or t.stride(1) != 1:
+        raise ValueError(f"{what} must be (k, {N}) with unit stride along rows")
+    return t.shape[0], max(t.stride(0), N)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return H1W_DT_F64
+    if t.dtype == torch.float32:
+        return H1W_DT_F32
+    raise ValueError("tensors must be float64 or float32")
+
+
+# ------------------------------------------------------------------ entry points
+def h1w_setup(shape, beta: float, precision: int = H1W_FP64, nu: int = 0, cheb=(0.0, 0.0),
+              coarse_max: int = 0, rhs_chunk: int = 0, stream=None):
+    """Create a context; returns the opaque handle (c_void_p)."""
+    d = h1w_grid_desc()
+    d.dim = len(shape)
+    for i, n in enumerate(shape):
+        d.n[i] = int(n)
+    d.beta, d.precision, d.nu = float(beta), int(precision), int(nu)
+    d.cheb_lo, d.cheb_hi = float(cheb[0]), float(cheb[1])
+    d.coarse_max, d.rhs_chunk, d.flags = int(coarse_max), int(rhs_chunk), 0
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    h = C.c_void_p()
+    st = lib.h1w_setup(C.byref(d), C.c_void_p(stream), C.byref(h))
+    if st != H1W_OK:
+        raise H1WError(st, lib.h1w_last_error(None).decode())
+    return h
+
+
+def h1w_destroy(ctx):
+    lib.h1w_destroy(ctx)
+
+
+def h1w_get_sizes(ctx):
+    N, L = C.c_int64(), C.c_int()
+    _check(ctx, lib.h1w_get_sizes(ctx, C.byref(N), C.byref(L)))
+    return N.value, L.value
+
+
+def h1w_operator_apply(ctx, X, Y):
+    N, _ = h1w_get_sizes(ctx)
+    k, ldx = _rows(X, N, "X")
+    k2, ldy = _rows(Y, N, "Y")
+    if k != k2 or X.dtype != Y.dtype:
+        raise ValueError("X and Y must have the same rows and dtype")
+    _check(ctx, lib.h1w_operator_apply(ctx, k, _ptr(X), ldx, _ptr(Y), ldy, _dtype_code(X)))
+    return Y
+
+
+def h1w_poisson_solve_batched(ctx, F, X, mode: int = H1W_VCYCLE_ONCE, rtol: float = 1e-10, maxit: int = 0):
+    N, _ = h1w_get_sizes(ctx)
+    k, ldf = _rows(F, N, "F")
+    k2, ldx = _rows(X, N, "X")
+    if k != k2 or F.dtype != X.dtype:
+        raise ValueError("F and X must have the same rows and dtype")
+    info = h1w_info()
+    _check(ctx, lib.h1w_poisson_solve_batched(ctx, k, _ptr(F), ldf, _ptr(X), ldx, _dtype_code(F), mode,
+                                              float(rtol), int(maxit), C.byref(info)))
+    return info
+
+
+def h1w_capacitance_build(ctx, J, alpha: float, factor: int = H1W_FACTOR_AUTO, S_out=None, Z_out=None):
+    N, _ = h1w_get_sizes(ctx)
+    m, ldj = _rows(J, N, "J")
+    lds = 0 if S_out is None else S_out.stride(0)
+    _, ldz = _rows(Z_out, N, "Z_out")
+    info = h1w_info()
+    _check(ctx, lib.h1w_capacitance_build(ctx, m, _ptr(J), ldj, float(alpha), int(factor), _ptr(S_out), lds,
+                                          _ptr(Z_out), ldz, C.byref(info)))
+    return info
+
+
+def h1w_precond_apply(ctx, R, Zout, zmode: int = H1W_Z_AUTO):
+    N, _ = h1w_get_sizes(ctx)
+    k, ldr = _rows(R, N, "R")
+    k2, ldz = _rows(Zout, N, "Zout")
+    if k != k2:
+        raise ValueError("R and Zout must have the same rows")
+    _check(ctx, lib.h1w_precond_apply(ctx, k, _ptr(R), ldr, _ptr(Zout), ldz, int(zmode)))
+    return Zout
+
+
+def h1w_gn_solve(ctx, J, alpha: float, x, b=None, d=None, res=None, rtol: float = 0.0, maxit: int = 0,
+                 zmode: int = H1W_Z_AUTO, factor: int = H1W_FACTOR_AUTO, raise_on_error: bool = True):
+    N, _ = h1w_get_sizes(ctx)
+    m, ldj = (0, N) if J is None else _rows(J, N, "J")
+    o = h1w_solve_opts(float(rtol), int(maxit), int(zmode), int(factor), 0, 0)
+    info = h1w_info()
+    st = lib.h1w_gn_solve(ctx, m, _ptr(J), ldj, float(alpha), _ptr(b), _ptr(d), _ptr(res), _ptr(x),
+                          C.byref(o), C.byref(info))
+    if raise_on_error:
+        _check(ctx, st)
+    return (info, st) if not raise_on_error else info
+
+
+def h1w_gn_apply(ctx, J, alpha: float, x, y):
+    N, _ = h1w_get_sizes(ctx)
+    m, ldj = (0, N) if J is None else _rows(J, N, "J")
+    _check(ctx, lib.h1w_gn_apply(ctx, m, _ptr(J), ldj, float(alpha), _ptr(x), _ptr(y)))
+    return y
+
+
+def h1w_ert_sensitivities(ctx, *args, **kwargs):
+    st = lib.h1w_ert_sensitivities(ctx, None, 0, None, 0, None, None, None, None, 0, None, None)
+    _check(ctx, st)

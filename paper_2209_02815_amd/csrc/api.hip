@@ -1,0 +1,285 @@
+// C ABI entry points (include/h1w.h): argument validation on the host,
+// translation of internal errors to status codes; no exception crosses the ABI.
+#include <cmath>
+#include <new>
+
+#include "context.h"
+
+struct h1w_ctx {
+    h1w::Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+template <typename Fn>
+h1w_status guarded(h1w_ctx* ctx, Fn&& fn) {
+    try {
+        fn();
+        if (ctx) ctx->c.err.clear();
+        return H1W_OK;
+    } catch (const h1w::Error& e) {
+        if (ctx) ctx->c.err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->c.err = "host allocation failed";
+        return H1W_ENOMEM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->c.err = e.what();
+        return H1W_EINVAL;
+    }
+}
+
+using h1w::require;
+
+void need_ptr(const void* p, size_t align, const char* what) {
+    require(p != nullptr, std::string(what) + " is NULL");
+    require(reinterpret_cast<uintptr_t>(p) % align == 0, std::string(what) + " is not aligned");
+}
+
+// rows [0, k) of length n with leading dimension ld, element size es
+bool overlap(const void* a, int64_t lda, const void* b, int64_t ldb, int k, int64_t n, size_t es) {
+    if (k <= 0) return false;
+    const char* a0 = static_cast<const char*>(a);
+    const char* b0 = static_cast<const char*>(b);
+    const char* a1 = a0 + ((int64_t)(k - 1) * lda + n) * es;
+    const char* b1 = b0 + ((int64_t)(k - 1) * ldb + n) * es;
+    return a0 < b1 && b0 < a1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* h1w_status_string(h1w_status s) {
+    switch (s) {
+        case H1W_OK: return "ok";
+        case H1W_EINVAL: return "invalid argument";
+        case H1W_ENOMEM: return "out of device memory";
+        case H1W_EHIP: return "HIP runtime error";
+        case H1W_ENOTSPD: return "capacitance matrix not positive definite";
+        case H1W_ENOCONV: return "no convergence within maxit";
+        case H1W_ENUMERIC: return "NaN or Inf encountered";
+        case H1W_ENOTIMPL: return "not implemented";
+        case H1W_ESTATE: return "call order violated";
+    }
+    return "unknown status";
+}
+
+h1w_status h1w_setup(const h1w_grid_desc* desc, void* hip_stream, h1w_ctx** out) {
+    g_setup_error.clear();
+    if (!desc || !out) {
+        g_setup_error = "desc and out must not be NULL";
+        return H1W_EINVAL;
+    }
+    *out = nullptr;
+    h1w_ctx* ctx = nullptr;
+    try {
+        ctx = new h1w_ctx();
+    } catch (...) {
+        g_setup_error = "host allocation failed";
+        return H1W_ENOMEM;
+    }
+    const h1w_status st = guarded(ctx, [&] { ctx->c.init(*desc, static_cast<hipStream_t>(hip_stream)); });
+    if (st != H1W_OK) {
+        g_setup_error = ctx->c.err;
+        delete ctx;
+        return st;
+    }
+    *out = ctx;
+    return H1W_OK;
+}
+
+void h1w_destroy(h1w_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->c.stream);
+    delete ctx;
+}
+
+const char* h1w_last_error(const h1w_ctx* ctx) { return ctx ? ctx->c.err.c_str() : g_setup_error.c_str(); }
+
+h1w_status h1w_get_sizes(const h1w_ctx* ctx, int64_t* N, int* nlevels) {
+    if (!ctx) return H1W_EINVAL;
+    if (N) *N = ctx->c.N();
+    if (nlevels) *nlevels = (int)ctx->c.lv.size();
+    return H1W_OK;
+}
+
+h1w_status h1w_operator_apply(h1w_ctx* ctx, int k, const void* X, int64_t ldx, void* Y, int64_t ldy, int dtype) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        const int64_t n = c.N();
+        require(k >= 0, "k must be >= 0");
+        require(dtype == H1W_DT_F64 || dtype == H1W_DT_F32, "dtype must be H1W_DT_F64 or H1W_DT_F32");
+        if (k == 0) return;
+        const size_t es = dtype == H1W_DT_F64 ? 8 : 4;
+        need_ptr(X, es, "X");
+        need_ptr(Y, es, "Y");
+        require(ldx >= n && ldy >= n, "leading dimensions must be >= N");
+        require(!overlap(X, ldx, Y, ldy, k, n, es), "X and Y overlap");
+        for (int r0 = 0; r0 < k; r0 += 65535) {
+            const int kk = std::min(65535, k - r0);
+            if (dtype == H1W_DT_F64)
+                h1w::launch_apply<double>(c.stream, c.dim, c.lv[0], kk, (const double*)X + (int64_t)r0 * ldx, ldx,
+                                          (double*)Y + (int64_t)r0 * ldy, ldy, 1.0);
+            else
+                h1w::launch_apply<float>(c.stream, c.dim, c.lv[0], kk, (const float*)X + (int64_t)r0 * ldx, ldx,
+                                         (float*)Y + (int64_t)r0 * ldy, ldy, 1.0);
+        }
+    });
+}
+
+h1w_status h1w_poisson_solve_batched(h1w_ctx* ctx, int k, const void* F, int64_t ldf, void* X, int64_t ldx,
+                                     int dtype, int mode, double rtol, int maxit, h1w_info* info) {
+    if (!ctx) return H1W_EINVAL;
+    if (info) *info = h1w_info{};
+    if (info) info->failed_pivot = -1;
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        const int64_t n = c.N();
+        require(k >= 0, "k must be >= 0");
+        require(mode == H1W_VCYCLE_ONCE || mode == H1W_MG_SOLVE, "mode must be H1W_VCYCLE_ONCE or H1W_MG_SOLVE");
+        if (mode == H1W_VCYCLE_ONCE)
+            require(dtype == (c.fp32 ? H1W_DT_F32 : H1W_DT_F64),
+                    "VCYCLE_ONCE needs dtype F64 for an FP64 context and F32 for a MIXED one");
+        else
+            require(dtype == H1W_DT_F64, "MG_SOLVE needs dtype F64");
+        if (info) info->nlevels = (int)c.lv.size();
+        if (k == 0) return;
+        const size_t es = dtype == H1W_DT_F64 ? 8 : 4;
+        need_ptr(F, es, "F");
+        need_ptr(X, es, "X");
+        require(ldf >= n && ldx >= n, "leading dimensions must be >= N");
+        require(!overlap(F, ldf, X, ldx, k, n, es), "F and X overlap");
+        if (mode == H1W_VCYCLE_ONCE) {
+            if (c.fp32)
+                c.vcycle<float>(k, (const float*)F, ldf, (float*)X, ldx);
+            else
+                c.vcycle<double>(k, (const double*)F, ldf, (double*)X, ldx);
+        } else {
+            require(std::isfinite(rtol) && rtol > 0.0, "rtol must be > 0");
+            require(maxit >= 0, "maxit must be >= 0");
+            c.mg_solve(k, (const double*)F, ldf, (double*)X, ldx, rtol, maxit > 0 ? maxit : 200, info);
+        }
+    });
+}
+
+h1w_status h1w_capacitance_build(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha, int factor,
+                                 double* S_out, int64_t lds, void* Z_out, int64_t ldz, h1w_info* info) {
+    if (!ctx) return H1W_EINVAL;
+    if (info) {
+        *info = h1w_info{};
+        info->failed_pivot = -1;
+    }
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        const int64_t n = c.N();
+        c.have_cap = false;
+        require(m >= 1 && m <= 4096, "m must be in [1, 4096]");
+        need_ptr(J, 8, "J");
+        require(ldj >= n, "ldj must be >= N");
+        require(std::isfinite(alpha) && alpha > 0.0, "alpha must be finite and > 0");
+        require(factor >= H1W_FACTOR_AUTO && factor <= H1W_FACTOR_LU, "factor must be AUTO, CHOL or LU");
+        if (S_out) {
+            need_ptr(S_out, 8, "S_out");
+            require(lds >= m, "lds must be >= m");
+        }
+        if (Z_out) {
+            need_ptr(Z_out, c.fp32 ? 4 : 8, "Z_out");
+            require(ldz >= n, "ldz must be >= N");
+        }
+        c.capacitance_build(m, J, ldj, alpha, factor, info);
+        if (S_out)
+            H1W_HIP(hipMemcpy2DAsync(S_out, lds * sizeof(double), c.Sbuf.p, m * sizeof(double), m * sizeof(double), m,
+                                     hipMemcpyDeviceToDevice, c.stream));
+        if (Z_out) {
+            const size_t es = c.fp32 ? 4 : 8;
+            H1W_HIP(hipMemcpy2DAsync(Z_out, ldz * es, c.Zbuf.p, c.ldz * es, n * es, m, hipMemcpyDeviceToDevice,
+                                     c.stream));
+        }
+        c.sync();
+    });
+}
+
+h1w_status h1w_precond_apply(h1w_ctx* ctx, int k, const double* R, int64_t ldr, double* Zout, int64_t ldz,
+                             int zmode) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        const int64_t n = c.N();
+        require(k >= 0, "k must be >= 0");
+        if (k == 0) return;
+        need_ptr(R, 8, "R");
+        need_ptr(Zout, 8, "Zout");
+        require(ldr >= n && ldz >= n, "leading dimensions must be >= N");
+        require(!overlap(R, ldr, Zout, ldz, k, n, 8), "R and Zout overlap");
+        c.precond_apply(k, R, ldr, Zout, ldz, zmode);
+    });
+}
+
+h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha, const double* b,
+                        const double* d, const double* res, double* x, const h1w_solve_opts* opts, h1w_info* info) {
+    if (!ctx) return H1W_EINVAL;
+    if (info) {
+        *info = h1w_info{};
+        info->failed_pivot = -1;
+    }
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        const int64_t n = c.N();
+        require(m >= 0 && m <= 4096, "m must be in [0, 4096]");
+        if (m > 0) {
+            need_ptr(J, 8, "J");
+            require(ldj >= n, "ldj must be >= N");
+        }
+        require(std::isfinite(alpha) && alpha > 0.0, "alpha must be finite and > 0");
+        need_ptr(x, 8, "x");
+        if (b) {
+            need_ptr(b, 8, "b");
+            require(!overlap(b, n, x, n, 1, n, 8), "b and x overlap");
+        } else {
+            need_ptr(d, 8, "d (b is NULL)");
+            if (m > 0) need_ptr(res, 8, "res (b is NULL)");
+            require(!overlap(d, n, x, n, 1, n, 8), "d and x overlap");
+        }
+        h1w_solve_opts o{};
+        if (opts) o = *opts;
+        require(std::isfinite(o.rtol) && o.rtol >= 0.0, "rtol must be >= 0");
+        require(o.maxit >= 0, "maxit must be >= 0");
+        require(o.zmode >= H1W_Z_AUTO && o.zmode <= H1W_Z_RECOMPUTE, "zmode must be AUTO, STORED or RECOMPUTE");
+        require(o.factor >= H1W_FACTOR_AUTO && o.factor <= H1W_FACTOR_LU, "factor must be AUTO, CHOL or LU");
+        require(o.check_every == 0 && o.flags == 0, "check_every and flags must be 0");
+        c.gn_solve(m, J, ldj, alpha, b, d, res, x, o, info);
+    });
+}
+
+h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha, const double* x,
+                        double* y) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        const int64_t n = c.N();
+        require(m >= 0, "m must be >= 0");
+        if (m > 0) {
+            need_ptr(J, 8, "J");
+            require(ldj >= n, "ldj must be >= N");
+        }
+        require(std::isfinite(alpha), "alpha must be finite");
+        need_ptr(x, 8, "x");
+        need_ptr(y, 8, "y");
+        require(!overlap(x, n, y, n, 1, n, 8), "x and y overlap");
+        c.ensure_cg_ws(m);
+        c.gn_apply(m, J, ldj, alpha, x, y);
+        c.sync();
+    });
+}
+
+h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double*, int, const int*, int, const int*, const double*,
+                                 double*, double*, int64_t, const h1w_solve_opts*, h1w_info*) {
+    if (ctx) ctx->c.err = "h1w_ert_sensitivities is not built in this version";
+    return H1W_ENOTIMPL;
+}
+
+}  // extern "C"

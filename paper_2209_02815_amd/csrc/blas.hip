@@ -1,0 +1,395 @@
+// Vector kernels of the Krylov loop and the passes over the dense m x N
+// matrices J (sensitivities) and Z (= B J^T). All reductions are two-stage
+// with a fixed order (per-block partial sums, then one block per output), so
+// a rerun with the same launch shapes is bitwise identical.
+#include <algorithm>
+
+#include "devutil.h"
+#include "internal.h"
+
+namespace h1w {
+
+namespace {
+
+constexpr int kDotBlocks = 1024;   // max blocks of a dot-product pass
+constexpr int kRowsPerBlock = 8;   // rows of J per block in J v
+constexpr int kRowChunk = kBlock * 16;  // nodes per block in J v
+constexpr int kTile = 256;         // rows of J staged in LDS per sweep in J^T v
+
+struct DotArgs {
+    const double* x[4];
+    const double* y[4];
+};
+
+template <int NP>
+__global__ __launch_bounds__(kBlock) void k_dots_partial(int64_t N, DotArgs a,
+                                                         double* __restrict__ partial) {
+    __shared__ double sh[kBlock / 64];
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) acc[q] += a.x[q][i] * a.y[q][i];
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const double s = block_sum<kBlock>(acc[q], sh);
+        if (threadIdx.x == 0) partial[q * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// out[v] = sum_b partial[v*nparts + b]; one block per output value.
+__global__ __launch_bounds__(kBlock) void k_reduce_parts(int nparts, const double* __restrict__ partial,
+                                                         double* __restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    const double* p = partial + (int64_t)blockIdx.x * nparts;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) acc += p[b];
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// partial[i*nchunk + c] = sum over chunk c of M[i, n] v[n], rows i of this block.
+__global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const double* __restrict__ M,
+                                                     int64_t ldm, const double* __restrict__ v,
+                                                     double* __restrict__ partial) {
+    __shared__ double sh[kBlock / 64];
+    const int nchunk = gridDim.x;
+    const int64_t base = (int64_t)blockIdx.x * kRowChunk;
+    constexpr int E = kRowChunk / kBlock;
+    double vv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t n = base + e * kBlock + threadIdx.x;
+        vv[e] = n < N ? v[n] : 0.0;
+    }
+    const int r0 = blockIdx.y * kRowsPerBlock;
+    for (int rr = 0; rr < kRowsPerBlock; ++rr) {
+        const int i = r0 + rr;
+        if (i >= m) break;
+        const double* row = M + (int64_t)i * ldm;
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t n = base + e * kBlock + threadIdx.x;
+            if (n < N) acc += row[n] * vv[e];
+        }
+        const double s = block_sum<kBlock>(acc, sh);
+        if (threadIdx.x == 0) partial[(int64_t)i * nchunk + blockIdx.x] = s;
+    }
+}
+
+// u = (r - J^T w) * inv_alpha ;  t = J^T jp
+__global__ __launch_bounds__(kBlock) void k_jt_u_t(int m, int64_t N, const double* __restrict__ J,
+                                                   int64_t ldj, const double* __restrict__ w,
+                                                   const double* __restrict__ jp,
+                                                   const double* __restrict__ r, double inv_alpha,
+                                                   double* __restrict__ u, double* __restrict__ t) {
+    __shared__ double sw[kTile], sj[kTile];
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double aw = 0.0, aj = 0.0;
+    for (int i0 = 0; i0 < m; i0 += kTile) {
+        const int cnt = std::min(kTile, m - i0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += kBlock) {
+            sw[q] = w[i0 + q];
+            sj[q] = jp[i0 + q];
+        }
+        __syncthreads();
+        if (n < N) {
+            const double* col = J + (int64_t)i0 * ldj + n;
+#pragma unroll 8
+            for (int q = 0; q < cnt; ++q) {
+                const double jv = col[(int64_t)q * ldj];
+                aw += jv * sw[q];
+                aj += jv * sj[q];
+            }
+        }
+    }
+    if (n < N) {
+        u[n] = (r[n] - aw) * inv_alpha;
+        t[n] = aj;
+    }
+}
+
+// out = J^T v + add_coef * add   (add may be null)
+__global__ __launch_bounds__(kBlock) void k_jt_plain(int m, int64_t N, const double* __restrict__ J,
+                                                     int64_t ldj, const double* __restrict__ v,
+                                                     double* __restrict__ out,
+                                                     const double* __restrict__ add,
+                                                     double add_coef) {
+    __shared__ double sv[kTile];
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double acc = 0.0;
+    for (int i0 = 0; i0 < m; i0 += kTile) {
+        const int cnt = std::min(kTile, m - i0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += kBlock) sv[q] = v[i0 + q];
+        __syncthreads();
+        if (n < N) {
+            const double* col = J + (int64_t)i0 * ldj + n;
+#pragma unroll 8
+            for (int q = 0; q < cnt; ++q) acc += col[(int64_t)q * ldj] * sv[q];
+        }
+    }
+    if (n < N) out[n] = add ? acc + add_coef * add[n] : acc;
+}
+
+// z = (y - Z^T w) * inv_alpha
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_z_stored(int m, int64_t N, const TZ* __restrict__ Z,
+                                                     int64_t ldz, const double* __restrict__ w,
+                                                     const double* __restrict__ y, double inv_alpha,
+                                                     double* __restrict__ z) {
+    __shared__ double sw[kTile];
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double acc = 0.0;
+    for (int i0 = 0; i0 < m; i0 += kTile) {
+        const int cnt = std::min(kTile, m - i0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += kBlock) sw[q] = w[i0 + q];
+        __syncthreads();
+        if (n < N) {
+            const TZ* col = Z + (int64_t)i0 * ldz + n;
+#pragma unroll 8
+            for (int q = 0; q < cnt; ++q) acc += double(col[(int64_t)q * ldz]) * sw[q];
+        }
+    }
+    if (n < N) z[n] = (y[n] - acc) * inv_alpha;
+}
+
+// p = (y - Z^T w) * inv_alpha + beta * p ;  t = J^T jp
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_p_stored(int m, int64_t N, const TZ* __restrict__ Z,
+                                                     int64_t ldz, const double* __restrict__ w,
+                                                     const double* __restrict__ J, int64_t ldj,
+                                                     const double* __restrict__ jp,
+                                                     const double* __restrict__ y, double inv_alpha,
+                                                     double beta, double* __restrict__ p,
+                                                     double* __restrict__ t) {
+    __shared__ double sw[kTile], sj[kTile];
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double az = 0.0, aj = 0.0;
+    for (int i0 = 0; i0 < m; i0 += kTile) {
+        const int cnt = std::min(kTile, m - i0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += kBlock) {
+            sw[q] = w[i0 + q];
+            sj[q] = jp[i0 + q];
+        }
+        __syncthreads();
+        if (n < N) {
+            const TZ* zc = Z + (int64_t)i0 * ldz + n;
+            const double* jc = J + (int64_t)i0 * ldj + n;
+#pragma unroll 8
+            for (int q = 0; q < cnt; ++q) {
+                az += double(zc[(int64_t)q * ldz]) * sw[q];
+                aj += jc[(int64_t)q * ldj] * sj[q];
+            }
+        }
+    }
+    if (n < N) {
+        p[n] = (y[n] - az) * inv_alpha + beta * p[n];
+        t[n] = aj;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(int64_t N, double a, const double* __restrict__ x,
+                                                  double b, double* __restrict__ y) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n < N) y[n] = a * x[n] + (b == 0.0 ? 0.0 : b * y[n]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub(int64_t N, const double* __restrict__ b,
+                                                const double* __restrict__ v,
+                                                double* __restrict__ out) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n < N) out[n] = b[n] - v[n];
+}
+
+// x += a p ; r -= a q ; partial sums of r.r
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, double a, const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ x, double* __restrict__ r,
+                                                      double* __restrict__ partial) {
+    __shared__ double sh[kBlock / 64];
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * kBlock) {
+        x[n] += a * p[n];
+        const double rn = r[n] - a * q[n];
+        r[n] = rn;
+        acc += rn * rn;
+    }
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// per-row dot products of a batch: partial[r*nb + b]
+__global__ __launch_bounds__(kBlock) void k_batched_dots(int64_t N, const double* __restrict__ X,
+                                                         int64_t ldx, const double* __restrict__ Y,
+                                                         int64_t ldy, double* __restrict__ partial) {
+    __shared__ double sh[kBlock / 64];
+    const int r = blockIdx.y;
+    const double* x = X + r * ldx;
+    const double* y = Y + r * ldy;
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * kBlock)
+        acc += x[n] * y[n];
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batched_cg_xr(int64_t N, const double* __restrict__ a,
+                                                          const double* __restrict__ P, int64_t ldp,
+                                                          const double* __restrict__ Q, int64_t ldq,
+                                                          double* __restrict__ X, int64_t ldx,
+                                                          double* __restrict__ R, int64_t ldr,
+                                                          const int* __restrict__ active) {
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    const double ar = a[r];
+    X[r * ldx + n] += ar * P[r * ldp + n];
+    R[r * ldr + n] -= ar * Q[r * ldq + n];
+}
+
+__global__ __launch_bounds__(kBlock) void k_batched_p(int64_t N, const double* __restrict__ b,
+                                                      const double* __restrict__ Z, int64_t ldz,
+                                                      double* __restrict__ P, int64_t ldp,
+                                                      const int* __restrict__ active) {
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    P[r * ldp + n] = Z[r * ldz + n] + b[r] * P[r * ldp + n];
+}
+
+int dot_blocks(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, cdiv(N, kBlock * 4))); }
+
+}  // namespace
+
+int launch_dots_partial(hipStream_t s, int64_t N, int npair, const double* const* X,
+                        const double* const* Y, double* partial) {
+    DotArgs a{};
+    for (int q = 0; q < npair; ++q) {
+        a.x[q] = X[q];
+        a.y[q] = Y[q];
+    }
+    const int nb = dot_blocks(N);
+    switch (npair) {
+        case 1: hipLaunchKernelGGL(k_dots_partial<1>, dim3(nb), dim3(kBlock), 0, s, N, a, partial); break;
+        case 2: hipLaunchKernelGGL(k_dots_partial<2>, dim3(nb), dim3(kBlock), 0, s, N, a, partial); break;
+        case 3: hipLaunchKernelGGL(k_dots_partial<3>, dim3(nb), dim3(kBlock), 0, s, N, a, partial); break;
+        case 4: hipLaunchKernelGGL(k_dots_partial<4>, dim3(nb), dim3(kBlock), 0, s, N, a, partial); break;
+        default: throw Error{H1W_EINVAL, "internal: npair out of range"};
+    }
+    H1W_LAUNCHED();
+    return nb;
+}
+
+void launch_reduce_parts(hipStream_t s, int nvec, int nparts, const double* partial, double* out) {
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nvec), dim3(kBlock), 0, s, nparts, partial, out);
+    H1W_LAUNCHED();
+}
+
+size_t rows_dot_partial_elems(int m, int64_t N) { return (size_t)m * (size_t)cdiv(N, kRowChunk); }
+
+void launch_rows_dot(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm, const double* v,
+                     double* partial, double* out) {
+    if (m <= 0) return;
+    const int nchunk = (int)cdiv(N, kRowChunk);
+    const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
+    hipLaunchKernelGGL(k_rows_dot, grid, dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
+    H1W_LAUNCHED();
+    launch_reduce_parts(s, m, nchunk, partial, out);
+}
+
+void launch_jt_u_t(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj, const double* w,
+                   const double* jp, const double* r, double inv_alpha, double* u, double* t) {
+    hipLaunchKernelGGL(k_jt_u_t, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, m, N, J, ldj,
+                       w, jp, r, inv_alpha, u, t);
+    H1W_LAUNCHED();
+}
+
+void launch_jt_plain(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj, const double* v,
+                     double* out, const double* add, double add_coef) {
+    hipLaunchKernelGGL(k_jt_plain, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, m, N, J, ldj,
+                       v, out, add, add_coef);
+    H1W_LAUNCHED();
+}
+
+template <typename TZ>
+void launch_z_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
+                     const double* y, double inv_alpha, double* z) {
+    hipLaunchKernelGGL((k_z_stored<TZ>), dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, m, N, Z,
+                       ldz, w, y, inv_alpha, z);
+    H1W_LAUNCHED();
+}
+
+template <typename TZ>
+void launch_p_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
+                     const double* J, int64_t ldj, const double* jp, const double* y, double inv_alpha,
+                     double beta, double* p, double* t) {
+    hipLaunchKernelGGL((k_p_stored<TZ>), dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, m, N, Z,
+                       ldz, w, J, ldj, jp, y, inv_alpha, beta, p, t);
+    H1W_LAUNCHED();
+}
+
+void launch_axpby(hipStream_t s, int64_t N, double a, const double* x, double b, double* y) {
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, a, x, b, y);
+    H1W_LAUNCHED();
+}
+
+void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, double* out) {
+    hipLaunchKernelGGL(k_sub, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, b, v, out);
+    H1W_LAUNCHED();
+}
+
+void launch_cg_update(hipStream_t s, int64_t N, double a, const double* p, const double* q, double* x,
+                      double* r, double* partial, int* nparts) {
+    const int nb = dot_blocks(N);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, a, p, q, x, r, partial);
+    H1W_LAUNCHED();
+    *nparts = nb;
+}
+
+void launch_batched_dots(hipStream_t s, int k, int64_t N, const double* X, int64_t ldx, const double* Y,
+                         int64_t ldy, double* partial, double* out) {
+    const int nb = (int)std::min<int64_t>(64, cdiv(N, kBlock * 4));
+    hipLaunchKernelGGL(k_batched_dots, dim3(nb, k), dim3(kBlock), 0, s, N, X, ldx, Y, ldy, partial);
+    H1W_LAUNCHED();
+    launch_reduce_parts(s, k, nb, partial, out);
+}
+
+void launch_batched_cg_xr(hipStream_t s, int k, int64_t N, const double* a, const double* P, int64_t ldp,
+                          const double* Q, int64_t ldq, double* X, int64_t ldx, double* R, int64_t ldr,
+                          const int* active) {
+    hipLaunchKernelGGL(k_batched_cg_xr, dim3((unsigned)cdiv(N, kBlock), k), dim3(kBlock), 0, s, N, a, P,
+                       ldp, Q, ldq, X, ldx, R, ldr, active);
+    H1W_LAUNCHED();
+}
+
+void launch_batched_p(hipStream_t s, int k, int64_t N, const double* b, const double* Z, int64_t ldz,
+                      double* P, int64_t ldp, const int* active) {
+    hipLaunchKernelGGL(k_batched_p, dim3((unsigned)cdiv(N, kBlock), k), dim3(kBlock), 0, s, N, b, Z, ldz,
+                       P, ldp, active);
+    H1W_LAUNCHED();
+}
+
+template void launch_z_stored<double>(hipStream_t, int, int64_t, const double*, int64_t, const double*,
+                                      const double*, double, double*);
+template void launch_z_stored<float>(hipStream_t, int, int64_t, const float*, int64_t, const double*,
+                                     const double*, double, double*);
+template void launch_p_stored<double>(hipStream_t, int, int64_t, const double*, int64_t, const double*,
+                                      const double*, int64_t, const double*, const double*, double,
+                                      double, double*, double*);
+template void launch_p_stored<float>(hipStream_t, int, int64_t, const float*, int64_t, const double*,
+                                     const double*, int64_t, const double*, const double*, double,
+                                     double, double*, double*);
+
+}  // namespace h1w

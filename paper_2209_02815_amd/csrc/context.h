@@ -1,0 +1,86 @@
+// The h1w context: one structured grid, its multigrid hierarchy and the
+// device workspace of the batched V-cycle, the capacitance system and the
+// Krylov loop.
+#pragma once
+
+#include <initializer_list>
+#include <utility>
+
+#include "devutil.h"
+#include "internal.h"
+
+namespace h1w {
+
+struct Ctx {
+    h1w_grid_desc d{};
+    int dim = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool fp32 = false;               // V-cycles and stored Z in FP32 (mixed precision)
+    std::vector<Geom> lv;            // levels, fine to coarsest
+    std::vector<int64_t> pitch;      // workspace row pitch per level (elements)
+    std::vector<double> w;           // Chebyshev step weights
+    int64_t Nc = 0;                  // nodes on the coarsest level
+    DevBuf cinv64, cinv32;           // dense inverse of the coarsest operator
+    int chunk = 1;                   // right-hand sides per V-cycle launch
+    DevBuf vws;                      // V-cycle level workspace
+    DevBuf stage;                    // FP32 staging (mixed precision)
+    DevBuf pcg;                      // MG-PCG batch vectors
+
+    // capacitance state (valid when have_cap)
+    bool have_cap = false;
+    int m = 0;
+    const double* J = nullptr;
+    int64_t ldj = 0;
+    double alpha = 0.0;
+    DevBuf Zbuf;                     // Z = B J^T, m x N (double or float), ld = ldz
+    int64_t ldz = 0;
+    DevBuf Sbuf;                     // S = alpha I + J Z^T (m x m)
+    DevBuf F1, F2, pivb;             // factors: Cholesky U / L=U^T, or LU / (LU)^T + pivots
+    int factor = 0;
+    int failed_pivot = -1;
+    double asym = 0.0;
+
+    // Krylov workspace
+    enum { kR, kP, kQ, kY, kU, kZ, kT, kB, kTmpN, kNVec };
+    enum { kJy, kW, kJz, kJp, kJx, kTmp, kMVec };
+    DevBuf nvec, mvec, part, jpart, gpart, scal, iflag;
+    int mstride = 1;                 // m-vector slot stride (grows only)
+    double* hscal = nullptr;         // pinned host copy of device scalars
+    hipEvent_t ev[8] = {};
+
+    ~Ctx();
+    void init(const h1w_grid_desc& desc, hipStream_t s);
+    int64_t N() const;
+    void sync();
+    void read_scal(int n);
+
+    template <typename T> const T* fp_cinv() const {
+        if constexpr (sizeof(T) == 8) return cinv64.as<double>();
+        else return cinv32.as<float>();
+    }
+    template <typename T> void vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx);
+    template <typename T> void vcycle(int k, const T* F, int64_t ldf, T* X, int64_t ldx);
+    void apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
+    void mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, double rtol, int maxit,
+                  h1w_info* info);
+
+    void capacitance_build(int m, const double* J, int64_t ldj, double alpha, int factor, h1w_info* info);
+    void solve_S(double* x);
+    void ensure_cg_ws(int mneed);
+    double* nv(int i);
+    double* mv(int i);
+    void dots(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs, int slot);
+    void woodbury_mspace(const double* y, double* Jy, double* w);
+    void precond_one(const double* r, double* z, int zmode);
+    void precond_apply(int k, const double* R, int64_t ldr, double* Zout, int64_t ldz, int zmode);
+    void gn_apply(int m, const double* J, int64_t ldj, double alpha, const double* x, double* y);
+    void gn_solve(int m, const double* J, int64_t ldj, double alpha, const double* b, const double* d,
+                  const double* res, double* x, const h1w_solve_opts& o, h1w_info* info);
+
+    void ev_reserve();
+    void ev_record(int i);
+    double ev_ms(int a, int b);
+};
+
+}  // namespace h1w

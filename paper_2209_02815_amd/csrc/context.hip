@@ -1,0 +1,765 @@
+// Host runtime of the h1w library: context and multigrid hierarchy, the
+// batched V-cycle B, MG-preconditioned CG for Poisson solves, the capacitance
+// build, the Woodbury preconditioner apply and the preconditioned CG driver
+// for the Gauss-Newton system G x = b, G = alpha*A + J^T J.
+#include "context.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace h1w {
+
+// ============================================================ setup
+
+static Geom make_geom(int dim, const int n[3], double beta) {
+    Geom g{};
+    g.nx = n[0];
+    g.ny = n[1];
+    g.nz = dim == 3 ? n[2] : 1;
+    g.N = (int64_t)g.nx * g.ny * g.nz;
+    auto ih2 = [](int nn) { return double(nn - 1) * double(nn - 1); };
+    g.ihx2 = ih2(g.nx);
+    g.ihy2 = ih2(g.ny);
+    g.ihz2 = dim == 3 ? ih2(g.nz) : 0.0;
+    g.beta = beta;
+    return g;
+}
+
+// Dense A on one (small) level, row-major, same stencil as the device kernels.
+static std::vector<double> dense_operator(int dim, const Geom& g) {
+    const int64_t N = g.N;
+    std::vector<double> A((size_t)(N * N), 0.0);
+    auto w = [](int i, int n) { return (i == 0 || i == n - 1) ? 0.5 : 1.0; };
+    for (int l = 0; l < g.nz; ++l)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                const int64_t p = i + (int64_t)g.nx * (j + (int64_t)g.ny * l);
+                const double wx = w(i, g.nx), wy = w(j, g.ny), wz = dim == 3 ? w(l, g.nz) : 1.0;
+                const double cx = g.ihx2 * wy * wz, cy = g.ihy2 * wx * wz, cz = dim == 3 ? g.ihz2 * wx * wy : 0.0;
+                double diag = g.beta * wx * wy * wz;
+                auto couple = [&](int64_t q, double c) {
+                    A[(size_t)(p * N + q)] -= c;
+                    diag += c;
+                };
+                if (i > 0) couple(p - 1, cx);
+                if (i < g.nx - 1) couple(p + 1, cx);
+                if (j > 0) couple(p - g.nx, cy);
+                if (j < g.ny - 1) couple(p + g.nx, cy);
+                if (dim == 3) {
+                    const int64_t pl = (int64_t)g.nx * g.ny;
+                    if (l > 0) couple(p - pl, cz);
+                    if (l < g.nz - 1) couple(p + pl, cz);
+                }
+                A[(size_t)(p * N + p)] = diag;
+            }
+    return A;
+}
+
+// Inverse of an SPD matrix through its Cholesky factor (host, FP64).
+static std::vector<double> spd_inverse(std::vector<double> A, int64_t n) {
+    for (int64_t k = 0; k < n; ++k) {  // lower Cholesky in place
+        double d = A[(size_t)(k * n + k)];
+        for (int64_t q = 0; q < k; ++q) d -= A[(size_t)(k * n + q)] * A[(size_t)(k * n + q)];
+        if (!(d > 0.0)) throw Error{H1W_ENUMERIC, "coarsest operator is not positive definite"};
+        d = std::sqrt(d);
+        A[(size_t)(k * n + k)] = d;
+        for (int64_t i = k + 1; i < n; ++i) {
+            double s = A[(size_t)(i * n + k)];
+            const double* ri = &A[(size_t)(i * n)];
+            const double* rk = &A[(size_t)(k * n)];
+            for (int64_t q = 0; q < k; ++q) s -= ri[q] * rk[q];
+            A[(size_t)(i * n + k)] = s / d;
+        }
+    }
+    // X = L^{-T} L^{-1} column by column
+    std::vector<double> X((size_t)(n * n), 0.0), y((size_t)n);
+    for (int64_t c = 0; c < n; ++c) {
+        for (int64_t i = 0; i < n; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            const double* ri = &A[(size_t)(i * n)];
+            for (int64_t q = c; q < i; ++q) s -= ri[q] * y[(size_t)q];
+            y[(size_t)i] = (i < c) ? 0.0 : s / ri[i];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = y[(size_t)i];
+            for (int64_t q = i + 1; q < n; ++q) s -= A[(size_t)(q * n + i)] * X[(size_t)(q * n + c)];
+            X[(size_t)(i * n + c)] = s / A[(size_t)(i * n + i)];
+        }
+    }
+    return X;
+}
+
+void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
+    d = desc;
+    stream = s;
+    dim = d.dim;
+    require(dim == 2 || dim == 3, "dim must be 2 or 3");
+    int n[3] = {d.n[0], d.n[1], dim == 3 ? d.n[2] : 1};
+    for (int a = 0; a < dim; ++a) require(n[a] >= 2, "every n[d] must be >= 2");
+    require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
+    require(d.precision == H1W_FP64 || d.precision == H1W_MIXED, "precision must be H1W_FP64 or H1W_MIXED");
+    require(d.nu >= 0 && d.nu <= 16, "nu must be in [0, 16]");
+    require(d.flags == 0, "flags must be 0");
+    require(d.coarse_max >= 0, "coarse_max must be >= 0");
+    require(d.rhs_chunk >= 0 && d.rhs_chunk <= 65535, "rhs_chunk must be in [0, 65535]");
+    if (d.nu == 0) d.nu = 2;
+    if (d.cheb_lo == 0.0 && d.cheb_hi == 0.0) {
+        d.cheb_lo = 0.3;
+        d.cheb_hi = 2.0;
+    }
+    require(d.cheb_lo > 0.0 && d.cheb_hi > d.cheb_lo && std::isfinite(d.cheb_hi), "need 0 < cheb_lo < cheb_hi");
+    if (d.coarse_max == 0) d.coarse_max = dim == 3 ? 729 : 289;
+    fp32 = d.precision == H1W_MIXED;
+    const int64_t N0 = (int64_t)n[0] * n[1] * n[2];
+    require(N0 < (int64_t(1) << 31), "grid too large: N must be < 2^31");
+
+    // hierarchy: halve while the level is above coarse_max and every n_d >= 5 is odd
+    lv.clear();
+    int cur[3] = {n[0], n[1], n[2]};
+    for (;;) {
+        lv.push_back(make_geom(dim, cur, d.beta));
+        const Geom& g = lv.back();
+        if (g.N <= d.coarse_max) break;
+        bool ok = true;
+        for (int a = 0; a < dim; ++a) ok = ok && cur[a] >= 5 && (cur[a] - 1) % 2 == 0;
+        if (!ok) break;
+        for (int a = 0; a < dim; ++a) cur[a] = (cur[a] - 1) / 2 + 1;
+    }
+    Nc = lv.back().N;
+    require(Nc <= 4096, "coarsest level has " + std::to_string(Nc) +
+                            " nodes (> 4096): use n_d = 2^k*c + 1 so the grid can be halved, or lower coarse_max");
+
+    // Chebyshev step weights: 1/theta_k, theta_k = (hi+lo)/2 + (hi-lo)/2 cos(pi (2k+1)/(2 nu))
+    w.resize(d.nu);
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < d.nu; ++k)
+        w[k] = 1.0 / (0.5 * (d.cheb_hi + d.cheb_lo) + 0.5 * (d.cheb_hi - d.cheb_lo) * std::cos(pi * (2 * k + 1) / (2.0 * d.nu)));
+
+    // dense inverse of the coarsest operator
+    const std::vector<double> inv = spd_inverse(dense_operator(dim, lv.back()), Nc);
+    cinv64.reserve(inv.size() * sizeof(double));
+    H1W_HIP(hipMemcpy(cinv64.p, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<float> inv32(inv.begin(), inv.end());
+    cinv32.reserve(inv32.size() * sizeof(float));
+    H1W_HIP(hipMemcpy(cinv32.p, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
+
+    pitch.resize(lv.size());
+    for (size_t l = 0; l < lv.size(); ++l) pitch[l] = cdiv(lv[l].N, 64) * 64;
+    chunk = d.rhs_chunk > 0 ? d.rhs_chunk : (int)std::clamp<int64_t>((int64_t(1) << 26) / N0, 1, 1024);
+
+    H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
+    scal.reserve(64 * sizeof(double));
+    iflag.reserve(16 * sizeof(int));
+}
+
+Ctx::~Ctx() {
+    if (hscal) (void)hipHostFree(hscal);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+int64_t Ctx::N() const { return lv[0].N; }
+
+void Ctx::sync() { H1W_HIP(hipStreamSynchronize(stream)); }
+
+// read n device scalars (blocks the host)
+void Ctx::read_scal(int n) {
+    H1W_HIP(hipMemcpyAsync(hscal, scal.p, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    sync();
+}
+
+// ============================================================ V-cycle
+
+template <typename T>
+void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
+    const int L = (int)lv.size();
+    const size_t es = sizeof(T);
+    if (L == 1) {
+        launch_coarse_solve<T>(stream, Nc, fp_cinv<T>(), k, F, ldf, X, ldx);
+        return;
+    }
+    // workspace: level 0 scratch t; levels >= 1: f, x, t (k rows of pitch each)
+    size_t need = (size_t)k * pitch[0];
+    for (int l = 1; l < L; ++l) need += (size_t)3 * k * pitch[l];
+    vws.reserve(need * es);
+    T* base = vws.as<T>();
+    std::vector<T*> tb(L), fb(L), xb(L);
+    size_t off = 0;
+    tb[0] = base;
+    off += (size_t)k * pitch[0];
+    for (int l = 1; l < L; ++l) {
+        fb[l] = base + off;
+        off += (size_t)k * pitch[l];
+        xb[l] = base + off;
+        off += (size_t)k * pitch[l];
+        tb[l] = base + off;
+        off += (size_t)k * pitch[l];
+    }
+    const int nu = d.nu;
+    std::vector<T*> cur(L), oth(L);
+    std::vector<int64_t> ldcur(L), ldoth(L);
+    auto fptr = [&](int l) { return l == 0 ? F : (const T*)fb[l]; };
+    auto fld = [&](int l) { return l == 0 ? ldf : pitch[l]; };
+    auto xptr = [&](int l) { return l == 0 ? X : xb[l]; };
+    auto xld = [&](int l) { return l == 0 ? ldx : pitch[l]; };
+
+    for (int l = 0; l < L - 1; ++l) {
+        const Geom& g = lv[l];
+        // pre-smoothing from zero: first step writes t so that 2nu-1 flips end in x
+        launch_smooth_first<T>(stream, dim, g, k, fptr(l), fld(l), tb[l], pitch[l], w[0]);
+        T* a = tb[l];
+        int64_t la = pitch[l];
+        T* b = xptr(l);
+        int64_t lb = xld(l);
+        for (int s = 1; s < nu; ++s) {
+            launch_smooth<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb, w[s]);
+            std::swap(a, b);
+            std::swap(la, lb);
+        }
+        launch_residual<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb);
+        launch_restrict<T>(stream, dim, g, lv[l + 1], k, b, lb, fb[l + 1], pitch[l + 1]);
+        cur[l] = a;
+        ldcur[l] = la;
+        oth[l] = b;
+        ldoth[l] = lb;
+    }
+    launch_coarse_solve<T>(stream, Nc, fp_cinv<T>(), k, fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
+    for (int l = L - 2; l >= 0; --l) {
+        const Geom& g = lv[l];
+        launch_prolong_add<T>(stream, dim, g, lv[l + 1], k, xb[l + 1], pitch[l + 1], cur[l], ldcur[l]);
+        T* a = cur[l];
+        int64_t la = ldcur[l];
+        T* b = oth[l];
+        int64_t lb = ldoth[l];
+        for (int s = nu - 1; s >= 0; --s) {
+            launch_smooth<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb, w[s]);
+            std::swap(a, b);
+            std::swap(la, lb);
+        }
+        if (a != xptr(l)) throw Error{H1W_EINVAL, "internal: V-cycle buffer parity"};
+    }
+}
+
+template <typename T>
+void Ctx::vcycle(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
+    for (int r0 = 0; r0 < k; r0 += chunk) {
+        const int kk = std::min(chunk, k - r0);
+        vcycle_chunk<T>(kk, F + (int64_t)r0 * ldf, ldf, X + (int64_t)r0 * ldx, ldx);
+    }
+}
+
+// y = B r for FP64 vectors in the context's V-cycle precision.
+void Ctx::apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
+    if (!fp32) {
+        vcycle<double>(k, F, ldf, X, ldx);
+        return;
+    }
+    const int64_t n = N();
+    for (int r0 = 0; r0 < k; r0 += chunk) {
+        const int kk = std::min(chunk, k - r0);
+        stage.reserve((size_t)2 * kk * pitch[0] * sizeof(float));
+        float* fin = stage.as<float>();
+        float* fout = fin + (size_t)kk * pitch[0];
+        launch_convert<double, float>(stream, n, kk, F + (int64_t)r0 * ldf, ldf, fin, pitch[0], 1.0);
+        vcycle_chunk<float>(kk, fin, pitch[0], fout, pitch[0]);
+        launch_convert<float, double>(stream, n, kk, fout, pitch[0], X + (int64_t)r0 * ldx, ldx, 1.0);
+    }
+}
+
+// ============================================================ MG-preconditioned CG (Poisson)
+
+void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, double rtol, int maxit,
+                   h1w_info* info) {
+    const int64_t n = N();
+    int max_iters = 0;
+    for (int r0 = 0; r0 < k; r0 += chunk) {
+        const int kk = std::min(chunk, k - r0);
+        const double* Fc = F + (int64_t)r0 * ldf;
+        double* Xc = X + (int64_t)r0 * ldx;
+        const int64_t P = pitch[0];
+        pcg.reserve((size_t)4 * kk * P * sizeof(double));
+        double* R = pcg.as<double>();
+        double* Zv = R + (size_t)kk * P;
+        double* Pv = Zv + (size_t)kk * P;
+        double* Q = Pv + (size_t)kk * P;
+        mvec.reserve((size_t)8 * kk * sizeof(double) + 16 * kk * sizeof(int));
+        double* dnrm = mvec.as<double>();       // kk
+        double* drz = dnrm + kk;                // kk
+        double* dpq = drz + kk;                 // kk
+        double* da = dpq + kk;                  // kk
+        double* db = da + kk;                   // kk
+        double* dzq = db + kk;                  // kk
+        int* dact = (int*)(dzq + kk);           // kk
+        part.reserve((size_t)kk * 64 * sizeof(double));
+        double* pp = part.as<double>();
+        std::vector<double> nb(kk), rz(kk), pq(kk), a(kk, 0.0), bcoef(kk, 0.0), rr(kk), zq(kk);
+        std::vector<int> act(kk, 1);
+        auto fetch = [&](const double* dsrc, std::vector<double>& dst) {
+            H1W_HIP(hipMemcpyAsync(dst.data(), dsrc, kk * sizeof(double), hipMemcpyDeviceToHost, stream));
+            sync();
+        };
+        auto put = [&](double* ddst, const void* src, size_t bytes) {
+            H1W_HIP(hipMemcpyAsync(ddst, src, bytes, hipMemcpyHostToDevice, stream));
+        };
+        H1W_HIP(hipMemset2DAsync(Xc, ldx * sizeof(double), 0, n * sizeof(double), kk, stream));
+        H1W_HIP(hipMemcpy2DAsync(R, P * sizeof(double), Fc, ldf * sizeof(double), n * sizeof(double), kk,
+                                 hipMemcpyDeviceToDevice, stream));
+        launch_batched_dots(stream, kk, n, R, P, R, P, pp, dnrm);
+        fetch(dnrm, nb);
+        for (int r = 0; r < kk; ++r) {
+            if (!std::isfinite(nb[r])) throw Error{H1W_ENUMERIC, "non-finite right-hand side"};
+            nb[r] = std::sqrt(nb[r]);
+            if (nb[r] == 0.0) act[r] = 0;
+        }
+        put((double*)dact, act.data(), kk * sizeof(int));
+        apply_B(kk, R, P, Zv, P);
+        H1W_HIP(hipMemcpy2DAsync(Pv, P * sizeof(double), Zv, P * sizeof(double), n * sizeof(double), kk,
+                                 hipMemcpyDeviceToDevice, stream));
+        launch_batched_dots(stream, kk, n, R, P, Zv, P, pp, drz);
+        fetch(drz, rz);
+        int it = 0;
+        bool done = std::none_of(act.begin(), act.end(), [](int v) { return v; });
+        while (!done) {
+            if (it >= maxit) {
+                if (info) info->iters = std::max(max_iters, it);
+                throw Error{H1W_ENOCONV, "MG-PCG did not converge in maxit iterations"};
+            }
+            launch_apply<double>(stream, dim, lv[0], kk, Pv, P, Q, P, 1.0);
+            launch_batched_dots(stream, kk, n, Pv, P, Q, P, pp, dpq);
+            fetch(dpq, pq);
+            for (int r = 0; r < kk; ++r) {
+                if (act[r] && !(pq[r] > 0.0)) throw Error{H1W_ENUMERIC, "MG-PCG breakdown (p.Ap <= 0 or NaN)"};
+                a[r] = act[r] ? rz[r] / pq[r] : 0.0;
+            }
+            put(da, a.data(), kk * sizeof(double));
+            launch_batched_cg_xr(stream, kk, n, da, Pv, P, Q, P, Xc, ldx, R, P, dact);
+            launch_batched_dots(stream, kk, n, R, P, R, P, pp, dnrm);
+            fetch(dnrm, rr);
+            ++it;
+            bool any = false;
+            for (int r = 0; r < kk; ++r) {
+                if (!act[r]) continue;
+                if (!std::isfinite(rr[r])) throw Error{H1W_ENUMERIC, "non-finite residual in MG-PCG"};
+                if (std::sqrt(rr[r]) <= rtol * nb[r]) act[r] = 0;
+                any = any || act[r];
+            }
+            put((double*)dact, act.data(), kk * sizeof(int));
+            if (!any) break;
+            apply_B(kk, R, P, Zv, P);
+            launch_batched_dots(stream, kk, n, R, P, Zv, P, pp, drz);
+            if (fp32) launch_batched_dots(stream, kk, n, Zv, P, Q, P, pp, dzq);
+            std::vector<double> rzn(kk);
+            fetch(drz, rzn);
+            if (fp32) fetch(dzq, zq);
+            for (int r = 0; r < kk; ++r) {
+                if (!act[r]) { bcoef[r] = 0.0; continue; }
+                // flexible (Polak-Ribiere) coefficient z.(r_new - r_old)/rz when B is an
+                // FP32 cycle, with r_new - r_old = -a q
+                bcoef[r] = fp32 ? -a[r] * zq[r] / rz[r] : rzn[r] / rz[r];
+                rz[r] = rzn[r];
+            }
+            put(db, bcoef.data(), kk * sizeof(double));
+            launch_batched_p(stream, kk, n, db, Zv, P, Pv, P, dact);
+        }
+        // verify with the true residual
+        launch_apply<double>(stream, dim, lv[0], kk, Xc, ldx, Q, P, 1.0);
+        for (int r = 0; r < kk; ++r)
+            launch_sub(stream, n, Fc + (int64_t)r * ldf, Q + (int64_t)r * P, R + (int64_t)r * P);
+        launch_batched_dots(stream, kk, n, R, P, R, P, pp, dnrm);
+        fetch(dnrm, rr);
+        double worst = 0.0;
+        for (int r = 0; r < kk; ++r) worst = std::max(worst, nb[r] > 0 ? std::sqrt(rr[r]) / nb[r] : 0.0);
+        if (info) info->relres_true = std::max(info->relres_true, worst);
+        max_iters = std::max(max_iters, it);
+    }
+    if (info) {
+        info->iters = max_iters;
+        info->nlevels = (int)lv.size();
+    }
+}
+
+// ============================================================ capacitance
+
+void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha_, int factor_, h1w_info* info) {
+    const int64_t n = N();
+    have_cap = false;
+    m = m_;
+    J = J_;
+    ldj = ldj_;
+    alpha = alpha_;
+    ev_record(0);
+    // Z = B J^T (row i = B J_i), kept in the context
+    const size_t zes = fp32 ? sizeof(float) : sizeof(double);
+    Zbuf.reserve((size_t)m * n * zes);
+    ldz = n;
+    if (!fp32) {
+        vcycle<double>(m, J, ldj, Zbuf.as<double>(), ldz);
+    } else {
+        for (int r0 = 0; r0 < m; r0 += chunk) {
+            const int kk = std::min(chunk, m - r0);
+            stage.reserve((size_t)kk * pitch[0] * sizeof(float));
+            launch_convert<double, float>(stream, n, kk, J + (int64_t)r0 * ldj, ldj, stage.as<float>(), pitch[0], 1.0);
+            vcycle_chunk<float>(kk, stage.as<float>(), pitch[0], Zbuf.as<float>() + (int64_t)r0 * ldz, ldz);
+        }
+    }
+    ev_record(1);
+    // S = alpha I + J Z^T  (lower triangle only when Z is FP64 and S will be Cholesky-factored)
+    int fac = factor_;
+    if (fac == H1W_FACTOR_AUTO) fac = fp32 ? H1W_FACTOR_LU : H1W_FACTOR_CHOL;
+    const bool lower = !fp32 && fac == H1W_FACTOR_CHOL;
+    Sbuf.reserve((size_t)m * m * sizeof(double));
+    const size_t pe = gemm_partial_elems(m, n);
+    gpart.reserve(pe * sizeof(double));
+    if (!fp32)
+        launch_capacitance_gemm<double>(stream, m, n, J, ldj, Zbuf.as<double>(), ldz, lower, alpha,
+                                        gpart.as<double>(), pe, Sbuf.as<double>(), m);
+    else
+        launch_capacitance_gemm<float>(stream, m, n, J, ldj, Zbuf.as<float>(), ldz, lower, alpha,
+                                       gpart.as<double>(), pe, Sbuf.as<double>(), m);
+    ev_record(2);
+    asym = 0.0;
+    if (!lower) {
+        launch_asym(stream, m, Sbuf.as<double>(), scal.as<double>());
+        read_scal(1);
+        asym = hscal[0] / alpha;
+    }
+    // factorisation
+    F1.reserve((size_t)m * m * sizeof(double));
+    F2.reserve((size_t)m * m * sizeof(double));
+    pivb.reserve((size_t)m * sizeof(int));
+    int* dinfo = iflag.as<int>();
+    int hinfo = -1;
+    failed_pivot = -1;
+    factor = 0;
+    if (fac == H1W_FACTOR_CHOL) {
+        H1W_HIP(hipMemcpyAsync(F1.p, Sbuf.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        launch_cholesky_upper(stream, m, F1.as<double>(), dinfo);
+        H1W_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, stream));
+        sync();
+        if (hinfo < 0) {
+            launch_transpose(stream, m, F1.as<double>(), F2.as<double>());
+            factor = H1W_FACTOR_CHOL;
+        } else {
+            failed_pivot = hinfo;
+            if (factor_ == H1W_FACTOR_CHOL) {
+                if (info) info->failed_pivot = hinfo;
+                throw Error{H1W_ENOTSPD, "Cholesky of S failed at column " + std::to_string(hinfo)};
+            }
+            fac = H1W_FACTOR_LU;
+        }
+    }
+    if (fac == H1W_FACTOR_LU) {
+        H1W_HIP(hipMemcpyAsync(F1.p, Sbuf.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        launch_lu(stream, m, F1.as<double>(), pivb.as<int>(), dinfo);
+        H1W_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, stream));
+        sync();
+        if (hinfo >= 0) throw Error{H1W_ENUMERIC, "LU of S met a zero pivot at column " + std::to_string(hinfo)};
+        launch_transpose(stream, m, F1.as<double>(), F2.as<double>());
+        factor = H1W_FACTOR_LU;
+    }
+    ev_record(3);
+    have_cap = true;
+    sync();
+    if (info) {
+        info->t_zbuild_ms = ev_ms(0, 1);
+        info->t_gemm_ms = ev_ms(1, 2);
+        info->t_factor_ms = ev_ms(2, 3);
+        info->factor_used = factor;
+        info->failed_pivot = failed_pivot;
+        info->asym_S_over_alpha = asym;
+        info->nlevels = (int)lv.size();
+    }
+}
+
+void Ctx::solve_S(double* x) {
+    if (factor == H1W_FACTOR_CHOL)
+        launch_chol_solve(stream, m, F1.as<double>(), F2.as<double>(), x);
+    else
+        launch_lu_solve(stream, m, F2.as<double>(), F1.as<double>(), pivb.as<int>(), x);
+}
+
+// ============================================================ workspace for the Krylov loop
+
+void Ctx::ensure_cg_ws(int mneed) {
+    const int64_t n = N();
+    mstride = std::max({mstride, mneed, 1});
+    nvec.reserve((size_t)kNVec * pitch[0] * sizeof(double));
+    mvec.reserve((size_t)kMVec * mstride * sizeof(double));
+    // dot partials: up to 4 x 1024 blocks, or one per block of the stencil+dot kernel
+    part.reserve((size_t)std::max<int64_t>(4 * 1024, cdiv(n, kBlock)) * sizeof(double));
+    jpart.reserve(rows_dot_partial_elems(mstride, n) * sizeof(double));
+}
+
+double* Ctx::nv(int i) { return nvec.as<double>() + (size_t)i * pitch[0]; }
+double* Ctx::mv(int i) { return mvec.as<double>() + (size_t)i * mstride; }
+
+// out[slot..] = dot products of the given pairs (device); returns after the
+// values are in hscal[slot..] when fetch is true.
+void Ctx::dots(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs, int slot) {
+    const double* X[4];
+    const double* Y[4];
+    int q = 0;
+    for (auto& pr : pairs) {
+        X[q] = pr.first;
+        Y[q] = pr.second;
+        ++q;
+    }
+    const int nb = launch_dots_partial(stream, len, q, X, Y, part.as<double>());
+    launch_reduce_parts(stream, q, nb, part.as<double>(), scal.as<double>() + slot);
+}
+
+// w = S^{-1} J y and the J-space update Jz, Jp (Jp = Jz + beta Jp)
+void Ctx::woodbury_mspace(const double* y, double* Jy, double* w) {
+    launch_rows_dot(stream, m, N(), J, ldj, y, jpart.as<double>(), Jy);
+    H1W_HIP(hipMemcpyAsync(w, Jy, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    solve_S(w);
+}
+
+// one preconditioner apply z = P^{-1} r without CG bookkeeping (h1w_precond_apply)
+void Ctx::precond_one(const double* r, double* z, int zm) {
+    const int64_t n = N();
+    double* y = nv(kY);
+    double* u = nv(kU);
+    double* Jy = mv(kJy);
+    double* w = mv(kW);
+    apply_B(1, r, n, y, n);
+    woodbury_mspace(y, Jy, w);
+    if (zm == H1W_Z_STORED) {
+        if (fp32)
+            launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, 1.0 / alpha, z);
+        else
+            launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, 1.0 / alpha, z);
+    } else {
+        double* dummy = mv(kTmp);
+        H1W_HIP(hipMemsetAsync(dummy, 0, (size_t)m * sizeof(double), stream));
+        launch_jt_u_t(stream, m, n, J, ldj, w, dummy, r, 1.0 / alpha, u, nv(kT));
+        apply_B(1, u, n, z, n);
+    }
+}
+
+void Ctx::precond_apply(int k, const double* R, int64_t ldr, double* Zout, int64_t ldzo, int zm) {
+    if (!have_cap) throw Error{H1W_ESTATE, "no capacitance matrix: call h1w_capacitance_build first"};
+    if (zm == H1W_Z_AUTO) zm = fp32 ? H1W_Z_STORED : H1W_Z_RECOMPUTE;
+    require(zm == H1W_Z_STORED || zm == H1W_Z_RECOMPUTE, "zmode must be AUTO, STORED or RECOMPUTE");
+    require(!(fp32 && zm == H1W_Z_RECOMPUTE), "a MIXED context needs zmode STORED");
+    ensure_cg_ws(m);
+    for (int i = 0; i < k; ++i) precond_one(R + (int64_t)i * ldr, Zout + (int64_t)i * ldzo, zm);
+    sync();
+}
+
+// y = alpha*A x + J^T (J x)
+void Ctx::gn_apply(int mm, const double* JJ, int64_t ldjj, double al, const double* x, double* y) {
+    const int64_t n = N();
+    double* tmp = nv(kTmpN);
+    double* Jx = mv(kJx);
+    launch_apply<double>(stream, dim, lv[0], 1, x, n, tmp, n, al);
+    if (mm > 0) {
+        launch_rows_dot(stream, mm, n, JJ, ldjj, x, jpart.as<double>(), Jx);
+        launch_jt_plain(stream, mm, n, JJ, ldjj, Jx, y, tmp, 1.0);
+    } else {
+        H1W_HIP(hipMemcpyAsync(y, tmp, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    }
+}
+
+// ============================================================ GN solve
+
+void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const double* b_, const double* dvec,
+                   const double* res, double* x, const h1w_solve_opts& o, h1w_info* info) {
+    const int64_t n = N();
+    ev_reserve();
+    H1W_HIP(hipEventRecord(ev[5], stream));
+    if (m_ > 0) {
+        capacitance_build(m_, J_, ldj_, alpha_, o.factor, info);
+    } else {
+        have_cap = false;
+        m = 0;
+        J = J_;
+        ldj = ldj_;
+        alpha = alpha_;
+    }
+    ensure_cg_ws(m);
+    int zm = o.zmode;
+    if (zm == H1W_Z_AUTO) zm = fp32 ? H1W_Z_STORED : H1W_Z_RECOMPUTE;
+    require(!(fp32 && zm == H1W_Z_RECOMPUTE), "a MIXED context needs zmode STORED");
+    const bool flexible = fp32;
+    const double rtol = o.rtol > 0 ? o.rtol : 1e-10;
+    const int maxit = o.maxit > 0 ? o.maxit : 500;
+    const double ia = 1.0 / alpha;
+    ev_record(4);
+
+    double *r = nv(kR), *p = nv(kP), *q = nv(kQ), *y = nv(kY), *u = nv(kU), *z = nv(kZ), *t = nv(kT),
+           *bb = nv(kB), *tmp = nv(kTmpN);
+    double *Jy = mv(kJy), *w = mv(kW), *Jz = mv(kJz), *Jp = mv(kJp);
+    const double* b = b_;
+    if (!b) {  // paper-form right-hand side b = -alpha*A d - J^T res
+        launch_apply<double>(stream, dim, lv[0], 1, dvec, n, tmp, n, alpha);
+        if (m > 0)
+            launch_jt_plain(stream, m, n, J, ldj, res, bb, tmp, 1.0);
+        else
+            H1W_HIP(hipMemcpyAsync(bb, tmp, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        launch_axpby(stream, n, -1.0, bb, 0.0, bb);
+        b = bb;
+    }
+    H1W_HIP(hipMemsetAsync(x, 0, n * sizeof(double), stream));
+    H1W_HIP(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    H1W_HIP(hipMemsetAsync(p, 0, n * sizeof(double), stream));
+    H1W_HIP(hipMemsetAsync(q, 0, n * sizeof(double), stream));
+    if (m > 0) H1W_HIP(hipMemsetAsync(Jp, 0, (size_t)m * sizeof(double), stream));
+    dots(n, {{b, b}}, 0);
+    read_scal(1);
+    const double bnorm = std::sqrt(hscal[0]);
+    if (!std::isfinite(bnorm)) throw Error{H1W_ENUMERIC, "non-finite right-hand side"};
+
+    int it = 0, restarts = 0;
+    double rz = 0.0, a = 0.0, relres_rec = 0.0, relres_true = 0.0;
+    h1w_status status = H1W_OK;
+
+    // z = P^{-1} r, p = z + beta p, t = J^T Jp; returns false if r.z <= 0 (converged to rounding)
+    auto precond_step = [&](bool first) -> bool {
+        apply_B(1, r, n, y, n);
+        if (m == 0) {
+            dots(n, {{r, y}, {y, q}}, 0);
+            read_scal(2);
+            const double rzn = hscal[0] * ia;
+            const double zq = hscal[1] * ia;
+            if (!(rzn > 0.0)) return false;
+            const double beta = first ? 0.0 : (flexible ? -a * zq / rz : rzn / rz);
+            rz = rzn;
+            launch_axpby(stream, n, ia, y, beta, p);
+            H1W_HIP(hipMemsetAsync(t, 0, n * sizeof(double), stream));
+            return true;
+        }
+        woodbury_mspace(y, Jy, w);
+        double beta = 0.0;
+        if (zm == H1W_Z_RECOMPUTE) {
+            dots(n, {{r, y}}, 0);
+            dots(m, {{w, Jy}}, 1);
+            read_scal(2);
+            const double rzn = (hscal[0] - hscal[1]) * ia;  // r.z with z = B(r - J^T w)/alpha
+            if (!(rzn > 0.0)) return false;
+            beta = first ? 0.0 : rzn / rz;
+            rz = rzn;
+            launch_jz_update(stream, m, Sbuf.as<double>(), alpha, Jy, w, beta, Jz, Jp);
+            launch_jt_u_t(stream, m, n, J, ldj, w, Jp, r, ia, u, t);
+            apply_B(1, u, n, z, n);
+            launch_axpby(stream, n, 1.0, z, beta, p);
+        } else {
+            if (fp32)
+                launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, z);
+            else
+                launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, ia, z);
+            dots(n, {{z, r}, {z, q}}, 0);
+            read_scal(2);
+            const double rzn = hscal[0], zq = hscal[1];
+            if (!(rzn > 0.0)) return false;
+            beta = first ? 0.0 : (flexible ? -a * zq / rz : rzn / rz);
+            rz = rzn;
+            launch_jz_update(stream, m, Sbuf.as<double>(), alpha, Jy, w, beta, Jz, Jp);
+            launch_axpby(stream, n, 1.0, z, beta, p);
+            launch_jt_plain(stream, m, n, J, ldj, Jp, t, nullptr, 0.0);
+        }
+        return true;
+    };
+    auto true_relres = [&]() -> double {
+        gn_apply(m, J, ldj, alpha, x, z);  // z is free here; gn_apply uses tmp internally
+        launch_sub(stream, n, b, z, u);
+        dots(n, {{u, u}}, 0);
+        read_scal(1);
+        return bnorm > 0 ? std::sqrt(hscal[0]) / bnorm : 0.0;
+    };
+
+    if (bnorm == 0.0) {
+        relres_true = 0.0;
+    } else {
+        bool ok = precond_step(true);
+        for (;;) {
+            if (ok) {
+                int np = 0;
+                launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np);
+                launch_reduce_parts(stream, 1, np, part.as<double>(), scal.as<double>());
+                read_scal(1);
+                const double pq = hscal[0];
+                if (!std::isfinite(pq)) {
+                    status = H1W_ENUMERIC;
+                    break;
+                }
+                if (pq <= 0.0) ok = false;
+            }
+            if (ok) {
+                a = rz / hscal[0];
+                int np = 0;
+                launch_cg_update(stream, n, a, p, q, x, r, part.as<double>(), &np);
+                launch_reduce_parts(stream, 1, np, part.as<double>(), scal.as<double>());
+                read_scal(1);
+                if (!std::isfinite(hscal[0])) {
+                    status = H1W_ENUMERIC;
+                    break;
+                }
+                relres_rec = std::sqrt(hscal[0]) / bnorm;
+                ++it;
+            }
+            if (!ok || relres_rec <= rtol) {
+                relres_true = true_relres();
+                if (!std::isfinite(relres_true)) {
+                    status = H1W_ENUMERIC;
+                    break;
+                }
+                if (relres_true <= rtol) break;
+                if (++restarts > 8 || it >= maxit) {
+                    status = H1W_ENOCONV;
+                    break;
+                }
+                // restart from the true residual
+                H1W_HIP(hipMemcpyAsync(r, u, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+                ok = precond_step(true);
+                if (!ok) {  // r.z <= 0 while the true residual is above tolerance
+                    status = H1W_ENOCONV;
+                    break;
+                }
+                continue;
+            }
+            if (it >= maxit) {
+                relres_true = true_relres();
+                status = relres_true <= rtol ? H1W_OK : H1W_ENOCONV;
+                break;
+            }
+            ok = precond_step(false);
+        }
+    }
+    ev_record(6);
+    sync();
+    if (info) {
+        info->iters = it;
+        info->restarts = restarts;
+        info->relres_true = relres_true;
+        info->relres_rec = relres_rec;
+        info->zmode_used = m > 0 ? zm : 0;
+        info->t_cg_ms = ev_ms(4, 6);
+        info->t_total_ms = ev_ms(5, 6);
+        info->nlevels = (int)lv.size();
+    }
+    if (status == H1W_ENOCONV) throw Error{H1W_ENOCONV, "GN-CG did not reach rtol within maxit iterations"};
+    if (status == H1W_ENUMERIC) throw Error{H1W_ENUMERIC, "NaN or Inf in the CG recurrences"};
+}
+
+// ============================================================ events
+
+void Ctx::ev_reserve() {
+    for (auto& e : ev)
+        if (!e) H1W_HIP(hipEventCreate(&e));
+}
+void Ctx::ev_record(int i) {
+    ev_reserve();
+    H1W_HIP(hipEventRecord(ev[i], stream));
+}
+double Ctx::ev_ms(int a, int b) {
+    float ms = 0.f;
+    H1W_HIP(hipEventElapsedTime(&ms, ev[a], ev[b]));
+    return ms;
+}
+
+template void Ctx::vcycle<double>(int, const double*, int64_t, double*, int64_t);
+template void Ctx::vcycle<float>(int, const float*, int64_t, float*, int64_t);
+
+}  // namespace h1w

@@ -1,0 +1,163 @@
+// Internal declarations of the h1w HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "h1w.h"
+
+namespace h1w {
+
+// Geometry of one grid level, passed by value to the stencil kernels.
+// 2D grids use nz = 1 and the DIM = 2 kernels.
+struct Geom {
+    int nx, ny, nz;
+    int64_t N;
+    double ihx2, ihy2, ihz2;  // 1/h_d^2
+    double beta;
+};
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    h1w_status st;
+    std::string msg;
+};
+
+#define H1W_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::h1w::Error{H1W_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define H1W_LAUNCHED() H1W_HIP(hipGetLastError())
+
+inline void require(bool ok, const std::string& msg) {
+    if (!ok) throw Error{H1W_EINVAL, msg};
+}
+
+// ---------------------------------------------------------------- device memory
+// Owning device buffer (the library's own workspace; caller arrays are raw pointers).
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        // work queued on any stream may still use the buffer
+        if (p) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+        }
+        p = nullptr;
+        bytes = 0;
+    }
+    // grow to at least `need` bytes (contents not preserved)
+    void reserve(size_t need) {
+        if (need <= bytes) return;
+        release();
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw Error{e == hipErrorOutOfMemory ? H1W_ENOMEM : H1W_EHIP,
+                        "hipMalloc of " + std::to_string(need) + " bytes failed: " + hipGetErrorName(e) + " (" +
+                            hipGetErrorString(e) + ")"};
+        }
+        bytes = need;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- kernel launchers
+// stencil.hip (T = double or float)
+template <typename T>
+void launch_apply(hipStream_t s, int dim, const Geom& g, int k, const T* X, int64_t ldx, T* Y,
+                  int64_t ldy, double scale);
+template <typename T>
+void launch_smooth_first(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
+                         T* X, int64_t ldx, double w);
+template <typename T>
+void launch_smooth(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
+                   const T* Xin, int64_t ldi, T* Xout, int64_t ldo, double w);
+template <typename T>
+void launch_residual(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
+                     const T* X, int64_t ldx, T* R, int64_t ldr);
+template <typename T>
+void launch_restrict(hipStream_t s, int dim, const Geom& gf, const Geom& gc, int k, const T* R,
+                     int64_t ldr, T* Fc, int64_t ldc);
+template <typename T>
+void launch_prolong_add(hipStream_t s, int dim, const Geom& gf, const Geom& gc, int k,
+                        const T* Ec, int64_t ldc, T* X, int64_t ldx);
+template <typename T>
+void launch_coarse_solve(hipStream_t s, int64_t Nc, const T* Cinv, int k, const T* F,
+                         int64_t ldf, T* X, int64_t ldx);
+template <typename TI, typename TO>
+void launch_convert(hipStream_t s, int64_t N, int k, const TI* X, int64_t ldx, TO* Y,
+                    int64_t ldy, double scale);
+// q = a*A p + t  and per-block partial sums of p.q  (double only)
+void launch_apply_plus_dot(hipStream_t s, int dim, const Geom& g, double a, const double* P,
+                           const double* Tv, double* Q, double* partial, int* nparts);
+
+// blas.hip
+// partial dot products of npair vector pairs over N entries; returns #parts
+int launch_dots_partial(hipStream_t s, int64_t N, int npair, const double* const* X,
+                        const double* const* Y, double* partial);
+void launch_reduce_parts(hipStream_t s, int nvec, int nparts, const double* partial,
+                         double* out);
+// per-row dot products out[i] = sum_n M[i,n] v[n] for i < m (M double), deterministic
+void launch_rows_dot(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm,
+                     const double* v, double* partial, double* out);
+size_t rows_dot_partial_elems(int m, int64_t N);
+// transpose products, see blas.hip for the epilogue modes
+void launch_jt_u_t(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
+                   const double* w, const double* jp, const double* r, double inv_alpha,
+                   double* u, double* t);
+void launch_jt_plain(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
+                     const double* v, double* out, const double* add, double add_coef);
+template <typename TZ>
+void launch_p_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
+                     const double* J, int64_t ldj, const double* jp, const double* y,
+                     double inv_alpha, double beta, double* p, double* t);
+template <typename TZ>
+void launch_z_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
+                     const double* y, double inv_alpha, double* z);
+void launch_axpby(hipStream_t s, int64_t N, double a, const double* x, double b, double* y);
+void launch_cg_update(hipStream_t s, int64_t N, double a, const double* p, const double* q,
+                      double* x, double* r, double* partial, int* nparts);
+void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, double* out);
+// batched (per-row coefficient) helpers for MG-PCG
+void launch_batched_dots(hipStream_t s, int k, int64_t N, const double* X, int64_t ldx,
+                         const double* Y, int64_t ldy, double* partial, double* out);
+void launch_batched_cg_xr(hipStream_t s, int k, int64_t N, const double* a, const double* P,
+                          int64_t ldp, const double* Q, int64_t ldq, double* X, int64_t ldx,
+                          double* R, int64_t ldr, const int* active);
+void launch_batched_p(hipStream_t s, int k, int64_t N, const double* b, const double* Z,
+                      int64_t ldz, double* P, int64_t ldp, const int* active);
+
+// gemm.hip: S = alpha*I + J Z^T with FP64 accumulation on MFMA
+template <typename TZ>
+void launch_capacitance_gemm(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
+                             const TZ* Z, int64_t ldz, bool lower_only, double alpha,
+                             double* partial, size_t partial_elems, double* S, int64_t lds);
+size_t gemm_partial_elems(int m, int64_t N);
+
+// dense.hip (single-workgroup factorisations for m <= a few thousand)
+void launch_cholesky_upper(hipStream_t s, int m, double* U, int* info);
+void launch_lu(hipStream_t s, int m, double* A, int* piv, int* info);
+void launch_transpose(hipStream_t s, int m, const double* A, double* At);
+void launch_chol_solve(hipStream_t s, int m, const double* U, const double* L, double* x);
+void launch_lu_solve(hipStream_t s, int m, const double* LUt, const double* LU, const int* piv,
+                     double* x);
+void launch_jz_update(hipStream_t s, int m, const double* S, double alpha, const double* Jy,
+                      const double* w, double beta, double* Jz, double* Jp);
+void launch_asym(hipStream_t s, int m, const double* S, double* out);
+
+}  // namespace h1w

@@ -1,0 +1,356 @@
+"""GPU parity: every entry point of the HIP library against the CPU oracle on
+the same seeded inputs (run through the C ABI via the ctypes binding).
+
+Tolerances:
+  * operator apply: elementwise |Y - Y*| <= c * eps * (|A| |X|) (forward error
+    of a 7-term sum), eps = 2^-52 (FP64) or 2^-23 (FP32).
+  * V-cycle B (FP64): relative 100 * eps * cond(A_coarsest) per row: the
+    same operator, but the coarsest solve is a dense-inverse product on the
+    GPU and an LU solve in the oracle, whose forward errors are each bounded
+    by a small multiple of eps * cond(A_coarsest). FP32 B: relative 2e-5.
+  * capacitance S (FP64): max |S - S*| <= (the V-cycle bound) * max |S*|.
+  * GN solve: the true relative residual ||b - G x||/||b||, recomputed by the
+    oracle in FP64 from the GPU's x, is <= rtol (1e-10 FP64, 1e-8 mixed), and
+    ||x - x*|| <= cond(G) * relres * ||x*|| where x* is the oracle's direct
+    solution and cond(G) is computed densely where N is small.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import h1w_inputs as H
+from oracle import gn, multigrid as mg, operator as op, poisson
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS64 = 2.0 ** -52
+EPS32 = 2.0 ** -23
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2209_02815_amd as P
+    return P
+
+
+def dev(a, dtype=None):
+    dtype = dtype or torch.float64
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0").to(dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def padded(rows, N, pad=7, dtype=None):
+    """(rows, N) view with leading dimension N + pad (exercises ld > N)."""
+    full = torch.zeros((rows, N + pad), dtype=dtype or torch.float64, device="cuda:0")
+    return full[:, :N]
+
+
+def rel_rows(X, Xref):
+    return np.linalg.norm(X - Xref, axis=-1) / np.linalg.norm(Xref, axis=-1)
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("shape", [(33, 33), (17, 9), (2, 2), (17, 17, 17), (9, 17, 5), (3, 5, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_operator_apply(P, shape, prec):
+    beta = 1e-2
+    N = int(np.prod(shape))
+    X = rng(0).standard_normal((3, N))
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    with P.Context(shape, beta) as ctx:
+        Xd = padded(3, N, dtype=tdt)
+        Xd.copy_(dev(X, tdt))
+        Yd = padded(3, N, pad=3, dtype=tdt)
+        ctx.operator_apply(Xd, Yd)
+        Y = host(Yd)
+    Xs = host(Xd)  # the exact (possibly FP32-rounded) input
+    A = op.gram_operator(shape, beta)
+    Yref = op.apply(shape, beta, Xs)
+    bound = (abs(A) @ np.abs(Xs).T).T
+    eps = EPS64 if prec == "fp64" else EPS32
+    assert np.all(np.abs(Y - Yref) <= 16 * eps * bound + 1e-300)
+
+
+# ------------------------------------------------------------------ V-cycle
+VC_CASES = [
+    ((33, 33), 9, 2), ((33, 33), 289, 2), ((65, 65), 25, 3), ((17, 9), 1, 1),
+    ((17, 17, 17), 27, 2), ((17, 17, 17), 729, 1), ((9, 17, 5), 1, 2), ((33, 33, 33), 125, 2),
+]
+
+
+@pytest.mark.parametrize("shape,cmax,nu", VC_CASES)
+def test_vcycle_fp64_matches_oracle(P, shape, cmax, nu):
+    beta = 1e-2
+    N = int(np.prod(shape))
+    F = rng(1).standard_normal((5, N))
+    with P.Context(shape, beta, nu=nu, coarse_max=cmax, rhs_chunk=2) as ctx:
+        Fd = padded(5, N)
+        Fd.copy_(dev(F))
+        Xd = padded(5, N, pad=11)
+        ctx.vcycle(Fd, Xd)
+        X = host(Xd)
+        nl = ctx.nlevels
+    V = mg.VCycle(shape, beta, nu=nu, coarse_max=cmax)
+    assert nl == V.nlevels
+    Xref = V.apply(F)
+    assert rel_rows(X, Xref).max() < 100 * EPS64 * np.linalg.cond(V.Acoarse)
+
+
+@pytest.mark.parametrize("shape,cmax,nu", [VC_CASES[0], VC_CASES[4], VC_CASES[7]])
+def test_vcycle_fp32_matches_oracle(P, shape, cmax, nu):
+    beta = 1e-2
+    N = int(np.prod(shape))
+    F = rng(2).standard_normal((4, N)).astype(np.float32)
+    with P.Context(shape, beta, precision="mixed", nu=nu, coarse_max=cmax) as ctx:
+        Fd = dev(F, torch.float32)
+        X = host(ctx.vcycle(Fd))
+    Xref = mg.VCycle(shape, beta, nu=nu, coarse_max=cmax).apply(F.astype(np.float64))
+    assert rel_rows(X, Xref).max() < 2e-5
+
+
+def test_vcycle_symmetric_and_linear(P):
+    shape, beta = (17, 17, 17), 1e-2
+    N = int(np.prod(shape))
+    U = rng(3).standard_normal((2, N))
+    with P.Context(shape, beta, coarse_max=27) as ctx:
+        BU = host(ctx.vcycle(dev(U)))
+        Bsum = host(ctx.vcycle(dev(U[:1] + 2.0 * U[1:])))
+    assert abs(U[0] @ BU[1] - U[1] @ BU[0]) <= 1e-13 * np.linalg.norm(U[0]) * np.linalg.norm(BU[1])
+    assert np.linalg.norm(Bsum[0] - BU[0] - 2 * BU[1]) <= 1e-13 * np.linalg.norm(Bsum[0])
+
+
+@pytest.mark.parametrize("shape,prec", [((33, 33), "fp64"), ((17, 17, 17), "fp64"), ((33, 33, 33), "fp64"),
+                                        ((17, 17, 17), "mixed")])
+def test_mg_solve(P, shape, prec):
+    beta = 1e-2
+    N = int(np.prod(shape))
+    F = rng(4).standard_normal((3, N))
+    with P.Context(shape, beta, precision=prec) as ctx:
+        X, info = ctx.mg_solve(dev(F), rtol=1e-10)
+        X = host(X)
+    A = op.gram_operator(shape, beta)
+    rr = np.linalg.norm(F - (A @ X.T).T, axis=1) / np.linalg.norm(F, axis=1)
+    assert rr.max() <= 1e-10 * 1.01
+    assert info.relres_true <= 1e-10 * 1.01
+    Xs = poisson.dct_solve(shape, beta, F)
+    # ||x - x*|| <= ||A^-1|| ||F - A x||, ||A^-1|| = 1/(beta * min W) (smallest generalised eigenvalue beta)
+    wmin = 0.5 ** len(shape)
+    bound = np.linalg.norm(F - (A @ X.T).T, axis=1) / (beta * wmin)
+    assert np.all(np.linalg.norm(X - Xs, axis=1) <= 1.01 * bound + 1e-12)
+
+
+# ------------------------------------------------------------------ capacitance
+def _bump_problem(name, m=None):
+    wl = H.workload(name)
+    if m is not None:
+        wl = wl.with_(m=m)
+    return wl, H.j_rows(wl), H.rhs_b(wl)
+
+
+@pytest.mark.parametrize("name,m,cmax", [("square33", None, 9), ("cube17", None, 27), ("square33", 130, 0),
+                                         ("cube17", 3, 0)])
+def test_capacitance_fp64(P, name, m, cmax):
+    wl, J, _ = _bump_problem(name, m)
+    with P.Context(wl.shape, wl.beta, coarse_max=cmax) as ctx:
+        S, Z, info = ctx.capacitance_build(dev(J), wl.alpha, want_S=True, want_Z=True)
+        S, Z = host(S), host(Z)
+    V = mg.VCycle(wl.shape, wl.beta, coarse_max=cmax or None)
+    Zref = V.apply(J)
+    Sref = wl.alpha * np.eye(J.shape[0]) + J @ Zref.T
+    tol = 100 * EPS64 * np.linalg.cond(V.Acoarse)   # Z inherits the coarsest-solve rounding
+    assert rel_rows(Z, Zref).max() < tol
+    assert np.abs(S - Sref).max() <= tol * np.abs(Sref).max()
+    assert info.factor_used == 1  # Cholesky
+    assert np.array_equal(S, S.T)
+
+
+@pytest.mark.parametrize("name,m", [("square33", 130), ("cube17", None)])
+def test_capacitance_mixed(P, name, m):
+    wl, J, _ = _bump_problem(name, m)
+    with P.Context(wl.shape, wl.beta, precision="mixed") as ctx:
+        S, Z, info = ctx.capacitance_build(dev(J), wl.alpha, want_S=True, want_Z=True)
+        S, Z = host(S), host(Z)
+    # the FP64 product of the given J and the GPU's FP32 Z (exact conversion)
+    Sref = wl.alpha * np.eye(J.shape[0]) + J @ Z.T
+    assert np.abs(S - Sref).max() <= 1e-13 * np.abs(Sref).max()
+    Zref = mg.VCycle(wl.shape, wl.beta).apply(J)
+    assert rel_rows(Z, Zref).max() < 2e-5
+    assert info.factor_used == 2  # LU
+    assert info.asym_S_over_alpha > 0
+
+
+# ------------------------------------------------------------------ preconditioner
+@pytest.mark.parametrize("zmode", [1, 2])
+def test_precond_apply_fp64(P, zmode):
+    wl, J, _ = _bump_problem("cube17")
+    R = rng(5).standard_normal((2, wl.N))
+    with P.Context(wl.shape, wl.beta) as ctx:
+        ctx.capacitance_build(dev(J), wl.alpha)
+        Zp = host(ctx.precond_apply(dev(R), zmode=zmode))
+    V = mg.VCycle(wl.shape, wl.beta)
+    ref = gn.woodbury_precond(V.apply, J, wl.alpha, R)
+    assert rel_rows(Zp, ref).max() < 1e-8
+    # (alpha B^-1 + J^T J) z = r  <=>  alpha z + B J^T J z = B r
+    lhs = wl.alpha * Zp + V.apply((J.T @ (J @ Zp.T)).T)
+    assert rel_rows(lhs, V.apply(R)).max() < 1e-8
+
+
+def test_precond_apply_mixed_consistency(P):
+    wl, J, _ = _bump_problem("cube17")
+    R = rng(6).standard_normal((1, wl.N))
+    with P.Context(wl.shape, wl.beta, precision="mixed") as ctx:
+        _, Z, _ = ctx.capacitance_build(dev(J), wl.alpha, want_Z=True)
+        Zp = host(ctx.precond_apply(dev(R)))
+        Z = host(Z)
+    # with S~ consistent with Z~: J z = w and y~ = alpha z + Z~^T w, y~ ~ B r (FP32 V-cycle)
+    ytil = wl.alpha * Zp[0] + Z.T @ (J @ Zp[0])
+    yref = mg.VCycle(wl.shape, wl.beta).apply(R[0])
+    assert np.linalg.norm(ytil - yref) <= 1e-4 * np.linalg.norm(yref)
+
+
+def test_precond_before_capacitance_is_state_error(P):
+    with P.Context((17, 17), 1e-2) as ctx:
+        with pytest.raises(P.H1WError) as e:
+            ctx.precond_apply(dev(np.ones((1, 289))))
+        assert e.value.status == -8
+
+
+# ------------------------------------------------------------------ GN solve
+def _cond_bound(wl, J):
+    G = gn.gn_dense(wl.shape, wl.beta, J, wl.alpha)
+    ev = np.linalg.eigvalsh(G)
+    return ev[-1] / ev[0]
+
+
+@pytest.mark.parametrize("prec,zmode,rtol", [("fp64", 2, 1e-10), ("fp64", 1, 1e-10), ("mixed", 1, 1e-8),
+                                             ("mixed", 1, 1e-10)])
+def test_gn_solve_square33(P, prec, zmode, rtol):
+    wl, J, b = _bump_problem("square33")
+    with P.Context(wl.shape, wl.beta, precision=prec) as ctx:
+        x, info = ctx.gn_solve(dev(J), wl.alpha, b=dev(b), rtol=rtol, zmode=zmode)
+        x = host(x)
+    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
+    assert rr <= rtol * 1.01, (rr, info.as_dict())
+    assert abs(rr - info.relres_true) <= 1e-3 * rtol + 1e-15
+    xs = gn.solve_dense(wl.shape, wl.beta, J, wl.alpha, b)
+    kappa = _cond_bound(wl, J)
+    assert np.linalg.norm(x - xs) <= 1.01 * kappa * rr * np.linalg.norm(xs)
+    assert info.iters <= 20
+
+
+@pytest.mark.parametrize("name,prec,rtol", [("cube17", "fp64", 1e-10), ("cube17", "mixed", 1e-8),
+                                            ("cube33", "fp64", 1e-10), ("cube33", "mixed", 1e-8),
+                                            ("square129", "fp64", 1e-10), ("square129", "mixed", 1e-8)])
+def test_gn_solve_bumps(P, name, prec, rtol):
+    wl, J, b = _bump_problem(name)
+    with P.Context(wl.shape, wl.beta, precision=prec) as ctx:
+        x, info = ctx.gn_solve(dev(J), wl.alpha, b=dev(b), rtol=rtol)
+        x = host(x)
+    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
+    assert rr <= rtol * 1.01, (rr, info.as_dict())
+    xs = gn.solve_woodbury(wl.shape, wl.beta, J, wl.alpha, b)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    print(f"{name} {prec}: iters={info.iters} relres={rr:.2e} err={err:.2e}")
+    assert info.iters <= 25
+
+
+def test_gn_paper_rhs_matches_closed_form_update(P):
+    wl, J, _ = _bump_problem("square33")
+    d, res = H.paper_data(wl)
+    with P.Context(wl.shape, wl.beta) as ctx:
+        x, info = ctx.gn_solve(dev(J), wl.alpha, d=dev(d), res=dev(res), rtol=1e-11)
+        x = host(x)
+    b = gn.paper_rhs(wl.shape, wl.beta, J, wl.alpha, d, res)
+    assert gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x) <= 1.01e-11
+    dm = gn.paper_update(wl.shape, wl.beta, J, wl.alpha, d, res)
+    kappa = _cond_bound(wl, J)
+    assert np.linalg.norm(x - dm) <= 1.01 * kappa * 1.01e-11 * np.linalg.norm(dm)
+
+
+def test_gn_without_rows_is_scaled_poisson(P):
+    shape, beta, alpha = (33, 33), 1e-2, 1e-3
+    b = rng(7).standard_normal(1089)
+    with P.Context(shape, beta) as ctx:
+        x, info = ctx.gn_solve(None, alpha, b=dev(b), rtol=1e-11)
+        x = host(x)
+    xs = poisson.dct_solve(shape, beta, b) / alpha
+    rr = np.linalg.norm(b - alpha * op.apply(shape, beta, x)) / np.linalg.norm(b)
+    assert rr <= 1.01e-11
+    assert np.linalg.norm(x - xs) <= np.linalg.norm(b - alpha * op.apply(shape, beta, x)) / (alpha * beta * 0.25) * 1.01
+
+
+def test_gn_maxit_reports_noconv_with_last_iterate(P):
+    wl, J, b = _bump_problem("square33")
+    with P.Context(wl.shape, wl.beta) as ctx:
+        xd = dev(np.zeros(wl.N))
+        info, st = P._native.h1w_gn_solve(ctx.handle, dev(J), wl.alpha, xd, b=dev(b), rtol=1e-14, maxit=1,
+                                          raise_on_error=False)
+        x = host(xd)
+    assert st == P._native.H1W_ENOCONV
+    assert info.iters == 1 and info.relres_true > 1e-14
+    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
+    assert abs(rr - info.relres_true) <= 1e-6 * rr
+
+
+def test_gn_nan_rhs_is_numeric_error(P):
+    wl, J, b = _bump_problem("square33")
+    b[5] = np.nan
+    with P.Context(wl.shape, wl.beta) as ctx:
+        with pytest.raises(P.H1WError) as e:
+            ctx.gn_solve(dev(J), wl.alpha, b=dev(b))
+        assert e.value.status == -6
+
+
+def test_gn_invalid_arguments(P):
+    wl, J, b = _bump_problem("square33")
+    with P.Context(wl.shape, wl.beta) as ctx:
+        with pytest.raises(P.H1WError) as e:
+            ctx.gn_solve(dev(J), -1.0, b=dev(b))
+        assert e.value.status == -1
+        with pytest.raises(P.H1WError):
+            ctx.gn_solve(dev(J), wl.alpha, b=dev(b), zmode=7)
+    with P.Context(wl.shape, wl.beta, precision="mixed") as ctx:
+        with pytest.raises(P.H1WError):
+            ctx.gn_solve(dev(J), wl.alpha, b=dev(b), zmode=2)
+
+
+def test_gn_apply_matches_oracle(P):
+    wl, J, b = _bump_problem("cube17")
+    x = rng(8).standard_normal(wl.N)
+    with P.Context(wl.shape, wl.beta) as ctx:
+        y = host(ctx.gn_apply(dev(J), wl.alpha, dev(x)))
+    yref = gn.gn_apply(wl.shape, wl.beta, J, wl.alpha, x)
+    assert np.linalg.norm(y - yref) <= 1e-13 * np.linalg.norm(yref)
+
+
+def test_alpha_robustness(P):
+    # Woodbury-PCG iteration counts do not grow as alpha shrinks (the paper's
+    # regularisation-sweep claim for the Laplace-Woodbury preconditioner).
+    wl, J, b = _bump_problem("square129")
+    its = []
+    with P.Context(wl.shape, wl.beta) as ctx:
+        for alpha in [1e-2, 1e-4, 1e-6]:
+            x, info = ctx.gn_solve(dev(J), alpha, b=dev(b), rtol=1e-10)
+            its.append(info.iters)
+            rr = gn.true_relres(wl.shape, wl.beta, J, alpha, b, host(x))
+            assert rr <= 1.01e-10
+    assert max(its) <= 15 and max(its) - min(its) <= 3, its
+
+
+def test_gn_solve_deterministic(P):
+    wl, J, b = _bump_problem("cube17")
+    with P.Context(wl.shape, wl.beta) as ctx:
+        Jd, bd = dev(J), dev(b)
+        x1, _ = ctx.gn_solve(Jd, wl.alpha, b=bd)
+        x2, _ = ctx.gn_solve(Jd, wl.alpha, b=bd)
+        assert torch.equal(x1, x2)
