@@ -1,0 +1,348 @@
+// Blocked factorisations of the m x m capacitance matrix S (Algorithm 3,
+// third step) and the triangular solves of the preconditioner apply.
+//
+// Right-looking, block size NB = 64, three launches per block column kb:
+//   diag   one work-group factors the NB x NB diagonal block in LDS
+//          (Cholesky S_kk = U^T U, or LU without pivoting) and writes the
+//          explicit inverses of its triangular factors (Dinv_fwd, Dinv_bwd)
+//   panel  Cholesky: U[kb, jb] = U_kk^{-T} A[kb, jb]                (jb > kb)
+//          LU:       U[kb, jb] = L_kk^{-1} A[kb, jb], L[ib, kb] = A[ib, kb] U_kk^{-1}
+//   update Cholesky: A[ib, jb] -= U[kb, ib]^T U[kb, jb]             (kb < ib <= jb)
+//          LU:       A[ib, jb] -= L[ib, kb] U[kb, jb]               (ib, jb > kb)
+// The NB x NB block products run on v_mfma_f64_16x16x4_f64: 4 waves, each a
+// 32 x 32 quadrant = 2 x 2 MFMA blocks, K = NB in 16 steps, operands read
+// straight from global memory (S is at most a few MB and stays in L2).
+// A failed pivot stops the factorisation: info[0] is set and every later
+// launch returns immediately.
+//
+// Triangular solves with a factor T run in one work-group: block by block,
+// the right-hand side is updated with the already-solved part (T accessed
+// through its transpose C, C[j][i] = T[i][j], so reads are coalesced) and
+// multiplied by the explicit inverse of the diagonal block.
+#include <algorithm>
+
+#include "devutil.h"
+#include "internal.h"
+
+namespace h1w {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int NB = 64;
+
+__device__ __forceinline__ double ld_blk(const double* A, int m, int r, int c) {
+    return (r < m && c < m) ? A[(int64_t)r * m + c] : 0.0;
+}
+
+// acc (this wave's 32x32 quadrant as 2x2 MFMA blocks) += op(X) * Y over K = NB.
+// op(X)[r][k] = X[r0 + r][k0 + k]  (tx = false) or X[k0 + k][r0 + r] (tx = true);
+// Y[k][c] = Y[y0 + k][c0 + c]. Out-of-range entries read as zero.
+__device__ __forceinline__ void mfma_block(const double* X, int xr0, int xk0, bool tx, const double* Y, int yk0,
+                                           int yc0, int m, d4 acc[2][2]) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int qr = (wave >> 1) * 32, qc = (wave & 1) * 32;
+#pragma unroll 4
+    for (int s = 0; s < NB / 4; ++s) {
+        const int k = 4 * s + g;
+        double a[2], b[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int r = qr + 16 * t + l16;
+            a[t] = tx ? ld_blk(X, m, xk0 + k, xr0 + r) : ld_blk(X, m, xr0 + r, xk0 + k);
+            const int c = qc + 16 * t + l16;
+            b[t] = ld_blk(Y, m, yk0 + k, yc0 + c);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Element (row, col) of the quadrant held by (lane, i, j, v): FP64 16x16 MFMA
+// accumulator layout is row = (lane/16) + 4v, col = lane%16.
+__device__ __forceinline__ void quad_pos(int i, int j, int v, int& r, int& c) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    r = (wave >> 1) * 32 + 16 * i + (lane >> 4) + 4 * v;
+    c = (wave & 1) * 32 + 16 * j + (lane & 15);
+}
+
+// ---------------------------------------------------------------- diag
+// mode 0: Cholesky (upper), mode 1: LU without pivoting.
+__global__ __launch_bounds__(256) void k_blk_diag(int m, double* __restrict__ A, int kb, int mode,
+                                                  double* __restrict__ Dfwd, double* __restrict__ Dbwd,
+                                                  int* __restrict__ info) {
+    __shared__ double D[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    __shared__ int fail;
+    if (info[0] >= 0) return;
+    const int o = kb * NB;
+    const int tid = threadIdx.x;
+    if (tid == 0) fail = -1;
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int r = e / NB, c = e % NB;
+        D[r][c] = (o + r < m && o + c < m) ? A[(int64_t)(o + r) * m + o + c] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int k = 0; k < NB; ++k) {
+        if (tid == 0) {
+            const double p = D[k][k];
+            const bool bad = mode == 0 ? !(p > 0.0) || !isfinite(p) : !(p != 0.0) || !isfinite(p);
+            if (bad) fail = o + k;
+            if (mode == 0) D[k][k] = sqrt(p);
+        }
+        __syncthreads();
+        if (fail >= 0) break;
+        const double p = D[k][k];
+        if (mode == 0) {
+            for (int j = k + 1 + tid; j < NB; j += 256) D[k][j] /= p;
+        } else {
+            for (int i = k + 1 + tid; i < NB; i += 256) D[i][k] /= p;
+        }
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int i = e / NB, j = e % NB;
+            if (i > k && j > k) {
+                if (mode == 0) {
+                    if (j >= i) D[i][j] -= D[k][i] * D[k][j];
+                } else {
+                    D[i][j] -= D[i][k] * D[k][j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (fail >= 0) {
+        if (tid == 0) info[0] = fail;
+        return;
+    }
+    // inverse of the upper factor: solve U X = I (one column per thread)
+    if (tid < NB) {
+        const int j = tid;
+        for (int i = NB - 1; i >= 0; --i) {
+            double s = (i == j) ? 1.0 : 0.0;
+            for (int l = i + 1; l <= j; ++l) s -= D[i][l] * X[l][j];
+            X[i][j] = (i <= j) ? s / D[i][i] : 0.0;
+        }
+    }
+    __syncthreads();
+    double* Fw = Dfwd + (int64_t)kb * NB * NB;
+    double* Bw = Dbwd + (int64_t)kb * NB * NB;
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int r = e / NB, c = e % NB;
+        Bw[e] = X[r][c];
+        if (mode == 0) Fw[e] = X[c][r];  // (U^T)^{-1} = (U^{-1})^T
+    }
+    __syncthreads();
+    if (mode == 1) {  // inverse of the unit-lower factor: L X = I
+        if (tid < NB) {
+            const int j = tid;
+            for (int i = 0; i < NB; ++i) {
+                double s = (i == j) ? 1.0 : 0.0;
+                for (int l = j; l < i; ++l) s -= D[i][l] * X[l][j];
+                X[i][j] = (i >= j) ? s : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += 256) Fw[e] = X[e / NB][e % NB];
+    }
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int r = e / NB, c = e % NB;
+        if (o + r < m && o + c < m) A[(int64_t)(o + r) * m + o + c] = D[r][c];
+    }
+}
+
+// ---------------------------------------------------------------- panel
+// blockIdx.x enumerates the blocks to the right of (and, for LU, below) kb.
+__global__ __launch_bounds__(256) void k_blk_panel(int m, double* __restrict__ A, int kb, int mode,
+                                                   const double* __restrict__ Dfwd, const double* __restrict__ Dbwd,
+                                                   const int* __restrict__ info) {
+    if (info[0] >= 0) return;
+    const int nb = (m + NB - 1) / NB;
+    const int rest = nb - kb - 1;
+    int b = blockIdx.x;
+    const bool row_panel = b < rest;  // U[kb, jb]
+    const int other = kb + 1 + (row_panel ? b : b - rest);
+    const int o = kb * NB;
+    d4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+    const double* F = Dfwd + (int64_t)kb * NB * NB;
+    const double* Bk = Dbwd + (int64_t)kb * NB * NB;
+    // block inverse stored as a full NB x NB row-major tile: index it as an
+    // m' = NB matrix with no bounds (pass m = NB to the loader).
+    if (row_panel) {
+        // out = Dfwd[kb] (NB x NB) * A[kb rows, other cols]
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int l16 = lane & 15, g = lane >> 4;
+        const int qr = (wave >> 1) * 32, qc = (wave & 1) * 32;
+        for (int s = 0; s < NB / 4; ++s) {
+            const int k = 4 * s + g;
+            double a[2], bb[2];
+            for (int t = 0; t < 2; ++t) {
+                a[t] = F[(qr + 16 * t + l16) * NB + k];
+                bb[t] = ld_blk(A, m, o + k, other * NB + qc + 16 * t + l16);
+            }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read the input block before it is overwritten
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int v = 0; v < 4; ++v) {
+                    int r, c;
+                    quad_pos(i, j, v, r, c);
+                    const int R = o + r, Cc = other * NB + c;
+                    if (R < m && Cc < m) A[(int64_t)R * m + Cc] = acc[i][j][v];
+                }
+    } else {
+        // out = A[other rows, kb cols] (NB x NB) * Dbwd[kb]
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int l16 = lane & 15, g = lane >> 4;
+        const int qr = (wave >> 1) * 32, qc = (wave & 1) * 32;
+        for (int s = 0; s < NB / 4; ++s) {
+            const int k = 4 * s + g;
+            double a[2], bb[2];
+            for (int t = 0; t < 2; ++t) {
+                a[t] = ld_blk(A, m, other * NB + qr + 16 * t + l16, o + k);
+                bb[t] = Bk[k * NB + qc + 16 * t + l16];
+            }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int v = 0; v < 4; ++v) {
+                    int r, c;
+                    quad_pos(i, j, v, r, c);
+                    const int R = other * NB + r, Cc = o + c;
+                    if (R < m && Cc < m) A[(int64_t)R * m + Cc] = acc[i][j][v];
+                }
+    }
+}
+
+// ---------------------------------------------------------------- trailing update
+__global__ __launch_bounds__(256) void k_blk_update(int m, double* __restrict__ A, int kb, int mode,
+                                                    const int* __restrict__ info) {
+    if (info[0] >= 0) return;
+    const int nb = (m + NB - 1) / NB;
+    const int rest = nb - kb - 1;
+    int ib, jb;
+    if (mode == 0) {  // upper-triangle blocks kb < ib <= jb, enumerated row by row
+        int t = blockIdx.x, i = 0;
+        while (t >= rest - i) {
+            t -= rest - i;
+            ++i;
+        }
+        ib = kb + 1 + i;
+        jb = ib + t;
+    } else {
+        ib = kb + 1 + blockIdx.x / rest;
+        jb = kb + 1 + blockIdx.x % rest;
+    }
+    const int o = kb * NB;
+    d4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+    if (mode == 0)
+        mfma_block(A, ib * NB, o, /*tx=*/true, A, o, jb * NB, m, acc);   // U[kb, ib]^T U[kb, jb]
+    else
+        mfma_block(A, ib * NB, o, /*tx=*/false, A, o, jb * NB, m, acc);  // L[ib, kb] U[kb, jb]
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) {
+                int r, c;
+                quad_pos(i, j, v, r, c);
+                const int R = ib * NB + r, Cc = jb * NB + c;
+                if (R < m && Cc < m) A[(int64_t)R * m + Cc] -= acc[i][j][v];
+            }
+}
+
+// ---------------------------------------------------------------- solves
+// Solve T x = b in place (x has m entries) for block-triangular T given by
+// C[j][i] = T[i][j] (row-major, ld m) and the inverses Dinv of its diagonal
+// blocks. lower: forward substitution, else backward.
+constexpr int kSolveThreads = 1024;
+constexpr int kMaxM = 4096;
+
+__global__ __launch_bounds__(kSolveThreads) void k_blk_trsv(int m, const double* __restrict__ C,
+                                                            const double* __restrict__ Dinv, int lower,
+                                                            double* __restrict__ x) {
+    __shared__ double sx[kMaxM];
+    __shared__ double part[16][NB + 1];
+    __shared__ double tvec[NB];
+    const int tid = threadIdx.x;
+    const int li = tid & 63, grp = tid >> 6;  // 64 entries x 16 groups
+    for (int i = tid; i < m; i += kSolveThreads) sx[i] = x[i];
+    __syncthreads();
+    const int nb = (m + NB - 1) / NB;
+    for (int s = 0; s < nb; ++s) {
+        const int kb = lower ? s : nb - 1 - s;
+        const int o = kb * NB;
+        const int i = o + li;
+        // t_i = x_i - sum over solved j of C[j][i] x_j
+        double acc = 0.0;
+        if (i < m) {
+            if (lower) {
+                for (int j = grp; j < o; j += 16) acc += C[(int64_t)j * m + i] * sx[j];
+            } else {
+                for (int j = o + NB + grp; j < m; j += 16) acc += C[(int64_t)j * m + i] * sx[j];
+            }
+        }
+        part[grp][li] = acc;
+        __syncthreads();
+        if (tid < NB) {
+            double t = 0.0;
+            for (int q = 0; q < 16; ++q) t += part[q][tid];
+            tvec[tid] = (o + tid < m) ? sx[o + tid] - t : 0.0;
+        }
+        __syncthreads();
+        // x_block = Dinv[kb] t
+        const double* Dk = Dinv + (int64_t)kb * NB * NB;
+        double y = 0.0;
+        for (int q = grp; q < NB; q += 16) y += Dk[li * NB + q] * tvec[q];
+        part[grp][li] = y;
+        __syncthreads();
+        if (tid < NB && o + tid < m) {
+            double t = 0.0;
+            for (int q = 0; q < 16; ++q) t += part[q][tid];
+            sx[o + tid] = t;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < m; i += kSolveThreads) x[i] = sx[i];
+}
+
+}  // namespace
+
+size_t blocked_inv_elems(int m) { return (size_t)((m + NB - 1) / NB) * NB * NB; }
+
+void launch_blocked_factor(hipStream_t s, int m, double* A, int mode, double* Dfwd, double* Dbwd, int* info) {
+    H1W_HIP(hipMemsetAsync(info, 0xff, sizeof(int), s));  // info = -1
+    const int nb = (m + NB - 1) / NB;
+    for (int kb = 0; kb < nb; ++kb) {
+        hipLaunchKernelGGL(k_blk_diag, dim3(1), dim3(256), 0, s, m, A, kb, mode, Dfwd, Dbwd, info);
+        H1W_LAUNCHED();
+        const int rest = nb - kb - 1;
+        if (rest == 0) break;
+        const int npanel = mode == 0 ? rest : 2 * rest;
+        hipLaunchKernelGGL(k_blk_panel, dim3(npanel), dim3(256), 0, s, m, A, kb, mode, Dfwd, Dbwd, info);
+        H1W_LAUNCHED();
+        const int nupd = mode == 0 ? rest * (rest + 1) / 2 : rest * rest;
+        hipLaunchKernelGGL(k_blk_update, dim3(nupd), dim3(256), 0, s, m, A, kb, mode, info);
+        H1W_LAUNCHED();
+    }
+}
+
+void launch_blocked_trsv(hipStream_t s, int m, const double* C, const double* Dinv, bool lower, double* x) {
+    if (m > kMaxM) throw Error{H1W_EINVAL, "m too large for the triangular solve"};
+    hipLaunchKernelGGL(k_blk_trsv, dim3(1), dim3(kSolveThreads), 0, s, m, C, Dinv, (int)lower, x);
+    H1W_LAUNCHED();
+}
+
+}  // namespace h1w

@@ -36,8 +36,10 @@ struct Ctx {
     DevBuf Zbuf;                     // Z = B J^T, m x N (double or float), ld = ldz
     int64_t ldz = 0;
     DevBuf Sbuf;                     // S = alpha I + J Z^T (m x m)
-    DevBuf F1, F2, pivb;             // factors: Cholesky U / L=U^T, or LU / (LU)^T + pivots
+    DevBuf F1, F2, pivb;             // factors: Cholesky U / L=U^T, or LU / (LU)^T (+ pivots)
+    DevBuf Dfwd, Dbwd;               // inverses of the 64x64 diagonal blocks of the factors
     int factor = 0;
+    bool lu_pivoted = false;         // fallback LU with partial pivoting in use
     int failed_pivot = -1;
     double asym = 0.0;
 

@@ -136,8 +136,14 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     for (int k = 0; k < d.nu; ++k)
         w[k] = 1.0 / (0.5 * (d.cheb_hi + d.cheb_lo) + 0.5 * (d.cheb_hi - d.cheb_lo) * std::cos(pi * (2 * k + 1) / (2.0 * d.nu)));
 
-    // dense inverse of the coarsest operator
-    const std::vector<double> inv = spd_inverse(dense_operator(dim, lv.back()), Nc);
+    // dense inverse of the coarsest operator, symmetrised so that the device
+    // kernel may read it by columns
+    std::vector<double> inv = spd_inverse(dense_operator(dim, lv.back()), Nc);
+    for (int64_t i = 0; i < Nc; ++i)
+        for (int64_t j = i + 1; j < Nc; ++j) {
+            const double a = 0.5 * (inv[(size_t)(i * Nc + j)] + inv[(size_t)(j * Nc + i)]);
+            inv[(size_t)(i * Nc + j)] = inv[(size_t)(j * Nc + i)] = a;
+        }
     cinv64.reserve(inv.size() * sizeof(double));
     H1W_HIP(hipMemcpy(cinv64.p, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
     std::vector<float> inv32(inv.begin(), inv.end());
@@ -424,20 +430,27 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
         read_scal(1);
         asym = hscal[0] / alpha;
     }
-    // factorisation
+    // factorisation: blocked Cholesky, else blocked LU without pivoting, else
+    // LU with partial pivoting
     F1.reserve((size_t)m * m * sizeof(double));
     F2.reserve((size_t)m * m * sizeof(double));
+    Dfwd.reserve(blocked_inv_elems(m) * sizeof(double));
+    Dbwd.reserve(blocked_inv_elems(m) * sizeof(double));
     pivb.reserve((size_t)m * sizeof(int));
     int* dinfo = iflag.as<int>();
     int hinfo = -1;
     failed_pivot = -1;
     factor = 0;
-    if (fac == H1W_FACTOR_CHOL) {
+    lu_pivoted = false;
+    auto blocked = [&](int mode) {
         H1W_HIP(hipMemcpyAsync(F1.p, Sbuf.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, stream));
-        launch_cholesky_upper(stream, m, F1.as<double>(), dinfo);
+        launch_blocked_factor(stream, m, F1.as<double>(), mode, Dfwd.as<double>(), Dbwd.as<double>(), dinfo);
         H1W_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, stream));
         sync();
-        if (hinfo < 0) {
+        return hinfo;
+    };
+    if (fac == H1W_FACTOR_CHOL) {
+        if (blocked(0) < 0) {
             launch_transpose(stream, m, F1.as<double>(), F2.as<double>());
             factor = H1W_FACTOR_CHOL;
         } else {
@@ -450,12 +463,17 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
         }
     }
     if (fac == H1W_FACTOR_LU) {
-        H1W_HIP(hipMemcpyAsync(F1.p, Sbuf.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, stream));
-        launch_lu(stream, m, F1.as<double>(), pivb.as<int>(), dinfo);
-        H1W_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, stream));
-        sync();
-        if (hinfo >= 0) throw Error{H1W_ENUMERIC, "LU of S met a zero pivot at column " + std::to_string(hinfo)};
-        launch_transpose(stream, m, F1.as<double>(), F2.as<double>());
+        if (blocked(1) < 0) {
+            launch_transpose(stream, m, F1.as<double>(), F2.as<double>());
+        } else {  // a zero pivot without pivoting: fall back to partial pivoting
+            H1W_HIP(hipMemcpyAsync(F1.p, Sbuf.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, stream));
+            launch_lu(stream, m, F1.as<double>(), pivb.as<int>(), dinfo);
+            H1W_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, stream));
+            sync();
+            if (hinfo >= 0) throw Error{H1W_ENUMERIC, "LU of S met a zero pivot at column " + std::to_string(hinfo)};
+            launch_transpose(stream, m, F1.as<double>(), F2.as<double>());
+            lu_pivoted = true;
+        }
         factor = H1W_FACTOR_LU;
     }
     ev_record(3);
@@ -473,10 +491,15 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
 }
 
 void Ctx::solve_S(double* x) {
-    if (factor == H1W_FACTOR_CHOL)
-        launch_chol_solve(stream, m, F1.as<double>(), F2.as<double>(), x);
-    else
+    if (factor == H1W_FACTOR_CHOL) {  // S = U^T U: U^T y = x, then U x = y
+        launch_blocked_trsv(stream, m, F1.as<double>(), Dfwd.as<double>(), true, x);
+        launch_blocked_trsv(stream, m, F2.as<double>(), Dbwd.as<double>(), false, x);
+    } else if (!lu_pivoted) {  // S = L U
+        launch_blocked_trsv(stream, m, F2.as<double>(), Dfwd.as<double>(), true, x);
+        launch_blocked_trsv(stream, m, F2.as<double>(), Dbwd.as<double>(), false, x);
+    } else {
         launch_lu_solve(stream, m, F2.as<double>(), F1.as<double>(), pivb.as<int>(), x);
+    }
 }
 
 // ============================================================ workspace for the Krylov loop

@@ -159,5 +159,10 @@ void launch_lu_solve(hipStream_t s, int m, const double* LUt, const double* LU, 
 void launch_jz_update(hipStream_t s, int m, const double* S, double alpha, const double* Jy,
                       const double* w, double beta, double* Jz, double* Jp);
 void launch_asym(hipStream_t s, int m, const double* S, double* out);
+// blocked.hip: right-looking blocked Cholesky (mode 0, upper) or LU without
+// pivoting (mode 1) in place, with diagonal-block inverses; triangular solves
+size_t blocked_inv_elems(int m);
+void launch_blocked_factor(hipStream_t s, int m, double* A, int mode, double* Dfwd, double* Dbwd, int* info);
+void launch_blocked_trsv(hipStream_t s, int m, const double* C, const double* Dinv, bool lower, double* x);
 
 }  // namespace h1w

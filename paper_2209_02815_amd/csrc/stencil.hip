@@ -191,20 +191,32 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, int k,
     }
 }
 
-// X_r = Cinv F_r on the coarsest level (Cinv = dense inverse, row-major Nc x Nc).
+// X_r = Cinv F_r on the coarsest level. Cinv is the symmetric dense inverse
+// (row-major Nc x Nc), so Cinv[j][i] = Cinv[i][j]: lane i of a wave reads
+// Cinv[j*Nc + i], coalesced across the wave. Block = 64 rows x 4 waves, each
+// wave summing a quarter of j; F_r is staged in LDS.
+constexpr int kCoarseMax = 4096;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(int Nc, const T* __restrict__ Cinv,
                                                          int k, const T* __restrict__ F,
                                                          int64_t ldf, T* __restrict__ X,
                                                          int64_t ldx) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Nc) return;
-    const T* row = Cinv + (int64_t)i * Nc;
+    __shared__ T sf[kCoarseMax];
+    __shared__ T part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int q = (Nc + 3) / 4;
+    const int j0 = wv * q, j1 = min(Nc, j0 + q);
     for (int r = blockIdx.y; r < k; r += gridDim.y) {
-        const T* f = F + r * ldf;
+        __syncthreads();
+        for (int j = threadIdx.x; j < Nc; j += kBlock) sf[j] = F[r * ldf + j];
+        __syncthreads();
         T acc = T(0);
-        for (int j = 0; j < Nc; ++j) acc += row[j] * f[j];
-        X[r * ldx + i] = acc;
+        if (i < Nc)
+            for (int j = j0; j < j1; ++j) acc += Cinv[(int64_t)j * Nc + i] * sf[j];
+        part[wv][lane] = acc;
+        __syncthreads();
+        if (wv == 0 && i < Nc) X[r * ldx + i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     }
 }
 
@@ -297,8 +309,9 @@ template <typename T>
 void launch_coarse_solve(hipStream_t s, int64_t Nc, const T* Cinv, int k, const T* F,
                          int64_t ldf, T* X, int64_t ldx) {
     if (k <= 0) return;
-    hipLaunchKernelGGL((k_coarse_solve<T>), grid_for(Nc, k), dim3(kBlock), 0, s, (int)Nc, Cinv,
-                       k, F, ldf, X, ldx);
+    if (Nc > kCoarseMax) throw Error{H1W_EINVAL, "coarsest level too large"};
+    const dim3 grid((unsigned)cdiv(Nc, 64), (unsigned)std::min(k, 65535));
+    hipLaunchKernelGGL((k_coarse_solve<T>), grid, dim3(kBlock), 0, s, (int)Nc, Cinv, k, F, ldf, X, ldx);
     H1W_LAUNCHED();
 }
 

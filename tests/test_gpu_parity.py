@@ -354,3 +354,21 @@ def test_gn_solve_deterministic(P):
         x1, _ = ctx.gn_solve(Jd, wl.alpha, b=bd)
         x2, _ = ctx.gn_solve(Jd, wl.alpha, b=bd)
         assert torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("m", [24, 130])
+def test_forced_lu_fp64(P, m):
+    # the blocked LU (no pivoting) of the symmetric FP64 capacitance matrix
+    wl, J, b = _bump_problem("square33", m)
+    R = rng(9).standard_normal((1, wl.N))
+    with P.Context(wl.shape, wl.beta) as ctx:
+        Jd = dev(J)
+        _, _, info = ctx.capacitance_build(Jd, wl.alpha, factor=2)
+        assert info.factor_used == 2
+        Zp = host(ctx.precond_apply(dev(R), zmode=1))
+        x, info = ctx.gn_solve(Jd, wl.alpha, b=dev(b), rtol=1e-10, factor=2)
+        x = host(x)
+    V = mg.VCycle(wl.shape, wl.beta)
+    ref = gn.woodbury_precond(V.apply, J, wl.alpha, R)
+    assert rel_rows(Zp, ref).max() < 1e-8
+    assert gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x) <= 1.01e-10
