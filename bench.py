@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one device copy of 1 GiB (a kernel of known size for PMC counter scaling)")
     return ap.parse_args()
 
 
@@ -40,11 +42,60 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# kernel class -> (bound, unit, kernel symbol(s) in a rocprofv3 kernel trace)
+KERNELS = {
+    "smooth": ("hbm", "k_march<*, 3, 2>"), "smooth_first": ("hbm", "k_smooth_first"),
+    "residual": ("hbm", "k_march<*, 3, 1>"), "restrict": ("hbm", "k_restrict"), "prolong": ("hbm", "k_prolong_add"),
+    "coarse": ("hbm", "k_coarse_solve"), "gemm": ("mfma", "k_cap_gemm"), "jv": ("hbm", "k_rows_dot"),
+    "jtv": ("hbm", "k_jt_u_t / k_jt_plain / k_z_stored"), "factor": ("mfma", "k_blk_*"),
+    "trsv": ("hbm", "k_blk_trsv"), "apply": ("hbm", "k_march<*, 3, 0> / k_apply_plus_dot"),
+}
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix
+
+
+def source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2209_02815_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def roofline(cls: str, st: dict) -> dict:
+    bound, _ = KERNELS[cls]
+    avg_ms = st["ms"] / st["launches"]
+    if bound == "mfma":
+        achieved = st["flops"] / st["launches"] / (avg_ms * 1e-3) / 1e12
+        peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
+    else:
+        achieved = st["bytes"] / st["launches"] / (avg_ms * 1e-3) / 1e9
+        peak, unit = PEAK_HBM_GBS, "GB/s"
+    traffic = None
+    tp = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tp):
+        t = json.load(open(tp))
+        if t.get("class") == cls and t.get("source_sha") == source_sha():
+            traffic = t.get("traffic_bytes_per_launch")
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": traffic, "kernel": cls, "symbol": KERNELS[cls][1], "launches": st["launches"],
+            "avg_launch_us": 1e3 * avg_ms, "algorithmic_bytes_per_launch": st["bytes"] / st["launches"],
+            "algorithmic_flops_per_launch": st["flops"] / st["launches"]}
+
+
 def time_solves(ctx, Jd, alpha, bd, xd, steps, warmup, rtol):
+    """Warmup (all kernel classes timed, to find the dominant one), then `steps`
+    timed solves with event timing of the dominant class only."""
     import torch
-    for _ in range(warmup):
+    ctx.set_kernel_timing("all")
+    for _ in range(max(1, warmup)):
         ctx.gn_solve(Jd, alpha, b=bd, x=xd, rtol=rtol)
     torch.cuda.synchronize()
+    kt = ctx.kernel_timing()
+    dominant = max(kt, key=lambda c: kt[c]["ms"])
+    ctx.reset_kernel_timing()
+    ctx.set_kernel_timing([dominant])
     infos = []
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -52,7 +103,10 @@ def time_solves(ctx, Jd, alpha, bd, xd, steps, warmup, rtol):
         infos.append(info.as_dict())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, infos
+    st = ctx.kernel_timing()[dominant]
+    ctx.set_kernel_timing([])
+    shares = {c: round(v["ms"] / max(1e-9, sum(x["ms"] for x in kt.values())), 4) for c, v in kt.items()}
+    return dt, infos, roofline(dominant, st), shares
 
 
 def cpu_baseline(wl, J, b, threads):
@@ -99,6 +153,14 @@ def main():
     import h1w_inputs as H
     import paper_2209_02815_amd as P
 
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
+
     wl = H.workload(args.workload)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     log(f"generating J ({wl.m} x {wl.N}) and b on {threads} threads")
@@ -116,7 +178,7 @@ def main():
     for mode in modes:
         with P.Context(wl.shape, wl.beta, precision=mode) as ctx:
             log(f"{mode}: warmup {args.warmup}, timing {args.steps} solves")
-            dt, infos = time_solves(ctx, Jd, wl.alpha, bd, xd, args.steps, args.warmup, args.rtol)
+            dt, infos, roof, shares = time_solves(ctx, Jd, wl.alpha, bd, xd, args.steps, args.warmup, args.rtol)
             # independent FP64 check of the last solution: ||b - G x|| / ||b|| via the library's GN apply
             y = ctx.gn_apply(Jd, wl.alpha, xd)
             rr = float(torch.linalg.norm(bd - y) / torch.linalg.norm(bd))
@@ -126,6 +188,7 @@ def main():
             "iters": int(np.median([i["iters"] for i in infos])), "relres_true": rr,
             "t_zbuild_ms": med("t_zbuild_ms"), "t_gemm_ms": med("t_gemm_ms"), "t_factor_ms": med("t_factor_ms"),
             "t_cg_ms": med("t_cg_ms"), "t_total_ms": med("t_total_ms"), "factor": infos[-1]["factor_used"],
+            "roofline": roof, "kernel_time_share": shares,
         }
         log(f"{mode}: {results[mode]}")
     del Jd
@@ -145,6 +208,7 @@ def main():
         "config": {"workload": f"{wl.name}: 3D {wl.shape[0]}^3 H1 Gram (beta={wl.beta}), m={wl.m} bump rows, "
                                f"alpha={wl.alpha}, rtol={args.rtol}", "N": wl.N, "m": wl.m,
                    "parallelism": "single GPU"},
+        "roofline": r64["roofline"],
         "fp64": r64,
         "mixed": results.get("mixed"),
         "cpu_baseline": cpu,

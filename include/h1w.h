@@ -194,6 +194,41 @@ h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
 h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha,
                         const double* x, double* y);
 
+/* ---------------------------------------------------------------- kernel timing
+ * Optional per-kernel-class timing with HIP events recorded on the context's
+ * stream around every launch of the selected classes (bit (1 << class) in
+ * mask; 0 switches timing off). Each launch also adds the algorithmic bytes
+ * it must move (its inputs read once, its outputs written once) and the
+ * algorithmic flops of its contraction, so achieved GB/s or TFLOP/s of a
+ * class = bytes / ms or flops / ms. Statistics accumulate until reset.
+ * Timing adds two event records per timed launch; it is off by default. */
+typedef enum {
+    H1W_K_SMOOTH = 0,      /* Chebyshev-Jacobi smoothing step (all levels) */
+    H1W_K_SMOOTH_FIRST = 1,/* first smoothing step from a zero guess */
+    H1W_K_RESIDUAL = 2,    /* r = f - A x */
+    H1W_K_RESTRICT = 3,    /* f_c = 2^-d P^T r */
+    H1W_K_PROLONG = 4,     /* x += P e_c */
+    H1W_K_COARSE = 5,      /* dense coarsest solve */
+    H1W_K_GEMM = 6,        /* capacitance GEMM J Z^T (MFMA) */
+    H1W_K_JV = 7,          /* J v pass */
+    H1W_K_JTV = 8,         /* J^T (and Z^T) passes with CG epilogues */
+    H1W_K_FACTOR = 9,      /* blocked factorisation of S */
+    H1W_K_TRSV = 10,       /* triangular solves with the factors of S */
+    H1W_K_APPLY = 11,      /* operator apply A x (incl. the CG q = alpha A p + t) */
+    H1W_K_NCLASS = 12
+} h1w_kclass;
+
+typedef struct {
+    int64_t launches;
+    double ms;       /* sum of event-measured launch durations */
+    double bytes;    /* sum of algorithmic bytes */
+    double flops;    /* sum of algorithmic flops */
+} h1w_kstat;
+
+h1w_status h1w_set_kernel_timing(h1w_ctx* ctx, unsigned mask);
+h1w_status h1w_get_kernel_timing(h1w_ctx* ctx, int kclass, h1w_kstat* out);
+h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx);
+
 /* ERT sensitivities (Section 4: forward model, adjoint derivative of the
  * pole-pole voltages). Not built in this version: always returns
  * H1W_ENOTIMPL without touching its arguments. */

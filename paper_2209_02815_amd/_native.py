@@ -19,10 +19,14 @@ H1W_VCYCLE_ONCE, H1W_MG_SOLVE = 0, 1
 H1W_Z_AUTO, H1W_Z_STORED, H1W_Z_RECOMPUTE = 0, 1, 2
 H1W_FACTOR_AUTO, H1W_FACTOR_CHOL, H1W_FACTOR_LU = 0, 1, 2
 
+KCLASS = ["smooth", "smooth_first", "residual", "restrict", "prolong", "coarse", "gemm", "jv", "jtv",
+          "factor", "trsv", "apply"]
+
 EXPORTED = [
     "h1w_setup", "h1w_destroy", "h1w_last_error", "h1w_status_string", "h1w_get_sizes",
     "h1w_operator_apply", "h1w_poisson_solve_batched", "h1w_capacitance_build",
     "h1w_precond_apply", "h1w_gn_solve", "h1w_gn_apply", "h1w_ert_sensitivities",
+    "h1w_set_kernel_timing", "h1w_get_kernel_timing", "h1w_reset_kernel_timing",
 ]
 
 
@@ -46,6 +50,10 @@ class h1w_info(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class h1w_kstat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 class H1WError(RuntimeError):
@@ -77,6 +85,9 @@ def _load():
         "h1w_gn_apply": (I, [P, I, P, I64, D, P, P]),
         "h1w_ert_sensitivities": (I, [P, P, I, P, I, P, P, P, P, I64, C.POINTER(h1w_solve_opts),
                                       C.POINTER(h1w_info)]),
+        "h1w_set_kernel_timing": (I, [P, C.c_uint]),
+        "h1w_get_kernel_timing": (I, [P, I, C.POINTER(h1w_kstat)]),
+        "h1w_reset_kernel_timing": (I, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -220,3 +231,17 @@ def h1w_gn_apply(ctx, J, alpha: float, x, y):
 def h1w_ert_sensitivities(ctx, *args, **kwargs):
     st = lib.h1w_ert_sensitivities(ctx, None, 0, None, 0, None, None, None, None, 0, None, None)
     _check(ctx, st)
+
+
+def h1w_set_kernel_timing(ctx, mask: int):
+    _check(ctx, lib.h1w_set_kernel_timing(ctx, int(mask)))
+
+
+def h1w_get_kernel_timing(ctx, kclass: int) -> dict:
+    st = h1w_kstat()
+    _check(ctx, lib.h1w_get_kernel_timing(ctx, int(kclass), C.byref(st)))
+    return {"launches": st.launches, "ms": st.ms, "bytes": st.bytes, "flops": st.flops}
+
+
+def h1w_reset_kernel_timing(ctx):
+    _check(ctx, lib.h1w_reset_kernel_timing(ctx))

@@ -276,6 +276,32 @@ h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
     });
 }
 
+h1w_status h1w_set_kernel_timing(h1w_ctx* ctx, unsigned mask) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        ctx->c.flush_timing();
+        ctx->c.tmask = mask & ((1u << H1W_K_NCLASS) - 1);
+    });
+}
+
+h1w_status h1w_get_kernel_timing(h1w_ctx* ctx, int kclass, h1w_kstat* out) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        require(kclass >= 0 && kclass < H1W_K_NCLASS, "kclass out of range");
+        require(out != nullptr, "out is NULL");
+        ctx->c.flush_timing();
+        *out = ctx->c.kst[kclass];
+    });
+}
+
+h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        ctx->c.flush_timing();
+        for (auto& s : ctx->c.kst) s = h1w_kstat{};
+    });
+}
+
 h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double*, int, const int*, int, const int*, const double*,
                                  double*, double*, int64_t, const h1w_solve_opts*, h1w_info*) {
     if (ctx) ctx->c.err = "h1w_ert_sensitivities is not built in this version";

@@ -299,14 +299,14 @@ void launch_reduce_parts(hipStream_t s, int nvec, int nparts, const double* part
 
 size_t rows_dot_partial_elems(int m, int64_t N) { return (size_t)m * (size_t)cdiv(N, kRowChunk); }
 
-void launch_rows_dot(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm, const double* v,
-                     double* partial, double* out) {
-    if (m <= 0) return;
+int launch_rows_dot_partial(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm, const double* v,
+                            double* partial) {
     const int nchunk = (int)cdiv(N, kRowChunk);
+    if (m <= 0) return nchunk;
     const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
     hipLaunchKernelGGL(k_rows_dot, grid, dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
     H1W_LAUNCHED();
-    launch_reduce_parts(s, m, nchunk, partial, out);
+    return nchunk;
 }
 
 void launch_jt_u_t(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj, const double* w,

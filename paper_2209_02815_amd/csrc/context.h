@@ -74,6 +74,7 @@ struct Ctx {
     double* mv(int i);
     void dots(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs, int slot);
     void woodbury_mspace(const double* y, double* Jy, double* w);
+    void rows_dot(int mm, const double* M, int64_t ldm, const double* v, double* out);
     void precond_one(const double* r, double* z, int zmode);
     void precond_apply(int k, const double* R, int64_t ldr, double* Zout, int64_t ldz, int zmode);
     void gn_apply(int m, const double* J, int64_t ldj, double alpha, const double* x, double* y);
@@ -83,6 +84,31 @@ struct Ctx {
     void ev_reserve();
     void ev_record(int i);
     double ev_ms(int a, int b);
+
+    // optional per-kernel-class timing (h1w_set_kernel_timing)
+    unsigned tmask = 0;
+    struct Pending {
+        int cls;
+        hipEvent_t a, b;
+        double bytes, flops;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> evpool;
+    h1w_kstat kst[H1W_K_NCLASS] = {};
+    hipEvent_t take_event();
+    void flush_timing();  // after the stream has been synchronised
+    template <typename Fn>
+    void timed(int cls, double bytes, double flops, Fn&& fn) {
+        if (!(tmask & (1u << cls))) {
+            fn();
+            return;
+        }
+        Pending p{cls, take_event(), take_event(), bytes, flops};
+        H1W_HIP(hipEventRecord(p.a, stream));
+        fn();
+        H1W_HIP(hipEventRecord(p.b, stream));
+        pending.push_back(p);
+    }
 };
 
 }  // namespace h1w

@@ -161,6 +161,11 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
 
 Ctx::~Ctx() {
     if (hscal) (void)hipHostFree(hscal);
+    for (auto& p : pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto& e : evpool) (void)hipEventDestroy(e);
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -181,8 +186,13 @@ template <typename T>
 void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
     const int L = (int)lv.size();
     const size_t es = sizeof(T);
+    const double ces = (double)es * k;
+    auto coarse = [&](const T* f, int64_t lf, T* x, int64_t lx) {
+        timed(H1W_K_COARSE, ces * 2 * Nc + (double)es * Nc * Nc, 2.0 * k * Nc * Nc,
+              [&] { launch_coarse_solve<T>(stream, Nc, fp_cinv<T>(), k, f, lf, x, lx); });
+    };
     if (L == 1) {
-        launch_coarse_solve<T>(stream, Nc, fp_cinv<T>(), k, F, ldf, X, ldx);
+        coarse(F, ldf, X, ldx);
         return;
     }
     // workspace: level 0 scratch t; levels >= 1: f, x, t (k rows of pitch each)
@@ -213,33 +223,42 @@ void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
     for (int l = 0; l < L - 1; ++l) {
         const Geom& g = lv[l];
         // pre-smoothing from zero: first step writes t so that 2nu-1 flips end in x
-        launch_smooth_first<T>(stream, dim, g, k, fptr(l), fld(l), tb[l], pitch[l], w[0]);
+        const double nl = (double)g.N;
+        timed(H1W_K_SMOOTH_FIRST, 2 * ces * nl, 0.0,
+              [&] { launch_smooth_first<T>(stream, dim, g, k, fptr(l), fld(l), tb[l], pitch[l], w[0]); });
         T* a = tb[l];
         int64_t la = pitch[l];
         T* b = xptr(l);
         int64_t lb = xld(l);
         for (int s = 1; s < nu; ++s) {
-            launch_smooth<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb, w[s]);
+            timed(H1W_K_SMOOTH, 3 * ces * nl, 0.0,
+                  [&] { launch_smooth<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb, w[s]); });
             std::swap(a, b);
             std::swap(la, lb);
         }
-        launch_residual<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb);
-        launch_restrict<T>(stream, dim, g, lv[l + 1], k, b, lb, fb[l + 1], pitch[l + 1]);
+        timed(H1W_K_RESIDUAL, 3 * ces * nl, 0.0,
+              [&] { launch_residual<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb); });
+        timed(H1W_K_RESTRICT, ces * (nl + (double)lv[l + 1].N), 0.0,
+              [&] { launch_restrict<T>(stream, dim, g, lv[l + 1], k, b, lb, fb[l + 1], pitch[l + 1]); });
         cur[l] = a;
         ldcur[l] = la;
         oth[l] = b;
         ldoth[l] = lb;
     }
-    launch_coarse_solve<T>(stream, Nc, fp_cinv<T>(), k, fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
+    coarse(fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
     for (int l = L - 2; l >= 0; --l) {
         const Geom& g = lv[l];
-        launch_prolong_add<T>(stream, dim, g, lv[l + 1], k, xb[l + 1], pitch[l + 1], cur[l], ldcur[l]);
+        const double nl = (double)g.N;
+        timed(H1W_K_PROLONG, ces * (2 * nl + (double)lv[l + 1].N), 0.0, [&] {
+            launch_prolong_add<T>(stream, dim, g, lv[l + 1], k, xb[l + 1], pitch[l + 1], cur[l], ldcur[l]);
+        });
         T* a = cur[l];
         int64_t la = ldcur[l];
         T* b = oth[l];
         int64_t lb = ldoth[l];
         for (int s = nu - 1; s >= 0; --s) {
-            launch_smooth<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb, w[s]);
+            timed(H1W_K_SMOOTH, 3 * ces * nl, 0.0,
+                  [&] { launch_smooth<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb, w[s]); });
             std::swap(a, b);
             std::swap(la, lb);
         }
@@ -417,12 +436,17 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     Sbuf.reserve((size_t)m * m * sizeof(double));
     const size_t pe = gemm_partial_elems(m, n);
     gpart.reserve(pe * sizeof(double));
-    if (!fp32)
-        launch_capacitance_gemm<double>(stream, m, n, J, ldj, Zbuf.as<double>(), ldz, lower, alpha,
-                                        gpart.as<double>(), pe, Sbuf.as<double>(), m);
-    else
-        launch_capacitance_gemm<float>(stream, m, n, J, ldj, Zbuf.as<float>(), ldz, lower, alpha,
-                                       gpart.as<double>(), pe, Sbuf.as<double>(), m);
+    int splits = 0;
+    const double gflops = lower ? (double)m * (m + 1) * n : 2.0 * m * m * n;
+    timed(H1W_K_GEMM, (double)m * n * (8 + zes), gflops, [&] {
+        if (!fp32)
+            splits = launch_capacitance_partial<double>(stream, m, n, J, ldj, Zbuf.as<double>(), ldz, lower,
+                                                        gpart.as<double>(), pe);
+        else
+            splits = launch_capacitance_partial<float>(stream, m, n, J, ldj, Zbuf.as<float>(), ldz, lower,
+                                                       gpart.as<double>(), pe);
+    });
+    launch_capacitance_reduce(stream, m, splits, gpart.as<double>(), lower, alpha, Sbuf.as<double>(), m);
     ev_record(2);
     asym = 0.0;
     if (!lower) {
@@ -444,7 +468,10 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     lu_pivoted = false;
     auto blocked = [&](int mode) {
         H1W_HIP(hipMemcpyAsync(F1.p, Sbuf.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, stream));
-        launch_blocked_factor(stream, m, F1.as<double>(), mode, Dfwd.as<double>(), Dbwd.as<double>(), dinfo);
+        const double mm = m;
+        timed(H1W_K_FACTOR, 16.0 * mm * mm, (mode == 0 ? 1.0 : 2.0) * mm * mm * mm / 3.0, [&] {
+            launch_blocked_factor(stream, m, F1.as<double>(), mode, Dfwd.as<double>(), Dbwd.as<double>(), dinfo);
+        });
         H1W_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, stream));
         sync();
         return hinfo;
@@ -479,6 +506,7 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     ev_record(3);
     have_cap = true;
     sync();
+    flush_timing();
     if (info) {
         info->t_zbuild_ms = ev_ms(0, 1);
         info->t_gemm_ms = ev_ms(1, 2);
@@ -491,12 +519,16 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
 }
 
 void Ctx::solve_S(double* x) {
+    const double tb = 4.0 * m * m + 8.0 * blocked_inv_elems(m), tf = (double)m * m;
+    auto trsv = [&](const double* C, const double* D, bool lower) {
+        timed(H1W_K_TRSV, tb, tf, [&] { launch_blocked_trsv(stream, m, C, D, lower, x); });
+    };
     if (factor == H1W_FACTOR_CHOL) {  // S = U^T U: U^T y = x, then U x = y
-        launch_blocked_trsv(stream, m, F1.as<double>(), Dfwd.as<double>(), true, x);
-        launch_blocked_trsv(stream, m, F2.as<double>(), Dbwd.as<double>(), false, x);
+        trsv(F1.as<double>(), Dfwd.as<double>(), true);
+        trsv(F2.as<double>(), Dbwd.as<double>(), false);
     } else if (!lu_pivoted) {  // S = L U
-        launch_blocked_trsv(stream, m, F2.as<double>(), Dfwd.as<double>(), true, x);
-        launch_blocked_trsv(stream, m, F2.as<double>(), Dbwd.as<double>(), false, x);
+        trsv(F2.as<double>(), Dfwd.as<double>(), true);
+        trsv(F2.as<double>(), Dbwd.as<double>(), false);
     } else {
         launch_lu_solve(stream, m, F2.as<double>(), F1.as<double>(), pivb.as<int>(), x);
     }
@@ -534,7 +566,7 @@ void Ctx::dots(int64_t len, std::initializer_list<std::pair<const double*, const
 
 // w = S^{-1} J y and the J-space update Jz, Jp (Jp = Jz + beta Jp)
 void Ctx::woodbury_mspace(const double* y, double* Jy, double* w) {
-    launch_rows_dot(stream, m, N(), J, ldj, y, jpart.as<double>(), Jy);
+    rows_dot(m, J, ldj, y, Jy);
     H1W_HIP(hipMemcpyAsync(w, Jy, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, stream));
     solve_S(w);
 }
@@ -576,10 +608,11 @@ void Ctx::gn_apply(int mm, const double* JJ, int64_t ldjj, double al, const doub
     const int64_t n = N();
     double* tmp = nv(kTmpN);
     double* Jx = mv(kJx);
-    launch_apply<double>(stream, dim, lv[0], 1, x, n, tmp, n, al);
+    timed(H1W_K_APPLY, 16.0 * n, 0.0, [&] { launch_apply<double>(stream, dim, lv[0], 1, x, n, tmp, n, al); });
     if (mm > 0) {
-        launch_rows_dot(stream, mm, n, JJ, ldjj, x, jpart.as<double>(), Jx);
-        launch_jt_plain(stream, mm, n, JJ, ldjj, Jx, y, tmp, 1.0);
+        rows_dot(mm, JJ, ldjj, x, Jx);
+        timed(H1W_K_JTV, 8.0 * mm * n + 24.0 * n, 2.0 * mm * n,
+              [&] { launch_jt_plain(stream, mm, n, JJ, ldjj, Jx, y, tmp, 1.0); });
     } else {
         H1W_HIP(hipMemcpyAsync(y, tmp, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
     }
@@ -664,14 +697,17 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
             beta = first ? 0.0 : rzn / rz;
             rz = rzn;
             launch_jz_update(stream, m, Sbuf.as<double>(), alpha, Jy, w, beta, Jz, Jp);
-            launch_jt_u_t(stream, m, n, J, ldj, w, Jp, r, ia, u, t);
+            timed(H1W_K_JTV, 8.0 * m * n + 24.0 * n, 4.0 * m * n,
+                  [&] { launch_jt_u_t(stream, m, n, J, ldj, w, Jp, r, ia, u, t); });
             apply_B(1, u, n, z, n);
             launch_axpby(stream, n, 1.0, z, beta, p);
         } else {
-            if (fp32)
-                launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, z);
-            else
-                launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, ia, z);
+            timed(H1W_K_JTV, (fp32 ? 4.0 : 8.0) * m * n + 16.0 * n, 2.0 * m * n, [&] {
+                if (fp32)
+                    launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, z);
+                else
+                    launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, ia, z);
+            });
             dots(n, {{z, r}, {z, q}}, 0);
             read_scal(2);
             const double rzn = hscal[0], zq = hscal[1];
@@ -680,7 +716,8 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
             rz = rzn;
             launch_jz_update(stream, m, Sbuf.as<double>(), alpha, Jy, w, beta, Jz, Jp);
             launch_axpby(stream, n, 1.0, z, beta, p);
-            launch_jt_plain(stream, m, n, J, ldj, Jp, t, nullptr, 0.0);
+            timed(H1W_K_JTV, 8.0 * m * n + 8.0 * n, 2.0 * m * n,
+                  [&] { launch_jt_plain(stream, m, n, J, ldj, Jp, t, nullptr, 0.0); });
         }
         return true;
     };
@@ -699,7 +736,8 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         for (;;) {
             if (ok) {
                 int np = 0;
-                launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np);
+                timed(H1W_K_APPLY, 24.0 * n, 0.0,
+                      [&] { launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np); });
                 launch_reduce_parts(stream, 1, np, part.as<double>(), scal.as<double>());
                 read_scal(1);
                 const double pq = hscal[0];
@@ -752,6 +790,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     }
     ev_record(6);
     sync();
+    flush_timing();
     if (info) {
         info->iters = it;
         info->restarts = restarts;
@@ -764,6 +803,46 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     }
     if (status == H1W_ENOCONV) throw Error{H1W_ENOCONV, "GN-CG did not reach rtol within maxit iterations"};
     if (status == H1W_ENUMERIC) throw Error{H1W_ENUMERIC, "NaN or Inf in the CG recurrences"};
+}
+
+// ============================================================ J v with timing
+
+void Ctx::rows_dot(int mm, const double* M, int64_t ldm, const double* v, double* out) {
+    const int64_t n = N();
+    int nchunk = 0;
+    timed(H1W_K_JV, 8.0 * mm * n + 8.0 * n, 2.0 * mm * n,
+          [&] { nchunk = launch_rows_dot_partial(stream, mm, n, M, ldm, v, jpart.as<double>()); });
+    if (mm > 0) launch_reduce_parts(stream, mm, nchunk, jpart.as<double>(), out);
+}
+
+// ============================================================ kernel timing
+
+hipEvent_t Ctx::take_event() {
+    if (!evpool.empty()) {
+        hipEvent_t e = evpool.back();
+        evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    H1W_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Ctx::flush_timing() {
+    if (pending.empty()) return;
+    sync();
+    for (const auto& p : pending) {
+        float ms = 0.f;
+        H1W_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        h1w_kstat& s = kst[p.cls];
+        s.launches += 1;
+        s.ms += ms;
+        s.bytes += p.bytes;
+        s.flops += p.flops;
+        evpool.push_back(p.a);
+        evpool.push_back(p.b);
+    }
+    pending.clear();
 }
 
 // ============================================================ events

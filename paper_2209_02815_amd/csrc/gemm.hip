@@ -184,10 +184,9 @@ size_t gemm_partial_elems(int m, int64_t N) {
 }
 
 template <typename TZ>
-void launch_capacitance_gemm(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj, const TZ* Z,
-                             int64_t ldz, bool lower_only, double alpha, double* partial,
-                             size_t partial_elems, double* S, int64_t lds) {
-    if (m <= 0) return;
+int launch_capacitance_partial(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj, const TZ* Z,
+                               int64_t ldz, bool lower_only, double* partial, size_t partial_elems) {
+    if (m <= 0) return 0;
     const GemmPlan p = plan(m, N, lower_only);
     if ((size_t)p.splits * m * m > partial_elems) throw Error{H1W_EINVAL, "internal: GEMM partial buffer too small"};
     const int total = p.ntile * p.splits;
@@ -195,14 +194,20 @@ void launch_capacitance_gemm(hipStream_t s, int m, int64_t N, const double* J, i
     hipLaunchKernelGGL((k_cap_gemm<TZ>), dim3(grid), dim3(kGemmThreads), 0, s, m, N, J, ldj, Z, ldz, p.T,
                        p.ntile, (int)lower_only, total, p.kper, partial, m);
     H1W_LAUNCHED();
+    return p.splits;
+}
+
+void launch_capacitance_reduce(hipStream_t s, int m, int splits, const double* partial, bool lower_only,
+                               double alpha, double* S, int64_t lds) {
+    if (m <= 0) return;
     hipLaunchKernelGGL(k_cap_reduce, dim3((unsigned)cdiv((int64_t)m * m, kBlock)), dim3(kBlock), 0, s, m, m,
-                       p.splits, partial, (int)lower_only, alpha, S, lds);
+                       splits, partial, (int)lower_only, alpha, S, lds);
     H1W_LAUNCHED();
 }
 
-template void launch_capacitance_gemm<double>(hipStream_t, int, int64_t, const double*, int64_t, const double*,
-                                              int64_t, bool, double, double*, size_t, double*, int64_t);
-template void launch_capacitance_gemm<float>(hipStream_t, int, int64_t, const double*, int64_t, const float*,
-                                             int64_t, bool, double, double*, size_t, double*, int64_t);
+template int launch_capacitance_partial<double>(hipStream_t, int, int64_t, const double*, int64_t,
+                                                const double*, int64_t, bool, double*, size_t);
+template int launch_capacitance_partial<float>(hipStream_t, int, int64_t, const double*, int64_t, const float*,
+                                               int64_t, bool, double*, size_t);
 
 }  // namespace h1w

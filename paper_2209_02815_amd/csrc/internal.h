@@ -113,8 +113,8 @@ int launch_dots_partial(hipStream_t s, int64_t N, int npair, const double* const
 void launch_reduce_parts(hipStream_t s, int nvec, int nparts, const double* partial,
                          double* out);
 // per-row dot products out[i] = sum_n M[i,n] v[n] for i < m (M double), deterministic
-void launch_rows_dot(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm,
-                     const double* v, double* partial, double* out);
+int launch_rows_dot_partial(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm,
+                            const double* v, double* partial);  // returns #chunks
 size_t rows_dot_partial_elems(int m, int64_t N);
 // transpose products, see blas.hip for the epilogue modes
 void launch_jt_u_t(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
@@ -143,10 +143,14 @@ void launch_batched_p(hipStream_t s, int k, int64_t N, const double* b, const do
                       int64_t ldz, double* P, int64_t ldp, const int* active);
 
 // gemm.hip: S = alpha*I + J Z^T with FP64 accumulation on MFMA
+// (partial: the MFMA kernel writing per-split partial sums; reduce: the
+// fixed-order sum over splits plus alpha on the diagonal)
 template <typename TZ>
-void launch_capacitance_gemm(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
-                             const TZ* Z, int64_t ldz, bool lower_only, double alpha,
-                             double* partial, size_t partial_elems, double* S, int64_t lds);
+int launch_capacitance_partial(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
+                               const TZ* Z, int64_t ldz, bool lower_only, double* partial,
+                               size_t partial_elems);
+void launch_capacitance_reduce(hipStream_t s, int m, int splits, const double* partial, bool lower_only,
+                               double alpha, double* S, int64_t lds);
 size_t gemm_partial_elems(int m, int64_t N);
 
 // dense.hip (single-workgroup factorisations for m <= a few thousand)

@@ -11,6 +11,8 @@
 //   (A u)_p = beta wx wy wz u_p + sum_axes c_axis * sum_nbrs (u_p - u_nbr),
 //   c_x = wy wz / hx^2, c_y = wx wz / hy^2, c_z = wx wy / hz^2
 // (2D: drop z). The diagonal is D_p = beta wx wy wz + sum_axes c_axis * #nbrs.
+#include <algorithm>
+
 #include "devutil.h"
 #include "internal.h"
 
@@ -71,123 +73,250 @@ __device__ __forceinline__ void decompose(const Geom& g, int p, int& i, int& j, 
     l = q / g.ny;
 }
 
-template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_apply(Geom g, int k, const T* __restrict__ X,
-                                                  int64_t ldx, T* __restrict__ Y, int64_t ldy,
-                                                  T scale) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= g.N) return;
-    int i, j, l;
-    decompose(g, p, i, j, l);
-    const auto c = node_coef<T, DIM>(g, i, j, l);
-    for (int r = blockIdx.y; r < k; r += gridDim.y)
-        Y[r * ldy + p] = scale * apply_at<T, DIM>(g, X + r * ldx, p, c);
+// ---------------------------------------------------------------- launch shape
+// Work item = (plane tile of kBlock consecutive in-plane indices q = j*nx + i,
+// run of zc consecutive z-planes, batch row r), tile index fastest. Each
+// thread owns one q and marches up its z-run, keeping the z-neighbours in
+// registers. Work-group ids are dealt round-robin to the 8 XCDs, so item w is
+// given to XCD w / per (contiguous ranges): work-groups that touch the same
+// planes share one L2.
+struct Sweep {
+    int PL;     // nodes per z-plane
+    int nqt;    // plane tiles
+    int zc;     // planes per run
+    int nzc;    // runs
+    int k;      // batch rows
+    int total;  // work items
+};
+
+Sweep make_sweep(const Geom& g, int k, int target_items = 4096) {
+    Sweep s;
+    s.PL = g.nx * g.ny;
+    s.nqt = (int)cdiv(s.PL, kBlock);
+    s.k = k;
+    const int64_t base = (int64_t)s.nqt * k;
+    int nzc = (int)std::clamp<int64_t>(cdiv(target_items, base), 1, g.nz);
+    s.zc = (int)cdiv(g.nz, nzc);
+    s.nzc = (int)cdiv(g.nz, s.zc);
+    s.total = (int)((int64_t)s.nqt * s.nzc * k);
+    return s;
 }
 
-template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_smooth_first(Geom g, int k, const T* __restrict__ F,
-                                                         int64_t ldf, T* __restrict__ X,
-                                                         int64_t ldx, T w) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= g.N) return;
-    int i, j, l;
-    decompose(g, p, i, j, l);
-    const auto c = node_coef<T, DIM>(g, i, j, l);
-    for (int r = blockIdx.y; r < k; r += gridDim.y) X[r * ldx + p] = w * F[r * ldf + p] / c.diag;
+unsigned sweep_grid(const Sweep& s) { return 8u * (unsigned)cdiv(s.total, 8); }
+
+__device__ __forceinline__ bool sweep_item(const Sweep& s, int& q, int& z0, int& z1, int& r, int nz) {
+    const int bid = blockIdx.x;
+    const int per = (s.total + 7) >> 3;
+    const int w = (bid & 7) * per + (bid >> 3);
+    if (w >= s.total) return false;
+    const int qt = w % s.nqt;
+    const int t = w / s.nqt;
+    const int zi = t % s.nzc;
+    r = t / s.nzc;
+    q = qt * kBlock + threadIdx.x;
+    z0 = zi * s.zc;
+    z1 = min(nz, z0 + s.zc);
+    return q < s.PL;
 }
 
+// In-plane part of the stencil at (i, j) and the z-dependent part at plane l.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int k, const T* __restrict__ F,
-                                                   int64_t ldf, const T* __restrict__ Xi,
-                                                   int64_t ldi, T* __restrict__ Xo, int64_t ldo,
-                                                   T w) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= g.N) return;
-    int i, j, l;
-    decompose(g, p, i, j, l);
-    const auto c = node_coef<T, DIM>(g, i, j, l);
-    for (int r = blockIdx.y; r < k; r += gridDim.y) {
-        const T* x = Xi + r * ldi;
-        const T res = F[r * ldf + p] - apply_at<T, DIM>(g, x, p, c);
-        Xo[r * ldo + p] = x[p] + w * res / c.diag;
+struct Column {
+    T wx, wy;
+    bool xm, xp, ym, yp;
+    __device__ Column(const Geom& g, int i, int j) {
+        wx = (i == 0 || i == g.nx - 1) ? T(0.5) : T(1);
+        wy = (j == 0 || j == g.ny - 1) ? T(0.5) : T(1);
+        xm = i > 0; xp = i < g.nx - 1;
+        ym = j > 0; yp = j < g.ny - 1;
+    }
+    // A x at node p of plane l; xb/xc/xa = x at planes l-1, l, l+1
+    __device__ __forceinline__ T apply(const Geom& g, const T* __restrict__ x, int64_t p, int l, T xb, T xc,
+                                       T xa, T& diag) const {
+        const bool zm = DIM == 3 && l > 0, zp = DIM == 3 && l < g.nz - 1;
+        const T wz = (DIM == 3 && (l == 0 || l == g.nz - 1)) ? T(0.5) : T(1);
+        const T cx = T(g.ihx2) * wy * wz, cy = T(g.ihy2) * wx * wz;
+        const T cz = DIM == 3 ? T(g.ihz2) * wx * wy : T(0);
+        const T mass = T(g.beta) * wx * wy * wz;
+        diag = mass + cx * T(int(xm) + int(xp)) + cy * T(int(ym) + int(yp)) + cz * T(int(zm) + int(zp));
+        T sx = T(0), sy = T(0), sz = T(0);
+        if (xm) sx += xc - x[p - 1];
+        if (xp) sx += xc - x[p + 1];
+        if (ym) sy += xc - x[p - g.nx];
+        if (yp) sy += xc - x[p + g.nx];
+        if (zm) sz += xc - xb;
+        if (zp) sz += xc - xa;
+        T acc = mass * xc;
+        acc += cx * sx;
+        acc += cy * sy;
+        if (DIM == 3) acc += cz * sz;
+        return acc;
+    }
+    __device__ __forceinline__ T diag_at(const Geom& g, int l) const {
+        const bool zm = DIM == 3 && l > 0, zp = DIM == 3 && l < g.nz - 1;
+        const T wz = (DIM == 3 && (l == 0 || l == g.nz - 1)) ? T(0.5) : T(1);
+        const T cx = T(g.ihx2) * wy * wz, cy = T(g.ihy2) * wx * wz;
+        const T cz = DIM == 3 ? T(g.ihz2) * wx * wy : T(0);
+        return T(g.beta) * wx * wy * wz + cx * T(int(xm) + int(xp)) + cy * T(int(ym) + int(yp)) +
+               cz * T(int(zm) + int(zp));
+    }
+};
+
+// MODE 0: Y = scale * A X          (F unused)
+// MODE 1: Y = F - A X              (residual)
+// MODE 2: Y = X + w D^-1 (F - A X) (smoothing step; scale = w)
+// The march is unrolled by kU planes: all loads of kU planes (z-neighbour,
+// in-plane neighbours, right-hand side) are issued before the arithmetic, so
+// each thread keeps several independent HBM requests in flight.
+constexpr int kU = 4;
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_march(Geom g, Sweep s, const T* __restrict__ F, int64_t ldf,
+                                                  const T* __restrict__ X, int64_t ldx, T* __restrict__ Y,
+                                                  int64_t ldy, T scale) {
+    int q, z0, z1, r;
+    if (!sweep_item(s, q, z0, z1, r, g.nz)) return;
+    const Column<T, DIM> col(g, q % g.nx, q / g.nx);
+    const T* x = X + r * ldx;
+    const T* f = F + r * ldf;
+    T* y = Y + r * ldy;
+    const int64_t PL = s.PL;
+    const int nx = g.nx;
+    T xb = (DIM == 3 && z0 > 0) ? x[(z0 - 1) * PL + q] : T(0);
+    T xc = x[z0 * PL + q];
+    for (int l0 = z0; l0 < z1; l0 += kU) {
+        T xa[kU], fv[kU], nxm[kU], nxp[kU], nym[kU], nyp[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int l = l0 + u;
+            const int64_t p = l * PL + q;
+            const bool in = l < z1;
+            xa[u] = (in && DIM == 3 && l + 1 < g.nz) ? x[p + PL] : T(0);
+            fv[u] = (in && MODE != 0) ? f[p] : T(0);
+            nxm[u] = (in && col.xm) ? x[p - 1] : T(0);
+            nxp[u] = (in && col.xp) ? x[p + 1] : T(0);
+            nym[u] = (in && col.ym) ? x[p - nx] : T(0);
+            nyp[u] = (in && col.yp) ? x[p + nx] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int l = l0 + u;
+            if (l >= z1) break;
+            const int64_t p = l * PL + q;
+            const bool zm = DIM == 3 && l > 0, zp = DIM == 3 && l < g.nz - 1;
+            const T wz = (DIM == 3 && (l == 0 || l == g.nz - 1)) ? T(0.5) : T(1);
+            const T cx = T(g.ihx2) * col.wy * wz, cy = T(g.ihy2) * col.wx * wz;
+            const T cz = DIM == 3 ? T(g.ihz2) * col.wx * col.wy : T(0);
+            const T mass = T(g.beta) * col.wx * col.wy * wz;
+            T sx = T(0), sy = T(0), sz = T(0);
+            if (col.xm) sx += xc - nxm[u];
+            if (col.xp) sx += xc - nxp[u];
+            if (col.ym) sy += xc - nym[u];
+            if (col.yp) sy += xc - nyp[u];
+            if (zm) sz += xc - xb;
+            if (zp) sz += xc - xa[u];
+            T acc = mass * xc;
+            acc += cx * sx;
+            acc += cy * sy;
+            if (DIM == 3) acc += cz * sz;
+            if (MODE == 0) y[p] = scale * acc;
+            if (MODE == 1) y[p] = fv[u] - acc;
+            if (MODE == 2) {
+                const T diag = mass + cx * T(int(col.xm) + int(col.xp)) + cy * T(int(col.ym) + int(col.yp)) +
+                               cz * T(int(zm) + int(zp));
+                y[p] = xc + scale * (fv[u] - acc) / diag;
+            }
+            xb = xc;
+            xc = xa[u];
+        }
     }
 }
 
+// X = w D^-1 F (first smoothing step from a zero initial guess)
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_residual(Geom g, int k, const T* __restrict__ F,
-                                                     int64_t ldf, const T* __restrict__ X,
-                                                     int64_t ldx, T* __restrict__ R,
-                                                     int64_t ldr) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= g.N) return;
-    int i, j, l;
-    decompose(g, p, i, j, l);
-    const auto c = node_coef<T, DIM>(g, i, j, l);
-    for (int r = blockIdx.y; r < k; r += gridDim.y)
-        R[r * ldr + p] = F[r * ldf + p] - apply_at<T, DIM>(g, X + r * ldx, p, c);
+__global__ __launch_bounds__(kBlock) void k_smooth_first(Geom g, Sweep s, const T* __restrict__ F, int64_t ldf,
+                                                         T* __restrict__ X, int64_t ldx, T w) {
+    int q, z0, z1, r;
+    if (!sweep_item(s, q, z0, z1, r, g.nz)) return;
+    const Column<T, DIM> col(g, q % g.nx, q / g.nx);
+    const T* f = F + r * ldf;
+    T* x = X + r * ldx;
+    for (int l = z0; l < z1; ++l) {
+        const int64_t p = (int64_t)l * s.PL + q;
+        x[p] = w * f[p] / col.diag_at(g, l);
+    }
 }
 
-// Fc = 2^-d P^T R: coarse node (I,J,L) gathers the fine nodes 2I+{-1,0,1} (per
-// axis) with weights 1 (centre) and 1/2 (neighbours). Loops run z, y, x in
-// ascending fine index.
+// Fc = 2^-d P^T R. One thread per coarse (I, J), marching over coarse planes L:
+// fine plane z contributes the in-plane weighted sum
+//   s(z) = sum_{dy,dx in {-1,0,1}} w(dy) w(dx) R[z][2J+dy][2I+dx],  w(0)=1, w(+-1)=1/2,
+// and Fc[L] = 2^-d (s(2L-1)/2 + s(2L) + s(2L+1)/2); s(2L+1) is reused for L+1.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int k,
-                                                     const T* __restrict__ R, int64_t ldr,
-                                                     T* __restrict__ Fc, int64_t ldc) {
-    const int pc = blockIdx.x * kBlock + threadIdx.x;
-    if (pc >= gc.N) return;
-    int I, J, L;
-    decompose(gc, pc, I, J, L);
-    const int fi = 2 * I, fj = 2 * J, fl = DIM == 3 ? 2 * L : 0;
-    const int pl = gf.nx * gf.ny;
-    const T scale = DIM == 3 ? T(0.125) : T(0.25);
-    for (int r = blockIdx.y; r < k; r += gridDim.y) {
-        const T* rr = R + r * ldr;
-        T acc = T(0);
-        const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
-        for (int dz = zlo; dz <= zhi; ++dz) {
-            const int z = fl + dz;
-            if (z < 0 || z >= gf.nz) continue;
-            const T wz = dz ? T(0.5) : T(1);
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int y = fj + dy;
-                if (y < 0 || y >= gf.ny) continue;
-                const T wy = dy ? T(0.5) : T(1);
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int x = fi + dx;
-                    if (x < 0 || x >= gf.nx) continue;
-                    const T wx = dx ? T(0.5) : T(1);
-                    acc += (wz * wy * wx) * rr[z * pl + y * gf.nx + x];
-                }
-            }
+__device__ __forceinline__ T plane_sum(const Geom& gf, const T* __restrict__ rz, int fi, int fj) {
+    T acc = T(0);
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int y = fj + dy;
+        if (y < 0 || y >= gf.ny) continue;
+        const T wy = dy ? T(0.5) : T(1);
+        T row = T(0);
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = fi + dx;
+            if (x < 0 || x >= gf.nx) continue;
+            const T wx = dx ? T(0.5) : T(1);
+            row += wx * rz[y * gf.nx + x];
         }
-        Fc[r * ldc + pc] = scale * acc;
+        acc += wy * row;
+    }
+    return acc;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, Sweep s, const T* __restrict__ R,
+                                                     int64_t ldr, T* __restrict__ Fc, int64_t ldc) {
+    int q, z0, z1, r;
+    if (!sweep_item(s, q, z0, z1, r, gc.nz)) return;
+    const int I = q % gc.nx, J = q / gc.nx;
+    const T* rr = R + r * ldr;
+    T* fc = Fc + r * ldc;
+    const int64_t PLf = (int64_t)gf.nx * gf.ny;
+    const T scale = DIM == 3 ? T(0.125) : T(0.25);
+    if (DIM == 2) {
+        fc[q] = scale * plane_sum<T, DIM>(gf, rr, 2 * I, 2 * J);
+        return;
+    }
+    T sb = (2 * z0 - 1 >= 0) ? plane_sum<T, DIM>(gf, rr + (2 * z0 - 1) * PLf, 2 * I, 2 * J) : T(0);
+    for (int L = z0; L < z1; ++L) {
+        const int z = 2 * L;
+        const T sc = plane_sum<T, DIM>(gf, rr + z * PLf, 2 * I, 2 * J);
+        const T sa = (z + 1 < gf.nz) ? plane_sum<T, DIM>(gf, rr + (z + 1) * PLf, 2 * I, 2 * J) : T(0);
+        fc[(int64_t)L * s.PL + q] = scale * (T(0.5) * sb + sc + T(0.5) * sa);
+        sb = sa;
     }
 }
 
 // X += P Ec: fine node (i,j,l) interpolates from the coarse nodes floor(i/2)
 // and, for odd i, floor(i/2)+1 (weights 1/2), per axis.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, int k,
-                                                        const T* __restrict__ Ec, int64_t ldc,
-                                                        T* __restrict__ X, int64_t ldx) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= gf.N) return;
-    int i, j, l;
-    decompose(gf, p, i, j, l);
-    const int ci = i >> 1, cj = j >> 1, cl = l >> 1;
-    const int ni = 1 + (i & 1), nj = 1 + (j & 1), nl = DIM == 3 ? 1 + (l & 1) : 1;
+__global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, Sweep s, const T* __restrict__ Ec,
+                                                        int64_t ldc, T* __restrict__ X, int64_t ldx) {
+    int q, z0, z1, r;
+    if (!sweep_item(s, q, z0, z1, r, gf.nz)) return;
+    const int i = q % gf.nx, j = q / gf.nx;
+    const int ci = i >> 1, cj = j >> 1;
+    const int ni = 1 + (i & 1), nj = 1 + (j & 1);
     const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1);
-    const T wl = (DIM == 3 && (l & 1)) ? T(0.5) : T(1);
-    const int pl = gc.nx * gc.ny;
-    for (int r = blockIdx.y; r < k; r += gridDim.y) {
-        const T* e = Ec + r * ldc;
+    const int64_t PLc = (int64_t)gc.nx * gc.ny;
+    const T* e = Ec + r * ldc;
+    T* x = X + r * ldx;
+    for (int l = z0; l < z1; ++l) {
+        const int cl = l >> 1;
+        const int nl = DIM == 3 ? 1 + (l & 1) : 1;
+        const T wl = (DIM == 3 && (l & 1)) ? T(0.5) : T(1);
         T acc = T(0);
         for (int a = 0; a < nl; ++a)
             for (int b = 0; b < nj; ++b)
                 for (int c = 0; c < ni; ++c)
-                    acc += (wl * wj * wi) * e[(cl + a) * pl + (cj + b) * gc.nx + (ci + c)];
-        X[r * ldx + p] += acc;
+                    acc += (wl * wj * wi) * e[(cl + a) * PLc + (cj + b) * gc.nx + (ci + c)];
+        x[(int64_t)l * s.PL + q] += acc;
     }
 }
 
@@ -263,46 +392,61 @@ dim3 grid_for(int64_t N, int k) { return dim3((unsigned)cdiv(N, kBlock), (unsign
         H1W_LAUNCHED();                                                                 \
     } while (0)
 
+#define H1W_MARCH(MODE, T, ...)                                                                        \
+    do {                                                                                               \
+        const Sweep sw = make_sweep(g, k);                                                             \
+        if (dim == 3)                                                                                  \
+            hipLaunchKernelGGL((k_march<T, 3, MODE>), dim3(sweep_grid(sw)), dim3(kBlock), 0, s, g, sw, \
+                               __VA_ARGS__);                                                           \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_march<T, 2, MODE>), dim3(sweep_grid(sw)), dim3(kBlock), 0, s, g, sw, \
+                               __VA_ARGS__);                                                           \
+        H1W_LAUNCHED();                                                                                \
+    } while (0)
+
 template <typename T>
 void launch_apply(hipStream_t s, int dim, const Geom& g, int k, const T* X, int64_t ldx, T* Y,
                   int64_t ldy, double scale) {
     if (k <= 0) return;
-    H1W_DIMCALL(k_apply, T, grid_for(g.N, k), g, k, X, ldx, Y, ldy, T(scale));
+    H1W_MARCH(0, T, (const T*)nullptr, (int64_t)0, X, ldx, Y, ldy, T(scale));
 }
 
 template <typename T>
 void launch_smooth_first(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
                          T* X, int64_t ldx, double w) {
     if (k <= 0) return;
-    H1W_DIMCALL(k_smooth_first, T, grid_for(g.N, k), g, k, F, ldf, X, ldx, T(w));
+    const Sweep sw = make_sweep(g, k);
+    H1W_DIMCALL(k_smooth_first, T, dim3(sweep_grid(sw)), g, sw, F, ldf, X, ldx, T(w));
 }
 
 template <typename T>
 void launch_smooth(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
                    const T* Xin, int64_t ldi, T* Xout, int64_t ldo, double w) {
     if (k <= 0) return;
-    H1W_DIMCALL(k_smooth, T, grid_for(g.N, k), g, k, F, ldf, Xin, ldi, Xout, ldo, T(w));
+    H1W_MARCH(2, T, F, ldf, Xin, ldi, Xout, ldo, T(w));
 }
 
 template <typename T>
 void launch_residual(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
                      const T* X, int64_t ldx, T* R, int64_t ldr) {
     if (k <= 0) return;
-    H1W_DIMCALL(k_residual, T, grid_for(g.N, k), g, k, F, ldf, X, ldx, R, ldr);
+    H1W_MARCH(1, T, F, ldf, X, ldx, R, ldr, T(1));
 }
 
 template <typename T>
 void launch_restrict(hipStream_t s, int dim, const Geom& gf, const Geom& gc, int k, const T* R,
                      int64_t ldr, T* Fc, int64_t ldc) {
     if (k <= 0) return;
-    H1W_DIMCALL(k_restrict, T, grid_for(gc.N, k), gf, gc, k, R, ldr, Fc, ldc);
+    const Sweep sw = make_sweep(gc, k);
+    H1W_DIMCALL(k_restrict, T, dim3(sweep_grid(sw)), gf, gc, sw, R, ldr, Fc, ldc);
 }
 
 template <typename T>
 void launch_prolong_add(hipStream_t s, int dim, const Geom& gf, const Geom& gc, int k,
                         const T* Ec, int64_t ldc, T* X, int64_t ldx) {
     if (k <= 0) return;
-    H1W_DIMCALL(k_prolong_add, T, grid_for(gf.N, k), gf, gc, k, Ec, ldc, X, ldx);
+    const Sweep sw = make_sweep(gf, k);
+    H1W_DIMCALL(k_prolong_add, T, dim3(sweep_grid(sw)), gf, gc, sw, Ec, ldc, X, ldx);
 }
 
 template <typename T>

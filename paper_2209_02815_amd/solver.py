@@ -82,3 +82,20 @@ class Context:
         import torch
         y = torch.empty_like(x) if y is None else y
         return nat.h1w_gn_apply(self.handle, J, alpha, x, y)
+
+    # ---------------------------------------------------------------- kernel timing
+    def set_kernel_timing(self, classes):
+        """Time the given kernel classes (names from _native.KCLASS, or 'all'; [] = off)."""
+        if classes == "all":
+            mask = (1 << len(nat.KCLASS)) - 1
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << nat.KCLASS.index(c)
+        nat.h1w_set_kernel_timing(self.handle, mask)
+
+    def kernel_timing(self) -> dict:
+        return {name: nat.h1w_get_kernel_timing(self.handle, i) for i, name in enumerate(nat.KCLASS)}
+
+    def reset_kernel_timing(self):
+        nat.h1w_reset_kernel_timing(self.handle)

@@ -372,3 +372,18 @@ def test_forced_lu_fp64(P, m):
     ref = gn.woodbury_precond(V.apply, J, wl.alpha, R)
     assert rel_rows(Zp, ref).max() < 1e-8
     assert gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x) <= 1.01e-10
+
+
+def test_kernel_timing_counts_launches(P):
+    wl, J, b = _bump_problem("cube17")
+    with P.Context(wl.shape, wl.beta) as ctx:
+        ctx.set_kernel_timing("all")
+        x, info = ctx.gn_solve(dev(J), wl.alpha, b=dev(b), rtol=1e-10)
+        kt = ctx.kernel_timing()
+        ctx.set_kernel_timing([])
+        ctx.reset_kernel_timing()
+        assert ctx.kernel_timing()["gemm"]["launches"] == 0
+    assert kt["gemm"]["launches"] == 1 and kt["gemm"]["flops"] == wl.m * (wl.m + 1) * wl.N
+    assert kt["factor"]["launches"] == 1
+    assert kt["smooth"]["launches"] > 0 and kt["smooth"]["ms"] > 0 and kt["smooth"]["bytes"] > 0
+    assert kt["jv"]["launches"] >= info.iters
