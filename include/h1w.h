@@ -82,8 +82,14 @@ typedef struct {
     int64_t coarse_max;  /* coarsest level: first level with <= coarse_max nodes
                             (or that cannot be halved); 0 -> 729 (3D) / 289 (2D) */
     int rhs_chunk;       /* right-hand sides per batched V-cycle launch (0 -> auto) */
-    unsigned flags;      /* reserved, must be 0 */
+    unsigned flags;      /* H1W_FLAG_* bits, other bits must be 0 */
 } h1w_grid_desc;
+
+/* grid_desc.flags: always stream Z in FP64 capacitance builds (Z is built in
+ * row chunks and multiplied against J chunk by chunk instead of being kept;
+ * the preconditioner then recomputes Z w as B (J^T w)). Without the flag this
+ * happens only when an FP64 Z would not fit next to J. */
+#define H1W_FLAG_STREAM_Z 1u
 
 /* Krylov options (h1w_gn_solve). A zeroed struct selects the defaults. */
 typedef struct {
@@ -163,7 +169,16 @@ h1w_status h1w_poisson_solve_batched(h1w_ctx* ctx, int k, const void* F, int64_t
  * next h1w_capacitance_build or h1w_gn_solve on this context.
  * S_out (optional, m x m row-major FP64, leading dimension lds >= m) receives S.
  * Z_out (optional, m x N, leading dimension ldz >= N, dtype of the context's
- * V-cycle precision) receives Z.
+ * V-cycle precision) receives Z; EINVAL if Z was streamed (H1W_FLAG_STREAM_Z,
+ * or an FP64 Z too large to keep), info->zmode_used tells which.
+ * MIXED contexts keep the constant mode of Z exactly: with the trapezoid node
+ * weights W1 and s_i = (J_i . 1) / sum(W1), the FP32 V-cycle is applied to
+ * J_i - s_i W1 and its W-weighted mean mu_i is projected out, so
+ * Z = Z1 - 1 mu^T + (B W1) s^T with Z1 stored in FP32 and B W1 (an FP64
+ * V-cycle) and mu, s in FP64; the preconditioner's own V-cycle on r is
+ * deflated the same way. S is formed consistently with that representation
+ * (FP64 accumulation), which keeps the Woodbury correction accurate when
+ * ||S||/alpha is large. Z_out then receives Z rounded to FP32.
  * Returns ENOTSPD if factor = CHOL was forced and a pivot is not positive. */
 h1w_status h1w_capacitance_build(h1w_ctx* ctx, int m, const double* J, int64_t ldj,
                                  double alpha, int factor, double* S_out, int64_t lds,

@@ -135,8 +135,11 @@ def _dtype_code(t):
 
 
 # ------------------------------------------------------------------ entry points
+H1W_FLAG_STREAM_Z = 1
+
+
 def h1w_setup(shape, beta: float, precision: int = H1W_FP64, nu: int = 0, cheb=(0.0, 0.0),
-              coarse_max: int = 0, rhs_chunk: int = 0, stream=None):
+              coarse_max: int = 0, rhs_chunk: int = 0, stream=None, flags: int = 0):
     """Create a context; returns the opaque handle (c_void_p)."""
     d = h1w_grid_desc()
     d.dim = len(shape)
@@ -144,7 +147,7 @@ def h1w_setup(shape, beta: float, precision: int = H1W_FP64, nu: int = 0, cheb=(
         d.n[i] = int(n)
     d.beta, d.precision, d.nu = float(beta), int(precision), int(nu)
     d.cheb_lo, d.cheb_hi = float(cheb[0]), float(cheb[1])
-    d.coarse_max, d.rhs_chunk, d.flags = int(coarse_max), int(rhs_chunk), 0
+    d.coarse_max, d.rhs_chunk, d.flags = int(coarse_max), int(rhs_chunk), int(flags)
     if stream is None:
         import torch
         stream = torch.cuda.current_stream().cuda_stream

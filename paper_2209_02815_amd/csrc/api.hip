@@ -191,13 +191,18 @@ h1w_status h1w_capacitance_build(h1w_ctx* ctx, int m, const double* J, int64_t l
             require(ldz >= n, "ldz must be >= N");
         }
         c.capacitance_build(m, J, ldj, alpha, factor, info);
+        require(!(Z_out && c.z_streamed), "Z was streamed (too large to keep): Z_out is not available");
         if (S_out)
             H1W_HIP(hipMemcpy2DAsync(S_out, lds * sizeof(double), c.Sbuf.p, m * sizeof(double), m * sizeof(double), m,
                                      hipMemcpyDeviceToDevice, c.stream));
         if (Z_out) {
-            const size_t es = c.fp32 ? 4 : 8;
-            H1W_HIP(hipMemcpy2DAsync(Z_out, ldz * es, c.Zbuf.p, c.ldz * es, n * es, m, hipMemcpyDeviceToDevice,
-                                     c.stream));
+            if (c.fp32) {  // full Z = Z1 + v s^T rounded to FP32
+                h1w::launch_zout_deflated(c.stream, m, n, c.Zbuf.as<float>(), c.ldz, c.sdef.as<double>(),
+                                          c.mudef.as<double>(), c.vdef.as<double>(), (float*)Z_out, ldz);
+            } else {
+                H1W_HIP(hipMemcpy2DAsync(Z_out, ldz * 8, c.Zbuf.p, c.ldz * 8, n * 8, m, hipMemcpyDeviceToDevice,
+                                         c.stream));
+            }
         }
         c.sync();
     });

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_parts(int nparts, const doubl
 }
 
 // partial[i*nchunk + c] = sum over chunk c of M[i, n] v[n], rows i of this block.
-__global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const double* __restrict__ M,
+template <typename TM>
+__global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const TM* __restrict__ M,
                                                      int64_t ldm, const double* __restrict__ v,
                                                      double* __restrict__ partial) {
     __shared__ double sh[kBlock / 64];
@@ -69,15 +70,54 @@ __global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const dou
     for (int rr = 0; rr < kRowsPerBlock; ++rr) {
         const int i = r0 + rr;
         if (i >= m) break;
-        const double* row = M + (int64_t)i * ldm;
+        const TM* row = M + (int64_t)i * ldm;
         double acc = 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int64_t n = base + e * kBlock + threadIdx.x;
-            if (n < N) acc += row[n] * vv[e];
+            if (n < N) acc += double(row[n]) * vv[e];
         }
         const double s = block_sum<kBlock>(acc, sh);
         if (threadIdx.x == 0) partial[(int64_t)i * nchunk + blockIdx.x] = s;
+    }
+}
+
+// Two products in one pass over M: partial sums of M[i,:].v1 and M[i,:].v2.
+__global__ __launch_bounds__(kBlock) void k_rows_dot2(int m, int64_t N, const double* __restrict__ M, int64_t ldm,
+                                                      const double* __restrict__ v1, const double* __restrict__ v2,
+                                                      double* __restrict__ part1, double* __restrict__ part2) {
+    __shared__ double sh[kBlock / 64];
+    const int nchunk = gridDim.x;
+    const int64_t base = (int64_t)blockIdx.x * kRowChunk;
+    constexpr int E = kRowChunk / kBlock;
+    double a1[E], a2[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t n = base + e * kBlock + threadIdx.x;
+        a1[e] = n < N ? v1[n] : 0.0;
+        a2[e] = n < N ? v2[n] : 0.0;
+    }
+    const int r0 = blockIdx.y * kRowsPerBlock;
+    for (int rr = 0; rr < kRowsPerBlock; ++rr) {
+        const int i = r0 + rr;
+        if (i >= m) break;
+        const double* row = M + (int64_t)i * ldm;
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t n = base + e * kBlock + threadIdx.x;
+            if (n < N) {
+                const double x = row[n];
+                s1 += x * a1[e];
+                s2 += x * a2[e];
+            }
+        }
+        const double t1 = block_sum<kBlock>(s1, sh);
+        const double t2 = block_sum<kBlock>(s2, sh);
+        if (threadIdx.x == 0) {
+            part1[(int64_t)i * nchunk + blockIdx.x] = t1;
+            part2[(int64_t)i * nchunk + blockIdx.x] = t2;
+        }
     }
 }
 
@@ -142,6 +182,7 @@ template <typename TZ>
 __global__ __launch_bounds__(kBlock) void k_z_stored(int m, int64_t N, const TZ* __restrict__ Z,
                                                      int64_t ldz, const double* __restrict__ w,
                                                      const double* __restrict__ y, double inv_alpha,
+                                                     const double* __restrict__ v, const double* __restrict__ cptr,
                                                      double* __restrict__ z) {
     __shared__ double sw[kTile];
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -157,7 +198,23 @@ __global__ __launch_bounds__(kBlock) void k_z_stored(int m, int64_t N, const TZ*
             for (int q = 0; q < cnt; ++q) acc += double(col[(int64_t)q * ldz]) * sw[q];
         }
     }
-    if (n < N) z[n] = (y[n] - acc) * inv_alpha;
+    if (n < N) z[n] = (y[n] - acc - (v ? cptr[0] * v[n] - cptr[1] : 0.0)) * inv_alpha;
+}
+
+// S[i][j] += a[i] b[j] + c[i] d[j]  (m x m, row-major)
+__global__ __launch_bounds__(kBlock) void k_rank2_add(int m, const double* __restrict__ a, const double* __restrict__ bv,
+                                                      const double* __restrict__ c, const double* __restrict__ dv,
+                                                      double* __restrict__ S) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (int64_t)m * m) return;
+    const int i = (int)(idx / m), j = (int)(idx - (int64_t)i * m);
+    S[idx] += a[i] * bv[j] + c[i] * dv[j];
+}
+
+// y = s * x  for m entries (tiny vectors)
+__global__ __launch_bounds__(kBlock) void k_scale(int m, double s, const double* __restrict__ x, double* __restrict__ y) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) y[i] = s * x[i];
 }
 
 // p = (y - Z^T w) * inv_alpha + beta * p ;  t = J^T jp
@@ -304,7 +361,17 @@ int launch_rows_dot_partial(hipStream_t s, int m, int64_t N, const double* M, in
     const int nchunk = (int)cdiv(N, kRowChunk);
     if (m <= 0) return nchunk;
     const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
-    hipLaunchKernelGGL(k_rows_dot, grid, dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
+    hipLaunchKernelGGL((k_rows_dot<double>), grid, dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
+    H1W_LAUNCHED();
+    return nchunk;
+}
+
+int launch_rows_dot_partial_f32(hipStream_t s, int m, int64_t N, const float* M, int64_t ldm, const double* v,
+                                double* partial) {
+    const int nchunk = (int)cdiv(N, kRowChunk);
+    if (m <= 0) return nchunk;
+    const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
+    hipLaunchKernelGGL((k_rows_dot<float>), grid, dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
     H1W_LAUNCHED();
     return nchunk;
 }
@@ -325,9 +392,72 @@ void launch_jt_plain(hipStream_t s, int m, int64_t N, const double* J, int64_t l
 
 template <typename TZ>
 void launch_z_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
-                     const double* y, double inv_alpha, double* z) {
+                     const double* y, double inv_alpha, const double* v, const double* cptr, double* z) {
     hipLaunchKernelGGL((k_z_stored<TZ>), dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, m, N, Z,
-                       ldz, w, y, inv_alpha, z);
+                       ldz, w, y, inv_alpha, v, cptr, z);
+    H1W_LAUNCHED();
+}
+
+int launch_rows_dot2_partial(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm, const double* v1,
+                             const double* v2, double* part1, double* part2) {
+    const int nchunk = (int)cdiv(N, kRowChunk);
+    if (m <= 0) return nchunk;
+    const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
+    hipLaunchKernelGGL(k_rows_dot2, grid, dim3(kBlock), 0, s, m, N, M, ldm, v1, v2, part1, part2);
+    H1W_LAUNCHED();
+    return nchunk;
+}
+
+void launch_rank2_add(hipStream_t s, int m, const double* a, const double* bv, const double* c, const double* dv,
+                      double* S) {
+    hipLaunchKernelGGL(k_rank2_add, dim3((unsigned)cdiv((int64_t)m * m, kBlock)), dim3(kBlock), 0, s, m, a, bv, c, dv,
+                       S);
+    H1W_LAUNCHED();
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t N, double v, double* __restrict__ y) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n < N) y[n] = v;
+}
+
+// Zout[i][n] = float(Z1[i][n] - mu_i + s_i v[n])  (full Z of a deflated FP32 capacitance)
+__global__ __launch_bounds__(kBlock) void k_zout_deflated(int m, int64_t N, const float* __restrict__ Z1, int64_t ldz,
+                                                          const double* __restrict__ sv, const double* __restrict__ mu,
+                                                          const double* __restrict__ v, float* __restrict__ out,
+                                                          int64_t ldo) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    const double vn = v[n];
+    for (int i = blockIdx.y; i < m; i += gridDim.y)
+        out[(int64_t)i * ldo + n] = float(double(Z1[(int64_t)i * ldz + n]) - mu[i] + sv[i] * vn);
+}
+
+void launch_zout_deflated(hipStream_t s, int m, int64_t N, const float* Z1, int64_t ldz, const double* sv,
+                          const double* mu, const double* v, float* out, int64_t ldo) {
+    hipLaunchKernelGGL(k_zout_deflated, dim3((unsigned)cdiv(N, kBlock), (unsigned)std::min(m, 65535)), dim3(kBlock), 0,
+                       s, m, N, Z1, ldz, sv, mu, v, out, ldo);
+    H1W_LAUNCHED();
+}
+
+// y = x - mu + c v  (FP64 result of a deflated FP32 V-cycle: x converted from float)
+__global__ __launch_bounds__(kBlock) void k_undeflate(int64_t N, const float* __restrict__ x, const double* __restrict__ cm,
+                                                      const double* __restrict__ v, double* __restrict__ y) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n < N) y[n] = double(x[n]) - cm[1] + cm[0] * v[n];
+}
+
+void launch_undeflate(hipStream_t s, int64_t N, const float* x, const double* cm, const double* v, double* y) {
+    hipLaunchKernelGGL(k_undeflate, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, x, cm, v, y);
+    H1W_LAUNCHED();
+}
+
+void launch_fill(hipStream_t s, int64_t N, double v, double* y) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, v, y);
+    H1W_LAUNCHED();
+}
+
+void launch_scale(hipStream_t s, int m, double a, const double* x, double* y) {
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)cdiv(m, kBlock)), dim3(kBlock), 0, s, m, a, x, y);
     H1W_LAUNCHED();
 }
 
@@ -382,9 +512,9 @@ void launch_batched_p(hipStream_t s, int k, int64_t N, const double* b, const do
 }
 
 template void launch_z_stored<double>(hipStream_t, int, int64_t, const double*, int64_t, const double*,
-                                      const double*, double, double*);
+                                      const double*, double, const double*, const double*, double*);
 template void launch_z_stored<float>(hipStream_t, int, int64_t, const float*, int64_t, const double*,
-                                     const double*, double, double*);
+                                     const double*, double, const double*, const double*, double*);
 template void launch_p_stored<double>(hipStream_t, int, int64_t, const double*, int64_t, const double*,
                                       const double*, int64_t, const double*, const double*, double,
                                       double, double*, double*);

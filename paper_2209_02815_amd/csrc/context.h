@@ -34,6 +34,16 @@ struct Ctx {
     int64_t ldj = 0;
     double alpha = 0.0;
     DevBuf Zbuf;                     // Z = B J^T, m x N (double or float), ld = ldz
+    DevBuf zchunk;                   // rows of Z when Z is streamed
+    bool z_streamed = false;         // Z not kept (FP64, too large next to J)
+    // mixed precision: the constant mode of Z is kept exactly in FP64,
+    // Z = Z1 - 1 mu^T + v s^T with v = B W1 (FP64 V-cycle), s_i = (J_i . 1) / sum(W),
+    // Z1 the FP32 cycle applied to J_i - s_i W1 and mu_i the W-mean of Z1_i
+    bool deflate = false;
+    double wsum = 0.0;
+    DevBuf wvec, ones, vdef, sdef, jvdef, dpart, mudef, jneg;
+    bool vdef_ready = false;
+    void ensure_deflation_vectors();
     int64_t ldz = 0;
     DevBuf Sbuf;                     // S = alpha I + J Z^T (m x m)
     DevBuf F1, F2, pivb;             // factors: Cholesky U / L=U^T, or LU / (LU)^T (+ pivots)

@@ -100,7 +100,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
     require(d.precision == H1W_FP64 || d.precision == H1W_MIXED, "precision must be H1W_FP64 or H1W_MIXED");
     require(d.nu >= 0 && d.nu <= 16, "nu must be in [0, 16]");
-    require(d.flags == 0, "flags must be 0");
+    require((d.flags & ~H1W_FLAG_STREAM_Z) == 0, "unknown bits in flags");
     require(d.coarse_max >= 0, "coarse_max must be >= 0");
     require(d.rhs_chunk >= 0 && d.rhs_chunk <= 65535, "rhs_chunk must be in [0, 65535]");
     if (d.nu == 0) d.nu = 2;
@@ -154,6 +154,9 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     for (size_t l = 0; l < lv.size(); ++l) pitch[l] = cdiv(lv[l].N, 64) * 64;
     chunk = d.rhs_chunk > 0 ? d.rhs_chunk : (int)std::clamp<int64_t>((int64_t(1) << 26) / N0, 1, 1024);
 
+    deflate = fp32;
+    wsum = 1.0;
+    for (int a = 0; a < dim; ++a) wsum *= double(n[a] - 1);  // sum of the trapezoid weights
     H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
     scal.reserve(64 * sizeof(double));
     iflag.reserve(16 * sizeof(int));
@@ -224,13 +227,22 @@ void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
         const Geom& g = lv[l];
         // pre-smoothing from zero: first step writes t so that 2nu-1 flips end in x
         const double nl = (double)g.N;
-        timed(H1W_K_SMOOTH_FIRST, 2 * ces * nl, 0.0,
-              [&] { launch_smooth_first<T>(stream, dim, g, k, fptr(l), fld(l), tb[l], pitch[l], w[0]); });
         T* a = tb[l];
         int64_t la = pitch[l];
         T* b = xptr(l);
         int64_t lb = xld(l);
-        for (int s = 1; s < nu; ++s) {
+        int s = 1;
+        if (nu >= 2) {  // steps 1 and 2 in one pass, written where step 2 would write
+            timed(H1W_K_SMOOTH_FIRST, 2 * ces * nl, 0.0,
+                  [&] { launch_pre2<T>(stream, dim, g, k, fptr(l), fld(l), b, lb, w[0], w[1]); });
+            std::swap(a, b);
+            std::swap(la, lb);
+            s = 2;
+        } else {
+            timed(H1W_K_SMOOTH_FIRST, 2 * ces * nl, 0.0,
+                  [&] { launch_smooth_first<T>(stream, dim, g, k, fptr(l), fld(l), tb[l], pitch[l], w[0]); });
+        }
+        for (; s < nu; ++s) {
             timed(H1W_K_SMOOTH, 3 * ces * nl, 0.0,
                   [&] { launch_smooth<T>(stream, dim, g, k, fptr(l), fld(l), a, la, b, lb, w[s]); });
             std::swap(a, b);
@@ -281,6 +293,26 @@ void Ctx::apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
         return;
     }
     const int64_t n = N();
+    if (k == 1 && deflate) {
+        // y = P B~(F - c W1) + c v: the constant mode (c = 1.F / sum W) is handled
+        // exactly in FP64 and the W-mean mu of the FP32 cycle's output (rounding
+        // error amplified by the coarse solve) is projected out
+        ensure_deflation_vectors();
+        ensure_cg_ws(m);
+        stage.reserve((size_t)2 * pitch[0] * sizeof(float));
+        float* fin = stage.as<float>();
+        float* fout = fin + pitch[0];
+        double* cm = scal.as<double>() + 12;  // cm[0] = c, cm[1] = mu
+        dots(n, {{ones.as<double>(), F}}, 14);
+        launch_scale(stream, 1, 1.0 / wsum, scal.as<double>() + 14, cm);
+        launch_convert_deflate(stream, n, 1, F, ldf, cm, wvec.as<double>(), fin, pitch[0]);
+        vcycle_chunk<float>(1, fin, pitch[0], fout, pitch[0]);
+        const int nch = launch_rows_dot_partial_f32(stream, 1, n, fout, pitch[0], wvec.as<double>(), jpart.as<double>());
+        launch_reduce_parts(stream, 1, nch, jpart.as<double>(), scal.as<double>() + 15);
+        launch_scale(stream, 1, 1.0 / wsum, scal.as<double>() + 15, cm + 1);
+        launch_undeflate(stream, n, fout, cm, vdef.as<double>(), X);
+        return;
+    }
     for (int r0 = 0; r0 < k; r0 += chunk) {
         const int kk = std::min(chunk, k - r0);
         stage.reserve((size_t)2 * kk * pitch[0] * sizeof(float));
@@ -414,42 +446,106 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     ldj = ldj_;
     alpha = alpha_;
     ev_record(0);
-    // Z = B J^T (row i = B J_i), kept in the context
-    const size_t zes = fp32 ? sizeof(float) : sizeof(double);
-    Zbuf.reserve((size_t)m * n * zes);
-    ldz = n;
-    if (!fp32) {
-        vcycle<double>(m, J, ldj, Zbuf.as<double>(), ldz);
-    } else {
-        for (int r0 = 0; r0 < m; r0 += chunk) {
-            const int kk = std::min(chunk, m - r0);
-            stage.reserve((size_t)kk * pitch[0] * sizeof(float));
-            launch_convert<double, float>(stream, n, kk, J + (int64_t)r0 * ldj, ldj, stage.as<float>(), pitch[0], 1.0);
-            vcycle_chunk<float>(kk, stage.as<float>(), pitch[0], Zbuf.as<float>() + (int64_t)r0 * ldz, ldz);
-        }
-    }
-    ev_record(1);
-    // S = alpha I + J Z^T  (lower triangle only when Z is FP64 and S will be Cholesky-factored)
     int fac = factor_;
     if (fac == H1W_FACTOR_AUTO) fac = fp32 ? H1W_FACTOR_LU : H1W_FACTOR_CHOL;
-    const bool lower = !fp32 && fac == H1W_FACTOR_CHOL;
+    const size_t zes = fp32 ? sizeof(float) : sizeof(double);
     Sbuf.reserve((size_t)m * m * sizeof(double));
-    const size_t pe = gemm_partial_elems(m, n);
-    gpart.reserve(pe * sizeof(double));
-    int splits = 0;
-    const double gflops = lower ? (double)m * (m + 1) * n : 2.0 * m * m * n;
-    timed(H1W_K_GEMM, (double)m * n * (8 + zes), gflops, [&] {
-        if (!fp32)
-            splits = launch_capacitance_partial<double>(stream, m, n, J, ldj, Zbuf.as<double>(), ldz, lower,
-                                                        gpart.as<double>(), pe);
-        else
-            splits = launch_capacitance_partial<float>(stream, m, n, J, ldj, Zbuf.as<float>(), ldz, lower,
-                                                       gpart.as<double>(), pe);
-    });
-    launch_capacitance_reduce(stream, m, splits, gpart.as<double>(), lower, alpha, Sbuf.as<double>(), m);
+    // Store Z = B J^T (row i = B J_i) unless it does not fit next to J: an FP64
+    // Z larger than ~45% of the free device memory is streamed instead, in row
+    // chunks that each meet the rows of J at and below them (S is symmetric).
+    size_t freeb = 0, totalb = 0;
+    H1W_HIP(hipMemGetInfo(&freeb, &totalb));
+    const size_t zbytes = (size_t)m * n * zes;
+    const size_t avail = freeb + Zbuf.bytes;
+    z_streamed = !fp32 && ((d.flags & H1W_FLAG_STREAM_Z) || zbytes > avail / 100 * 45);
+    if (fp32 && zbytes > avail / 100 * 90)
+        throw Error{H1W_ENOMEM, "the FP32 Z of a MIXED context does not fit in device memory"};
+    double gflops = 0.0;
+    if (!z_streamed) {
+        Zbuf.reserve(zbytes);
+        ldz = n;
+        if (!fp32) {
+            vcycle<double>(m, J, ldj, Zbuf.as<double>(), ldz);
+        } else {
+            // FP32 V-cycles on J_i - s_i W1; the constant mode s_i v stays exact in FP64
+            ensure_deflation_vectors();
+            sdef.reserve((size_t)m * sizeof(double));
+            jvdef.reserve((size_t)m * sizeof(double));
+            const size_t pe = rows_dot_partial_elems(m, n);
+            dpart.reserve(2 * pe * sizeof(double));
+            const int nch = launch_rows_dot2_partial(stream, m, n, J, ldj, ones.as<double>(), vdef.as<double>(),
+                                                     dpart.as<double>(), dpart.as<double>() + pe);
+            launch_reduce_parts(stream, m, nch, dpart.as<double>(), sdef.as<double>());
+            launch_reduce_parts(stream, m, nch, dpart.as<double>() + pe, jvdef.as<double>());
+            launch_scale(stream, m, 1.0 / wsum, sdef.as<double>(), sdef.as<double>());
+            for (int r0 = 0; r0 < m; r0 += chunk) {
+                const int kk = std::min(chunk, m - r0);
+                stage.reserve((size_t)kk * pitch[0] * sizeof(float));
+                launch_convert_deflate(stream, n, kk, J + (int64_t)r0 * ldj, ldj, sdef.as<double>() + r0,
+                                       wvec.as<double>(), stage.as<float>(), pitch[0]);
+                vcycle_chunk<float>(kk, stage.as<float>(), pitch[0], Zbuf.as<float>() + (int64_t)r0 * ldz, ldz);
+            }
+        }
+        ev_record(1);
+        // S = alpha I + J Z^T (lower triangle only when Z is FP64 and S will be Cholesky-factored)
+        const bool lower = !fp32 && fac == H1W_FACTOR_CHOL;
+        const size_t pe = gemm_partial_elems(m, m, n);
+        gpart.reserve(pe * sizeof(double));
+        int splits = 0;
+        gflops = lower ? (double)m * (m + 1) * n : 2.0 * m * m * n;
+        timed(H1W_K_GEMM, (double)m * n * (8 + zes), gflops, [&] {
+            if (!fp32)
+                splits = launch_capacitance_partial<double>(stream, m, m, n, J, ldj, Zbuf.as<double>(), ldz, lower,
+                                                            gpart.as<double>(), pe);
+            else
+                splits = launch_capacitance_partial<float>(stream, m, m, n, J, ldj, Zbuf.as<float>(), ldz, lower,
+                                                           gpart.as<double>(), pe);
+        });
+        launch_capacitance_reduce(stream, m, m, splits, gpart.as<double>(), lower, alpha, Sbuf.as<double>(), m);
+        if (fp32) {
+            // Z = Z1 - 1 mu^T + v s^T with mu_i the W-mean of the stored row Z1_i:
+            // S += (J v) s^T - (J 1) mu^T, J 1 = wsum * s
+            mudef.reserve((size_t)m * sizeof(double));
+            jneg.reserve((size_t)m * sizeof(double));
+            const int nch = launch_rows_dot_partial_f32(stream, m, n, Zbuf.as<float>(), ldz, wvec.as<double>(),
+                                                        dpart.as<double>());
+            launch_reduce_parts(stream, m, nch, dpart.as<double>(), mudef.as<double>());
+            launch_scale(stream, m, 1.0 / wsum, mudef.as<double>(), mudef.as<double>());
+            launch_scale(stream, m, -wsum, sdef.as<double>(), jneg.as<double>());
+            launch_rank2_add(stream, m, jvdef.as<double>(), sdef.as<double>(), jneg.as<double>(), mudef.as<double>(),
+                             Sbuf.as<double>());
+        }
+    } else {
+        Zbuf.release();
+        ldz = n;
+        // rows of Z per chunk: a multiple of 128 using at most ~30% of the free memory
+        int zc = (int)std::min<size_t>((size_t)m, (avail / 100 * 30) / ((size_t)n * sizeof(double)));
+        zc = std::max(1, zc >= 128 ? zc / 128 * 128 : zc);
+        if (d.flags & H1W_FLAG_STREAM_Z) zc = std::min(zc, 128);  // forced: 128-row chunks
+        zchunk.reserve((size_t)zc * n * sizeof(double));
+        size_t pe = 0;
+        for (int c0 = 0; c0 < m; c0 += zc) pe = std::max(pe, gemm_partial_elems(m - c0, std::min(zc, m - c0), n));
+        gpart.reserve(pe * sizeof(double));
+        for (int c0 = 0; c0 < m; c0 += zc) {
+            const int cc = std::min(zc, m - c0);
+            vcycle<double>(cc, J + (int64_t)c0 * ldj, ldj, zchunk.as<double>(), n);
+            // S[c0:m, c0:c0+cc] = J[c0:m] Zc^T (+ alpha on the diagonal)
+            const int rows = m - c0;
+            int splits = 0;
+            timed(H1W_K_GEMM, (double)(rows + cc) * n * 8, 2.0 * rows * cc * n, [&] {
+                splits = launch_capacitance_partial<double>(stream, rows, cc, n, J + (int64_t)c0 * ldj, ldj,
+                                                            zchunk.as<double>(), n, false, gpart.as<double>(), pe);
+            });
+            launch_capacitance_reduce(stream, rows, cc, splits, gpart.as<double>(), false, alpha,
+                                      Sbuf.as<double>() + (int64_t)c0 * m + c0, m);
+            gflops += 2.0 * rows * cc * n;
+        }
+        launch_mirror_lower(stream, m, Sbuf.as<double>());
+        ev_record(1);
+    }
     ev_record(2);
     asym = 0.0;
-    if (!lower) {
+    if (fp32 || fac != H1W_FACTOR_CHOL) {
         launch_asym(stream, m, Sbuf.as<double>(), scal.as<double>());
         read_scal(1);
         asym = hscal[0] / alpha;
@@ -508,8 +604,11 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     sync();
     flush_timing();
     if (info) {
+        // with a streamed Z the V-cycles and the GEMM chunks interleave: their
+        // sum is reported as the Z build and the GEMM time is 0
         info->t_zbuild_ms = ev_ms(0, 1);
         info->t_gemm_ms = ev_ms(1, 2);
+        info->zmode_used = z_streamed ? H1W_Z_RECOMPUTE : H1W_Z_STORED;
         info->t_factor_ms = ev_ms(2, 3);
         info->factor_used = factor;
         info->failed_pivot = failed_pivot;
@@ -581,10 +680,13 @@ void Ctx::precond_one(const double* r, double* z, int zm) {
     apply_B(1, r, n, y, n);
     woodbury_mspace(y, Jy, w);
     if (zm == H1W_Z_STORED) {
-        if (fp32)
-            launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, 1.0 / alpha, z);
-        else
-            launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, 1.0 / alpha, z);
+        if (fp32) {
+            dots(m, {{sdef.as<double>(), w}, {mudef.as<double>(), w}}, 8);  // s.w, mu.w for the rank-1 parts of Z
+            launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, 1.0 / alpha, vdef.as<double>(),
+                                   scal.as<double>() + 8, z);
+        } else {
+            launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, 1.0 / alpha, nullptr, nullptr, z);
+        }
     } else {
         double* dummy = mv(kTmp);
         H1W_HIP(hipMemsetAsync(dummy, 0, (size_t)m * sizeof(double), stream));
@@ -598,6 +700,7 @@ void Ctx::precond_apply(int k, const double* R, int64_t ldr, double* Zout, int64
     if (zm == H1W_Z_AUTO) zm = fp32 ? H1W_Z_STORED : H1W_Z_RECOMPUTE;
     require(zm == H1W_Z_STORED || zm == H1W_Z_RECOMPUTE, "zmode must be AUTO, STORED or RECOMPUTE");
     require(!(fp32 && zm == H1W_Z_RECOMPUTE), "a MIXED context needs zmode STORED");
+    require(!(z_streamed && zm == H1W_Z_STORED), "Z was streamed (not stored): use zmode RECOMPUTE");
     ensure_cg_ws(m);
     for (int i = 0; i < k; ++i) precond_one(R + (int64_t)i * ldr, Zout + (int64_t)i * ldzo, zm);
     sync();
@@ -638,6 +741,10 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     int zm = o.zmode;
     if (zm == H1W_Z_AUTO) zm = fp32 ? H1W_Z_STORED : H1W_Z_RECOMPUTE;
     require(!(fp32 && zm == H1W_Z_RECOMPUTE), "a MIXED context needs zmode STORED");
+    if (m > 0 && z_streamed) {
+        require(zm != H1W_Z_STORED || o.zmode == H1W_Z_AUTO, "Z was streamed (not stored): use zmode RECOMPUTE");
+        zm = H1W_Z_RECOMPUTE;
+    }
     const bool flexible = fp32;
     const double rtol = o.rtol > 0 ? o.rtol : 1e-10;
     const int maxit = o.maxit > 0 ? o.maxit : 500;
@@ -703,10 +810,13 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
             launch_axpby(stream, n, 1.0, z, beta, p);
         } else {
             timed(H1W_K_JTV, (fp32 ? 4.0 : 8.0) * m * n + 16.0 * n, 2.0 * m * n, [&] {
-                if (fp32)
-                    launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, z);
-                else
-                    launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, ia, z);
+                if (fp32) {
+                    dots(m, {{sdef.as<double>(), w}, {mudef.as<double>(), w}}, 8);
+                    launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, vdef.as<double>(),
+                                           scal.as<double>() + 8, z);
+                } else {
+                    launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, ia, nullptr, nullptr, z);
+                }
             });
             dots(n, {{z, r}, {z, q}}, 0);
             read_scal(2);
@@ -803,6 +913,20 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     }
     if (status == H1W_ENOCONV) throw Error{H1W_ENOCONV, "GN-CG did not reach rtol within maxit iterations"};
     if (status == H1W_ENUMERIC) throw Error{H1W_ENUMERIC, "NaN or Inf in the CG recurrences"};
+}
+
+// ============================================================ constant-mode deflation (mixed)
+
+void Ctx::ensure_deflation_vectors() {
+    if (vdef_ready) return;
+    const int64_t n = N();
+    wvec.reserve((size_t)n * sizeof(double));
+    ones.reserve((size_t)n * sizeof(double));
+    vdef.reserve((size_t)n * sizeof(double));
+    launch_node_weights(stream, dim, lv[0], wvec.as<double>());
+    launch_fill(stream, n, 1.0, ones.as<double>());
+    vcycle<double>(1, wvec.as<double>(), n, vdef.as<double>(), n);  // v = B W1 in FP64
+    vdef_ready = true;
 }
 
 // ============================================================ J v with timing

@@ -8,7 +8,9 @@
 // writes it to partial[split]; a second kernel sums the splits in a fixed
 // order (deterministic) and adds alpha on the diagonal. When S is known to be
 // symmetric (FP64 Z), only tiles on or below the diagonal are computed and
-// the upper triangle is mirrored.
+// the upper triangle is mirrored. The product is general rectangular
+// (m rows of J against m2 rows of Z), which also serves a capacitance built
+// from Z in row chunks when Z does not fit next to J.
 //
 // Each wave owns a 64 x 64 sub-tile = 4 x 4 blocks of v_mfma_f64_16x16x4_f64.
 // The MFMA contracts 4 k-values held by the 4 groups of 16 lanes; any
@@ -41,11 +43,10 @@ constexpr int kResidentWG = 256;  // 256 CUs x 1 work-group (occupancy 1 wave/SI
 constexpr size_t kMaxPartialBytes = size_t(256) << 20;
 
 template <typename TZ>
-__global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, const double* __restrict__ J,
+__global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int m2, int64_t N, const double* __restrict__ J,
                                                            int64_t ldj, const TZ* __restrict__ Z, int64_t ldz,
-                                                           int T, int ntile, int lower, int total,
-                                                           int64_t kper, double* __restrict__ partial,
-                                                           int mp) {
+                                                           int T, int T2, int ntile, int lower, int total,
+                                                           int64_t kper, double* __restrict__ partial) {
     const int bid = blockIdx.x;
     const int per = (total + 7) / 8;
     const int u = (bid & 7) * per + (bid >> 3);
@@ -58,8 +59,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, con
         while ((tr + 1) * (tr + 2) / 2 <= tile) ++tr;
         tc = tile - tr * (tr + 1) / 2;
     } else {
-        tr = tile / T;
-        tc = tile - tr * T;
+        tr = tile / T2;
+        tc = tile - tr * T2;
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int l16 = lane & 15, g = lane >> 4;
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, con
         va[b] = r < m;
         pa[b] = J + (int64_t)(va[b] ? r : 0) * ldj;
         const int c = col0 + b * 16 + l16;
-        vb[b] = c < m;
+        vb[b] = c < m2;
         pb[b] = Z + (int64_t)(vb[b] ? c : 0) * ldz;
     }
     d4 acc[4][4];
@@ -86,10 +87,11 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, con
 
     const int64_t k0 = (int64_t)split * kper;
     const int64_t k1 = std::min<int64_t>(N, k0 + kper);
-    int64_t k = k0;
-    for (; k + KSTEP <= k1; k += KSTEP) {
+    // Operands for one k-step: KL consecutive k-values per lane for 4 row
+    // blocks of J and 4 of Z. Two register sets alternate so that the loads of
+    // step s+1 are in flight while the MFMAs of step s run.
+    auto load = [&](int64_t k, double (&a)[4][KL], double (&b)[4][KL]) {
         const int64_t kk = k + g * KL;
-        double a[4][KL], b[4][KL];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -99,6 +101,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, con
                 const double y = double(pb[r][kk + t]);
                 b[r][t] = vb[r] ? y : 0.0;
             }
+    };
+    auto mma = [&](const double (&a)[4][KL], const double (&b)[4][KL]) {
 #pragma unroll
         for (int t = 0; t < KL; ++t)
 #pragma unroll
@@ -106,6 +110,24 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, con
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][t], b[c][t], acc[r][c], 0, 0, 0);
+    };
+    const int64_t nfull = (k1 - k0) / KSTEP;  // full k-steps in this split
+    int64_t k = k0;
+    if (nfull > 0) {
+        double a0[4][KL], b0[4][KL], a1[4][KL], b1[4][KL];
+        load(k, a0, b0);
+        int64_t s = 0;
+        for (; s + 2 <= nfull; s += 2) {
+            load(k + KSTEP, a1, b1);
+            mma(a0, b0);
+            if (s + 2 < nfull) load(k + 2 * KSTEP, a0, b0);
+            mma(a1, b1);
+            k += 2 * KSTEP;
+        }
+        if (s < nfull) {  // one full step left, already loaded in a0/b0
+            mma(a0, b0);
+            k += KSTEP;
+        }
     }
     if (k < k1) {  // ragged tail: k-values at or beyond k1 contribute zero
         const int64_t kk = k + g * KL;
@@ -121,15 +143,9 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, con
                 const double y = double(pb[r][kc]);
                 b[r][t] = (vb[r] && in) ? y : 0.0;
             }
-#pragma unroll
-        for (int t = 0; t < KL; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][t], b[c][t], acc[r][c], 0, 0, 0);
+        mma(a, b);
     }
-    double* P = partial + (int64_t)split * mp * mp;
+    double* P = partial + (int64_t)split * m * m2;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -138,35 +154,48 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int64_t N, con
             for (int v = 0; v < 4; ++v) {
                 const int row = row0 + r * 16 + g + 4 * v;
                 const int col = col0 + c * 16 + l16;
-                if (row < m && col < m) P[(int64_t)row * mp + col] = acc[r][c][v];
+                if (row < m && col < m2) P[(int64_t)row * m2 + col] = acc[r][c][v];
             }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cap_reduce(int m, int mp, int splits, const double* __restrict__ partial,
+// S[i][j] (block of m x m2 at S, leading dimension lds) = sum over splits of
+// the partials (+ alpha on the block diagonal i == j). lower: the square
+// product was computed on and below the diagonal only; S[i][j] for i < j is
+// taken from the partial at (j, i).
+__global__ __launch_bounds__(kBlock) void k_cap_reduce(int m, int m2, int splits, const double* __restrict__ partial,
                                                        int lower, double alpha, double* __restrict__ S,
                                                        int64_t lds) {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= (int64_t)m * m) return;
-    const int i = (int)(idx / m), j = (int)(idx - (int64_t)i * m);
+    if (idx >= (int64_t)m * m2) return;
+    const int i = (int)(idx / m2), j = (int)(idx - (int64_t)i * m2);
     const int si = (lower && i < j) ? j : i;
     const int sj = (lower && i < j) ? i : j;
-    const double* p = partial + (int64_t)si * mp + sj;
+    const double* p = partial + (int64_t)si * m2 + sj;
     double acc = 0.0;
-    for (int s = 0; s < splits; ++s) acc += p[(int64_t)s * mp * mp];
+    for (int s = 0; s < splits; ++s) acc += p[(int64_t)s * m * m2];
     if (i == j) acc += alpha;
     S[(int64_t)i * lds + j] = acc;
 }
 
+// S[i][j] = S[j][i] for i < j (upper triangle from the lower one)
+__global__ __launch_bounds__(kBlock) void k_mirror_lower(int m, double* __restrict__ S) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (int64_t)m * m) return;
+    const int i = (int)(idx / m), j = (int)(idx - (int64_t)i * m);
+    if (i < j) S[(int64_t)i * m + j] = S[(int64_t)j * m + i];
+}
+
 struct GemmPlan {
-    int T, ntile, splits;
+    int T, T2, ntile, splits;
     int64_t kper;
 };
 
-GemmPlan plan(int m, int64_t N, bool lower) {
+GemmPlan plan(int m, int m2, int64_t N, bool lower) {
     GemmPlan p;
     p.T = (int)cdiv(m, kTileMN);
-    p.ntile = lower ? p.T * (p.T + 1) / 2 : p.T * p.T;
-    const size_t per_split = (size_t)m * m * sizeof(double);
+    p.T2 = (int)cdiv(m2, kTileMN);
+    p.ntile = lower ? p.T * (p.T + 1) / 2 : p.T * p.T2;
+    const size_t per_split = (size_t)m * m2 * sizeof(double);
     int splits = std::max(1, kResidentWG / p.ntile);
     splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, cdiv(N, 256)));
     splits = (int)std::max<size_t>(1, std::min<size_t>(splits, kMaxPartialBytes / per_split));
@@ -177,37 +206,44 @@ GemmPlan plan(int m, int64_t N, bool lower) {
 
 }  // namespace
 
-size_t gemm_partial_elems(int m, int64_t N) {
-    const GemmPlan p = plan(m, N, false);
-    const GemmPlan q = plan(m, N, true);
-    return (size_t)std::max(p.splits, q.splits) * m * m;
+size_t gemm_partial_elems(int m, int m2, int64_t N) {
+    const GemmPlan p = plan(m, m2, N, false);
+    size_t e = (size_t)p.splits * m * m2;
+    if (m == m2) e = std::max(e, (size_t)plan(m, m, N, true).splits * m * m);
+    return e;
 }
 
 template <typename TZ>
-int launch_capacitance_partial(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj, const TZ* Z,
+int launch_capacitance_partial(hipStream_t s, int m, int m2, int64_t N, const double* J, int64_t ldj, const TZ* Z,
                                int64_t ldz, bool lower_only, double* partial, size_t partial_elems) {
-    if (m <= 0) return 0;
-    const GemmPlan p = plan(m, N, lower_only);
-    if ((size_t)p.splits * m * m > partial_elems) throw Error{H1W_EINVAL, "internal: GEMM partial buffer too small"};
+    if (m <= 0 || m2 <= 0) return 0;
+    if (lower_only && m != m2) throw Error{H1W_EINVAL, "internal: lower-triangle GEMM needs a square output"};
+    const GemmPlan p = plan(m, m2, N, lower_only);
+    if ((size_t)p.splits * m * m2 > partial_elems) throw Error{H1W_EINVAL, "internal: GEMM partial buffer too small"};
     const int total = p.ntile * p.splits;
     const int grid = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL((k_cap_gemm<TZ>), dim3(grid), dim3(kGemmThreads), 0, s, m, N, J, ldj, Z, ldz, p.T,
-                       p.ntile, (int)lower_only, total, p.kper, partial, m);
+    hipLaunchKernelGGL((k_cap_gemm<TZ>), dim3(grid), dim3(kGemmThreads), 0, s, m, m2, N, J, ldj, Z, ldz, p.T, p.T2,
+                       p.ntile, (int)lower_only, total, p.kper, partial);
     H1W_LAUNCHED();
     return p.splits;
 }
 
-void launch_capacitance_reduce(hipStream_t s, int m, int splits, const double* partial, bool lower_only,
+void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const double* partial, bool lower_only,
                                double alpha, double* S, int64_t lds) {
-    if (m <= 0) return;
-    hipLaunchKernelGGL(k_cap_reduce, dim3((unsigned)cdiv((int64_t)m * m, kBlock)), dim3(kBlock), 0, s, m, m,
+    if (m <= 0 || m2 <= 0) return;
+    hipLaunchKernelGGL(k_cap_reduce, dim3((unsigned)cdiv((int64_t)m * m2, kBlock)), dim3(kBlock), 0, s, m, m2,
                        splits, partial, (int)lower_only, alpha, S, lds);
     H1W_LAUNCHED();
 }
 
-template int launch_capacitance_partial<double>(hipStream_t, int, int64_t, const double*, int64_t,
+void launch_mirror_lower(hipStream_t s, int m, double* S) {
+    hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)cdiv((int64_t)m * m, kBlock)), dim3(kBlock), 0, s, m, S);
+    H1W_LAUNCHED();
+}
+
+template int launch_capacitance_partial<double>(hipStream_t, int, int, int64_t, const double*, int64_t,
                                                 const double*, int64_t, bool, double*, size_t);
-template int launch_capacitance_partial<float>(hipStream_t, int, int64_t, const double*, int64_t, const float*,
+template int launch_capacitance_partial<float>(hipStream_t, int, int, int64_t, const double*, int64_t, const float*,
                                                int64_t, bool, double*, size_t);
 
 }  // namespace h1w

@@ -87,6 +87,10 @@ void launch_smooth_first(hipStream_t s, int dim, const Geom& g, int k, const T* 
 template <typename T>
 void launch_smooth(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
                    const T* Xin, int64_t ldi, T* Xout, int64_t ldo, double w);
+// first two smoothing steps from zero fused: X = x1 + w1 D^-1 (F - A x1), x1 = w0 D^-1 F
+template <typename T>
+void launch_pre2(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf, T* X, int64_t ldx,
+                 double w0, double w1);
 template <typename T>
 void launch_residual(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
                      const T* X, int64_t ldx, T* R, int64_t ldr);
@@ -126,9 +130,24 @@ template <typename TZ>
 void launch_p_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
                      const double* J, int64_t ldj, const double* jp, const double* y,
                      double inv_alpha, double beta, double* p, double* t);
+// z = (y - Z^T w - c0 v + c1) * inv_alpha with (c0, c1) = cptr[0..1] (v may be null: no extra terms)
 template <typename TZ>
 void launch_z_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
-                     const double* y, double inv_alpha, double* z);
+                     const double* y, double inv_alpha, const double* v, const double* cptr, double* z);
+int launch_rows_dot2_partial(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm, const double* v1,
+                             const double* v2, double* part1, double* part2);
+void launch_rank2_add(hipStream_t s, int m, const double* a, const double* b, const double* c, const double* d,
+                      double* S);
+int launch_rows_dot_partial_f32(hipStream_t s, int m, int64_t N, const float* M, int64_t ldm, const double* v,
+                                double* partial);
+void launch_undeflate(hipStream_t s, int64_t N, const float* x, const double* cm, const double* v, double* y);
+void launch_scale(hipStream_t s, int m, double a, const double* x, double* y);
+void launch_fill(hipStream_t s, int64_t N, double v, double* y);
+void launch_zout_deflated(hipStream_t s, int m, int64_t N, const float* Z1, int64_t ldz, const double* sv,
+                          const double* mu, const double* v, float* out, int64_t ldo);
+void launch_node_weights(hipStream_t s, int dim, const Geom& g, double* out);
+void launch_convert_deflate(hipStream_t s, int64_t N, int k, const double* X, int64_t ldx, const double* sv,
+                            const double* wv, float* Y, int64_t ldy);
 void launch_axpby(hipStream_t s, int64_t N, double a, const double* x, double b, double* y);
 void launch_cg_update(hipStream_t s, int64_t N, double a, const double* p, const double* q,
                       double* x, double* r, double* partial, int* nparts);
@@ -145,13 +164,16 @@ void launch_batched_p(hipStream_t s, int k, int64_t N, const double* b, const do
 // gemm.hip: S = alpha*I + J Z^T with FP64 accumulation on MFMA
 // (partial: the MFMA kernel writing per-split partial sums; reduce: the
 // fixed-order sum over splits plus alpha on the diagonal)
+// C (m x m2) = J (m rows) Z^T (m2 rows); lower_only requires m == m2 and Z
+// symmetric-compatible (S mirrored from its lower triangle)
 template <typename TZ>
-int launch_capacitance_partial(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
+int launch_capacitance_partial(hipStream_t s, int m, int m2, int64_t N, const double* J, int64_t ldj,
                                const TZ* Z, int64_t ldz, bool lower_only, double* partial,
                                size_t partial_elems);
-void launch_capacitance_reduce(hipStream_t s, int m, int splits, const double* partial, bool lower_only,
+void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const double* partial, bool lower_only,
                                double alpha, double* S, int64_t lds);
-size_t gemm_partial_elems(int m, int64_t N);
+void launch_mirror_lower(hipStream_t s, int m, double* S);
+size_t gemm_partial_elems(int m, int m2, int64_t N);
 
 // dense.hip (single-workgroup factorisations for m <= a few thousand)
 void launch_cholesky_upper(hipStream_t s, int m, double* U, int* info);

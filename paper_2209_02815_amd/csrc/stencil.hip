@@ -231,6 +231,83 @@ __global__ __launch_bounds__(kBlock) void k_march(Geom g, Sweep s, const T* __re
     }
 }
 
+// Diagonal of A at node (i, j, l) from its position alone.
+template <typename T, int DIM>
+__device__ __forceinline__ T diag_node(const Geom& g, int i, int j, int l) {
+    const T wx = (i == 0 || i == g.nx - 1) ? T(0.5) : T(1);
+    const T wy = (j == 0 || j == g.ny - 1) ? T(0.5) : T(1);
+    const T wz = (DIM == 3 && (l == 0 || l == g.nz - 1)) ? T(0.5) : T(1);
+    const int dx = int(i > 0) + int(i < g.nx - 1), dy = int(j > 0) + int(j < g.ny - 1);
+    const int dz = DIM == 3 ? int(l > 0) + int(l < g.nz - 1) : 0;
+    T d = T(g.beta) * wx * wy * wz + T(g.ihx2) * wy * wz * T(dx) + T(g.ihy2) * wx * wz * T(dy);
+    if (DIM == 3) d += T(g.ihz2) * wx * wy * T(dz);
+    return d;
+}
+
+// The first two smoothing steps from a zero initial guess in one pass:
+//   x1 = w0 D^-1 f  (pointwise), x2 = x1 + w1 D^-1 (f - A x1).
+// x1 at the stencil neighbours is rebuilt from f and the neighbours'
+// diagonals, so only f is read and only x2 is written.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_pre2(Geom g, Sweep s, const T* __restrict__ F, int64_t ldf,
+                                                 T* __restrict__ Y, int64_t ldy, T w0, T w1) {
+    int q, z0, z1, r;
+    if (!sweep_item(s, q, z0, z1, r, g.nz)) return;
+    const int i = q % g.nx, j = q / g.nx;
+    const Column<T, DIM> col(g, i, j);
+    const T* f = F + r * ldf;
+    T* y = Y + r * ldy;
+    const int64_t PL = s.PL;
+    const int nx = g.nx;
+    // x1 below / at the current plane (carried along the march)
+    T x1b = (DIM == 3 && z0 > 0) ? w0 * f[(z0 - 1) * PL + q] / diag_node<T, DIM>(g, i, j, z0 - 1) : T(0);
+    T fc = f[z0 * PL + q];
+    T x1c = w0 * fc / diag_node<T, DIM>(g, i, j, z0);
+    for (int l0 = z0; l0 < z1; l0 += kU) {
+        T fa[kU], nxm[kU], nxp[kU], nym[kU], nyp[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int l = l0 + u;
+            const int64_t p = l * PL + q;
+            const bool in = l < z1;
+            fa[u] = (in && DIM == 3 && l + 1 < g.nz) ? f[p + PL] : T(0);
+            nxm[u] = (in && col.xm) ? f[p - 1] : T(0);
+            nxp[u] = (in && col.xp) ? f[p + 1] : T(0);
+            nym[u] = (in && col.ym) ? f[p - nx] : T(0);
+            nyp[u] = (in && col.yp) ? f[p + nx] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int l = l0 + u;
+            if (l >= z1) break;
+            const int64_t p = l * PL + q;
+            const bool zm = DIM == 3 && l > 0, zp = DIM == 3 && l < g.nz - 1;
+            const T wz = (DIM == 3 && (l == 0 || l == g.nz - 1)) ? T(0.5) : T(1);
+            const T cx = T(g.ihx2) * col.wy * wz, cy = T(g.ihy2) * col.wx * wz;
+            const T cz = DIM == 3 ? T(g.ihz2) * col.wx * col.wy : T(0);
+            const T mass = T(g.beta) * col.wx * col.wy * wz;
+            const T diag = mass + cx * T(int(col.xm) + int(col.xp)) + cy * T(int(col.ym) + int(col.yp)) +
+                           cz * T(int(zm) + int(zp));
+            const T x1a = zp ? w0 * fa[u] / diag_node<T, DIM>(g, i, j, l + 1) : T(0);
+            T sx = T(0), sy = T(0), sz = T(0);
+            if (col.xm) sx += x1c - w0 * nxm[u] / diag_node<T, DIM>(g, i - 1, j, l);
+            if (col.xp) sx += x1c - w0 * nxp[u] / diag_node<T, DIM>(g, i + 1, j, l);
+            if (col.ym) sy += x1c - w0 * nym[u] / diag_node<T, DIM>(g, i, j - 1, l);
+            if (col.yp) sy += x1c - w0 * nyp[u] / diag_node<T, DIM>(g, i, j + 1, l);
+            if (zm) sz += x1c - x1b;
+            if (zp) sz += x1c - x1a;
+            T acc = mass * x1c;
+            acc += cx * sx;
+            acc += cy * sy;
+            if (DIM == 3) acc += cz * sz;
+            y[p] = x1c + w1 * (fc - acc) / diag;
+            x1b = x1c;
+            x1c = x1a;
+            fc = fa[u];
+        }
+    }
+}
+
 // X = w D^-1 F (first smoothing step from a zero initial guess)
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_smooth_first(Geom g, Sweep s, const T* __restrict__ F, int64_t ldf,
@@ -358,6 +435,28 @@ __global__ __launch_bounds__(kBlock) void k_convert(int64_t N, int k, const TI* 
     for (int r = blockIdx.y; r < k; r += gridDim.y) Y[r * ldy + p] = TO(scale * X[r * ldx + p]);
 }
 
+// W 1: trapezoid node weights wx wy wz (the lumped mass diagonal without beta)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_node_weights(Geom g, double* __restrict__ out) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= g.N) return;
+    int i, j, l;
+    decompose(g, p, i, j, l);
+    const double wx = (i == 0 || i == g.nx - 1) ? 0.5 : 1.0, wy = (j == 0 || j == g.ny - 1) ? 0.5 : 1.0;
+    const double wz = (DIM == 3 && (l == 0 || l == g.nz - 1)) ? 0.5 : 1.0;
+    out[p] = wx * wy * wz;
+}
+
+// Y_r = float(X_r - s_r W 1): FP32 right-hand sides with the constant mode removed
+__global__ __launch_bounds__(kBlock) void k_convert_deflate(int64_t N, int k, const double* __restrict__ X, int64_t ldx,
+                                                            const double* __restrict__ sv, const double* __restrict__ wv,
+                                                            float* __restrict__ Y, int64_t ldy) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= N) return;
+    const double w = wv[p];
+    for (int r = blockIdx.y; r < k; r += gridDim.y) Y[r * ldy + p] = float(X[r * ldx + p] - sv[r] * w);
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_apply_plus_dot(Geom g, double a,
                                                            const double* __restrict__ P,
@@ -420,6 +519,14 @@ void launch_smooth_first(hipStream_t s, int dim, const Geom& g, int k, const T* 
 }
 
 template <typename T>
+void launch_pre2(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf, T* X, int64_t ldx,
+                 double w0, double w1) {
+    if (k <= 0) return;
+    const Sweep sw = make_sweep(g, k);
+    H1W_DIMCALL(k_pre2, T, dim3(sweep_grid(sw)), g, sw, F, ldf, X, ldx, T(w0), T(w1));
+}
+
+template <typename T>
 void launch_smooth(hipStream_t s, int dim, const Geom& g, int k, const T* F, int64_t ldf,
                    const T* Xin, int64_t ldi, T* Xout, int64_t ldo, double w) {
     if (k <= 0) return;
@@ -468,6 +575,22 @@ void launch_convert(hipStream_t s, int64_t N, int k, const TI* X, int64_t ldx, T
     H1W_LAUNCHED();
 }
 
+void launch_node_weights(hipStream_t s, int dim, const Geom& g, double* out) {
+    const dim3 grid((unsigned)cdiv(g.N, kBlock));
+    if (dim == 3)
+        hipLaunchKernelGGL((k_node_weights<3>), grid, dim3(kBlock), 0, s, g, out);
+    else
+        hipLaunchKernelGGL((k_node_weights<2>), grid, dim3(kBlock), 0, s, g, out);
+    H1W_LAUNCHED();
+}
+
+void launch_convert_deflate(hipStream_t s, int64_t N, int k, const double* X, int64_t ldx, const double* sv,
+                            const double* wv, float* Y, int64_t ldy) {
+    if (k <= 0) return;
+    hipLaunchKernelGGL(k_convert_deflate, grid_for(N, k), dim3(kBlock), 0, s, N, k, X, ldx, sv, wv, Y, ldy);
+    H1W_LAUNCHED();
+}
+
 void launch_apply_plus_dot(hipStream_t s, int dim, const Geom& g, double a, const double* P,
                            const double* Tv, double* Q, double* partial, int* nparts) {
     const dim3 grid((unsigned)cdiv(g.N, kBlock));
@@ -484,6 +607,8 @@ void launch_apply_plus_dot(hipStream_t s, int dim, const Geom& g, double a, cons
                                   int64_t, double);                                              \
     template void launch_smooth_first<T>(hipStream_t, int, const Geom&, int, const T*, int64_t,  \
                                          T*, int64_t, double);                                   \
+    template void launch_pre2<T>(hipStream_t, int, const Geom&, int, const T*, int64_t, T*, int64_t,  \
+                                 double, double);                                                 \
     template void launch_smooth<T>(hipStream_t, int, const Geom&, int, const T*, int64_t,        \
                                    const T*, int64_t, T*, int64_t, double);                      \
     template void launch_residual<T>(hipStream_t, int, const Geom&, int, const T*, int64_t,      \
