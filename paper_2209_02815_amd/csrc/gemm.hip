@@ -12,15 +12,13 @@
 // (m rows of J against m2 rows of Z), which also serves a capacitance built
 // from Z in row chunks when Z does not fit next to J.
 //
-// Each wave owns a 64 x 64 sub-tile = 4 x 4 blocks of v_mfma_f64_16x16x4_f64.
-// The MFMA contracts 4 k-values held by the 4 groups of 16 lanes; any
-// assignment of physical k to (lane group, step) gives the same sum, so lane
-// group g walks KL consecutive k-values per step: lanes read 8-byte words of
-// contiguous rows straight from global memory (no LDS), and one step covers
-// 4*KL = 16 k-values. Accumulator layout of the FP64 16x16 block: lane l,
-// element v holds row (l/16) + 4v, column l%16.
+// Each wave owns a 64 x 64 sub-tile = 4 x 4 blocks of v_mfma_f64_16x16x4_f64
+// whose operands come from LDS copies of the work-group's 128-row tiles of J
+// and Z (each element is read from HBM once per work-group, not once per
+// wave). Accumulator layout of the FP64 16x16 block: lane l, element v holds
+// row (l/16) + 4v, column l%16.
 //
-// Launch: one work-group per (tile, split), at most ~2 resident per CU.
+// Launch: one work-group per (tile, split), two resident per CU.
 // Work items are ordered split-major and dealt to the 8 XCDs in contiguous
 // ranges (work-group ids go round-robin over XCDs), so the tiles that share a
 // K range share one XCD's L2.
@@ -36,17 +34,28 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTileMN = 128;
-constexpr int KL = 4;
-constexpr int KSTEP = 4 * KL;
 constexpr int kGemmThreads = 256;
-constexpr int kResidentWG = 256;  // 256 CUs x 1 work-group (occupancy 1 wave/SIMD)
+constexpr int kResidentWG = 512;  // 256 CUs x 2 work-groups
 constexpr size_t kMaxPartialBytes = size_t(256) << 20;
 
+// K is consumed in chunks of KB = 16: the 256 threads copy the 128 x KB
+// tiles of J and Z into LDS (double-buffered; rows padded to an odd stride so
+// the MFMA operand reads do not collide on banks), then each wave runs its
+// 4 x 4 MFMA blocks over the chunk (4 k-steps). The global loads of chunk
+// c+1 are in flight while chunk c is computed; one barrier per chunk.
+// Loader mapping: thread t owns column k = t % 16 of rows t/16 + 16u
+// (u = 0..7), so one load instruction of a wave reads 4 whole 128-byte row
+// segments.
+constexpr int KB = 16;
+constexpr int LDT = KB + 1;  // LDS row stride (doubles)
+
 template <typename TZ>
-__global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int m2, int64_t N, const double* __restrict__ J,
-                                                           int64_t ldj, const TZ* __restrict__ Z, int64_t ldz,
-                                                           int T, int T2, int ntile, int lower, int total,
-                                                           int64_t kper, double* __restrict__ partial) {
+__global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int64_t N, const double* __restrict__ J,
+                                                              int64_t ldj, const TZ* __restrict__ Z, int64_t ldz,
+                                                              int T, int T2, int ntile, int lower, int total,
+                                                              int64_t kper, double* __restrict__ partial) {
+    __shared__ double sA[2][kTileMN * LDT];
+    __shared__ double sB[2][kTileMN * LDT];
     const int bid = blockIdx.x;
     const int per = (total + 7) / 8;
     const int u = (bid & 7) * per + (bid >> 3);
@@ -62,88 +71,81 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int m2, int64_
         tr = tile / T2;
         tc = tile - tr * T2;
     }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int l16 = lane & 15, g = lane >> 4;
-    const int row0 = tr * kTileMN + (wave >> 1) * 64;
-    const int col0 = tc * kTileMN + (wave & 1) * 64;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int arow0 = tr * kTileMN, brow0 = tc * kTileMN;
 
-    const double* pa[4];
-    const TZ* pb[4];
-    bool va[4], vb[4];
+    // loader: column lk of rows lr + 16 q, q = 0..7
+    const int lk = tid & 15, lr = tid >> 4;
+    const double* pa[8];
+    const TZ* pb[8];
+    bool va[8], vb[8];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int r = row0 + b * 16 + l16;
-        va[b] = r < m;
-        pa[b] = J + (int64_t)(va[b] ? r : 0) * ldj;
-        const int c = col0 + b * 16 + l16;
-        vb[b] = c < m2;
-        pb[b] = Z + (int64_t)(vb[b] ? c : 0) * ldz;
+    for (int q = 0; q < 8; ++q) {
+        const int r = arow0 + lr + 16 * q;
+        va[q] = r < m;
+        pa[q] = J + (int64_t)(va[q] ? r : 0) * ldj;
+        const int c = brow0 + lr + 16 * q;
+        vb[q] = c < m2;
+        pb[q] = Z + (int64_t)(vb[q] ? c : 0) * ldz;
     }
+    const int64_t k0 = (int64_t)split * kper;
+    const int64_t k1 = std::min<int64_t>(N, k0 + kper);
+    const int nchunk = (int)((k1 - k0 + KB - 1) / KB);
+    double ra[8], rb[8];
+    auto gload = [&](int c) {
+        const int64_t k = k0 + (int64_t)c * KB + lk;
+        const bool in = k < k1;
+        const int64_t kc = in ? k : k0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double x = pa[q][kc];
+            ra[q] = (va[q] && in) ? x : 0.0;
+            const double y = double(pb[q][kc]);
+            rb[q] = (vb[q] && in) ? y : 0.0;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            sA[buf][(lr + 16 * q) * LDT + lk] = ra[q];
+            sB[buf][(lr + 16 * q) * LDT + lk] = rb[q];
+        }
+    };
     d4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-    const int64_t k0 = (int64_t)split * kper;
-    const int64_t k1 = std::min<int64_t>(N, k0 + kper);
-    // Operands for one k-step: KL consecutive k-values per lane for 4 row
-    // blocks of J and 4 of Z. Two register sets alternate so that the loads of
-    // step s+1 are in flight while the MFMAs of step s run.
-    auto load = [&](int64_t k, double (&a)[4][KL], double (&b)[4][KL]) {
-        const int64_t kk = k + g * KL;
+    if (nchunk > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunk) gload(c + 1);
+        const double* A = sA[buf];
+        const double* B = sB[buf];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int s4 = 0; s4 < KB / 4; ++s4) {
+            const int kk = 4 * s4 + g;
+            double a[4], b[4];
 #pragma unroll
-            for (int t = 0; t < KL; ++t) {
-                const double x = pa[r][kk + t];
-                a[r][t] = va[r] ? x : 0.0;
-                const double y = double(pb[r][kk + t]);
-                b[r][t] = vb[r] ? y : 0.0;
+            for (int r = 0; r < 4; ++r) {
+                a[r] = A[(wr + 16 * r + l16) * LDT + kk];
+                b[r] = B[(wc + 16 * r + l16) * LDT + kk];
             }
-    };
-    auto mma = [&](const double (&a)[4][KL], const double (&b)[4][KL]) {
-#pragma unroll
-        for (int t = 0; t < KL; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][t], b[c][t], acc[r][c], 0, 0, 0);
-    };
-    const int64_t nfull = (k1 - k0) / KSTEP;  // full k-steps in this split
-    int64_t k = k0;
-    if (nfull > 0) {
-        double a0[4][KL], b0[4][KL], a1[4][KL], b1[4][KL];
-        load(k, a0, b0);
-        int64_t s = 0;
-        for (; s + 2 <= nfull; s += 2) {
-            load(k + KSTEP, a1, b1);
-            mma(a0, b0);
-            if (s + 2 < nfull) load(k + 2 * KSTEP, a0, b0);
-            mma(a1, b1);
-            k += 2 * KSTEP;
+                for (int cc = 0; cc < 4; ++cc)
+                    acc[r][cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[cc], acc[r][cc], 0, 0, 0);
         }
-        if (s < nfull) {  // one full step left, already loaded in a0/b0
-            mma(a0, b0);
-            k += KSTEP;
-        }
-    }
-    if (k < k1) {  // ragged tail: k-values at or beyond k1 contribute zero
-        const int64_t kk = k + g * KL;
-        double a[4][KL], b[4][KL];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int t = 0; t < KL; ++t) {
-                const bool in = kk + t < k1;
-                const int64_t kc = in ? kk + t : k0;
-                const double x = pa[r][kc];
-                a[r][t] = (va[r] && in) ? x : 0.0;
-                const double y = double(pb[r][kc]);
-                b[r][t] = (vb[r] && in) ? y : 0.0;
-            }
-        mma(a, b);
+        if (c + 1 < nchunk) lstore(buf ^ 1);
+        __syncthreads();
     }
     double* P = partial + (int64_t)split * m * m2;
 #pragma unroll
@@ -152,8 +154,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_cap_gemm(int m, int m2, int64_
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = row0 + r * 16 + g + 4 * v;
-                const int col = col0 + c * 16 + l16;
+                const int row = arow0 + wr + r * 16 + g + 4 * v;
+                const int col = brow0 + wc + c * 16 + l16;
                 if (row < m && col < m2) P[(int64_t)row * m2 + col] = acc[r][c][v];
             }
 }
@@ -199,7 +201,7 @@ GemmPlan plan(int m, int m2, int64_t N, bool lower) {
     int splits = std::max(1, kResidentWG / p.ntile);
     splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, cdiv(N, 256)));
     splits = (int)std::max<size_t>(1, std::min<size_t>(splits, kMaxPartialBytes / per_split));
-    p.kper = cdiv(cdiv(N, splits), KSTEP) * KSTEP;
+    p.kper = cdiv(cdiv(N, splits), KB) * KB;
     p.splits = (int)cdiv(N, p.kper);
     return p;
 }

@@ -415,3 +415,23 @@ def test_streamed_z_capacitance_and_solve(P):
     ref = gn.woodbury_precond(V.apply, J, wl.alpha, R)
     assert rel_rows(Zp, ref).max() < 1e-8
     assert gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x) <= 1.01e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_size_cube129(P, prec):
+    # The benchmark workload at its full size (129^3, m = 512, 8.8 GB J) in the
+    # launch configuration bench.py times; checked through the oracle's FP64
+    # true residual of the GPU's solution (the direct solution is too costly here).
+    wl = H.workload("cube129")
+    J, b = H.j_rows(wl), H.rhs_b(wl)
+    rtol = 1e-8
+    with P.Context(wl.shape, wl.beta, precision=prec) as ctx:
+        Jd = dev(J)
+        x, info = ctx.gn_solve(Jd, wl.alpha, b=dev(b), rtol=rtol)
+        x = host(x)
+        del Jd
+    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
+    print(f"cube129 {prec}: iters={info.iters} relres(oracle)={rr:.3e} relres(GPU)={info.relres_true:.3e}")
+    assert rr <= rtol * 1.01
+    assert abs(rr - info.relres_true) <= 1e-3 * rtol
+    assert info.iters <= 12
