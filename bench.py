@@ -49,6 +49,7 @@ KERNELS = {
     "coarse": ("hbm", "k_coarse_solve"), "gemm": ("mfma", "k_cap_gemm"), "jv": ("hbm", "k_rows_dot"),
     "jtv": ("hbm", "k_jt_u_t / k_jt_plain / k_z_stored"), "factor": ("mfma", "k_blk_*"),
     "trsv": ("hbm", "k_blk_trsv"), "apply": ("hbm", "k_march<*, 3, 0> / k_apply_plus_dot"),
+    "vdown": ("hbm", "k_down"), "vup": ("hbm", "k_up"),
 }
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix

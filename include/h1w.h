@@ -90,6 +90,10 @@ typedef struct {
  * the preconditioner then recomputes Z w as B (J^T w)). Without the flag this
  * happens only when an FP64 Z would not fit next to J. */
 #define H1W_FLAG_STREAM_Z 1u
+/* grid_desc.flags: run 3D V-cycles with two smoothing steps per side as the
+ * sequence of single-step stencil kernels instead of the fused down/up passes
+ * (same cycle, same result up to rounding; more memory traffic). */
+#define H1W_FLAG_UNFUSED_VCYCLE 2u
 
 /* Krylov options (h1w_gn_solve). A zeroed struct selects the defaults. */
 typedef struct {
@@ -230,7 +234,9 @@ typedef enum {
     H1W_K_FACTOR = 9,      /* blocked factorisation of S */
     H1W_K_TRSV = 10,       /* triangular solves with the factors of S */
     H1W_K_APPLY = 11,      /* operator apply A x (incl. the CG q = alpha A p + t) */
-    H1W_K_NCLASS = 12
+    H1W_K_VDOWN = 12,      /* fused 3D pass: two pre-smoothing steps, residual, restriction */
+    H1W_K_VUP = 13,        /* fused 3D pass: interpolation, two post-smoothing steps */
+    H1W_K_NCLASS = 14
 } h1w_kclass;
 
 typedef struct {

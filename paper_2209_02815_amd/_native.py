@@ -20,7 +20,7 @@ H1W_Z_AUTO, H1W_Z_STORED, H1W_Z_RECOMPUTE = 0, 1, 2
 H1W_FACTOR_AUTO, H1W_FACTOR_CHOL, H1W_FACTOR_LU = 0, 1, 2
 
 KCLASS = ["smooth", "smooth_first", "residual", "restrict", "prolong", "coarse", "gemm", "jv", "jtv",
-          "factor", "trsv", "apply"]
+          "factor", "trsv", "apply", "vdown", "vup"]
 
 EXPORTED = [
     "h1w_setup", "h1w_destroy", "h1w_last_error", "h1w_status_string", "h1w_get_sizes",
@@ -136,6 +136,7 @@ def _dtype_code(t):
 
 # ------------------------------------------------------------------ entry points
 H1W_FLAG_STREAM_Z = 1
+H1W_FLAG_UNFUSED_VCYCLE = 2
 
 
 def h1w_setup(shape, beta: float, precision: int = H1W_FP64, nu: int = 0, cheb=(0.0, 0.0),

@@ -20,6 +20,7 @@ struct Ctx {
     std::vector<Geom> lv;            // levels, fine to coarsest
     std::vector<int64_t> pitch;      // workspace row pitch per level (elements)
     std::vector<double> w;           // Chebyshev step weights
+    bool fused = false;              // V-cycles as fused down/up passes (3D, nu = 2)
     int64_t Nc = 0;                  // nodes on the coarsest level
     DevBuf cinv64, cinv32;           // dense inverse of the coarsest operator
     int chunk = 1;                   // right-hand sides per V-cycle launch

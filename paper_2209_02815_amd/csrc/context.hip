@@ -100,7 +100,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
     require(d.precision == H1W_FP64 || d.precision == H1W_MIXED, "precision must be H1W_FP64 or H1W_MIXED");
     require(d.nu >= 0 && d.nu <= 16, "nu must be in [0, 16]");
-    require((d.flags & ~H1W_FLAG_STREAM_Z) == 0, "unknown bits in flags");
+    require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE)) == 0, "unknown bits in flags");
     require(d.coarse_max >= 0, "coarse_max must be >= 0");
     require(d.rhs_chunk >= 0 && d.rhs_chunk <= 65535, "rhs_chunk must be in [0, 65535]");
     if (d.nu == 0) d.nu = 2;
@@ -149,6 +149,9 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     std::vector<float> inv32(inv.begin(), inv.end());
     cinv32.reserve(inv32.size() * sizeof(float));
     H1W_HIP(hipMemcpy(cinv32.p, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
+
+    fused = dim == 3 && d.nu == 2 && lv.size() >= 2 && !(d.flags & H1W_FLAG_UNFUSED_VCYCLE);
+    for (size_t l = 0; fused && l + 1 < lv.size(); ++l) fused = fused_levels_ok(lv[l], lv[l + 1]);
 
     pitch.resize(lv.size());
     for (size_t l = 0; l < lv.size(); ++l) pitch[l] = cdiv(lv[l].N, 64) * 64;
@@ -222,6 +225,27 @@ void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
     auto fld = [&](int l) { return l == 0 ? ldf : pitch[l]; };
     auto xptr = [&](int l) { return l == 0 ? X : xb[l]; };
     auto xld = [&](int l) { return l == 0 ? ldx : pitch[l]; };
+
+    if (fused) {
+        // 3D, two smoothing steps per side: one pass down and one pass up per
+        // level; the pre-smoothed iterate of level l is kept in tb[l]
+        for (int l = 0; l < L - 1; ++l) {
+            const double nl = (double)lv[l].N, nc = (double)lv[l + 1].N;
+            timed(H1W_K_VDOWN, ces * (2 * nl + nc), 0.0, [&] {
+                launch_vdown<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], fb[l + 1],
+                                pitch[l + 1], w[0], w[1]);
+            });
+        }
+        coarse(fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
+        for (int l = L - 2; l >= 0; --l) {
+            const double nl = (double)lv[l].N, nc = (double)lv[l + 1].N;
+            timed(H1W_K_VUP, ces * (3 * nl + nc), 0.0, [&] {
+                launch_vup<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], xb[l + 1],
+                              pitch[l + 1], xptr(l), xld(l), w[1], w[0]);
+            });
+        }
+        return;
+    }
 
     for (int l = 0; l < L - 1; ++l) {
         const Geom& g = lv[l];

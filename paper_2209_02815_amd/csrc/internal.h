@@ -110,6 +110,17 @@ void launch_convert(hipStream_t s, int64_t N, int k, const TI* X, int64_t ldx, T
 void launch_apply_plus_dot(hipStream_t s, int dim, const Geom& g, double a, const double* P,
                            const double* Tv, double* Q, double* partial, int* nparts);
 
+// vfused.hip: fused V-cycle passes on nested 3D levels (two smoothing steps per side)
+bool fused_levels_ok(const Geom& gf, const Geom& gc);
+// X = two pre-smoothing steps from zero on F (weights w0, w1), Fc = 2^-3 P^T (F - A X)
+template <typename T>
+void launch_vdown(hipStream_t s, const Geom& gf, const Geom& gc, int k, const T* F, int64_t ldf, T* X, int64_t ldx,
+                  T* Fc, int64_t ldc, double w0, double w1);
+// Y = two post-smoothing steps (weights wa, wb) on F from X0 + P Ec (Y must not alias X0)
+template <typename T>
+void launch_vup(hipStream_t s, const Geom& gf, const Geom& gc, int k, const T* F, int64_t ldf, const T* X0,
+                int64_t ldx0, const T* Ec, int64_t ldc, T* Y, int64_t ldy, double wa, double wb);
+
 // blas.hip
 // partial dot products of npair vector pairs over N entries; returns #parts
 int launch_dots_partial(hipStream_t s, int64_t N, int npair, const double* const* X,

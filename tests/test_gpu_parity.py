@@ -118,6 +118,41 @@ def test_vcycle_fp32_matches_oracle(P, shape, cmax, nu):
     assert rel_rows(X, Xref).max() < 2e-5
 
 
+# 3D, two smoothing steps per side: the fused down/up passes against the
+# sequence of single-step kernels (same cycle; the fused passes multiply by
+# 1/D where the single-step kernels divide by D, so the two agree to rounding
+# amplified at most like the oracle comparison above). Shapes: non-cubic with
+# nz > nx > ny, several right-hand-side chunks, padded leading dimensions, a
+# 65^3 grid whose tiles are ragged in x, y and z.
+@pytest.mark.parametrize("shape,cmax,k,chunk", [((17, 17, 17), 27, 3, 2), ((33, 17, 65), 0, 5, 2),
+                                                ((65, 65, 65), 0, 3, 0), ((9, 17, 5), 1, 4, 1)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vcycle_fused_matches_unfused(P, shape, cmax, k, chunk, prec):
+    beta = 1e-2
+    N = int(np.prod(shape))
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    F = rng(12).standard_normal((k, N))
+    out = []
+    for fused in (True, False):
+        with P.Context(shape, beta, precision="fp64" if prec == "fp64" else "mixed", coarse_max=cmax,
+                       rhs_chunk=chunk, fused_vcycle=fused) as ctx:
+            Fd = padded(k, N, dtype=tdt)
+            Fd.copy_(dev(F, tdt))
+            Xd = padded(k, N, pad=5, dtype=tdt)
+            ctx.set_kernel_timing("all")
+            ctx.vcycle(Fd, Xd)
+            kt = ctx.kernel_timing()
+            ctx.set_kernel_timing([])
+            out.append(host(Xd))
+            assert (kt["vdown"]["launches"] > 0) == fused and (kt["smooth"]["launches"] > 0) == (not fused)
+    V = mg.VCycle(shape, beta, coarse_max=cmax or 729)
+    tol = 100 * EPS64 * np.linalg.cond(V.Acoarse) if prec == "fp64" else 2e-5
+    assert rel_rows(out[0], out[1]).max() < tol
+    if N <= 40000:  # and both against the oracle
+        Xref = V.apply(F if prec == "fp64" else F.astype(np.float32).astype(np.float64))
+        assert rel_rows(out[0], Xref).max() < tol
+
+
 def test_vcycle_symmetric_and_linear(P):
     shape, beta = (17, 17, 17), 1e-2
     N = int(np.prod(shape))
@@ -388,7 +423,10 @@ def test_kernel_timing_counts_launches(P):
         assert ctx.kernel_timing()["gemm"]["launches"] == 0
     assert kt["gemm"]["launches"] == 1 and kt["gemm"]["flops"] == wl.m * (wl.m + 1) * wl.N
     assert kt["factor"]["launches"] == 1
-    assert kt["smooth"]["launches"] > 0 and kt["smooth"]["ms"] > 0 and kt["smooth"]["bytes"] > 0
+    # 3D with two smoothing steps per side: the fused down/up passes run
+    for c in ("vdown", "vup"):
+        assert kt[c]["launches"] > 0 and kt[c]["ms"] > 0 and kt[c]["bytes"] > 0
+    assert kt["smooth"]["launches"] == 0 and kt["residual"]["launches"] == 0
     assert kt["jv"]["launches"] >= info.iters
 
 
