@@ -36,7 +36,10 @@ namespace {
 constexpr int kFT = 256;           // threads per work-group
 constexpr int kCPT = 2;            // region columns per thread
 constexpr int kReg = kFT * kCPT;   // region columns per work-group (max)
-constexpr int kCReg = 200;         // coarse columns staged by the up pass (max)
+constexpr int kCReg = 200;         // coarse columns staged by the up pass (max, < kFT)
+constexpr int kPad = 64;           // LDS margin around each plane (>= region width)
+constexpr int kSlot = kReg + kPad; // distance between the two planes of an LDS array
+constexpr int kLds = 2 * kSlot + kPad;
 
 struct FTile {
     int TX, TY;     // tile size in nodes of the tiled level
@@ -62,84 +65,67 @@ __device__ __forceinline__ bool ftile_item(const FTile& s, int& tx, int& ty, int
     return true;
 }
 
-// One region column owned by a thread: position, ring membership and the
-// stencil's in-plane weights. invd0/1/2 = 1/D on the first, an interior and
-// the last z-plane (the only z-dependence of D).
+// LDS plane `slot` of an array laid out as [margin | plane 0 | margin | plane 1
+// | margin]: region index p and its neighbours p +- 1, p +- RW are inside the
+// array for every p < kReg, so stages read them without bounds tests (values
+// read for columns whose result is discarded are never used).
+template <typename T>
+__device__ __forceinline__ T* plane(T* arr, int slot) {
+    return arr + kPad + slot * kSlot;
+}
+
+// One region column owned by a thread. The stencil is used in diagonal form,
+//   (A x)_p = D_p x_p - S_p,  S_p = wz (cx (x_w + x_e) + cy (x_s + x_n)) + cz (x_b + x_a),
+// with every neighbour outside the grid held as 0 (LDS planes and z registers
+// are zero there), which drops exactly the couplings a Neumann boundary node
+// lacks. cx, cy, cz are the couplings on interior planes (wz = 1); on the
+// first and last plane wz = 1/2 and D = dgb.
 template <typename T>
 struct RCol {
-    int p;          // region index (a + b * RW), -1 if beyond the region
-    int64_t off;    // in-plane offset j * nx + i
+    int p;          // region index (a + b * RW); >= RW * RH: idle column
+    int64_t off;    // in-plane offset j * nx + i (0 outside the grid)
     bool ing;       // inside the grid
     bool r1, r2;    // inside the grid and at least 1 / 2 columns from the region edge
     bool own;       // written by this work-group
-    bool xm, xp, ym, yp;
-    T wx, wy;
-    T invd0, invd1, invd2;
+    T cx, cy, cz;
+    T dgi, dgb;     // D on interior / first-last planes
+    T ivi, ivb;     // 1/D (0 outside the grid)
 };
-
-template <typename T>
-__device__ __forceinline__ T diag3(const Geom& g, const RCol<T>& c, T wz, int nzn) {
-    const T cx = T(g.ihx2) * c.wy * wz, cy = T(g.ihy2) * c.wx * wz, cz = T(g.ihz2) * c.wx * c.wy;
-    return T(g.beta) * c.wx * c.wy * wz + cx * T(int(c.xm) + int(c.xp)) + cy * T(int(c.ym) + int(c.yp)) +
-           cz * T(nzn);
-}
 
 template <typename T>
 __device__ __forceinline__ void rcol_init(RCol<T>& c, const Geom& g, int p, int RW, int RH, int i0, int j0,
                                           int own_lo) {
     const bool valid = p < RW * RH;
-    const int a = valid ? p % RW : 0, b = valid ? p / RW : 0;
+    const int a = p % RW, b = p / RW;
     const int i = i0 + a, j = j0 + b;
-    c.p = valid ? p : -1;
+    c.p = p;
     c.ing = valid && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
     c.off = c.ing ? (int64_t)j * g.nx + i : 0;
     c.r1 = c.ing && a >= 1 && a <= RW - 2 && b >= 1 && b <= RH - 2;
     c.r2 = c.ing && a >= 2 && a <= RW - 3 && b >= 2 && b <= RH - 3;
     c.own = c.ing && a >= own_lo && a <= RW - 3 && b >= own_lo && b <= RH - 3;
-    c.xm = i > 0;
-    c.xp = i < g.nx - 1;
-    c.ym = j > 0;
-    c.yp = j < g.ny - 1;
-    c.wx = (i == 0 || i == g.nx - 1) ? T(0.5) : T(1);
-    c.wy = (j == 0 || j == g.ny - 1) ? T(0.5) : T(1);
-    c.invd0 = T(1) / diag3(g, c, T(0.5), 1);
-    c.invd1 = T(1) / diag3(g, c, T(1), 2);
-    c.invd2 = T(1) / diag3(g, c, T(0.5), 1);
+    const T wx = (i == 0 || i == g.nx - 1) ? T(0.5) : T(1);
+    const T wy = (j == 0 || j == g.ny - 1) ? T(0.5) : T(1);
+    const int nxn = int(i > 0) + int(i < g.nx - 1), nyn = int(j > 0) + int(j < g.ny - 1);
+    c.cx = T(g.ihx2) * wy;
+    c.cy = T(g.ihy2) * wx;
+    c.cz = T(g.ihz2) * wx * wy;
+    const T inplane = T(g.beta) * wx * wy + c.cx * T(nxn) + c.cy * T(nyn);
+    c.dgi = inplane + c.cz * T(2);
+    c.dgb = T(0.5) * inplane + c.cz;
+    c.ivi = c.ing ? T(1) / c.dgi : T(0);
+    c.ivb = c.ing ? T(1) / c.dgb : T(0);
+    if (!c.ing) c.cx = c.cy = c.cz = T(0);
 }
 
-// (selects values, not fields: a select between field addresses would keep
-// the column record in scratch memory)
+// S_p at plane class (wz) from the LDS plane P and the z-neighbours xb, xa
 template <typename T>
-__device__ __forceinline__ T invd_at(const RCol<T>& c, int l, int nz) {
-    const T v0 = c.invd0, v1 = c.invd1, v2 = c.invd2;
-    T v = v1;
-    if (l == 0) v = v0;
-    if (l == nz - 1) v = v2;
-    return v;
-}
-
-// (A x) at plane l of column c: xc centre, xb / xa below / above, xw xe xs xn
-// the in-plane neighbours (-x, +x, -y, +y). Same arithmetic order as the
-// unfused stencil kernels.
-template <typename T>
-__device__ __forceinline__ T stencil3(const Geom& g, const RCol<T>& c, int l, T xc, T xb, T xa, T xw, T xe, T xs,
-                                      T xn) {
-    const bool zm = l > 0, zp = l < g.nz - 1;
-    const T wz = (l == 0 || l == g.nz - 1) ? T(0.5) : T(1);
-    const T cx = T(g.ihx2) * c.wy * wz, cy = T(g.ihy2) * c.wx * wz, cz = T(g.ihz2) * c.wx * c.wy;
-    const T mass = T(g.beta) * c.wx * c.wy * wz;
-    T sx = T(0), sy = T(0), sz = T(0);
-    if (c.xm) sx += xc - xw;
-    if (c.xp) sx += xc - xe;
-    if (c.ym) sy += xc - xs;
-    if (c.yp) sy += xc - xn;
-    if (zm) sz += xc - xb;
-    if (zp) sz += xc - xa;
-    T acc = mass * xc;
-    acc += cx * sx;
-    acc += cy * sy;
-    acc += cz * sz;
-    return acc;
+__device__ __forceinline__ T nbr_sum(const RCol<T>& c, T wz, const T* P, int RW, T xb, T xa) {
+    const int p = c.p;
+    T s = c.cx * (P[p - 1] + P[p + 1]);
+    s = fma(c.cy, P[p - RW] + P[p + RW], s);
+    s *= wz;
+    return fma(c.cz, xb + xa, s);
 }
 
 // ---------------------------------------------------------------- down pass
@@ -149,13 +135,14 @@ __device__ __forceinline__ T stencil3(const Geom& g, const RCol<T>& c, int l, T 
 // nodes), owned fine columns 2 cX0 .. 2 cX0 + 2 TX - 1.
 // Pipeline at step n: A f, x1 on plane n; B x2 on n-1; C r on n-2;
 // D plane sum of r on n-3 into the coarse plane (n-3)/2.
+// Smoothing step in diagonal form: x + w D^-1 (f - A x) = (1 - w) x + w D^-1 (f + S).
 template <typename T>
 __global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
                                               T* __restrict__ X, int64_t ldx, T* __restrict__ Fc, int64_t ldc,
                                               T w0, T w1) {
-    __shared__ T s1[2][kReg];
-    __shared__ T s2[2][kReg];
-    __shared__ T sr[2][kReg];
+    __shared__ T s1[kLds];
+    __shared__ T s2[kLds];
+    __shared__ T sr[kLds];
     int tx, ty, zr, r;
     if (!ftile_item(s, tx, ty, zr, r)) return;
     const int RW = s.RW, RH = s.RH;
@@ -179,6 +166,7 @@ __global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T
     const int bLo = max(0, 2 * cz0 - 2), bHi = min(nz - 1, 2 * cz1);      // x2
     const int rLo = max(0, 2 * cz0 - 1), rHi = min(nz - 1, 2 * cz1 - 1);  // r and its plane sums
     const int oLo = 2 * cz0, oHi = min(nz - 1, 2 * cz1 - 1);              // x2 written
+    const T om1 = T(1) - w1;
 
     T f0[kCPT], f1[kCPT], f2[kCPT];  // f  on planes n-2, n-1, n
     T a0[kCPT], a1[kCPT], a2[kCPT];  // x1 on planes n-2, n-1, n
@@ -202,48 +190,52 @@ __global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T
     }
 
     for (int n = aLo; n <= rHi + 3; ++n) {
-        // A: f and x1 on plane n
+        // A: f and x1 = w0 D^-1 f on plane n
+        {
+            const bool bnd = n == 0 || n == nz - 1;
+            T* P = plane(s1, n & 1);
 #pragma unroll
-        for (int u = 0; u < kCPT; ++u) {
-            const T raw = q0[u];
-            q0[u] = q1[u];
-            q1[u] = f[fidx(u, n + 2)];
-            const T fv = (n <= aHi && c[u].ing) ? raw : T(0);
-            f2[u] = fv;
-            a2[u] = w0 * fv * invd_at(c[u], n, nz);
-            if (c[u].p >= 0) s1[n & 1][c[u].p] = a2[u];
+            for (int u = 0; u < kCPT; ++u) {
+                const T raw = q0[u];
+                q0[u] = q1[u];
+                q1[u] = f[fidx(u, n + 2)];
+                const T fv = (n <= aHi && c[u].ing) ? raw : T(0);
+                f2[u] = fv;
+                a2[u] = (w0 * (bnd ? c[u].ivb : c[u].ivi)) * fv;
+                P[c[u].p] = a2[u];
+            }
         }
         // B: x2 on plane n - 1
         {
             const int m = n - 1;
-            const bool in = m >= bLo && m <= bHi;
-            const T* P = s1[m & 1];
+            const bool in = m >= bLo && m <= bHi, wr = m >= oLo && m <= oHi;
+            const bool bnd = m == 0 || m == nz - 1;
+            const T wz = bnd ? T(0.5) : T(1);
+            T* P = plane(s1, m & 1);
+            T* Q = plane(s2, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                T v = T(0);
-                if (in && c[u].r1) {
-                    const int p = c[u].p;
-                    const T ax = stencil3(gf, c[u], m, a1[u], a0[u], a2[u], P[p - 1], P[p + 1], P[p - RW], P[p + RW]);
-                    v = a1[u] + w1 * (f1[u] - ax) * invd_at(c[u], m, nz);
-                    if (c[u].own && m >= oLo && m <= oHi) x[m * PL + c[u].off] = v;
-                }
+                const T sn = nbr_sum(c[u], wz, P, RW, a0[u], a2[u]);
+                T v = fma(w1 * (bnd ? c[u].ivb : c[u].ivi), f1[u] + sn, om1 * a1[u]);
+                v = (in && c[u].r1) ? v : T(0);
+                if (wr && c[u].own) x[m * PL + c[u].off] = v;
                 b2[u] = v;
-                if (c[u].p >= 0) s2[m & 1][c[u].p] = v;
+                Q[c[u].p] = v;
             }
         }
-        // C: r on plane n - 2 (zero outside the grid)
+        // C: r = f - D x2 + S on plane n - 2 (zero outside the r ring)
         {
             const int m = n - 2;
             const bool in = m >= rLo && m <= rHi;
-            const T* P = s2[m & 1];
+            const bool bnd = m == 0 || m == nz - 1;
+            const T wz = bnd ? T(0.5) : T(1);
+            T* P = plane(s2, m & 1);
+            T* R = plane(sr, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                T v = T(0);
-                if (in && c[u].r2) {
-                    const int p = c[u].p;
-                    v = f0[u] - stencil3(gf, c[u], m, b1[u], b0[u], b2[u], P[p - 1], P[p + 1], P[p - RW], P[p + RW]);
-                }
-                if (c[u].p >= 0) sr[m & 1][c[u].p] = v;
+                const T sn = nbr_sum(c[u], wz, P, RW, b0[u], b2[u]);
+                T v = fma(-(bnd ? c[u].dgb : c[u].dgi), b1[u], f0[u]) + sn;
+                R[c[u].p] = (in && c[u].r2) ? v : T(0);
             }
         }
         // D: in-plane full-weighting sum of r on plane n - 3; coarse plane L
@@ -251,7 +243,7 @@ __global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T
         {
             const int m = n - 3;
             if (cact && m >= rLo && m <= rHi) {
-                const T* R = sr[m & 1];
+                const T* R = plane(sr, m & 1);
                 T sum = T(0);
 #pragma unroll
                 for (int dy = -1; dy <= 1; ++dy) {
@@ -288,11 +280,9 @@ __global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T
 // Tile = TX x TY fine columns; region = tile + 2 columns each side: y0 on all
 // of it, y1 one column in, y on the tile. The coarse correction is staged per
 // coarse plane in LDS (two planes: fine plane n interpolates from coarse
-// planes n/2 and, for odd n, n/2 + 1).
+// planes n/2 and, for odd n, n/2 + 1); thread t < CRW * CRH stages coarse
+// column t of the region (zero outside the coarse grid).
 // Pipeline at step n: A y0 on plane n; B y1 on n-1; C y on n-2.
-// Thread t < CRW * CRH stages coarse column t of the region (CRW * CRH <=
-// kCReg < kFT, one column per thread). cidx: its in-plane offset, -1 if the
-// column is outside the coarse grid.
 __device__ __forceinline__ int64_t coarse_idx(const Geom& gc, int64_t cidx, int L) {
     return (cidx >= 0 && L < gc.nz) ? L * ((int64_t)gc.nx * gc.ny) + cidx : 0;
 }
@@ -301,8 +291,8 @@ template <typename T>
 __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
                                             const T* __restrict__ X0, int64_t ldx0, const T* __restrict__ Ec,
                                             int64_t ldc, T* __restrict__ Y, int64_t ldy, T wa, T wb) {
-    __shared__ T s0[2][kReg];
-    __shared__ T s1[2][kReg];
+    __shared__ T s0[kLds];
+    __shared__ T s1[kLds];
     __shared__ T se[2][kCReg];
     int tx, ty, zr, r;
     if (!ftile_item(s, tx, ty, zr, r)) return;
@@ -318,22 +308,27 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
     const T* e = Ec + r * ldc;
     T* y = Y + r * ldy;
 
+    // per column: staged coarse index of the lower interpolation corner and
+    // the x / y interpolation weights (1, 0) on even, (1/2, 1/2) on odd nodes
     RCol<T> c[kCPT];
-    int cb[kCPT];      // staged coarse index of the column's lower interpolation corner
-    bool oi[kCPT], oj[kCPT];
+    int cb[kCPT];
+    T wxl[kCPT], wxh[kCPT], wyl[kCPT], wyh[kCPT];
 #pragma unroll
     for (int u = 0; u < kCPT; ++u) {
         const int p = threadIdx.x + u * kFT;
         rcol_init(c[u], gf, p, RW, RH, i0, j0, 2);
         const int i = i0 + (p % RW), j = j0 + (p / RW);
-        oi[u] = i & 1;
-        oj[u] = j & 1;
         cb[u] = c[u].ing ? ((i >> 1) - cI0) + ((j >> 1) - cJ0) * s.CRW : 0;
+        wxl[u] = (i & 1) ? T(0.5) : T(1);
+        wxh[u] = (i & 1) ? T(0.5) : T(0);
+        wyl[u] = (j & 1) ? T(0.5) : T(1);
+        wyh[u] = (j & 1) ? T(0.5) : T(0);
     }
 
     const int aLo = max(0, z0 - 2), aHi = min(nz - 1, z1 + 1);  // y0
     const int bLo = max(0, z0 - 1), bHi = min(nz - 1, z1);      // y1
     const int cLo = z0, cHi = z1 - 1;                           // y
+    const T oma = T(1) - wa, omb = T(1) - wb;
 
     // staged coarse column of this thread
     const int ct = threadIdx.x;
@@ -347,7 +342,7 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
         if (cst) se[L & 1][ct] = (cidx >= 0 && L < gc.nz) ? e[coarse_idx(gc, cidx, L)] : T(0);
     };
     stage_now(aLo >> 1);
-    if (aLo & 1) stage_now((aLo >> 1) + 1);
+    stage_now((aLo >> 1) + 1);
     // the coarse plane staged at the first even step, loaded now
     const int nEven = aLo + (aLo & 1);
     T cq = e[coarse_idx(gc, cidx, (nEven >> 1) + 1)];
@@ -385,8 +380,9 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
         {
             const bool in = n <= aHi;
             const int L = n >> 1;
-            const int nl = 1 + (n & 1);
-            const T wl = (n & 1) ? T(0.5) : T(1);
+            const T* E0 = se[L & 1];
+            const T* E1 = se[(L + 1) & 1];
+            T* P = plane(s0, n & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
                 const T xr = xq0[u], fr = fq0[u];
@@ -394,56 +390,49 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
                 fq0[u] = fq1[u];
                 xq1[u] = x0[xidx(u, n + 2)];
                 fq1[u] = f[fidx(u, n + 2)];
-                T v = T(0), fv = T(0);
-                if (in && c[u].ing) {
-                    const int nj = 1 + int(oj[u]), ni = 1 + int(oi[u]);
-                    const T wj = oj[u] ? T(0.5) : T(1), wi = oi[u] ? T(0.5) : T(1);
-                    T pe = T(0);
-                    for (int a = 0; a < nl; ++a) {
-                        const T* E = se[(L + a) & 1];
-                        for (int bb = 0; bb < nj; ++bb)
-                            for (int cc = 0; cc < ni; ++cc) pe += (wl * wj * wi) * E[cb[u] + bb * s.CRW + cc];
-                    }
-                    v = xr;
-                    v += pe;
-                    if (c[u].r1) fv = fr;
+                const int b = cb[u], CW = s.CRW;
+                T pe = wyl[u] * fma(wxl[u], E0[b], wxh[u] * E0[b + 1]);
+                pe = fma(wyh[u], fma(wxl[u], E0[b + CW], wxh[u] * E0[b + CW + 1]), pe);
+                if (n & 1) {
+                    T p1v = wyl[u] * fma(wxl[u], E1[b], wxh[u] * E1[b + 1]);
+                    p1v = fma(wyh[u], fma(wxl[u], E1[b + CW], wxh[u] * E1[b + CW + 1]), p1v);
+                    pe = T(0.5) * (pe + p1v);
                 }
+                const T v = (in && c[u].ing) ? xr + pe : T(0);
                 p2[u] = v;
-                f2[u] = fv;
-                if (c[u].p >= 0) s0[n & 1][c[u].p] = v;
+                f2[u] = (in && c[u].r1) ? fr : T(0);
+                P[c[u].p] = v;
             }
         }
         // B: y1 on plane n - 1
         {
             const int m = n - 1;
             const bool in = m >= bLo && m <= bHi;
-            const T* P = s0[m & 1];
+            const bool bnd = m == 0 || m == nz - 1;
+            const T wz = bnd ? T(0.5) : T(1);
+            T* P = plane(s0, m & 1);
+            T* Q = plane(s1, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                T v = T(0);
-                if (in && c[u].r1) {
-                    const int p = c[u].p;
-                    const T ax = stencil3(gf, c[u], m, p1[u], p0[u], p2[u], P[p - 1], P[p + 1], P[p - RW], P[p + RW]);
-                    v = p1[u] + wa * (f1[u] - ax) * invd_at(c[u], m, nz);
-                }
+                const T sn = nbr_sum(c[u], wz, P, RW, p0[u], p2[u]);
+                T v = fma(wa * (bnd ? c[u].ivb : c[u].ivi), f1[u] + sn, oma * p1[u]);
+                v = (in && c[u].r1) ? v : T(0);
                 q2[u] = v;
-                if (c[u].p >= 0) s1[m & 1][c[u].p] = v;
+                Q[c[u].p] = v;
             }
         }
         // C: y on plane n - 2
         {
             const int m = n - 2;
-            if (m >= cLo && m <= cHi) {
-                const T* P = s1[m & 1];
+            const bool in = m >= cLo && m <= cHi;
+            const bool bnd = m == 0 || m == nz - 1;
+            const T wz = bnd ? T(0.5) : T(1);
+            T* P = plane(s1, m & 1);
 #pragma unroll
-                for (int u = 0; u < kCPT; ++u) {
-                    if (c[u].own) {
-                        const int p = c[u].p;
-                        const T ax =
-                            stencil3(gf, c[u], m, q1[u], q0[u], q2[u], P[p - 1], P[p + 1], P[p - RW], P[p + RW]);
-                        y[m * PL + c[u].off] = q1[u] + wb * (f0[u] - ax) * invd_at(c[u], m, nz);
-                    }
-                }
+            for (int u = 0; u < kCPT; ++u) {
+                const T sn = nbr_sum(c[u], wz, P, RW, q0[u], q2[u]);
+                const T v = fma(wb * (bnd ? c[u].ivb : c[u].ivi), f0[u] + sn, omb * q1[u]);
+                if (in && c[u].own) y[m * PL + c[u].off] = v;
             }
         }
 #pragma unroll
@@ -470,6 +459,7 @@ FTile plan_tiles(int nx, int ny, int nzt, int k, bool down, int zmin, int es) {
             const int RW = down ? 2 * TX + 5 : TX + 4;
             const int RH = down ? 2 * TY + 5 : TY + 4;
             if (RW * RH > kReg) break;
+            if (RW > kPad) break;
             if (down && TX * TY > kFT) break;
             const int CRW = (RW + 1) / 2 + 2, CRH = (RH + 1) / 2 + 2;
             if (!down && CRW * CRH > kCReg) break;
