@@ -15,16 +15,19 @@
 // 14 for the unfused sequence.
 //
 // Work item = (in-plane tile, z-run, batch row); work-group ids are dealt to
-// the 8 XCDs in contiguous ranges of items. A work-group owns a region of at
-// most kReg in-plane columns: its tile plus a halo ring wide enough that
-// every stage is computed from the group's own data (halo columns are
-// recomputed by neighbouring tiles; their loads hit L2). Each of the 256
-// threads owns kCPT columns and marches up z, stage s of the pipeline
-// working on plane n - s at step n. Z-neighbours stay in registers; in-plane
+// the 8 XCDs in contiguous ranges of items. A work-group of NT threads owns a
+// region of at most 2 NT in-plane columns: its tile plus a halo ring wide
+// enough that every stage is computed from the group's own data (halo
+// columns are recomputed by neighbouring tiles; their loads hit L2). Each
+// thread owns 2 columns and marches up z, stage s of the pipeline working on
+// plane n - s at step n. Z-neighbours stay in registers (three rotating sets;
+// the march is unrolled by three so that the rotation is static); in-plane
 // neighbours come from LDS planes that were written in step n - 1 (double
 // buffered), so a single barrier per step orders every read after its write
-// and every overwrite after its last read.
+// and every overwrite after its last read. Global loads are issued three
+// steps ahead of their use.
 #include <algorithm>
+#include <type_traits>
 
 #include "devutil.h"
 #include "internal.h"
@@ -33,13 +36,27 @@ namespace h1w {
 
 namespace {
 
-constexpr int kFT = 256;           // threads per work-group
-constexpr int kCPT = 2;            // region columns per thread
-constexpr int kReg = kFT * kCPT;   // region columns per work-group (max)
-constexpr int kCReg = 200;         // coarse columns staged by the up pass (max, < kFT)
-constexpr int kPad = 64;           // LDS margin around each plane (>= region width)
-constexpr int kSlot = kReg + kPad; // distance between the two planes of an LDS array
-constexpr int kLds = 2 * kSlot + kPad;
+constexpr int kCPT = 2;             // region columns per thread
+constexpr int kPad = 64;            // LDS margin around each plane (>= region width)
+constexpr int kCReg = 200;          // coarse columns staged by the up pass (max, < its thread count)
+constexpr int kDownThreads = 512;   // down pass: the 3-column halo favours large regions
+constexpr int kUpThreads = 256;
+
+// LDS array of two planes of NT * kCPT region columns laid out as
+// [margin | plane 0 | margin | plane 1 | margin]: region index p and its
+// neighbours p +- 1, p +- RW are inside the array for every p < NT * kCPT, so
+// stages read them without bounds tests (values read for columns whose
+// result is discarded are never used).
+template <int NT>
+struct Lds {
+    static constexpr int REG = NT * kCPT;
+    static constexpr int SLOT = REG + kPad;
+    static constexpr int SIZE = 2 * SLOT + kPad;
+    template <typename T>
+    static __device__ __forceinline__ T* plane(T* arr, int slot) {
+        return arr + kPad + slot * SLOT;
+    }
+};
 
 struct FTile {
     int TX, TY;     // tile size in nodes of the tiled level
@@ -65,25 +82,17 @@ __device__ __forceinline__ bool ftile_item(const FTile& s, int& tx, int& ty, int
     return true;
 }
 
-// LDS plane `slot` of an array laid out as [margin | plane 0 | margin | plane 1
-// | margin]: region index p and its neighbours p +- 1, p +- RW are inside the
-// array for every p < kReg, so stages read them without bounds tests (values
-// read for columns whose result is discarded are never used).
-template <typename T>
-__device__ __forceinline__ T* plane(T* arr, int slot) {
-    return arr + kPad + slot * kSlot;
-}
-
 // One region column owned by a thread. The stencil is used in diagonal form,
 //   (A x)_p = D_p x_p - S_p,  S_p = wz (cx (x_w + x_e) + cy (x_s + x_n)) + cz (x_b + x_a),
 // with every neighbour outside the grid held as 0 (LDS planes and z registers
 // are zero there), which drops exactly the couplings a Neumann boundary node
 // lacks. cx, cy, cz are the couplings on interior planes (wz = 1); on the
-// first and last plane wz = 1/2 and D = dgb.
+// first and last plane wz = 1/2 and D = dgb. Offsets are 32-bit (a grid
+// vector has fewer than 2^31 nodes).
 template <typename T>
 struct RCol {
     int p;          // region index (a + b * RW); >= RW * RH: idle column
-    int64_t off;    // in-plane offset j * nx + i (0 outside the grid)
+    int off;        // in-plane offset j * nx + i (0 outside the grid)
     bool ing;       // inside the grid
     bool r1, r2;    // inside the grid and at least 1 / 2 columns from the region edge
     bool own;       // written by this work-group
@@ -100,7 +109,7 @@ __device__ __forceinline__ void rcol_init(RCol<T>& c, const Geom& g, int p, int 
     const int i = i0 + a, j = j0 + b;
     c.p = p;
     c.ing = valid && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-    c.off = c.ing ? (int64_t)j * g.nx + i : 0;
+    c.off = c.ing ? j * g.nx + i : 0;
     c.r1 = c.ing && a >= 1 && a <= RW - 2 && b >= 1 && b <= RH - 2;
     c.r2 = c.ing && a >= 2 && a <= RW - 3 && b >= 2 && b <= RH - 3;
     c.own = c.ing && a >= own_lo && a <= RW - 3 && b >= own_lo && b <= RH - 3;
@@ -128,6 +137,20 @@ __device__ __forceinline__ T nbr_sum(const RCol<T>& c, T wz, const T* P, int RW,
     return fma(c.cz, xb + xa, s);
 }
 
+// Runs step(n, integral_constant<R>) for n = n0 .. n1 with R = (n - n0) % 3.
+template <typename F>
+__device__ __forceinline__ void march3(int n0, int n1, F&& step) {
+    for (int n = n0;;) {
+        if (n > n1) break;
+        step(n, std::integral_constant<int, 0>{});
+        if (++n > n1) break;
+        step(n, std::integral_constant<int, 1>{});
+        if (++n > n1) break;
+        step(n, std::integral_constant<int, 2>{});
+        ++n;
+    }
+}
+
 // ---------------------------------------------------------------- down pass
 // Tile = TX x TY coarse columns; the region is the fine columns
 // [2 cX0 - 3, 2 (cX0 + TX) + 1] (width 2 TX + 5): x1 on all of it, x2 one
@@ -136,106 +159,102 @@ __device__ __forceinline__ T nbr_sum(const RCol<T>& c, T wz, const T* P, int RW,
 // Pipeline at step n: A f, x1 on plane n; B x2 on n-1; C r on n-2;
 // D plane sum of r on n-3 into the coarse plane (n-3)/2.
 // Smoothing step in diagonal form: x + w D^-1 (f - A x) = (1 - w) x + w D^-1 (f + S).
-template <typename T>
-__global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
-                                              T* __restrict__ X, int64_t ldx, T* __restrict__ Fc, int64_t ldc,
-                                              T w0, T w1) {
-    __shared__ T s1[kLds];
-    __shared__ T s2[kLds];
-    __shared__ T sr[kLds];
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_down(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
+                                             T* __restrict__ X, int64_t ldx, T* __restrict__ Fc, int64_t ldc,
+                                             T w0, T w1) {
+    using L = Lds<NT>;
+    __shared__ T s1[L::SIZE];
+    __shared__ T s2[L::SIZE];
+    __shared__ T sr[L::SIZE];
     int tx, ty, zr, r;
     if (!ftile_item(s, tx, ty, zr, r)) return;
     const int RW = s.RW, RH = s.RH;
     const int cX0 = tx * s.TX, cY0 = ty * s.TY;
     const int cz0 = zr * s.zc, cz1 = min(gc.nz, cz0 + s.zc);
     const int nz = gf.nz;
-    const int64_t PL = (int64_t)gf.nx * gf.ny, PLc = (int64_t)gc.nx * gc.ny;
+    const int PL = gf.nx * gf.ny, PLc = gc.nx * gc.ny;
     const T* f = F + r * ldf;
     T* x = X + r * ldx;
     T* fc = Fc + r * ldc;
 
     RCol<T> c[kCPT];
 #pragma unroll
-    for (int u = 0; u < kCPT; ++u) rcol_init(c[u], gf, threadIdx.x + u * kFT, RW, RH, 2 * cX0 - 3, 2 * cY0 - 3, 3);
+    for (int u = 0; u < kCPT; ++u) rcol_init(c[u], gf, threadIdx.x + u * NT, RW, RH, 2 * cX0 - 3, 2 * cY0 - 3, 3);
     const int ci = threadIdx.x % s.TX, cj = threadIdx.x / s.TX;
     const bool cact = (int)threadIdx.x < s.TX * s.TY && cX0 + ci < gc.nx && cY0 + cj < gc.ny;
     const int pc = (2 * ci + 3) + (2 * cj + 3) * RW;
-    const int64_t coff = cact ? (int64_t)(cY0 + cj) * gc.nx + (cX0 + ci) : 0;
+    const int coff = cact ? (cY0 + cj) * gc.nx + (cX0 + ci) : 0;
 
     const int aLo = max(0, 2 * cz0 - 3), aHi = min(nz - 1, 2 * cz1 + 1);  // f, x1
     const int bLo = max(0, 2 * cz0 - 2), bHi = min(nz - 1, 2 * cz1);      // x2
     const int rLo = max(0, 2 * cz0 - 1), rHi = min(nz - 1, 2 * cz1 - 1);  // r and its plane sums
     const int oLo = 2 * cz0, oHi = min(nz - 1, 2 * cz1 - 1);              // x2 written
     const T om1 = T(1) - w1;
-
-    T f0[kCPT], f1[kCPT], f2[kCPT];  // f  on planes n-2, n-1, n
-    T a0[kCPT], a1[kCPT], a2[kCPT];  // x1 on planes n-2, n-1, n
-    T b0[kCPT], b1[kCPT], b2[kCPT];  // x2 on planes n-3, n-2, n-1
-#pragma unroll
-    for (int u = 0; u < kCPT; ++u) {
-        f0[u] = f1[u] = a0[u] = a1[u] = b0[u] = b1[u] = T(0);
-    }
-    T half = T(0), acc = T(0);
     const T scale = T(0.125);
 
-    // f is loaded two steps ahead of its use (raw values; the validity test is
-    // applied at use), with clamped addresses so that every load is issued
-    // unconditionally and stays in flight across the barriers.
-    auto fidx = [&](int u, int pl) -> int64_t { return (c[u].ing && pl <= aHi) ? pl * PL + c[u].off : 0; };
-    T q0[kCPT], q1[kCPT];
+    // register sets: plane n of f / x1 in set (n - aLo) % 3, x2 of plane n - 1
+    // likewise; Qr: raw f loads of planes n .. n+2 (validity applied at use;
+    // clamped addresses keep every load unconditional)
+    T Fr[3][kCPT], Ar[3][kCPT], Br[3][kCPT], Qr[3][kCPT];
+    auto fidx = [&](int u, int pl) -> int { return (c[u].ing && pl <= aHi) ? pl * PL + c[u].off : 0; };
 #pragma unroll
-    for (int u = 0; u < kCPT; ++u) {
-        q0[u] = f[fidx(u, aLo)];
-        q1[u] = f[fidx(u, aLo + 1)];
-    }
+    for (int k3 = 0; k3 < 3; ++k3)
+#pragma unroll
+        for (int u = 0; u < kCPT; ++u) {
+            Fr[k3][u] = Ar[k3][u] = Br[k3][u] = T(0);
+            Qr[k3][u] = f[fidx(u, aLo + k3)];
+        }
+    T half = T(0), acc = T(0);
 
-    for (int n = aLo; n <= rHi + 3; ++n) {
+    march3(aLo, rHi + 3, [&](int n, auto Rc) {
+        constexpr int R = decltype(Rc)::value, R1 = (R + 2) % 3, R2 = (R + 1) % 3;
         // A: f and x1 = w0 D^-1 f on plane n
         {
             const bool bnd = n == 0 || n == nz - 1;
-            T* P = plane(s1, n & 1);
+            T* P = L::plane(s1, n & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                const T raw = q0[u];
-                q0[u] = q1[u];
-                q1[u] = f[fidx(u, n + 2)];
+                const T raw = Qr[R][u];
+                Qr[R][u] = f[fidx(u, n + 3)];
                 const T fv = (n <= aHi && c[u].ing) ? raw : T(0);
-                f2[u] = fv;
-                a2[u] = (w0 * (bnd ? c[u].ivb : c[u].ivi)) * fv;
-                P[c[u].p] = a2[u];
+                Fr[R][u] = fv;
+                Ar[R][u] = (w0 * (bnd ? c[u].ivb : c[u].ivi)) * fv;
+                P[c[u].p] = Ar[R][u];
             }
         }
-        // B: x2 on plane n - 1
+        // B: x2 on plane n - 1 (x1 of n-2, n-1, n in Ar[R2], Ar[R1], Ar[R])
         {
             const int m = n - 1;
             const bool in = m >= bLo && m <= bHi, wr = m >= oLo && m <= oHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
-            T* P = plane(s1, m & 1);
-            T* Q = plane(s2, m & 1);
+            const T* P = L::plane(s1, m & 1);
+            T* Q = L::plane(s2, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                const T sn = nbr_sum(c[u], wz, P, RW, a0[u], a2[u]);
-                T v = fma(w1 * (bnd ? c[u].ivb : c[u].ivi), f1[u] + sn, om1 * a1[u]);
+                const T sn = nbr_sum(c[u], wz, P, RW, Ar[R2][u], Ar[R][u]);
+                T v = fma(w1 * (bnd ? c[u].ivb : c[u].ivi), Fr[R1][u] + sn, om1 * Ar[R1][u]);
                 v = (in && c[u].r1) ? v : T(0);
                 if (wr && c[u].own) x[m * PL + c[u].off] = v;
-                b2[u] = v;
+                Br[R][u] = v;
                 Q[c[u].p] = v;
             }
         }
-        // C: r = f - D x2 + S on plane n - 2 (zero outside the r ring)
+        // C: r = f - D x2 + S on plane n - 2 (x2 of n-3, n-2, n-1 in Br[R2],
+        // Br[R1], Br[R]; zero outside the r ring)
         {
             const int m = n - 2;
             const bool in = m >= rLo && m <= rHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
-            T* P = plane(s2, m & 1);
-            T* R = plane(sr, m & 1);
+            const T* P = L::plane(s2, m & 1);
+            T* Rp = L::plane(sr, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                const T sn = nbr_sum(c[u], wz, P, RW, b0[u], b2[u]);
-                T v = fma(-(bnd ? c[u].dgb : c[u].dgi), b1[u], f0[u]) + sn;
-                R[c[u].p] = (in && c[u].r2) ? v : T(0);
+                const T sn = nbr_sum(c[u], wz, P, RW, Br[R2][u], Br[R][u]);
+                const T v = fma(-(bnd ? c[u].dgb : c[u].dgi), Br[R1][u], Fr[R2][u]) + sn;
+                Rp[c[u].p] = (in && c[u].r2) ? v : T(0);
             }
         }
         // D: in-plane full-weighting sum of r on plane n - 3; coarse plane L
@@ -243,37 +262,28 @@ __global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T
         {
             const int m = n - 3;
             if (cact && m >= rLo && m <= rHi) {
-                const T* R = plane(sr, m & 1);
+                const T* Rp = L::plane(sr, m & 1);
                 T sum = T(0);
 #pragma unroll
                 for (int dy = -1; dy <= 1; ++dy) {
                     const T wy = dy ? T(0.5) : T(1);
                     T row = T(0);
 #pragma unroll
-                    for (int dx = -1; dx <= 1; ++dx) row += (dx ? T(0.5) : T(1)) * R[pc + dy * RW + dx];
+                    for (int dx = -1; dx <= 1; ++dx) row += (dx ? T(0.5) : T(1)) * Rp[pc + dy * RW + dx];
                     sum += wy * row;
                 }
-                const int L = m >> 1;
+                const int Lc = m >> 1;
                 if ((m & 1) == 0) {
                     acc = half + sum;
-                    if (m + 1 >= nz && L >= cz0 && L < cz1) fc[L * PLc + coff] = scale * acc;
+                    if (m + 1 >= nz && Lc >= cz0 && Lc < cz1) fc[Lc * PLc + coff] = scale * acc;
                 } else {
-                    if (L >= cz0 && L < cz1) fc[L * PLc + coff] = scale * (acc + T(0.5) * sum);
+                    if (Lc >= cz0 && Lc < cz1) fc[Lc * PLc + coff] = scale * (acc + T(0.5) * sum);
                     half = T(0.5) * sum;
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < kCPT; ++u) {
-            f0[u] = f1[u];
-            f1[u] = f2[u];
-            a0[u] = a1[u];
-            a1[u] = a2[u];
-            b0[u] = b1[u];
-            b1[u] = b2[u];
-        }
         __syncthreads();
-    }
+    });
 }
 
 // ---------------------------------------------------------------- up pass
@@ -283,16 +293,18 @@ __global__ __launch_bounds__(kFT) void k_down(Geom gf, Geom gc, FTile s, const T
 // planes n/2 and, for odd n, n/2 + 1); thread t < CRW * CRH stages coarse
 // column t of the region (zero outside the coarse grid).
 // Pipeline at step n: A y0 on plane n; B y1 on n-1; C y on n-2.
-__device__ __forceinline__ int64_t coarse_idx(const Geom& gc, int64_t cidx, int L) {
-    return (cidx >= 0 && L < gc.nz) ? L * ((int64_t)gc.nx * gc.ny) + cidx : 0;
+__device__ __forceinline__ int coarse_idx(const Geom& gc, int cidx, int L) {
+    return (cidx >= 0 && L < gc.nz) ? L * (gc.nx * gc.ny) + cidx : 0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
-                                            const T* __restrict__ X0, int64_t ldx0, const T* __restrict__ Ec,
-                                            int64_t ldc, T* __restrict__ Y, int64_t ldy, T wa, T wb) {
-    __shared__ T s0[kLds];
-    __shared__ T s1[kLds];
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_up(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
+                                           const T* __restrict__ X0, int64_t ldx0, const T* __restrict__ Ec,
+                                           int64_t ldc, T* __restrict__ Y, int64_t ldy, T wa, T wb) {
+    static_assert(kCReg <= NT, "one staged coarse column per thread");
+    using L = Lds<NT>;
+    __shared__ T s0[L::SIZE];
+    __shared__ T s1[L::SIZE];
     __shared__ T se[2][kCReg];
     int tx, ty, zr, r;
     if (!ftile_item(s, tx, ty, zr, r)) return;
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
     const int gx0 = tx * s.TX, gy0 = ty * s.TY;
     const int z0 = zr * s.zc, z1 = min(gf.nz, z0 + s.zc);
     const int nz = gf.nz;
-    const int64_t PL = (int64_t)gf.nx * gf.ny;
+    const int PL = gf.nx * gf.ny;
     const int i0 = gx0 - 2, j0 = gy0 - 2;
     const int cI0 = i0 >> 1, cJ0 = j0 >> 1;  // floor
     const T* f = F + r * ldf;
@@ -315,7 +327,7 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
     T wxl[kCPT], wxh[kCPT], wyl[kCPT], wyh[kCPT];
 #pragma unroll
     for (int u = 0; u < kCPT; ++u) {
-        const int p = threadIdx.x + u * kFT;
+        const int p = threadIdx.x + u * NT;
         rcol_init(c[u], gf, p, RW, RH, i0, j0, 2);
         const int i = i0 + (p % RW), j = j0 + (p / RW);
         cb[u] = c[u].ing ? ((i >> 1) - cI0) + ((j >> 1) - cJ0) * s.CRW : 0;
@@ -333,13 +345,13 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
     // staged coarse column of this thread
     const int ct = threadIdx.x;
     const bool cst = ct < s.CRW * s.CRH;
-    int64_t cidx = -1;
+    int cidx = -1;
     if (cst) {
         const int I = cI0 + ct % s.CRW, J = cJ0 + ct / s.CRW;
-        if (I >= 0 && I < gc.nx && J >= 0 && J < gc.ny) cidx = (int64_t)J * gc.nx + I;
+        if (I >= 0 && I < gc.nx && J >= 0 && J < gc.ny) cidx = J * gc.nx + I;
     }
-    auto stage_now = [&](int L) {
-        if (cst) se[L & 1][ct] = (cidx >= 0 && L < gc.nz) ? e[coarse_idx(gc, cidx, L)] : T(0);
+    auto stage_now = [&](int Lc) {
+        if (cst) se[Lc & 1][ct] = (cidx >= 0 && Lc < gc.nz) ? e[coarse_idx(gc, cidx, Lc)] : T(0);
     };
     stage_now(aLo >> 1);
     stage_now((aLo >> 1) + 1);
@@ -348,49 +360,43 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
     T cq = e[coarse_idx(gc, cidx, (nEven >> 1) + 1)];
     __syncthreads();
 
-    // x0 and f are loaded two steps ahead of their use (see the down pass)
-    auto xidx = [&](int u, int pl) -> int64_t { return (c[u].ing && pl <= aHi) ? pl * PL + c[u].off : 0; };
-    auto fidx = [&](int u, int pl) -> int64_t { return (c[u].r1 && pl <= aHi) ? pl * PL + c[u].off : 0; };
-    T xq0[kCPT], xq1[kCPT], fq0[kCPT], fq1[kCPT];
+    // register sets as in the down pass: y0, f of plane n and y1 of plane
+    // n - 1 in set (n - aLo) % 3; XQ, FQ: raw loads of planes n .. n+2
+    auto xidx = [&](int u, int pl) -> int { return (c[u].ing && pl <= aHi) ? pl * PL + c[u].off : 0; };
+    auto fidx = [&](int u, int pl) -> int { return (c[u].r1 && pl <= aHi) ? pl * PL + c[u].off : 0; };
+    T Pr[3][kCPT], Fr[3][kCPT], Yr[3][kCPT], XQ[3][kCPT], FQ[3][kCPT];
 #pragma unroll
-    for (int u = 0; u < kCPT; ++u) {
-        xq0[u] = x0[xidx(u, aLo)];
-        fq0[u] = f[fidx(u, aLo)];
-        xq1[u] = x0[xidx(u, aLo + 1)];
-        fq1[u] = f[fidx(u, aLo + 1)];
-    }
-
-    T p0[kCPT], p1[kCPT], p2[kCPT];  // y0 on planes n-2, n-1, n
-    T f0[kCPT], f1[kCPT], f2[kCPT];  // f  on planes n-2, n-1, n
-    T q0[kCPT], q1[kCPT], q2[kCPT];  // y1 on planes n-3, n-2, n-1
+    for (int k3 = 0; k3 < 3; ++k3)
 #pragma unroll
-    for (int u = 0; u < kCPT; ++u) {
-        p0[u] = p1[u] = f0[u] = f1[u] = q0[u] = q1[u] = T(0);
-    }
+        for (int u = 0; u < kCPT; ++u) {
+            Pr[k3][u] = Fr[k3][u] = Yr[k3][u] = T(0);
+            XQ[k3][u] = x0[xidx(u, aLo + k3)];
+            FQ[k3][u] = f[fidx(u, aLo + k3)];
+        }
 
-    for (int n = aLo; n <= cHi + 2; ++n) {
+    march3(aLo, cHi + 2, [&](int n, auto Rc) {
+        constexpr int R = decltype(Rc)::value, R1 = (R + 2) % 3, R2 = (R + 1) % 3;
         // the coarse plane that step n + 1 adds (odd n + 1 needs n/2 + 1), and
         // the load of the one the next even step adds
         if (!(n & 1)) {
-            const int L = (n >> 1) + 1;
-            if (n + 1 <= aHi && cst) se[L & 1][ct] = (cidx >= 0 && L < gc.nz) ? cq : T(0);
-            cq = e[coarse_idx(gc, cidx, L + 1)];
+            const int Lc = (n >> 1) + 1;
+            if (n + 1 <= aHi && cst) se[Lc & 1][ct] = (cidx >= 0 && Lc < gc.nz) ? cq : T(0);
+            cq = e[coarse_idx(gc, cidx, Lc + 1)];
         }
         // A: y0 = x2 + P e on plane n
         {
             const bool in = n <= aHi;
-            const int L = n >> 1;
-            const T* E0 = se[L & 1];
-            const T* E1 = se[(L + 1) & 1];
-            T* P = plane(s0, n & 1);
+            const int Lc = n >> 1;
+            const T* E0 = se[Lc & 1];
+            const T* E1 = se[(Lc + 1) & 1];
+            T* P = L::plane(s0, n & 1);
+            const int CW = s.CRW;
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                const T xr = xq0[u], fr = fq0[u];
-                xq0[u] = xq1[u];
-                fq0[u] = fq1[u];
-                xq1[u] = x0[xidx(u, n + 2)];
-                fq1[u] = f[fidx(u, n + 2)];
-                const int b = cb[u], CW = s.CRW;
+                const T xr = XQ[R][u], fr = FQ[R][u];
+                XQ[R][u] = x0[xidx(u, n + 3)];
+                FQ[R][u] = f[fidx(u, n + 3)];
+                const int b = cb[u];
                 T pe = wyl[u] * fma(wxl[u], E0[b], wxh[u] * E0[b + 1]);
                 pe = fma(wyh[u], fma(wxl[u], E0[b + CW], wxh[u] * E0[b + CW + 1]), pe);
                 if (n & 1) {
@@ -399,72 +405,64 @@ __global__ __launch_bounds__(kFT) void k_up(Geom gf, Geom gc, FTile s, const T* 
                     pe = T(0.5) * (pe + p1v);
                 }
                 const T v = (in && c[u].ing) ? xr + pe : T(0);
-                p2[u] = v;
-                f2[u] = (in && c[u].r1) ? fr : T(0);
+                Pr[R][u] = v;
+                Fr[R][u] = (in && c[u].r1) ? fr : T(0);
                 P[c[u].p] = v;
             }
         }
-        // B: y1 on plane n - 1
+        // B: y1 on plane n - 1 (y0 of n-2, n-1, n in Pr[R2], Pr[R1], Pr[R])
         {
             const int m = n - 1;
             const bool in = m >= bLo && m <= bHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
-            T* P = plane(s0, m & 1);
-            T* Q = plane(s1, m & 1);
+            const T* P = L::plane(s0, m & 1);
+            T* Q = L::plane(s1, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                const T sn = nbr_sum(c[u], wz, P, RW, p0[u], p2[u]);
-                T v = fma(wa * (bnd ? c[u].ivb : c[u].ivi), f1[u] + sn, oma * p1[u]);
+                const T sn = nbr_sum(c[u], wz, P, RW, Pr[R2][u], Pr[R][u]);
+                T v = fma(wa * (bnd ? c[u].ivb : c[u].ivi), Fr[R1][u] + sn, oma * Pr[R1][u]);
                 v = (in && c[u].r1) ? v : T(0);
-                q2[u] = v;
+                Yr[R][u] = v;
                 Q[c[u].p] = v;
             }
         }
-        // C: y on plane n - 2
+        // C: y on plane n - 2 (y1 of n-3, n-2, n-1 in Yr[R2], Yr[R1], Yr[R])
         {
             const int m = n - 2;
             const bool in = m >= cLo && m <= cHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
-            T* P = plane(s1, m & 1);
+            const T* P = L::plane(s1, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
-                const T sn = nbr_sum(c[u], wz, P, RW, q0[u], q2[u]);
-                const T v = fma(wb * (bnd ? c[u].ivb : c[u].ivi), f0[u] + sn, omb * q1[u]);
+                const T sn = nbr_sum(c[u], wz, P, RW, Yr[R2][u], Yr[R][u]);
+                const T v = fma(wb * (bnd ? c[u].ivb : c[u].ivi), Fr[R2][u] + sn, omb * Yr[R1][u]);
                 if (in && c[u].own) y[m * PL + c[u].off] = v;
             }
         }
-#pragma unroll
-        for (int u = 0; u < kCPT; ++u) {
-            p0[u] = p1[u];
-            p1[u] = p2[u];
-            f0[u] = f1[u];
-            f1[u] = f2[u];
-            q0[u] = q1[u];
-            q1[u] = q2[u];
-        }
         __syncthreads();
-    }
+    });
 }
 
-// Tile shape: the region must fit kReg columns; the cost of a plane is
+// Tile shape: the region must fit 2 NT columns; the cost of a plane is
 // (work-groups) x (fixed cost of one group + 128-byte lines its region rows
 // touch), so wide rows (coalesced loads) and few groups both count.
-FTile plan_tiles(int nx, int ny, int nzt, int k, bool down, int zmin, int es) {
+FTile plan_tiles(int nx, int ny, int nzt, int k, bool down, int zmin, int es, int nt_threads) {
+    const int reg = nt_threads * kCPT;
     FTile best{};
     int64_t best_cost = -1, best_nt = 0;
     for (int TX = 1; TX <= nx; ++TX) {
         for (int TY = 1; TY <= ny; ++TY) {
             const int RW = down ? 2 * TX + 5 : TX + 4;
             const int RH = down ? 2 * TY + 5 : TY + 4;
-            if (RW * RH > kReg) break;
+            if (RW * RH > reg) break;
             if (RW > kPad) break;
-            if (down && TX * TY > kFT) break;
+            if (down && TX * TY > nt_threads) break;
             const int CRW = (RW + 1) / 2 + 2, CRH = (RH + 1) / 2 + 2;
             if (!down && CRW * CRH > kCReg) break;
             const int64_t nt = cdiv(nx, TX) * cdiv(ny, TY);
-            const int64_t cost = nt * ((int64_t)kReg * 8 + (int64_t)RH * (cdiv(RW * es, 128) + 1) * 128);
+            const int64_t cost = nt * ((int64_t)reg * 8 + (int64_t)RH * (cdiv(RW * es, 128) + 1) * 128);
             if (best_cost < 0 || cost < best_cost) {
                 best_cost = cost;
                 best_nt = nt;
@@ -502,9 +500,9 @@ void launch_vdown(hipStream_t st, const Geom& gf, const Geom& gc, int k, const T
                   T* Fc, int64_t ldc, double w0, double w1) {
     if (k <= 0) return;
     require(fused_levels_ok(gf, gc), "internal: fused pass on non-nested levels");
-    const FTile s = plan_tiles(gc.nx, gc.ny, gc.nz, k, true, 4, (int)sizeof(T));
-    hipLaunchKernelGGL(k_down<T>, dim3(ftile_grid(s)), dim3(kFT), 0, st, gf, gc, s, F, ldf, X, ldx, Fc, ldc, T(w0),
-                       T(w1));
+    const FTile s = plan_tiles(gc.nx, gc.ny, gc.nz, k, true, 4, (int)sizeof(T), kDownThreads);
+    hipLaunchKernelGGL((k_down<T, kDownThreads>), dim3(ftile_grid(s)), dim3(kDownThreads), 0, st, gf, gc, s, F, ldf,
+                       X, ldx, Fc, ldc, T(w0), T(w1));
     H1W_LAUNCHED();
 }
 
@@ -513,9 +511,9 @@ void launch_vup(hipStream_t st, const Geom& gf, const Geom& gc, int k, const T* 
                 int64_t ldx0, const T* Ec, int64_t ldc, T* Y, int64_t ldy, double wa, double wb) {
     if (k <= 0) return;
     require(fused_levels_ok(gf, gc), "internal: fused pass on non-nested levels");
-    const FTile s = plan_tiles(gf.nx, gf.ny, gf.nz, k, false, 8, (int)sizeof(T));
-    hipLaunchKernelGGL(k_up<T>, dim3(ftile_grid(s)), dim3(kFT), 0, st, gf, gc, s, F, ldf, X0, ldx0, Ec, ldc, Y, ldy,
-                       T(wa), T(wb));
+    const FTile s = plan_tiles(gf.nx, gf.ny, gf.nz, k, false, 8, (int)sizeof(T), kUpThreads);
+    hipLaunchKernelGGL((k_up<T, kUpThreads>), dim3(ftile_grid(s)), dim3(kUpThreads), 0, st, gf, gc, s, F, ldf, X0,
+                       ldx0, Ec, ldc, Y, ldy, T(wa), T(wb));
     H1W_LAUNCHED();
 }
 
