@@ -23,6 +23,8 @@ struct Ctx {
     bool fused = false;              // V-cycles as fused down/up passes (3D, nu = 2)
     int64_t Nc = 0;                  // nodes on the coarsest level
     DevBuf cinv64, cinv32;           // dense inverse of the coarsest operator
+    DevBuf cpart;                    // partial sums of the coarsest solve (split over j)
+    size_t cpart_elems = 0;
     int chunk = 1;                   // right-hand sides per V-cycle launch
     DevBuf vws;                      // V-cycle level workspace
     DevBuf stage;                    // FP32 staging (mixed precision)

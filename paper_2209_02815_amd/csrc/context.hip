@@ -149,6 +149,8 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     std::vector<float> inv32(inv.begin(), inv.end());
     cinv32.reserve(inv32.size() * sizeof(float));
     H1W_HIP(hipMemcpy(cinv32.p, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
+    cpart_elems = coarse_part_elems(Nc);
+    if (cpart_elems) cpart.reserve(cpart_elems * sizeof(double));
 
     fused = dim == 3 && d.nu == 2 && lv.size() >= 2 && !(d.flags & H1W_FLAG_UNFUSED_VCYCLE);
     for (size_t l = 0; fused && l + 1 < lv.size(); ++l) fused = fused_levels_ok(lv[l], lv[l + 1]);
@@ -195,7 +197,7 @@ void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
     const double ces = (double)es * k;
     auto coarse = [&](const T* f, int64_t lf, T* x, int64_t lx) {
         timed(H1W_K_COARSE, ces * 2 * Nc + (double)es * Nc * Nc, 2.0 * k * Nc * Nc,
-              [&] { launch_coarse_solve<T>(stream, Nc, fp_cinv<T>(), k, f, lf, x, lx); });
+              [&] { launch_coarse_solve<T>(stream, Nc, fp_cinv<T>(), k, f, lf, x, lx, cpart.as<T>(), cpart_elems); });
     };
     if (L == 1) {
         coarse(F, ldf, X, ldx);

@@ -100,9 +100,12 @@ void launch_restrict(hipStream_t s, int dim, const Geom& gf, const Geom& gc, int
 template <typename T>
 void launch_prolong_add(hipStream_t s, int dim, const Geom& gf, const Geom& gc, int k,
                         const T* Ec, int64_t ldc, T* X, int64_t ldx);
+// X = Cinv F (k rows); part: partial-sum workspace of part_elems elements
+// (may be null: no j splitting), at most coarse_part_elems(Nc) are used
 template <typename T>
 void launch_coarse_solve(hipStream_t s, int64_t Nc, const T* Cinv, int k, const T* F,
-                         int64_t ldf, T* X, int64_t ldx);
+                         int64_t ldf, T* X, int64_t ldx, T* part, size_t part_elems);
+size_t coarse_part_elems(int64_t Nc);
 template <typename TI, typename TO>
 void launch_convert(hipStream_t s, int64_t N, int k, const TI* X, int64_t ldx, TO* Y,
                     int64_t ldy, double scale);

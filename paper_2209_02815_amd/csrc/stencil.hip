@@ -399,31 +399,55 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, Sweep 
 
 // X_r = Cinv F_r on the coarsest level. Cinv is the symmetric dense inverse
 // (row-major Nc x Nc), so Cinv[j][i] = Cinv[i][j]: lane i of a wave reads
-// Cinv[j*Nc + i], coalesced across the wave. Block = 64 rows x 4 waves, each
-// wave summing a quarter of j; F_r is staged in LDS.
+// Cinv[j*Nc + i], coalesced across the wave. Work-group = 64 outputs i x
+// (its share of j, split over 4 waves) x (every gridDim.z-th right-hand
+// side). With few right-hand sides the j range is also split over
+// gridDim.y work-groups whose partial sums go to part[split][r][i] and are
+// added in a fixed order by k_coarse_reduce; with one split the sum is
+// written to X directly.
 constexpr int kCoarseMax = 4096;
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_solve(int Nc, const T* __restrict__ Cinv,
-                                                         int k, const T* __restrict__ F,
-                                                         int64_t ldf, T* __restrict__ X,
-                                                         int64_t ldx) {
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int Nc, const T* __restrict__ Cinv, int k,
+                                                         const T* __restrict__ F, int64_t ldf, T* __restrict__ X,
+                                                         int64_t ldx, T* __restrict__ part) {
     __shared__ T sf[kCoarseMax];
-    __shared__ T part[4][64];
+    __shared__ T red[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
-    const int q = (Nc + 3) / 4;
-    const int j0 = wv * q, j1 = min(Nc, j0 + q);
-    for (int r = blockIdx.y; r < k; r += gridDim.y) {
+    const int splits = gridDim.y;
+    const int js = (Nc + splits - 1) / splits;
+    const int ja = blockIdx.y * js, jb = min(Nc, ja + js);
+    const int q = (jb - ja + 3) / 4;
+    const int j0 = ja + wv * q, j1 = min(jb, j0 + q);
+    const int ic = min(i, Nc - 1);
+    for (int r = blockIdx.z; r < k; r += gridDim.z) {
         __syncthreads();
-        for (int j = threadIdx.x; j < Nc; j += kBlock) sf[j] = F[r * ldf + j];
+        for (int j = ja + (int)threadIdx.x; j < jb; j += kBlock) sf[j] = F[r * ldf + j];
         __syncthreads();
         T acc = T(0);
-        if (i < Nc)
-            for (int j = j0; j < j1; ++j) acc += Cinv[(int64_t)j * Nc + i] * sf[j];
-        part[wv][lane] = acc;
+#pragma unroll 8
+        for (int j = j0; j < j1; ++j) acc += Cinv[(int64_t)j * Nc + ic] * sf[j];
+        red[wv][lane] = acc;
         __syncthreads();
-        if (wv == 0 && i < Nc) X[r * ldx + i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+        if (wv == 0 && i < Nc) {
+            const T v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+            if (splits == 1)
+                X[r * ldx + i] = v;
+            else
+                part[((int64_t)blockIdx.y * k + r) * Nc + i] = v;
+        }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_reduce(int Nc, int k, int splits, const T* __restrict__ part,
+                                                          T* __restrict__ X, int64_t ldx) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)k * Nc) return;
+    const int r = (int)(t / Nc), i = (int)(t % Nc);
+    T acc = T(0);
+    for (int s = 0; s < splits; ++s) acc += part[((int64_t)s * k + r) * Nc + i];
+    X[r * ldx + i] = acc;
 }
 
 template <typename TI, typename TO>
@@ -556,14 +580,40 @@ void launch_prolong_add(hipStream_t s, int dim, const Geom& gf, const Geom& gc, 
     H1W_DIMCALL(k_prolong_add, T, dim3(sweep_grid(sw)), gf, gc, sw, Ec, ldc, X, ldx);
 }
 
+// Splits of the j range: enough work-groups to spread the read of Cinv over
+// the chip when there are few right-hand sides, within the partial buffer.
+int coarse_splits(int64_t Nc, int k, size_t part_elems) {
+    const int64_t iblocks = cdiv(Nc, 64);
+    int64_t sp = std::clamp<int64_t>(512 / std::max<int64_t>(1, iblocks * k), 1, cdiv(Nc, 32));
+    while (sp > 1 && (size_t)(sp * k * Nc) > part_elems) --sp;
+    return (int)sp;
+}
+
+size_t coarse_part_elems(int64_t Nc) {
+    // the largest split count times k * Nc over k >= 1 (splits > 1 needs iblocks * k < 512)
+    size_t best = 0;
+    for (int k = 1; k <= 512; ++k) {
+        const int64_t iblocks = cdiv(Nc, 64);
+        const int64_t sp = std::clamp<int64_t>(512 / std::max<int64_t>(1, iblocks * k), 1, cdiv(Nc, 32));
+        if (sp > 1) best = std::max(best, (size_t)(sp * k * Nc));
+    }
+    return best;
+}
+
 template <typename T>
-void launch_coarse_solve(hipStream_t s, int64_t Nc, const T* Cinv, int k, const T* F,
-                         int64_t ldf, T* X, int64_t ldx) {
+void launch_coarse_solve(hipStream_t s, int64_t Nc, const T* Cinv, int k, const T* F, int64_t ldf, T* X,
+                         int64_t ldx, T* part, size_t part_elems) {
     if (k <= 0) return;
     if (Nc > kCoarseMax) throw Error{H1W_EINVAL, "coarsest level too large"};
-    const dim3 grid((unsigned)cdiv(Nc, 64), (unsigned)std::min(k, 65535));
-    hipLaunchKernelGGL((k_coarse_solve<T>), grid, dim3(kBlock), 0, s, (int)Nc, Cinv, k, F, ldf, X, ldx);
+    const int splits = part ? coarse_splits(Nc, k, part_elems) : 1;
+    const dim3 grid((unsigned)cdiv(Nc, 64), (unsigned)splits, (unsigned)std::min(k, 65535));
+    hipLaunchKernelGGL((k_coarse_solve<T>), grid, dim3(kBlock), 0, s, (int)Nc, Cinv, k, F, ldf, X, ldx, part);
     H1W_LAUNCHED();
+    if (splits > 1) {
+        hipLaunchKernelGGL((k_coarse_reduce<T>), dim3((unsigned)cdiv((int64_t)k * Nc, kBlock)), dim3(kBlock), 0, s,
+                           (int)Nc, k, splits, (const T*)part, X, ldx);
+        H1W_LAUNCHED();
+    }
 }
 
 template <typename TI, typename TO>
@@ -618,7 +668,7 @@ void launch_apply_plus_dot(hipStream_t s, int dim, const Geom& g, double a, cons
     template void launch_prolong_add<T>(hipStream_t, int, const Geom&, const Geom&, int,         \
                                         const T*, int64_t, T*, int64_t);                         \
     template void launch_coarse_solve<T>(hipStream_t, int64_t, const T*, int, const T*, int64_t, \
-                                         T*, int64_t);
+                                         T*, int64_t, T*, size_t);
 H1W_INST(double)
 H1W_INST(float)
 template void launch_convert<double, float>(hipStream_t, int64_t, int, const double*, int64_t,
