@@ -86,9 +86,12 @@ __device__ __forceinline__ bool ftile_item(const FTile& s, int& tx, int& ty, int
 //   (A x)_p = D_p x_p - S_p,  S_p = wz (cx (x_w + x_e) + cy (x_s + x_n)) + cz (x_b + x_a),
 // with every neighbour outside the grid held as 0 (LDS planes and z registers
 // are zero there), which drops exactly the couplings a Neumann boundary node
-// lacks. cx, cy, cz are the couplings on interior planes (wz = 1); on the
-// first and last plane wz = 1/2 and D = dgb. Offsets are 32-bit (a grid
-// vector has fewer than 2^31 nodes).
+// lacks. cx, cy, cz are the couplings on interior planes (wz = 1). On the
+// first and last plane wz = 1/2, which halves every in-plane term of D while
+// the single z-coupling cz replaces the interior 2 cz: D there is exactly
+// D/2 of the interior, so one per-plane factor (uniform across the group)
+// covers both plane classes. Offsets are 32-bit (a grid vector has fewer
+// than 2^31 nodes).
 template <typename T>
 struct RCol {
     int p;          // region index (a + b * RW); >= RW * RH: idle column
@@ -97,8 +100,8 @@ struct RCol {
     bool r1, r2;    // inside the grid and at least 1 / 2 columns from the region edge
     bool own;       // written by this work-group
     T cx, cy, cz;
-    T dgi, dgb;     // D on interior / first-last planes
-    T ivi, ivb;     // 1/D (0 outside the grid)
+    T dg;           // D on interior planes
+    T iv;           // 1/D on interior planes (0 outside the grid)
 };
 
 template <typename T>
@@ -119,11 +122,8 @@ __device__ __forceinline__ void rcol_init(RCol<T>& c, const Geom& g, int p, int 
     c.cx = T(g.ihx2) * wy;
     c.cy = T(g.ihy2) * wx;
     c.cz = T(g.ihz2) * wx * wy;
-    const T inplane = T(g.beta) * wx * wy + c.cx * T(nxn) + c.cy * T(nyn);
-    c.dgi = inplane + c.cz * T(2);
-    c.dgb = T(0.5) * inplane + c.cz;
-    c.ivi = c.ing ? T(1) / c.dgi : T(0);
-    c.ivb = c.ing ? T(1) / c.dgb : T(0);
+    c.dg = T(g.beta) * wx * wy + c.cx * T(nxn) + c.cy * T(nyn) + c.cz * T(2);
+    c.iv = c.ing ? T(1) / c.dg : T(0);
     if (!c.ing) c.cx = c.cy = c.cz = T(0);
 }
 
@@ -159,6 +159,11 @@ __device__ __forceinline__ void march3(int n0, int n1, F&& step) {
 // Pipeline at step n: A f, x1 on plane n; B x2 on n-1; C r on n-2;
 // D plane sum of r on n-3 into the coarse plane (n-3)/2.
 // Smoothing step in diagonal form: x + w D^-1 (f - A x) = (1 - w) x + w D^-1 (f + S).
+// Columns outside the grid carry zero coefficients and zero f, so their x1,
+// x2 and r come out exactly 0 (the LDS starts zeroed, so every value read is
+// finite); halo columns whose stencil reaches beyond the region compute
+// values that no later stage reads. x2 on the planes -1 and nz (the absent
+// z-neighbours of the first and last plane) is held at zero explicitly.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_down(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
                                              T* __restrict__ X, int64_t ldx, T* __restrict__ Fc, int64_t ldc,
@@ -177,6 +182,7 @@ __global__ __launch_bounds__(NT) void k_down(Geom gf, Geom gc, FTile s, const T*
     const T* f = F + r * ldf;
     T* x = X + r * ldx;
     T* fc = Fc + r * ldc;
+    for (int t = threadIdx.x; t < L::SIZE; t += NT) s1[t] = s2[t] = sr[t] = T(0);
 
     RCol<T> c[kCPT];
 #pragma unroll
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(NT) void k_down(Geom gf, Geom gc, FTile s, const T*
     const int coff = cact ? (cY0 + cj) * gc.nx + (cX0 + ci) : 0;
 
     const int aLo = max(0, 2 * cz0 - 3), aHi = min(nz - 1, 2 * cz1 + 1);  // f, x1
-    const int bLo = max(0, 2 * cz0 - 2), bHi = min(nz - 1, 2 * cz1);      // x2
+    // x2 is needed on planes max(0, 2 cz0 - 2) .. min(nz - 1, 2 cz1)
     const int rLo = max(0, 2 * cz0 - 1), rHi = min(nz - 1, 2 * cz1 - 1);  // r and its plane sums
     const int oLo = 2 * cz0, oHi = min(nz - 1, 2 * cz1 - 1);              // x2 written
     const T om1 = T(1) - w1;
@@ -197,55 +203,59 @@ __global__ __launch_bounds__(NT) void k_down(Geom gf, Geom gc, FTile s, const T*
     // likewise; Qr: raw f loads of planes n .. n+2 (validity applied at use;
     // clamped addresses keep every load unconditional)
     T Fr[3][kCPT], Ar[3][kCPT], Br[3][kCPT], Qr[3][kCPT];
-    auto fidx = [&](int u, int pl) -> int { return (c[u].ing && pl <= aHi) ? pl * PL + c[u].off : 0; };
 #pragma unroll
-    for (int k3 = 0; k3 < 3; ++k3)
+    for (int k3 = 0; k3 < 3; ++k3) {
+        const T* fp = f + min(aLo + k3, aHi) * PL;
 #pragma unroll
         for (int u = 0; u < kCPT; ++u) {
             Fr[k3][u] = Ar[k3][u] = Br[k3][u] = T(0);
-            Qr[k3][u] = f[fidx(u, aLo + k3)];
+            Qr[k3][u] = fp[c[u].off];
         }
+    }
     T half = T(0), acc = T(0);
+    __syncthreads();
 
     march3(aLo, rHi + 3, [&](int n, auto Rc) {
         constexpr int R = decltype(Rc)::value, R1 = (R + 2) % 3, R2 = (R + 1) % 3;
         // A: f and x1 = w0 D^-1 f on plane n
         {
-            const bool bnd = n == 0 || n == nz - 1;
+            const T w0s = (n == 0 || n == nz - 1) ? T(2) * w0 : w0;
             T* P = L::plane(s1, n & 1);
+            const T* fp = f + min(n + 3, aHi) * PL;
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
                 const T raw = Qr[R][u];
-                Qr[R][u] = f[fidx(u, n + 3)];
+                Qr[R][u] = fp[c[u].off];
                 const T fv = (n <= aHi && c[u].ing) ? raw : T(0);
                 Fr[R][u] = fv;
-                Ar[R][u] = (w0 * (bnd ? c[u].ivb : c[u].ivi)) * fv;
+                Ar[R][u] = (w0s * c[u].iv) * fv;
                 P[c[u].p] = Ar[R][u];
             }
         }
         // B: x2 on plane n - 1 (x1 of n-2, n-1, n in Ar[R2], Ar[R1], Ar[R])
         {
             const int m = n - 1;
-            const bool in = m >= bLo && m <= bHi, wr = m >= oLo && m <= oHi;
+            const bool wr = m >= oLo && m <= oHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
+            const T w1s = bnd ? T(2) * w1 : w1;
+            const T keep = (m >= 0 && m < nz) ? T(1) : T(0);
             const T* P = L::plane(s1, m & 1);
             T* Q = L::plane(s2, m & 1);
+            T* xp = x + max(m, 0) * PL;
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
                 const T sn = nbr_sum(c[u], wz, P, RW, Ar[R2][u], Ar[R][u]);
-                T v = fma(w1 * (bnd ? c[u].ivb : c[u].ivi), Fr[R1][u] + sn, om1 * Ar[R1][u]);
-                v = (in && c[u].r1) ? v : T(0);
-                if (wr && c[u].own) x[m * PL + c[u].off] = v;
+                const T v = keep * fma(w1s * c[u].iv, Fr[R1][u] + sn, om1 * Ar[R1][u]);
+                if (wr && c[u].own) xp[c[u].off] = v;
                 Br[R][u] = v;
                 Q[c[u].p] = v;
             }
         }
         // C: r = f - D x2 + S on plane n - 2 (x2 of n-3, n-2, n-1 in Br[R2],
-        // Br[R1], Br[R]; zero outside the r ring)
+        // Br[R1], Br[R])
         {
             const int m = n - 2;
-            const bool in = m >= rLo && m <= rHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
             const T* P = L::plane(s2, m & 1);
@@ -253,8 +263,7 @@ __global__ __launch_bounds__(NT) void k_down(Geom gf, Geom gc, FTile s, const T*
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
                 const T sn = nbr_sum(c[u], wz, P, RW, Br[R2][u], Br[R][u]);
-                const T v = fma(-(bnd ? c[u].dgb : c[u].dgi), Br[R1][u], Fr[R2][u]) + sn;
-                Rp[c[u].p] = (in && c[u].r2) ? v : T(0);
+                Rp[c[u].p] = fma(-wz * c[u].dg, Br[R1][u], Fr[R2][u]) + sn;
             }
         }
         // D: in-plane full-weighting sum of r on plane n - 3; coarse plane L
@@ -293,12 +302,15 @@ __global__ __launch_bounds__(NT) void k_down(Geom gf, Geom gc, FTile s, const T*
 // planes n/2 and, for odd n, n/2 + 1); thread t < CRW * CRH stages coarse
 // column t of the region (zero outside the coarse grid).
 // Pipeline at step n: A y0 on plane n; B y1 on n-1; C y on n-2.
+// Columns outside the grid carry zero coefficients and zero x2, so their y0
+// and y1 come out exactly 0; y1 on the planes -1 and nz is held at zero
+// explicitly (see the down pass).
 __device__ __forceinline__ int coarse_idx(const Geom& gc, int cidx, int L) {
     return (cidx >= 0 && L < gc.nz) ? L * (gc.nx * gc.ny) + cidx : 0;
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_up(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
+__global__ __launch_bounds__(NT, 4) void k_up(Geom gf, Geom gc, FTile s, const T* __restrict__ F, int64_t ldf,
                                            const T* __restrict__ X0, int64_t ldx0, const T* __restrict__ Ec,
                                            int64_t ldc, T* __restrict__ Y, int64_t ldy, T wa, T wb) {
     static_assert(kCReg <= NT, "one staged coarse column per thread");
@@ -319,26 +331,28 @@ __global__ __launch_bounds__(NT) void k_up(Geom gf, Geom gc, FTile s, const T* _
     const T* x0 = X0 + r * ldx0;
     const T* e = Ec + r * ldc;
     T* y = Y + r * ldy;
+    for (int t = threadIdx.x; t < L::SIZE; t += NT) s0[t] = s1[t] = T(0);
 
     // per column: staged coarse index of the lower interpolation corner and
-    // the x / y interpolation weights (1, 0) on even, (1/2, 1/2) on odd nodes
+    // the x / y weight h of the upper corner (0 on even, 1/2 on odd nodes:
+    // value = lo + h (hi - lo)); fo: the f offset, 0 (a harmless address)
+    // where f is not needed
     RCol<T> c[kCPT];
-    int cb[kCPT];
-    T wxl[kCPT], wxh[kCPT], wyl[kCPT], wyh[kCPT];
+    int cb[kCPT], fo[kCPT];
+    T hx[kCPT], hy[kCPT];
 #pragma unroll
     for (int u = 0; u < kCPT; ++u) {
         const int p = threadIdx.x + u * NT;
         rcol_init(c[u], gf, p, RW, RH, i0, j0, 2);
         const int i = i0 + (p % RW), j = j0 + (p / RW);
         cb[u] = c[u].ing ? ((i >> 1) - cI0) + ((j >> 1) - cJ0) * s.CRW : 0;
-        wxl[u] = (i & 1) ? T(0.5) : T(1);
-        wxh[u] = (i & 1) ? T(0.5) : T(0);
-        wyl[u] = (j & 1) ? T(0.5) : T(1);
-        wyh[u] = (j & 1) ? T(0.5) : T(0);
+        fo[u] = c[u].r1 ? c[u].off : 0;
+        hx[u] = (i & 1) ? T(0.5) : T(0);
+        hy[u] = (j & 1) ? T(0.5) : T(0);
     }
 
     const int aLo = max(0, z0 - 2), aHi = min(nz - 1, z1 + 1);  // y0
-    const int bLo = max(0, z0 - 1), bHi = min(nz - 1, z1);      // y1
+    // y1 is needed on planes max(0, z0 - 1) .. min(nz - 1, z1)
     const int cLo = z0, cHi = z1 - 1;                           // y
     const T oma = T(1) - wa, omb = T(1) - wb;
 
@@ -362,17 +376,18 @@ __global__ __launch_bounds__(NT) void k_up(Geom gf, Geom gc, FTile s, const T* _
 
     // register sets as in the down pass: y0, f of plane n and y1 of plane
     // n - 1 in set (n - aLo) % 3; XQ, FQ: raw loads of planes n .. n+2
-    auto xidx = [&](int u, int pl) -> int { return (c[u].ing && pl <= aHi) ? pl * PL + c[u].off : 0; };
-    auto fidx = [&](int u, int pl) -> int { return (c[u].r1 && pl <= aHi) ? pl * PL + c[u].off : 0; };
     T Pr[3][kCPT], Fr[3][kCPT], Yr[3][kCPT], XQ[3][kCPT], FQ[3][kCPT];
 #pragma unroll
-    for (int k3 = 0; k3 < 3; ++k3)
+    for (int k3 = 0; k3 < 3; ++k3) {
+        const T* xp = x0 + min(aLo + k3, aHi) * PL;
+        const T* fp = f + min(aLo + k3, aHi) * PL;
 #pragma unroll
         for (int u = 0; u < kCPT; ++u) {
             Pr[k3][u] = Fr[k3][u] = Yr[k3][u] = T(0);
-            XQ[k3][u] = x0[xidx(u, aLo + k3)];
-            FQ[k3][u] = f[fidx(u, aLo + k3)];
+            XQ[k3][u] = xp[c[u].off];
+            FQ[k3][u] = fp[fo[u]];
         }
+    }
 
     march3(aLo, cHi + 2, [&](int n, auto Rc) {
         constexpr int R = decltype(Rc)::value, R1 = (R + 2) % 3, R2 = (R + 1) % 3;
@@ -391,38 +406,40 @@ __global__ __launch_bounds__(NT) void k_up(Geom gf, Geom gc, FTile s, const T* _
             const T* E1 = se[(Lc + 1) & 1];
             T* P = L::plane(s0, n & 1);
             const int CW = s.CRW;
+            const T* xp = x0 + min(n + 3, aHi) * PL;
+            const T* fp = f + min(n + 3, aHi) * PL;
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
                 const T xr = XQ[R][u], fr = FQ[R][u];
-                XQ[R][u] = x0[xidx(u, n + 3)];
-                FQ[R][u] = f[fidx(u, n + 3)];
+                XQ[R][u] = xp[c[u].off];
+                FQ[R][u] = fp[fo[u]];
                 const int b = cb[u];
-                T pe = wyl[u] * fma(wxl[u], E0[b], wxh[u] * E0[b + 1]);
-                pe = fma(wyh[u], fma(wxl[u], E0[b + CW], wxh[u] * E0[b + CW + 1]), pe);
-                if (n & 1) {
-                    T p1v = wyl[u] * fma(wxl[u], E1[b], wxh[u] * E1[b + 1]);
-                    p1v = fma(wyh[u], fma(wxl[u], E1[b + CW], wxh[u] * E1[b + CW + 1]), p1v);
-                    pe = T(0.5) * (pe + p1v);
-                }
+                auto bilin = [&](const T* E) {
+                    const T lo = fma(hx[u], E[b + 1] - E[b], E[b]);
+                    const T hi = fma(hx[u], E[b + CW + 1] - E[b + CW], E[b + CW]);
+                    return fma(hy[u], hi - lo, lo);
+                };
+                T pe = bilin(E0);
+                if (n & 1) pe = T(0.5) * (pe + bilin(E1));
                 const T v = (in && c[u].ing) ? xr + pe : T(0);
                 Pr[R][u] = v;
-                Fr[R][u] = (in && c[u].r1) ? fr : T(0);
+                Fr[R][u] = fr;
                 P[c[u].p] = v;
             }
         }
         // B: y1 on plane n - 1 (y0 of n-2, n-1, n in Pr[R2], Pr[R1], Pr[R])
         {
             const int m = n - 1;
-            const bool in = m >= bLo && m <= bHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
+            const T was = bnd ? T(2) * wa : wa;
+            const T keep = (m >= 0 && m < nz) ? T(1) : T(0);
             const T* P = L::plane(s0, m & 1);
             T* Q = L::plane(s1, m & 1);
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
                 const T sn = nbr_sum(c[u], wz, P, RW, Pr[R2][u], Pr[R][u]);
-                T v = fma(wa * (bnd ? c[u].ivb : c[u].ivi), Fr[R1][u] + sn, oma * Pr[R1][u]);
-                v = (in && c[u].r1) ? v : T(0);
+                const T v = keep * fma(was * c[u].iv, Fr[R1][u] + sn, oma * Pr[R1][u]);
                 Yr[R][u] = v;
                 Q[c[u].p] = v;
             }
@@ -433,12 +450,14 @@ __global__ __launch_bounds__(NT) void k_up(Geom gf, Geom gc, FTile s, const T* _
             const bool in = m >= cLo && m <= cHi;
             const bool bnd = m == 0 || m == nz - 1;
             const T wz = bnd ? T(0.5) : T(1);
+            const T wbs = bnd ? T(2) * wb : wb;
             const T* P = L::plane(s1, m & 1);
+            T* yp = y + max(m, 0) * PL;
 #pragma unroll
             for (int u = 0; u < kCPT; ++u) {
                 const T sn = nbr_sum(c[u], wz, P, RW, Yr[R2][u], Yr[R][u]);
-                const T v = fma(wb * (bnd ? c[u].ivb : c[u].ivi), Fr[R2][u] + sn, omb * Yr[R1][u]);
-                if (in && c[u].own) y[m * PL + c[u].off] = v;
+                const T v = fma(wbs * c[u].iv, Fr[R2][u] + sn, omb * Yr[R1][u]);
+                if (in && c[u].own) yp[c[u].off] = v;
             }
         }
         __syncthreads();
