@@ -117,7 +117,9 @@ typedef struct {
     int zmode_used;          /* h1w_zmode actually used */
     int failed_pivot;        /* first non-positive Cholesky pivot, -1 if none */
     int nlevels;             /* multigrid levels */
-    int restarts;            /* CG restarts after a failed true-residual check */
+    int restarts;            /* CG restarts from the true residual: after a failed final check, and
+                                (recompute form) the one replacement made once the recursive
+                                residual is below sqrt(rtol) */
     double relres_true;      /* ||b - G x|| / ||b|| recomputed from x in FP64 */
     double relres_rec;       /* recursive residual estimate at exit */
     double t_zbuild_ms;      /* batched V-cycles for Z */
