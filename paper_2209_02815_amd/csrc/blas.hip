@@ -13,7 +13,7 @@ namespace {
 
 constexpr int kDotBlocks = 1024;   // max blocks of a dot-product pass
 constexpr int kRowsPerBlock = 8;   // rows of J per block in J v
-constexpr int kRowChunk = kBlock * 16;  // nodes per block in J v
+constexpr int kRowChunk = kBlock * 8;   // nodes per block in J v
 constexpr int kTile = 256;         // rows of J staged in LDS per sweep in J^T v
 
 struct DotArgs {
@@ -52,11 +52,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce_parts(int nparts, const doubl
 }
 
 // partial[i*nchunk + c] = sum over chunk c of M[i, n] v[n], rows i of this block.
+// The block's kRowsPerBlock rows are accumulated back to back (loads of every
+// row in flight, no barrier between rows) and reduced together at the end, in
+// a fixed order (wave sums, then the 4 waves in order).
 template <typename TM>
 __global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const TM* __restrict__ M,
                                                      int64_t ldm, const double* __restrict__ v,
                                                      double* __restrict__ partial) {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[kRowsPerBlock][kBlock / 64];
     const int nchunk = gridDim.x;
     const int64_t base = (int64_t)blockIdx.x * kRowChunk;
     constexpr int E = kRowChunk / kBlock;
@@ -67,18 +70,32 @@ __global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const TM*
         vv[e] = n < N ? v[n] : 0.0;
     }
     const int r0 = blockIdx.y * kRowsPerBlock;
+    double acc[kRowsPerBlock];
+#pragma unroll
     for (int rr = 0; rr < kRowsPerBlock; ++rr) {
-        const int i = r0 + rr;
-        if (i >= m) break;
-        const TM* row = M + (int64_t)i * ldm;
-        double acc = 0.0;
+        acc[rr] = 0.0;
+        const TM* row = M + (int64_t)min(r0 + rr, m - 1) * ldm;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int64_t n = base + e * kBlock + threadIdx.x;
-            if (n < N) acc += double(row[n]) * vv[e];
+            if (n < N) acc[rr] += double(row[n]) * vv[e];
         }
-        const double s = block_sum<kBlock>(acc, sh);
-        if (threadIdx.x == 0) partial[(int64_t)i * nchunk + blockIdx.x] = s;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerBlock; ++rr) {
+        const double t = wave_sum(acc[rr]);
+        if (lane == 0) sh[rr][wid] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kRowsPerBlock) {
+        const int i = r0 + threadIdx.x;
+        if (i < m) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) t += sh[threadIdx.x][w];
+            partial[(int64_t)i * nchunk + blockIdx.x] = t;
+        }
     }
 }
 
