@@ -107,8 +107,24 @@ typedef struct {
     int factor;          /* h1w_factor: AUTO = Cholesky for FP64 (LU if it fails),
                             LU for MIXED */
     int check_every;     /* reserved (0) */
-    unsigned flags;      /* reserved, must be 0 */
+    unsigned flags;      /* H1W_SOLVE_* bits (at most one), other bits must be 0 */
 } h1w_solve_opts;
+
+/* h1w_solve_opts.flags: comparison modes of the Gauss-Newton solve.
+ * LAPLACE_ONLY (the Laplace preconditioner of Algorithm 4, without the
+ *   Woodbury correction): CG on G x = b preconditioned by B / alpha; no
+ *   capacitance is built and each iteration passes over J twice (J p, then
+ *   J^T (J p)). Its iteration count grows with m and 1/alpha.
+ * EXACT_B (the exact Woodbury inverse of Algorithm 1, with the Poisson solve
+ *   done by multigrid instead of a sparse factorisation): every application of
+ *   B, in the capacitance and in the preconditioner, is an MG-preconditioned
+ *   CG solve of A to a relative residual of 1e-12, so the preconditioner is
+ *   G^-1 up to that tolerance and CG stops after one or two iterations.
+ *   Needs an FP64 context. The capacitance it leaves in the context belongs
+ *   to this B and is discarded at return (h1w_precond_apply then needs a new
+ *   h1w_capacitance_build). */
+#define H1W_SOLVE_LAPLACE_ONLY 1u
+#define H1W_SOLVE_EXACT_B 2u
 
 /* Diagnostics filled by the calls that take an h1w_info* (may be NULL). */
 typedef struct {

@@ -137,6 +137,8 @@ def _dtype_code(t):
 # ------------------------------------------------------------------ entry points
 H1W_FLAG_STREAM_Z = 1
 H1W_FLAG_UNFUSED_VCYCLE = 2
+H1W_SOLVE_LAPLACE_ONLY = 1
+H1W_SOLVE_EXACT_B = 2
 
 
 def h1w_setup(shape, beta: float, precision: int = H1W_FP64, nu: int = 0, cheb=(0.0, 0.0),
@@ -213,10 +215,11 @@ def h1w_precond_apply(ctx, R, Zout, zmode: int = H1W_Z_AUTO):
 
 
 def h1w_gn_solve(ctx, J, alpha: float, x, b=None, d=None, res=None, rtol: float = 0.0, maxit: int = 0,
-                 zmode: int = H1W_Z_AUTO, factor: int = H1W_FACTOR_AUTO, raise_on_error: bool = True):
+                 zmode: int = H1W_Z_AUTO, factor: int = H1W_FACTOR_AUTO, raise_on_error: bool = True,
+                 flags: int = 0):
     N, _ = h1w_get_sizes(ctx)
     m, ldj = (0, N) if J is None else _rows(J, N, "J")
-    o = h1w_solve_opts(float(rtol), int(maxit), int(zmode), int(factor), 0, 0)
+    o = h1w_solve_opts(float(rtol), int(maxit), int(zmode), int(factor), 0, int(flags))
     info = h1w_info()
     st = lib.h1w_gn_solve(ctx, m, _ptr(J), ldj, float(alpha), _ptr(b), _ptr(d), _ptr(res), _ptr(x),
                           C.byref(o), C.byref(info))

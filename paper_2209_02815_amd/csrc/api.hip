@@ -255,7 +255,10 @@ h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
         require(o.maxit >= 0, "maxit must be >= 0");
         require(o.zmode >= H1W_Z_AUTO && o.zmode <= H1W_Z_RECOMPUTE, "zmode must be AUTO, STORED or RECOMPUTE");
         require(o.factor >= H1W_FACTOR_AUTO && o.factor <= H1W_FACTOR_LU, "factor must be AUTO, CHOL or LU");
-        require(o.check_every == 0 && o.flags == 0, "check_every and flags must be 0");
+        require(o.check_every == 0, "check_every must be 0");
+        require((o.flags & ~(H1W_SOLVE_LAPLACE_ONLY | H1W_SOLVE_EXACT_B)) == 0, "unknown bits in flags");
+        require(o.flags != (H1W_SOLVE_LAPLACE_ONLY | H1W_SOLVE_EXACT_B), "LAPLACE_ONLY and EXACT_B exclude each other");
+        require(!(o.flags & H1W_SOLVE_EXACT_B) || !c.fp32, "EXACT_B needs an FP64 context");
         c.gn_solve(m, J, ldj, alpha, b, d, res, x, o, info);
     });
 }

@@ -76,7 +76,12 @@ struct Ctx {
     }
     template <typename T> void vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx);
     template <typename T> void vcycle(int k, const T* F, int64_t ldf, T* X, int64_t ldx);
+    // y = B r: one V-cycle in the context precision (vcycle_B), or an MG-PCG
+    // solve to exact_rtol while exact_b is set (the EXACT_B solve mode)
     void apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
+    void vcycle_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
+    bool exact_b = false;
+    double exact_rtol = 1e-12;
     void mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, double rtol, int maxit,
                   h1w_info* info);
 

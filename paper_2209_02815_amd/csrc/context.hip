@@ -312,8 +312,16 @@ void Ctx::vcycle(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
     }
 }
 
-// y = B r for FP64 vectors in the context's V-cycle precision.
 void Ctx::apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
+    if (exact_b) {
+        mg_solve(k, F, ldf, X, ldx, exact_rtol, 200, nullptr);
+        return;
+    }
+    vcycle_B(k, F, ldf, X, ldx);
+}
+
+// y = B r for FP64 vectors in the context's V-cycle precision.
+void Ctx::vcycle_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
     if (!fp32) {
         vcycle<double>(k, F, ldf, X, ldx);
         return;
@@ -396,7 +404,7 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
             if (nb[r] == 0.0) act[r] = 0;
         }
         put((double*)dact, act.data(), kk * sizeof(int));
-        apply_B(kk, R, P, Zv, P);
+        vcycle_B(kk, R, P, Zv, P);
         H1W_HIP(hipMemcpy2DAsync(Pv, P * sizeof(double), Zv, P * sizeof(double), n * sizeof(double), kk,
                                  hipMemcpyDeviceToDevice, stream));
         launch_batched_dots(stream, kk, n, R, P, Zv, P, pp, drz);
@@ -429,7 +437,7 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
             }
             put((double*)dact, act.data(), kk * sizeof(int));
             if (!any) break;
-            apply_B(kk, R, P, Zv, P);
+            vcycle_B(kk, R, P, Zv, P);
             launch_batched_dots(stream, kk, n, R, P, Zv, P, pp, drz);
             if (fp32) launch_batched_dots(stream, kk, n, Zv, P, Q, P, pp, dzq);
             std::vector<double> rzn(kk);
@@ -491,7 +499,7 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
         Zbuf.reserve(zbytes);
         ldz = n;
         if (!fp32) {
-            vcycle<double>(m, J, ldj, Zbuf.as<double>(), ldz);
+            apply_B(m, J, ldj, Zbuf.as<double>(), ldz);
         } else {
             // FP32 V-cycles on J_i - s_i W1; the constant mode s_i v stays exact in FP64
             ensure_deflation_vectors();
@@ -554,7 +562,7 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
         gpart.reserve(pe * sizeof(double));
         for (int c0 = 0; c0 < m; c0 += zc) {
             const int cc = std::min(zc, m - c0);
-            vcycle<double>(cc, J + (int64_t)c0 * ldj, ldj, zchunk.as<double>(), n);
+            apply_B(cc, J + (int64_t)c0 * ldj, ldj, zchunk.as<double>(), n);
             // S[c0:m, c0:c0+cc] = J[c0:m] Zc^T (+ alpha on the diagonal)
             const int rows = m - c0;
             int splits = 0;
@@ -752,13 +760,25 @@ void Ctx::gn_apply(int mm, const double* JJ, int64_t ldjj, double al, const doub
 void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const double* b_, const double* dvec,
                    const double* res, double* x, const h1w_solve_opts& o, h1w_info* info) {
     const int64_t n = N();
+    const bool laplace = (o.flags & H1W_SOLVE_LAPLACE_ONLY) != 0;
+    // EXACT_B: B = A^-1 (MG-PCG to exact_rtol) for the whole call; the
+    // capacitance it builds is discarded at return
+    struct ExactScope {
+        Ctx& c;
+        bool on;
+        ExactScope(Ctx& cc, bool o) : c(cc), on(o) { c.exact_b = o; }
+        ~ExactScope() {
+            c.exact_b = false;
+            if (on) c.have_cap = false;
+        }
+    } exact_scope(*this, (o.flags & H1W_SOLVE_EXACT_B) != 0);
     ev_reserve();
     H1W_HIP(hipEventRecord(ev[5], stream));
-    if (m_ > 0) {
+    if (m_ > 0 && !laplace) {
         capacitance_build(m_, J_, ldj_, alpha_, o.factor, info);
     } else {
         have_cap = false;
-        m = 0;
+        m = laplace ? m_ : 0;
         J = J_;
         ldj = ldj_;
         alpha = alpha_;
@@ -766,8 +786,8 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     ensure_cg_ws(m);
     int zm = o.zmode;
     if (zm == H1W_Z_AUTO) zm = fp32 ? H1W_Z_STORED : H1W_Z_RECOMPUTE;
-    require(!(fp32 && zm == H1W_Z_RECOMPUTE), "a MIXED context needs zmode STORED");
-    if (m > 0 && z_streamed) {
+    require(laplace || !(fp32 && zm == H1W_Z_RECOMPUTE), "a MIXED context needs zmode STORED");
+    if (m > 0 && !laplace && z_streamed) {
         require(zm != H1W_Z_STORED || o.zmode == H1W_Z_AUTO, "Z was streamed (not stored): use zmode RECOMPUTE");
         zm = H1W_Z_RECOMPUTE;
     }
@@ -809,14 +829,15 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     // the iteration. One replacement of r by the true residual once the
     // recursive residual is below sqrt(rtol) bounds the later drift far below
     // rtol (otherwise the final check fails and forces a late restart).
-    const double replace_tol = (m > 0 && zm == H1W_Z_RECOMPUTE) ? std::sqrt(rtol) : 0.0;
+    const double replace_tol = (m > 0 && !laplace && zm == H1W_Z_RECOMPUTE) ? std::sqrt(rtol) : 0.0;
     bool replaced = false;
     h1w_status status = H1W_OK;
 
     // z = P^{-1} r, p = z + beta p, t = J^T Jp; returns false if r.z <= 0 (converged to rounding)
     auto precond_step = [&](bool first) -> bool {
         apply_B(1, r, n, y, n);
-        if (m == 0) {
+        if (m == 0 || laplace) {
+            // z = B r / alpha (no Woodbury correction); t = J^T (J p) by two passes
             dots(n, {{r, y}, {y, q}}, 0);
             read_scal(2);
             const double rzn = hscal[0] * ia;
@@ -825,7 +846,13 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
             const double beta = first ? 0.0 : (flexible ? -a * zq / rz : rzn / rz);
             rz = rzn;
             launch_axpby(stream, n, ia, y, beta, p);
-            H1W_HIP(hipMemsetAsync(t, 0, n * sizeof(double), stream));
+            if (m == 0) {
+                H1W_HIP(hipMemsetAsync(t, 0, n * sizeof(double), stream));
+            } else {
+                rows_dot(m, J, ldj, p, Jp);
+                timed(H1W_K_JTV, 8.0 * m * n + 8.0 * n, 2.0 * m * n,
+                      [&] { launch_jt_plain(stream, m, n, J, ldj, Jp, t, nullptr, 0.0); });
+            }
             return true;
         }
         woodbury_mspace(y, Jy, w);
@@ -954,7 +981,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         info->restarts = restarts;
         info->relres_true = relres_true;
         info->relres_rec = relres_rec;
-        info->zmode_used = m > 0 ? zm : 0;
+        info->zmode_used = (m > 0 && !laplace) ? zm : 0;
         info->t_cg_ms = ev_ms(4, 6);
         info->t_total_ms = ev_ms(5, 6);
         info->nlevels = (int)lv.size();

@@ -76,6 +76,11 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
     const int l16 = lane & 15, g = lane >> 4;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int arow0 = tr * kTileMN, brow0 = tc * kTileMN;
+    // on a diagonal tile of the lower-triangle product the wave at rows 0-63,
+    // columns 64-127 lies strictly above the diagonal, whose entries the
+    // reduction never reads: it keeps loading and synchronising with the
+    // group but skips its MFMAs (its SIMD time goes to the co-resident group)
+    const bool idle = lower && tr == tc && wr < wc;
 
     // loader: column lk of rows lr + 16 q, q = 0..7
     const int lk = tid & 15, lr = tid >> 4;
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
         const double* A = sA[buf];
         const double* B = sB[buf];
 #pragma unroll
-        for (int s4 = 0; s4 < KB / 4; ++s4) {
+        for (int s4 = 0; s4 < KB / 4 && !idle; ++s4) {
             const int kk = 4 * s4 + g;
             double a[4], b[4];
 #pragma unroll
@@ -147,6 +152,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
         if (c + 1 < nchunk) lstore(buf ^ 1);
         __syncthreads();
     }
+    if (idle) return;
     double* P = partial + (int64_t)split * m * m2;
 #pragma unroll
     for (int r = 0; r < 4; ++r)

@@ -72,12 +72,18 @@ class Context:
         out = torch.empty_like(R) if out is None else out
         return nat.h1w_precond_apply(self.handle, R, out, zmode)
 
+    MODES = {"woodbury": 0, "laplace": nat.H1W_SOLVE_LAPLACE_ONLY, "exact": nat.H1W_SOLVE_EXACT_B}
+
     def gn_solve(self, J, alpha, b=None, d=None, res=None, x=None, rtol=0.0, maxit=0,
-                 zmode=nat.H1W_Z_AUTO, factor=nat.H1W_FACTOR_AUTO):
+                 zmode=nat.H1W_Z_AUTO, factor=nat.H1W_FACTOR_AUTO, mode="woodbury"):
+        """mode: 'woodbury' (the method), 'laplace' (B/alpha only, Algorithm 4's
+        preconditioner) or 'exact' (B = A^-1 by MG-PCG to 1e-12, Algorithm 1's
+        exact Woodbury inverse; FP64 contexts)."""
         import torch
         ref = b if b is not None else d
         x = torch.empty_like(ref) if x is None else x
-        info = nat.h1w_gn_solve(self.handle, J, alpha, x, b, d, res, rtol, maxit, zmode, factor)
+        info = nat.h1w_gn_solve(self.handle, J, alpha, x, b, d, res, rtol, maxit, zmode, factor,
+                                flags=self.MODES[mode])
         self._J = J  # the capacitance left in the context refers to J
         return x, info
 

@@ -385,6 +385,80 @@ def test_alpha_robustness(P):
     assert max(its) <= 15 and max(its) - min(its) <= 3, its
 
 
+# ------------------------------------------------------------------ comparison modes
+@pytest.mark.parametrize("name,prec,rtol", [("square33", "fp64", 1e-10), ("cube17", "fp64", 1e-10),
+                                            ("cube17", "mixed", 1e-8)])
+def test_laplace_only_mode_matches_oracle(P, name, prec, rtol):
+    # Algorithm 4's preconditioner (B / alpha, no Woodbury correction, no
+    # capacitance): the same solution, reached in more iterations.
+    wl, J, b = _bump_problem(name)
+    with P.Context(wl.shape, wl.beta, precision=prec) as ctx:
+        Jd, bd = dev(J), dev(b)
+        x, info = ctx.gn_solve(Jd, wl.alpha, b=bd, rtol=rtol, mode="laplace", maxit=2000)
+        x = host(x)
+        _, infow = ctx.gn_solve(Jd, wl.alpha, b=bd, rtol=rtol)
+    assert info.zmode_used == 0 and info.t_gemm_ms == 0.0
+    assert info.iters > 2 * infow.iters
+    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
+    assert rr <= 1.01 * rtol and abs(rr - info.relres_true) <= 1e-3 * rtol + 1e-14
+    if wl.N <= 1100:  # against the oracle's direct solution (dense cond is cheap here)
+        xs = gn.solve_dense(wl.shape, wl.beta, J, wl.alpha, b)
+        assert np.linalg.norm(x - xs) <= 1.01 * _cond_bound(wl, J) * rr * np.linalg.norm(xs)
+
+
+def test_laplace_only_iterations_grow_as_alpha_shrinks(P):
+    # The robustness contrast of the paper's regularisation sweep: without the
+    # Woodbury correction the iteration count grows with 1/alpha (the m large
+    # eigenvalues of J^T J / alpha); with it the count stays flat.
+    wl, J, b = _bump_problem("square129")
+    lap, wood = [], []
+    with P.Context(wl.shape, wl.beta) as ctx:
+        Jd, bd = dev(J), dev(b)
+        for alpha in [1e-1, 1e-3, 1e-5]:
+            _, il = ctx.gn_solve(Jd, alpha, b=bd, rtol=1e-10, mode="laplace", maxit=4000)
+            _, iw = ctx.gn_solve(Jd, alpha, b=bd, rtol=1e-10)
+            lap.append(il.iters)
+            wood.append(iw.iters)
+    assert lap[0] < lap[1] < lap[2] and lap[2] > 3 * lap[0], lap
+    assert max(wood) - min(wood) <= 2 and max(wood) < lap[0], (wood, lap)
+
+
+@pytest.mark.parametrize("name", ["square33", "cube17", "square129"])
+def test_exact_b_mode_converges_in_one_or_two(P, name):
+    # Algorithm 1's exact Woodbury inverse with the Poisson solve B = A^-1 by
+    # MG-PCG (to 1e-12): the preconditioner is G^-1 up to that tolerance, so CG
+    # needs one iteration, two when the one residual replacement of the
+    # recompute form triggers.
+    wl, J, b = _bump_problem(name)
+    with P.Context(wl.shape, wl.beta) as ctx:
+        x, info = ctx.gn_solve(dev(J), wl.alpha, b=dev(b), rtol=1e-10, mode="exact")
+        x = host(x)
+        assert 1 <= info.iters <= 2
+        with pytest.raises(P.H1WError) as e:  # the exact-B capacitance is not kept
+            ctx.precond_apply(dev(b[None]), zmode=1)
+        assert e.value.status == -8
+    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
+    assert rr <= 1.01e-10
+    if wl.N <= 1100:
+        xs = gn.solve_dense(wl.shape, wl.beta, J, wl.alpha, b)
+        assert np.linalg.norm(x - xs) <= 1.01 * _cond_bound(wl, J) * rr * np.linalg.norm(xs)
+
+
+def test_solve_mode_invalid_combinations(P):
+    wl, J, b = _bump_problem("square33")
+    from paper_2209_02815_amd import _native as nat
+    with P.Context(wl.shape, wl.beta, precision="mixed") as ctx:
+        with pytest.raises(P.H1WError) as e:
+            ctx.gn_solve(dev(J), wl.alpha, b=dev(b), mode="exact")
+        assert e.value.status == -1
+    with P.Context(wl.shape, wl.beta) as ctx:
+        x = torch.empty(wl.N, dtype=torch.float64, device="cuda:0")
+        for flags in (nat.H1W_SOLVE_LAPLACE_ONLY | nat.H1W_SOLVE_EXACT_B, 4):
+            info, st = nat.h1w_gn_solve(ctx.handle, dev(J), wl.alpha, x, dev(b), None, None, 1e-10, 0,
+                                        raise_on_error=False, flags=flags)
+            assert st == -1
+
+
 def test_gn_solve_deterministic(P):
     wl, J, b = _bump_problem("cube17")
     with P.Context(wl.shape, wl.beta) as ctx:
