@@ -33,6 +33,10 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch of 256 uneven 2D instances (h1w_batch_solve)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison solve modes (Laplace-only and exact-B preconditioners)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of 1 GiB (a kernel of known size for PMC counter scaling)")
     return ap.parse_args()
@@ -140,6 +144,43 @@ def cpu_baseline(wl, J, b, threads):
     }
 
 
+def batch_bench(args, threads):
+    """256 independent 2D instances of uneven size (sides {65,129,193,257}, m in
+    [16,128], log-uniform alpha in [1e-5,1e-2]) solved by h1w_batch_solve: FP64
+    and mixed with the executor's 4 workers and the autotuner, and FP64 with one
+    worker (no overlap) for reference. One warmup pass, then the batch is timed."""
+    import torch
+    import h1w_inputs as H
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads()
+    log(f"batch: generating {len(wls)} instances, {sum(w.m for w in wls)} rows of J")
+    items = []
+    for wl in wls:
+        items.append(dict(shape=wl.shape, beta=wl.beta, alpha=wl.alpha,
+                          J=torch.from_numpy(H.j_rows(wl, threads=threads)).to("cuda:0"),
+                          b=torch.from_numpy(H.rhs_b(wl)).to("cuda:0"),
+                          x=torch.zeros(wl.N, dtype=torch.float64, device="cuda:0")))
+    torch.cuda.synchronize()
+    out = {"workload": f"{len(wls)} 2D instances, sides {H.BATCH_DEFAULT['sides']}, m in [16, 128], "
+                       f"alpha log-uniform in [1e-5, 1e-2], beta 1e-2, rtol {args.rtol}",
+           "rows": sum(w.m for w in wls), "nodes": sum(w.N for w in wls)}
+    for label, prec, nw, tune in (("fp64", nat.H1W_FP64, 4, True), ("mixed", nat.H1W_MIXED, 4, True),
+                                  ("fp64_one_worker", nat.H1W_FP64, 1, False)):
+        nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, stats, rep = nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        worst = max(i.relres_true for i in infos)
+        out[label] = {"instances_per_s": len(items) / dt, "ms": 1e3 * dt, "workers": rep.nworkers,
+                      "autotune": tune, "iters_total": int(sum(i.iters for i in infos)),
+                      "worst_relres_true": worst,
+                      "nu_chosen": sorted({rep.tuned[k].nu for k in range(rep.ntuned)}) if tune else None}
+        log(f"batch {label}: {out[label]}")
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -203,8 +244,31 @@ def main():
             "roofline": roof, "kernel_time_share": shares,
         }
         log(f"{mode}: {results[mode]}")
+    # comparison modes on the same system (FP64): the Laplace-only preconditioner
+    # (B / alpha, no Woodbury correction) and the exact Woodbury inverse with
+    # B = A^-1 by MG-PCG; context for the Woodbury preconditioner's robustness
+    compare = None
+    if not args.no_compare:
+        compare = {}
+        with P.Context(wl.shape, wl.beta, precision="fp64") as ctx:
+            for mode, warm, steps in (("exact", 1, 2), ("laplace", 0, 1)):
+                log(f"comparison mode {mode}: warmup {warm}, timing {steps} solve(s)")
+                for _ in range(warm):
+                    ctx.gn_solve(Jd, wl.alpha, b=bd, x=xd, rtol=args.rtol, mode=mode, maxit=20000)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    _, info = ctx.gn_solve(Jd, wl.alpha, b=bd, x=xd, rtol=args.rtol, mode=mode, maxit=20000)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / steps
+                compare[mode] = {"solves_per_s": 1.0 / dt, "ms_per_solve": 1e3 * dt, "iters": info.iters,
+                                 "relres_true": info.relres_true, "t_zbuild_ms": info.t_zbuild_ms,
+                                 "t_cg_ms": info.t_cg_ms}
+                log(f"{mode}: {compare[mode]}")
     del Jd
     torch.cuda.empty_cache()
+
+    batch = None if args.no_batch else batch_bench(args, threads)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -223,6 +287,8 @@ def main():
         "roofline": r64["roofline"],
         "fp64": r64,
         "mixed": results.get("mixed"),
+        "comparison_modes": compare,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

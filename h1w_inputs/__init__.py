@@ -26,7 +26,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "WORKLOADS", "workload", "grid_shape", "num_nodes", "axis_coords",
-    "j_rows", "rhs_b", "paper_data", "rng_for",
+    "j_rows", "rhs_b", "paper_data", "rng_for", "batch_workloads",
 ]
 
 
@@ -83,6 +83,24 @@ WORKLOADS = {
 
 def workload(name: str) -> Workload:
     return WORKLOADS[name]
+
+
+# A batch of independent instances of uneven size: 2D unit squares with sides
+# drawn uniformly from `sides`, m uniform in [m_lo, m_hi], log10(alpha) uniform
+# in [log10 a_lo, log10 a_hi], beta = 1e-2, bump rows (as cube129, in 2D) and
+# b ~ N(0,1). Instance k has workload id batch_id * 100000 + k; the drawing of
+# (side, m, alpha) uses stream 4 of batch_id.
+BATCH_DEFAULT = dict(count=256, sides=(65, 129, 193, 257), m_lo=16, m_hi=128, a_lo=1e-5, a_hi=1e-2)
+
+
+def batch_workloads(count: int = 256, batch_id: int = 5, sides=(65, 129, 193, 257), m_lo: int = 16,
+                    m_hi: int = 128, a_lo: float = 1e-5, a_hi: float = 1e-2) -> list:
+    rng = rng_for(batch_id, 4)
+    side = rng.choice(np.asarray(sides), size=count)
+    m = rng.integers(m_lo, m_hi + 1, size=count)
+    alpha = 10.0 ** rng.uniform(np.log10(a_lo), np.log10(a_hi), size=count)
+    return [Workload(f"batch{batch_id}_{k}", batch_id * 100000 + k, (int(side[k]), int(side[k])), 1e-2,
+                     float(alpha[k]), int(m[k]), "bumps") for k in range(count)]
 
 
 def grid_shape(wl: Workload) -> tuple:

@@ -154,7 +154,9 @@ h1w_status h1w_setup(const h1w_grid_desc* desc, void* hip_stream, h1w_ctx** out)
 /* Free the context and all device memory it owns. NULL is ignored. */
 void h1w_destroy(h1w_ctx* ctx);
 
-/* Message for the last failed call on ctx (valid until the next call). */
+/* Message for the last failed call on ctx (valid until the next call); with
+ * ctx == NULL, of the calling thread's last failed h1w_setup or
+ * h1w_batch_solve. */
 const char* h1w_last_error(const h1w_ctx* ctx);
 
 /* Static description of a status code. */
@@ -267,6 +269,65 @@ typedef struct {
 h1w_status h1w_set_kernel_timing(h1w_ctx* ctx, unsigned mask);
 h1w_status h1w_get_kernel_timing(h1w_ctx* ctx, int kclass, h1w_kstat* out);
 h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Batched solves of many independent Gauss-Newton systems of uneven size
+ * (each one the system of h1w_gn_solve on its own grid, Algorithm 3 with the
+ * multigrid Poisson solver): a native executor overlaps them on one GPU.
+ *
+ * The items are ordered by decreasing work N * (m + 1) and pulled from one
+ * queue by opts.nworkers host threads; each thread owns a HIP stream (default
+ * priority) and one context per (grid, precision, smoothing steps) it meets,
+ * reused by later items of that key. With opts.autotune, the first items of
+ * each (grid, precision, ceil(log2 m)) key are solved with nu = 2, 1 and 3
+ * smoothing steps per side and the later items of the key use the one with
+ * the smallest wall time per N * (m + 1) (the tuning solves are kept as
+ * results). Items of one grid must share beta. All pointers are device
+ * pointers owned by the caller; J, b, x follow h1w_gn_solve (J m x N with
+ * leading dimension ldj, x receives the solution). infos and status (count
+ * entries each, may be NULL) receive each item's diagnostics and status;
+ * the call returns H1W_OK when every item succeeded, else the first failing
+ * item's status (in the queue order), and blocks until all items are done.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int dim;             /* 2 or 3 */
+    int n[3];            /* nodes per axis (n[2] ignored in 2D) */
+    double beta;         /* mass weight of A */
+    double alpha;        /* regularisation weight (> 0) */
+    int m;               /* rows of J (>= 0) */
+    const double* J;     /* m x N, leading dimension ldj (may be NULL if m == 0) */
+    int64_t ldj;
+    const double* b;     /* right-hand side (N) */
+    double* x;           /* solution (N) */
+} h1w_batch_item;
+
+typedef struct {
+    int precision;       /* H1W_FP64 or H1W_MIXED, for every item */
+    int nworkers;        /* host threads / streams (0 -> 4, at most 16) */
+    int autotune;        /* 1: choose the smoothing steps per key as described above */
+    int nu;              /* smoothing steps when not tuned (0 -> 2) */
+    double rtol;         /* as h1w_solve_opts.rtol (0 -> 1e-10) */
+    int maxit;           /* as h1w_solve_opts.maxit (0 -> 500) */
+} h1w_batch_opts;
+
+#define H1W_BATCH_MAX_KEYS 64
+typedef struct {
+    int dim;
+    int n[3];
+    int m_bucket;        /* ceil(log2 m) */
+    int nu;              /* chosen smoothing steps */
+    double ms_per_unit;  /* its wall time per N * (m + 1), in ms */
+} h1w_batch_tuned;
+
+typedef struct {
+    double t_total_ms;   /* wall time of the whole batch */
+    int nworkers;
+    int ntuned;          /* entries of tuned[] (autotune) */
+    h1w_batch_tuned tuned[H1W_BATCH_MAX_KEYS];
+} h1w_batch_report;
+
+h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts* opts,
+                           h1w_info* infos, h1w_status* status, h1w_batch_report* report);
 
 /* ERT sensitivities (Section 4: forward model, adjoint derivative of the
  * pole-pole voltages). Not built in this version: always returns

@@ -26,7 +26,7 @@ EXPORTED = [
     "h1w_setup", "h1w_destroy", "h1w_last_error", "h1w_status_string", "h1w_get_sizes",
     "h1w_operator_apply", "h1w_poisson_solve_batched", "h1w_capacitance_build",
     "h1w_precond_apply", "h1w_gn_solve", "h1w_gn_apply", "h1w_ert_sensitivities",
-    "h1w_set_kernel_timing", "h1w_get_kernel_timing", "h1w_reset_kernel_timing",
+    "h1w_set_kernel_timing", "h1w_get_kernel_timing", "h1w_reset_kernel_timing", "h1w_batch_solve",
 ]
 
 
@@ -50,6 +50,29 @@ class h1w_info(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class h1w_batch_item(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("beta", C.c_double), ("alpha", C.c_double),
+                ("m", C.c_int), ("J", C.c_void_p), ("ldj", C.c_int64), ("b", C.c_void_p), ("x", C.c_void_p)]
+
+
+class h1w_batch_opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("nworkers", C.c_int), ("autotune", C.c_int), ("nu", C.c_int),
+                ("rtol", C.c_double), ("maxit", C.c_int)]
+
+
+H1W_BATCH_MAX_KEYS = 64
+
+
+class h1w_batch_tuned(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("m_bucket", C.c_int), ("nu", C.c_int),
+                ("ms_per_unit", C.c_double)]
+
+
+class h1w_batch_report(C.Structure):
+    _fields_ = [("t_total_ms", C.c_double), ("nworkers", C.c_int), ("ntuned", C.c_int),
+                ("tuned", h1w_batch_tuned * H1W_BATCH_MAX_KEYS)]
 
 
 class h1w_kstat(C.Structure):
@@ -88,6 +111,8 @@ def _load():
         "h1w_set_kernel_timing": (I, [P, C.c_uint]),
         "h1w_get_kernel_timing": (I, [P, I, C.POINTER(h1w_kstat)]),
         "h1w_reset_kernel_timing": (I, [P]),
+        "h1w_batch_solve": (I, [I, C.POINTER(h1w_batch_item), C.POINTER(h1w_batch_opts), C.POINTER(h1w_info),
+                                C.POINTER(C.c_int), C.POINTER(h1w_batch_report)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -252,3 +277,38 @@ def h1w_get_kernel_timing(ctx, kclass: int) -> dict:
 
 def h1w_reset_kernel_timing(ctx):
     _check(ctx, lib.h1w_reset_kernel_timing(ctx))
+
+
+def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotune: bool = False, nu: int = 0,
+                    rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True):
+    """items: list of dicts with shape, beta, alpha, J (CUDA (m, N) float64 or None), b, x.
+    Returns (infos, statuses, report); raises on the first failing item unless raise_on_error is False."""
+    arr = (h1w_batch_item * max(1, len(items)))()
+    for i, it in enumerate(items):
+        shape = tuple(it["shape"])
+        N = 1
+        for nn in shape:
+            N *= int(nn)
+        e = arr[i]
+        e.dim = len(shape)
+        for a, nn in enumerate(shape):
+            e.n[a] = int(nn)
+        e.beta, e.alpha = float(it["beta"]), float(it["alpha"])
+        J = it.get("J")
+        m, ldj = _rows(J, N, "J") if J is not None else (0, N)
+        e.m, e.ldj = m, ldj
+        e.J = None if J is None else J.data_ptr()
+        for name in ("b", "x"):
+            t = it[name]
+            if not t.is_cuda or t.dtype != __import__("torch").float64 or t.numel() != N or not t.is_contiguous():
+                raise ValueError(f"item {i}: {name} must be a contiguous float64 CUDA vector of N entries")
+        e.b, e.x = it["b"].data_ptr(), it["x"].data_ptr()
+    opts = h1w_batch_opts(int(precision), int(nworkers), int(bool(autotune)), int(nu), float(rtol), int(maxit))
+    infos = (h1w_info * max(1, len(items)))()
+    stats = (C.c_int * max(1, len(items)))()
+    rep = h1w_batch_report()
+    st = lib.h1w_batch_solve(len(items), arr, C.byref(opts), infos, stats, C.byref(rep))
+    out = ([infos[i] for i in range(len(items))], [stats[i] for i in range(len(items))], rep)
+    if raise_on_error and st != H1W_OK:
+        raise H1WError(st, lib.h1w_last_error(None).decode())
+    return out

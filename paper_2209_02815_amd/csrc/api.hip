@@ -2,6 +2,7 @@
 // translation of internal errors to status codes; no exception crosses the ABI.
 #include <cmath>
 #include <new>
+#include <vector>
 
 #include "context.h"
 
@@ -308,6 +309,40 @@ h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx) {
         ctx->c.flush_timing();
         for (auto& s : ctx->c.kst) s = h1w_kstat{};
     });
+}
+
+h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts* opts,
+                           h1w_info* infos, h1w_status* status, h1w_batch_report* report) {
+    g_setup_error.clear();
+    h1w_status st = H1W_OK;
+    try {
+        require(count >= 0, "count must be >= 0");
+        require(count == 0 || items != nullptr, "items is NULL");
+        require(opts != nullptr, "opts is NULL");
+        require(opts->precision == H1W_FP64 || opts->precision == H1W_MIXED, "precision must be FP64 or MIXED");
+        require(opts->nworkers >= 0 && opts->nu >= 0 && opts->nu <= 16 && opts->maxit >= 0,
+                "nworkers, nu and maxit must be >= 0 (nu <= 16)");
+        require(std::isfinite(opts->rtol) && opts->rtol >= 0.0, "rtol must be >= 0");
+        std::vector<h1w_status> own;
+        h1w_status* stp = status;
+        if (!stp) {
+            own.assign((size_t)count, H1W_OK);
+            stp = own.data();
+        }
+        h1w::batch_solve(count, items, *opts, infos, stp, report);
+        for (int i = 0; i < count && st == H1W_OK; ++i) st = stp[i];
+    } catch (const h1w::Error& e) {
+        g_setup_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_setup_error = "host allocation failed";
+        return H1W_ENOMEM;
+    } catch (const std::exception& e) {
+        g_setup_error = e.what();
+        return H1W_EINVAL;
+    }
+    if (st != H1W_OK) g_setup_error = std::string("a batch item failed: ") + h1w_status_string(st);
+    return st;
 }
 
 h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double*, int, const int*, int, const int*, const double*,

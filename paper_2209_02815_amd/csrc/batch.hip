@@ -1,0 +1,222 @@
+// Batched Gauss-Newton solves of many independent instances of uneven size
+// (different grids, row counts and regularisation weights): a native executor
+// that overlaps the instances on the GPU, and a small autotuner.
+//
+// Executor: the instances are sorted by decreasing work (N * (m + 1)) and
+// pulled from a shared queue by nworkers host threads. Each thread owns one
+// HIP stream (default priority) and keeps one context per (grid, precision,
+// smoother steps) it has met, so the hierarchy, the coarsest inverse and the
+// device workspace are set up once per key and reused by later instances.
+// The solve of one instance is the library's own h1w_gn_solve path; the
+// threads' streams let the small kernels and host round trips of different
+// instances overlap.
+//
+// Autotuner: for each (grid, precision, row bucket ceil(log2 m)) key the first
+// instances are solved with nu = 2, 1 and 3 smoothing steps per side; the
+// wall time of each, divided by N * (m + 1), ranks the candidates, and the
+// later instances of the key use the fastest. Tuning instances are ordinary
+// solves (their results are kept).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "context.h"
+
+namespace h1w {
+
+namespace {
+
+constexpr int kTuneCandidates[] = {2, 1, 3};
+constexpr int kNumCandidates = 3;
+
+struct GridKey {
+    int dim, n0, n1, n2, precision, nu;
+    bool operator<(const GridKey& o) const {
+        return std::tie(dim, n0, n1, n2, precision, nu) < std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu);
+    }
+};
+
+struct TuneKey {
+    int dim, n0, n1, n2, precision, bucket;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(dim, n0, n1, n2, precision, bucket) <
+               std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.bucket);
+    }
+};
+
+int row_bucket(int m) {
+    int b = 0;
+    while ((1 << b) < std::max(1, m)) ++b;
+    return b;
+}
+
+// Candidate choice for one tuning key, shared by all workers.
+struct TuneState {
+    int issued = 0;                          // tuning solves handed out
+    double best = -1.0;                      // best normalised time so far
+    int best_nu = kTuneCandidates[0];
+    int done = 0;                            // tuning solves finished
+};
+
+struct Worker {
+    hipStream_t stream = nullptr;
+    std::map<GridKey, std::unique_ptr<Ctx>> ctxs;
+};
+
+}  // namespace
+
+void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
+                 h1w_status* status, h1w_batch_report* report) {
+    int device = 0;
+    H1W_HIP(hipGetDevice(&device));
+    const int nworkers = std::clamp(o.nworkers > 0 ? o.nworkers : 4, 1, 16);
+    const int nu_fixed = o.nu > 0 ? o.nu : 2;
+
+    // decreasing work first, so the long solves do not finish last
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto work = [&](int i) {
+        const h1w_batch_item& it = items[i];
+        double nn = 1.0;
+        for (int a = 0; a < it.dim; ++a) nn *= it.n[a];
+        return nn * (it.m + 1);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+
+    std::mutex tune_mu;
+    std::map<TuneKey, TuneState> tune;
+    std::atomic<int> next{0};
+    std::vector<Worker> workers(nworkers);
+    std::vector<std::string> worker_err(nworkers);
+
+    auto choose_nu = [&](const TuneKey& tk, bool& tuning) -> int {
+        tuning = false;
+        if (!o.autotune) return nu_fixed;
+        std::lock_guard<std::mutex> lk(tune_mu);
+        TuneState& ts = tune[tk];
+        if (ts.issued < kNumCandidates) {
+            tuning = true;
+            return kTuneCandidates[ts.issued++];
+        }
+        return ts.best_nu;
+    };
+    auto record = [&](const TuneKey& tk, int nu, double t_norm) {
+        std::lock_guard<std::mutex> lk(tune_mu);
+        TuneState& ts = tune[tk];
+        ++ts.done;
+        if (ts.best < 0.0 || t_norm < ts.best) {
+            ts.best = t_norm;
+            ts.best_nu = nu;
+        }
+    };
+
+    auto run = [&](int w) {
+        Worker& me = workers[w];
+        try {
+            H1W_HIP(hipSetDevice(device));
+            H1W_HIP(hipStreamCreateWithFlags(&me.stream, hipStreamNonBlocking));
+        } catch (const Error& e) {
+            worker_err[w] = e.msg;
+            return;
+        }
+        for (;;) {
+            const int q = next.fetch_add(1);
+            if (q >= count) break;
+            const int i = order[q];
+            const h1w_batch_item& it = items[i];
+            h1w_info inf{};
+            h1w_status st = H1W_OK;
+            try {
+                require(it.dim == 2 || it.dim == 3, "item dim must be 2 or 3");
+                require(it.m >= 0, "item m must be >= 0");
+                require(it.b != nullptr && it.x != nullptr && (it.m == 0 || it.J != nullptr),
+                        "item b, x (and J when m > 0) must not be NULL");
+                const int n2 = it.dim == 3 ? it.n[2] : 1;
+                TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision, row_bucket(it.m)};
+                bool tuning = false;
+                // a later instance whose key is still being tuned uses the default
+                int nu = choose_nu(tk, tuning);
+                if (!tuning && o.autotune) {
+                    std::lock_guard<std::mutex> lk(tune_mu);
+                    if (tune[tk].done < kNumCandidates) nu = nu_fixed;
+                }
+                GridKey gk{it.dim, it.n[0], it.n[1], n2, o.precision, nu};
+                auto& slot = me.ctxs[gk];
+                if (!slot) {
+                    h1w_grid_desc d{};
+                    d.dim = it.dim;
+                    d.n[0] = it.n[0];
+                    d.n[1] = it.n[1];
+                    d.n[2] = n2;
+                    d.beta = it.beta;
+                    d.precision = o.precision;
+                    d.nu = nu;
+                    auto c = std::make_unique<Ctx>();
+                    c->init(d, me.stream);
+                    slot = std::move(c);
+                }
+                require(std::isfinite(it.beta) && it.beta == slot->d.beta,
+                        "items of one grid must share beta within a batch");
+                require(std::isfinite(it.alpha) && it.alpha > 0.0, "item alpha must be finite and > 0");
+                require(it.m == 0 || it.ldj >= slot->N(), "item ldj must be >= N");
+                h1w_solve_opts so{};
+                so.rtol = o.rtol;
+                so.maxit = o.maxit;
+                const auto t0 = std::chrono::steady_clock::now();
+                slot->gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
+                const double ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                if (tuning) record(tk, nu, ms / work(i));
+            } catch (const Error& e) {
+                st = e.st;
+            } catch (const std::bad_alloc&) {
+                st = H1W_ENOMEM;
+            } catch (const std::exception&) {
+                st = H1W_EINVAL;
+            }
+            if (infos) infos[i] = inf;
+            if (status) status[i] = st;
+        }
+    };
+
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::thread> threads;
+    threads.reserve(nworkers);
+    for (int w = 0; w < nworkers; ++w) threads.emplace_back(run, w);
+    for (auto& t : threads) t.join();
+    const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+
+    // tear down after every worker has stopped (buffer release synchronises the device)
+    for (auto& w : workers) {
+        w.ctxs.clear();
+        if (w.stream) (void)hipStreamDestroy(w.stream);
+    }
+    for (const auto& e : worker_err)
+        if (!e.empty()) throw Error{H1W_EHIP, "batch worker setup failed: " + e};
+    if (report) {
+        *report = h1w_batch_report{};
+        report->t_total_ms = total_ms;
+        report->nworkers = nworkers;
+        int k = 0;
+        for (const auto& [tk, ts] : tune) {
+            if (k >= H1W_BATCH_MAX_KEYS) break;
+            h1w_batch_tuned& r = report->tuned[k++];
+            r.dim = tk.dim;
+            r.n[0] = tk.n0;
+            r.n[1] = tk.n1;
+            r.n[2] = tk.n2;
+            r.m_bucket = tk.bucket;
+            r.nu = ts.best_nu;
+            r.ms_per_unit = ts.best;
+        }
+        report->ntuned = k;
+    }
+}
+
+}  // namespace h1w

@@ -124,6 +124,11 @@ template <typename T>
 void launch_vup(hipStream_t s, const Geom& gf, const Geom& gc, int k, const T* F, int64_t ldf, const T* X0,
                 int64_t ldx0, const T* Ec, int64_t ldc, T* Y, int64_t ldy, double wa, double wb);
 
+// batch.hip: the executor behind h1w_batch_solve (throws Error on setup failures;
+// per-item failures go to status[])
+void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
+                 h1w_status* status, h1w_batch_report* report);
+
 // blas.hip
 // partial dot products of npair vector pairs over N entries; returns #parts
 int launch_dots_partial(hipStream_t s, int64_t N, int npair, const double* const* X,

@@ -1,0 +1,100 @@
+"""GPU: the batched executor (h1w_batch_solve) over independent GN systems of
+uneven size, checked item by item against the CPU oracle's FP64 true residual
+and against single-instance solves of the same systems."""
+import numpy as np
+import pytest
+
+import h1w_inputs as H
+from oracle import gn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2209_02815_amd as P
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def small_batch():
+    # uneven 2D instances plus one 3D instance and one without rows
+    wls = H.batch_workloads(count=10, batch_id=7, sides=(17, 33, 65), m_lo=1, m_hi=40)
+    wls.append(H.workload("cube17").with_(name="b3d", wid=700011, alpha=3e-4, m=11))
+    wls.append(H.workload("square33").with_(name="b0", wid=700012, m=0))
+    return wls
+
+
+def make_items(wls):
+    items, host = [], []
+    for wl in wls:
+        J = H.j_rows(wl) if wl.m > 0 else None
+        b = H.rhs_b(wl)
+        items.append(dict(shape=wl.shape, beta=wl.beta, alpha=wl.alpha, J=None if J is None else dev(J),
+                          b=dev(b), x=torch.zeros(wl.N, dtype=torch.float64, device="cuda:0")))
+        host.append((J, b))
+    return items, host
+
+
+@pytest.mark.parametrize("prec,rtol,nworkers", [("fp64", 1e-10, 4), ("mixed", 1e-8, 3), ("fp64", 1e-10, 1)])
+def test_batch_matches_oracle(P, prec, rtol, nworkers):
+    from paper_2209_02815_amd import _native as nat
+    wls = small_batch()
+    items, host = make_items(wls)
+    precision = nat.H1W_FP64 if prec == "fp64" else nat.H1W_MIXED
+    infos, stats, rep = nat.h1w_batch_solve(items, precision=precision, nworkers=nworkers, rtol=rtol)
+    assert all(s == 0 for s in stats) and rep.nworkers == nworkers and rep.t_total_ms > 0
+    for wl, it, (J, b), info in zip(wls, items, host, infos):
+        x = it["x"].cpu().numpy()
+        Jm = J if J is not None else np.zeros((0, wl.N))
+        rr = gn.true_relres(wl.shape, wl.beta, Jm, wl.alpha, b, x)
+        assert rr <= 1.01 * rtol, (wl.name, rr, info.as_dict())
+        assert abs(rr - info.relres_true) <= 1e-3 * rtol + 1e-14
+
+
+def test_batch_equals_single_solves(P):
+    # the executor runs the library's own solve: same iterations and the same
+    # solution as one-at-a-time calls on the same grid settings
+    from paper_2209_02815_amd import _native as nat
+    wls = small_batch()[:6]
+    items, host = make_items(wls)
+    infos, stats, _ = nat.h1w_batch_solve(items, nworkers=4, rtol=1e-10)
+    assert all(s == 0 for s in stats)
+    for wl, it, info in zip(wls, items, infos):
+        with P.Context(wl.shape, wl.beta) as ctx:
+            x, si = ctx.gn_solve(it["J"], wl.alpha, b=it["b"], rtol=1e-10)
+        assert si.iters == info.iters
+        xb = it["x"].cpu().numpy()
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(xb - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_batch_autotune_reports_choices(P):
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads(count=14, batch_id=8, sides=(33, 65), m_lo=20, m_hi=30)
+    items, host = make_items(wls)
+    infos, stats, rep = nat.h1w_batch_solve(items, nworkers=2, autotune=True, rtol=1e-10)
+    assert all(s == 0 for s in stats)
+    keys = {(rep.tuned[k].n[0], rep.tuned[k].m_bucket) for k in range(rep.ntuned)}
+    assert keys == {(wl.shape[0], int(np.ceil(np.log2(wl.m)))) for wl in wls}
+    assert all(rep.tuned[k].nu in (1, 2, 3) and rep.tuned[k].ms_per_unit > 0 for k in range(rep.ntuned))
+    for wl, it, (J, b) in zip(wls, items, host):
+        rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy())
+        assert rr <= 1.01e-10
+
+
+def test_batch_bad_item_fails_alone(P):
+    from paper_2209_02815_amd import _native as nat
+    wls = small_batch()[:4]
+    items, host = make_items(wls)
+    items[2]["alpha"] = -1.0
+    infos, stats, _ = nat.h1w_batch_solve(items, nworkers=2, rtol=1e-10, raise_on_error=False)
+    assert stats[2] == nat.H1W_EINVAL
+    assert [s for k, s in enumerate(stats) if k != 2] == [0, 0, 0]
+    with pytest.raises(P.H1WError) as e:
+        nat.h1w_batch_solve(items, nworkers=2, rtol=1e-10)
+    assert e.value.status == nat.H1W_EINVAL
