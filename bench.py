@@ -46,30 +46,33 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# kernel class -> (bound, unit, kernel symbol(s) in a rocprofv3 kernel trace)
+# kernel class -> (bound, kernel symbol(s) in a rocprofv3 kernel trace, source file under csrc/)
 KERNELS = {
-    "smooth": ("hbm", "k_march<*, 3, 2>"), "smooth_first": ("hbm", "k_smooth_first"),
-    "residual": ("hbm", "k_march<*, 3, 1>"), "restrict": ("hbm", "k_restrict"), "prolong": ("hbm", "k_prolong_add"),
-    "coarse": ("hbm", "k_coarse_solve"), "gemm": ("mfma", "k_cap_gemm"), "jv": ("hbm", "k_rows_dot"),
-    "jtv": ("hbm", "k_jt_u_t / k_jt_plain / k_z_stored"), "factor": ("mfma", "k_blk_*"),
-    "trsv": ("hbm", "k_blk_trsv"), "apply": ("hbm", "k_march<*, 3, 0> / k_apply_plus_dot"),
-    "vdown": ("hbm", "k_down"), "vup": ("hbm", "k_up"),
+    "smooth": ("hbm", "k_march<*, 3, 2>", "stencil.hip"), "smooth_first": ("hbm", "k_smooth_first", "stencil.hip"),
+    "residual": ("hbm", "k_march<*, 3, 1>", "stencil.hip"), "restrict": ("hbm", "k_restrict", "stencil.hip"),
+    "prolong": ("hbm", "k_prolong_add", "stencil.hip"), "coarse": ("hbm", "k_coarse_solve", "stencil.hip"),
+    "gemm": ("mfma", "k_cap_gemm", "gemm.hip"), "jv": ("hbm", "k_rows_dot", "blas.hip"),
+    "jtv": ("hbm", "k_jt_u_t / k_jt_plain / k_z_stored", "blas.hip"), "factor": ("mfma", "k_blk_*", "blocked.hip"),
+    "trsv": ("hbm", "k_blk_trsv", "blocked.hip"), "apply": ("hbm", "k_march<*, 3, 0> / k_apply_plus_dot", "stencil.hip"),
+    "vdown": ("hbm", "k_down", "vfused.hip"), "vup": ("hbm", "k_up", "vfused.hip"),
 }
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix
 
 
-def source_sha() -> str:
+def source_sha(cls: str) -> str:
+    """Hash of the source file holding the kernel class (and the device helpers
+    it includes): PMC traffic recorded for a kernel stays valid while it is unchanged."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2209_02815_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in (KERNELS[cls][2], "devutil.h"):
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def roofline(cls: str, st: dict) -> dict:
-    bound, _ = KERNELS[cls]
+    bound = KERNELS[cls][0]
     avg_ms = st["ms"] / st["launches"]
     if bound == "mfma":
         achieved = st["flops"] / st["launches"] / (avg_ms * 1e-3) / 1e12
@@ -81,7 +84,7 @@ def roofline(cls: str, st: dict) -> dict:
     tp = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tp):
         t = json.load(open(tp))
-        if t.get("class") == cls and t.get("source_sha") == source_sha():
+        if t.get("class") == cls and t.get("source_sha") == source_sha(cls):
             traffic = t.get("traffic_bytes_per_launch")
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": traffic, "kernel": cls, "symbol": KERNELS[cls][1], "launches": st["launches"],
