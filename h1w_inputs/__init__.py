@@ -14,7 +14,16 @@ localised fields, and an N-vector right-hand side.
 Seeding: every array is drawn from numpy's PCG64 seeded with
 SeedSequence([workload_id, stream, row]); stream 0 = rows of J (noise),
 1 = right-hand side b, 2 = bump parameters of the rows of J, 3 = paper-form
-data d and res. Per-row seeds let a large J be regenerated in row chunks.
+data d and res, 4 = instance parameters of an uneven batch, 5 = the white noise
+of an ERT conductivity field. Per-row seeds let a large J be regenerated in
+row chunks.
+
+ERT surveys (the forward problem of Section 4 that produces J): a structured
+grid of the unit cube, a log-conductivity field drawn as a Gaussian random
+field, and a lattice of electrodes on the top face (z = 1) whose pole sources
+and pole-pole pairs define the measurements. Only the layout and the random
+field are drawn here; the forward map, the geometric factors and the
+sensitivities belong to the solvers.
 """
 from __future__ import annotations
 
@@ -27,6 +36,7 @@ import numpy as np
 __all__ = [
     "Workload", "WORKLOADS", "workload", "grid_shape", "num_nodes", "axis_coords",
     "j_rows", "rhs_b", "paper_data", "rng_for", "batch_workloads",
+    "ErtSurvey", "ert_survey", "ert_logsig", "ERT_DIRICHLET_DEFAULT",
 ]
 
 
@@ -189,3 +199,99 @@ def paper_data(wl: Workload) -> tuple:
     d = np.ascontiguousarray(d).reshape(-1) + 0.1 * g.standard_normal(wl.N)
     res = g.standard_normal(wl.m)
     return d, res
+
+
+# ---------------------------------------------------------------- ERT surveys
+
+# Faces with u = 0, one bit each: x = 0, x = 1, y = 0, y = 1, z = 0, z = 1.
+# Default: every face but the top (z = 1), where the electrodes sit (Neumann).
+ERT_DIRICHLET_DEFAULT = 0x1F
+
+
+@dataclasses.dataclass(frozen=True)
+class ErtSurvey:
+    """A pole-pole ERT survey on the n^3 unit-cube grid.
+
+    electrodes  node indices (x fastest) of the electrodes on the top face,
+                ordered with the lattice's x index fastest
+    ex, ey      their lattice node coordinates (ix, iy); iz = n - 1
+    pairs       (n_meas, 2) int32, every electrode pair (a, b) with a < b
+                (source a, receiver b; the return electrode is at infinity)
+    wid         workload id of the conductivity field's seed
+    """
+    name: str
+    wid: int
+    shape: tuple
+    electrodes: np.ndarray
+    ex: np.ndarray
+    ey: np.ndarray
+    pairs: np.ndarray
+    mask: int = ERT_DIRICHLET_DEFAULT
+    log10_mean: float = -2.0
+    log10_std: float = 0.5
+    corr: float = 0.2
+
+    @property
+    def N(self) -> int:
+        return num_nodes(self.shape)
+
+    @property
+    def n_src(self) -> int:
+        return len(self.electrodes)
+
+    @property
+    def n_meas(self) -> int:
+        return len(self.pairs)
+
+
+def ert_survey(n: int = 65, nex: int = 8, ney: int = 4, spacing: int | None = None, wid: int = 3,
+               name: str | None = None) -> ErtSurvey:
+    """Centred nex x ney electrode lattice with `spacing` nodes between
+    neighbours on the top face of the n^3 grid. n = 65 with the defaults gives
+    ix in {11, 17, ..., 53}, iy in {23, 29, 35, 41}: 32 electrodes, 496 pairs."""
+    if spacing is None:
+        spacing = max(1, round(6 * (n - 1) / 64))
+    c = (n - 1) / 2
+    ox, oy = c - spacing * (nex - 1) / 2, c - spacing * (ney - 1) / 2
+    if ox != int(ox) or oy != int(oy):
+        raise ValueError("lattice not centred on nodes: make (nex-1)*spacing and (ney-1)*spacing even")
+    ix = int(ox) + spacing * np.arange(nex)
+    iy = int(oy) + spacing * np.arange(ney)
+    if ix[0] < 1 or iy[0] < 1 or ix[-1] > n - 2 or iy[-1] > n - 2:
+        raise ValueError("electrode lattice does not fit inside the top face")
+    ex = np.tile(ix, ney)
+    ey = np.repeat(iy, nex)
+    nodes = ex + n * (ey + n * (n - 1))
+    a, b = np.triu_indices(len(nodes), k=1)
+    pairs = np.stack([a, b], axis=1).astype(np.int32)
+    return ErtSurvey(name or f"ert{n}", wid, (n, n, n), nodes.astype(np.int64), ex, ey, pairs)
+
+
+def ert_logsig(sv: ErtSurvey) -> np.ndarray:
+    """Natural-log conductivity at the nodes (N,), x fastest.
+
+    log10(sigma) is a Gaussian random field with covariance
+    0.25 exp(-r^2 / (2 corr^2)) sampled by circulant embedding: the covariance
+    is evaluated on a periodic grid of 2 n_d nodes per axis with the grid's
+    spacing (wrapped distances), white noise from stream 5 is filtered by the
+    square root of its non-negative spectrum, the first n_d nodes per axis
+    are kept, and the result is shifted and scaled to the survey's mean and
+    standard deviation exactly."""
+    shape = sv.shape
+    M = [2 * n for n in shape]
+    r2 = 0.0
+    for ax in range(len(shape)):
+        k = np.arange(M[ax])
+        dist = np.minimum(k, M[ax] - k) / (shape[ax] - 1)
+        # array axes are (z, y, x): axis ax of the grid is array axis -1 - ax
+        view = [1] * len(shape)
+        view[len(shape) - 1 - ax] = M[ax]
+        r2 = r2 + (dist ** 2).reshape(view)
+    cov = 0.25 * np.exp(-r2 / (2.0 * sv.corr ** 2))
+    lam = np.maximum(np.fft.fftn(cov).real, 0.0)
+    noise = rng_for(sv.wid, 5).standard_normal(tuple(reversed(M)))
+    field = np.fft.ifftn(np.sqrt(lam) * np.fft.fftn(noise)).real
+    crop = field[tuple(slice(0, n) for n in reversed(shape))]
+    crop = (crop - crop.mean()) / crop.std()
+    log10 = sv.log10_mean + sv.log10_std * crop
+    return np.ascontiguousarray(np.log(10.0) * log10).reshape(-1)

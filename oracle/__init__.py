@@ -18,9 +18,12 @@ definitions state:
   gn         the GN system (alpha*A + J^T J) x = b by three independent routes,
              the paper's right-hand side and closed-form update, and the
              Woodbury preconditioner apply                          (gn)
+  ert        the ERT forward map of Section 4 on the structured grid: the
+             conductance operator, pole fields by sparse LU, pole-pole
+             voltages and their sensitivities by the adjoint formula  (ert)
 
 Each function names the passage of Blechta & Ernst (arXiv 2209.02815) it
 follows. Pins (closed forms, invariants, special cases, brute force) live in
 tests/test_oracle_*.py; no function here is "parity unpinned".
 """
-from . import operator, poisson, multigrid, gn  # noqa: F401
+from . import operator, poisson, multigrid, gn, ert  # noqa: F401
