@@ -68,6 +68,7 @@ typedef enum { H1W_DT_F64 = 0, H1W_DT_F32 = 1 } h1w_dtype;
 typedef enum { H1W_VCYCLE_ONCE = 0, H1W_MG_SOLVE = 1 } h1w_poisson_mode;
 typedef enum { H1W_Z_AUTO = 0, H1W_Z_STORED = 1, H1W_Z_RECOMPUTE = 2 } h1w_zmode;
 typedef enum { H1W_FACTOR_AUTO = 0, H1W_FACTOR_CHOL = 1, H1W_FACTOR_LU = 2 } h1w_factor;
+typedef enum { H1W_OP_H1GRAM = 0, H1W_OP_ERT = 1 } h1w_opkind;
 
 /* Grid and multigrid description (h1w_setup). Zero fields take defaults. */
 typedef struct {
@@ -83,6 +84,12 @@ typedef struct {
                             (or that cannot be halved); 0 -> 729 (3D) / 289 (2D) */
     int rhs_chunk;       /* right-hand sides per batched V-cycle launch (0 -> auto) */
     unsigned flags;      /* H1W_FLAG_* bits, other bits must be 0 */
+    int op;              /* h1w_opkind: H1W_OP_H1GRAM (the regularisation operator A
+                            above) or H1W_OP_ERT (the conductivity operator of the
+                            ERT forward problem, see the ERT section below) */
+    unsigned dirichlet_mask; /* ERT only: bit f set = u = 0 on face f, faces ordered
+                            x=0, x=1, y=0, y=1, z=0, z=1 (bits 0..5), at least one
+                            bit; 0 -> 0x1f (every face but the top z = 1) */
 } h1w_grid_desc;
 
 /* grid_desc.flags: always stream Z in FP64 capacitance builds (Z is built in
@@ -256,7 +263,9 @@ typedef enum {
     H1W_K_APPLY = 11,      /* operator apply A x (incl. the CG q = alpha A p + t) */
     H1W_K_VDOWN = 12,      /* fused 3D pass: two pre-smoothing steps, residual, restriction */
     H1W_K_VUP = 13,        /* fused 3D pass: interpolation, two post-smoothing steps */
-    H1W_K_NCLASS = 14
+    H1W_K_ERT_STENCIL = 14,/* ERT operator: apply, residual, smoothing steps, restriction */
+    H1W_K_ERT_SENS = 15,   /* ERT pairwise-gradient sensitivities (J) and their transpose product */
+    H1W_K_NCLASS = 16
 } h1w_kclass;
 
 typedef struct {
@@ -329,13 +338,72 @@ typedef struct {
 h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts* opts,
                            h1w_info* infos, h1w_status* status, h1w_batch_report* report);
 
-/* ERT sensitivities (Section 4: forward model, adjoint derivative of the
- * pole-pole voltages). Not built in this version: always returns
- * H1W_ENOTIMPL without touching its arguments. */
+/* ------------------------------------------------------------------------
+ * ERT forward map and sensitivities (Section 4: eq. (model), the pole-pole
+ * voltages of eqs. (ert_qoi2)/(ert_qoi_scaling) and their derivative,
+ * eq. (ert_qoi_derivative), in the log parametrisation m = log sigma).
+ *
+ * A context created with desc.op = H1W_OP_ERT (3D, FP64, beta ignored) holds
+ * the operator -div(sigma grad u) on the grid of the unit cube in its
+ * vertex-centred finite-volume form: the edge (p, q) along axis d carries the
+ * conductance (sigma_p + sigma_q)/2 * (dual-face area)/h_d, the dual-face area
+ * being the product of the other axes' h, halved for each of them on which
+ * the edge lies in a boundary face; nodes on the faces of dirichlet_mask have
+ * u = 0 (their rows are the identity, their couplings are removed), the other
+ * faces have zero normal flux. A unit pole source at node a is the nodal load
+ * e_a, so u_a = A_sigma^{-1} e_a. The pole-pole voltage of pair i = (a, b)
+ * (return electrodes at infinity, as the paper's B electrode) is
+ *     g_i = k_i u_a(x_b),   k_i = 2 pi |x_a - x_b|   (default geometric factor),
+ * and its sensitivity to m_j, the adjoint field of b being u_b (A symmetric):
+ *     J[i, j] = -k_i sum_{edges (j, q)} (sigma_j/2) (area/h) (u_a(j) - u_a(q)) (u_b(j) - u_b(q)).
+ * Multigrid: the same geometric V-cycle as the H1 context (Chebyshev-Jacobi
+ * smoothing, R = P^T with the Dirichlet nodes masked, multilinear P), with
+ * the coarse conductivities recomputed from the fine ones by full-weighting
+ * averages at every h1w_ert_set_conductivity, rediscretised coarse operators
+ * and a dense coarsest inverse (at most 128 nodes) computed on the device.
+ * h1w_operator_apply (F64) and h1w_poisson_solve_batched (F64) work on an
+ * ERT context once a conductivity is set (ESTATE before); the Gauss-Newton
+ * entry points need an H1 context (EINVAL on an ERT one).
+ * Index arrays (src_node, pair) are device int32 arrays; they are copied to
+ * the host and validated before any kernel runs, so these calls synchronise.
+ * ------------------------------------------------------------------------ */
+
+/* sigma = exp(logsig) at the N nodes (device FP64); builds every level's
+ * coefficients and the coarsest inverse on the device. ENUMERIC if some
+ * sigma is not finite and positive. */
+h1w_status h1w_ert_set_conductivity(h1w_ctx* ctx, const double* logsig);
+
+/* Pole fields, voltages and (optionally) the sensitivity matrix.
+ * logsig      N log-conductivities, or NULL to keep the current conductivity
+ * src_node    n_src node indices of the pole sources (1 <= n_src <= 64; not on
+ *             a Dirichlet face)
+ * pair        n_meas x 2 indices into src_node: (a, b), a != b
+ * kgeo        n_meas geometric factors, or NULL for 2 pi |x_a - x_b|
+ * g_out       n_meas voltages g_i (may be NULL)
+ * J_out       n_meas x N sensitivities, row-major with leading dimension
+ *             ldj >= N (may be NULL)
+ * U_out       n_src x N pole fields u_a, leading dimension ldu >= N (may be
+ *             NULL: the context keeps them for h1w_ert_vjp with U = NULL)
+ * opts        rtol (0 -> 1e-12) and maxit (0 -> 500) of the batched
+ *             MG-preconditioned CG for the n_src fields (all in one batch)
+ * info        iters (largest over the fields), relres_true (worst field
+ *             residual), t_zbuild_ms (conductivity setup), t_cg_ms (field
+ *             solves), t_gemm_ms (voltages and sensitivities), t_total_ms.
+ * Returns ENOCONV if a field does not reach rtol in maxit iterations. Blocks
+ * the host. */
 h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double* logsig, int n_src,
                                  const int* src_node, int n_meas, const int* pair,
                                  const double* kgeo, double* g_out, double* J_out,
-                                 int64_t ldj, const h1w_solve_opts* opts, h1w_info* info);
+                                 int64_t ldj, double* U_out, int64_t ldu,
+                                 const h1w_solve_opts* opts, h1w_info* info);
+
+/* grad = J^T gbar (N, FP64) without forming J, for the current conductivity
+ * and the pole fields U (n_src x N, leading dimension ldu; NULL = the fields
+ * of the last h1w_ert_sensitivities call on this context). src_node is
+ * needed only when kgeo is NULL. */
+h1w_status h1w_ert_vjp(h1w_ctx* ctx, int n_src, const int* src_node, const double* U,
+                       int64_t ldu, int n_meas, const int* pair, const double* kgeo,
+                       const double* gbar, double* grad);
 
 #ifdef __cplusplus
 }

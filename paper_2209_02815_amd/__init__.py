@@ -5,9 +5,11 @@ parameter identification (Blechta & Ernst, arXiv 2209.02815).
 
 solved by conjugate gradients with the Woodbury preconditioner around a
 batched geometric-multigrid V-cycle, all in the HIP library libh1w.so
-(C ABI in include/h1w.h). This package is the Python binding: argument
+(C ABI in include/h1w.h), plus the ERT forward map and its adjoint that
+produce J (Section 4). This package is the Python binding: argument
 marshalling with torch tensors that live on the GPU.
 """
 from ._native import *  # noqa: F401,F403
 from ._native import H1WError, h1w_info, lib  # noqa: F401
 from .solver import Context  # noqa: F401
+from .ert import ErtContext, ert_voltages  # noqa: F401

@@ -20,20 +20,22 @@ H1W_Z_AUTO, H1W_Z_STORED, H1W_Z_RECOMPUTE = 0, 1, 2
 H1W_FACTOR_AUTO, H1W_FACTOR_CHOL, H1W_FACTOR_LU = 0, 1, 2
 
 KCLASS = ["smooth", "smooth_first", "residual", "restrict", "prolong", "coarse", "gemm", "jv", "jtv",
-          "factor", "trsv", "apply", "vdown", "vup"]
+          "factor", "trsv", "apply", "vdown", "vup", "ert_stencil", "ert_sens"]
 
 EXPORTED = [
     "h1w_setup", "h1w_destroy", "h1w_last_error", "h1w_status_string", "h1w_get_sizes",
     "h1w_operator_apply", "h1w_poisson_solve_batched", "h1w_capacitance_build",
     "h1w_precond_apply", "h1w_gn_solve", "h1w_gn_apply", "h1w_ert_sensitivities",
     "h1w_set_kernel_timing", "h1w_get_kernel_timing", "h1w_reset_kernel_timing", "h1w_batch_solve",
+    "h1w_ert_set_conductivity", "h1w_ert_vjp",
 ]
 
 
 class h1w_grid_desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("beta", C.c_double), ("precision", C.c_int),
                 ("nu", C.c_int), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
-                ("coarse_max", C.c_int64), ("rhs_chunk", C.c_int), ("flags", C.c_uint)]
+                ("coarse_max", C.c_int64), ("rhs_chunk", C.c_int), ("flags", C.c_uint),
+                ("op", C.c_int), ("dirichlet_mask", C.c_uint)]
 
 
 class h1w_solve_opts(C.Structure):
@@ -106,8 +108,10 @@ def _load():
         "h1w_precond_apply": (I, [P, I, P, I64, P, I64, I]),
         "h1w_gn_solve": (I, [P, I, P, I64, D, P, P, P, P, C.POINTER(h1w_solve_opts), C.POINTER(h1w_info)]),
         "h1w_gn_apply": (I, [P, I, P, I64, D, P, P]),
-        "h1w_ert_sensitivities": (I, [P, P, I, P, I, P, P, P, P, I64, C.POINTER(h1w_solve_opts),
+        "h1w_ert_sensitivities": (I, [P, P, I, P, I, P, P, P, P, I64, P, I64, C.POINTER(h1w_solve_opts),
                                       C.POINTER(h1w_info)]),
+        "h1w_ert_set_conductivity": (I, [P, P]),
+        "h1w_ert_vjp": (I, [P, I, P, P, I64, I, P, P, P, P]),
         "h1w_set_kernel_timing": (I, [P, C.c_uint]),
         "h1w_get_kernel_timing": (I, [P, I, C.POINTER(h1w_kstat)]),
         "h1w_reset_kernel_timing": (I, [P]),
@@ -164,10 +168,12 @@ H1W_FLAG_STREAM_Z = 1
 H1W_FLAG_UNFUSED_VCYCLE = 2
 H1W_SOLVE_LAPLACE_ONLY = 1
 H1W_SOLVE_EXACT_B = 2
+H1W_OP_H1GRAM, H1W_OP_ERT = 0, 1
 
 
 def h1w_setup(shape, beta: float, precision: int = H1W_FP64, nu: int = 0, cheb=(0.0, 0.0),
-              coarse_max: int = 0, rhs_chunk: int = 0, stream=None, flags: int = 0):
+              coarse_max: int = 0, rhs_chunk: int = 0, stream=None, flags: int = 0, op: int = H1W_OP_H1GRAM,
+              dirichlet_mask: int = 0):
     """Create a context; returns the opaque handle (c_void_p)."""
     d = h1w_grid_desc()
     d.dim = len(shape)
@@ -176,6 +182,7 @@ def h1w_setup(shape, beta: float, precision: int = H1W_FP64, nu: int = 0, cheb=(
     d.beta, d.precision, d.nu = float(beta), int(precision), int(nu)
     d.cheb_lo, d.cheb_hi = float(cheb[0]), float(cheb[1])
     d.coarse_max, d.rhs_chunk, d.flags = int(coarse_max), int(rhs_chunk), int(flags)
+    d.op, d.dirichlet_mask = int(op), int(dirichlet_mask)
     if stream is None:
         import torch
         stream = torch.cuda.current_stream().cuda_stream
@@ -260,9 +267,56 @@ def h1w_gn_apply(ctx, J, alpha: float, x, y):
     return y
 
 
-def h1w_ert_sensitivities(ctx, *args, **kwargs):
-    st = lib.h1w_ert_sensitivities(ctx, None, 0, None, 0, None, None, None, None, 0, None, None)
-    _check(ctx, st)
+def _ints(t, what: str, cols: int = 1):
+    import torch
+    if t is None:
+        return 0
+    if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous int32 CUDA tensor")
+    if cols > 1 and (t.dim() != 2 or t.shape[1] != cols):
+        raise ValueError(f"{what} must have shape (n, {cols})")
+    return t.shape[0]
+
+
+def h1w_ert_set_conductivity(ctx, logsig):
+    N, _ = h1w_get_sizes(ctx)
+    _rows(logsig, N, "logsig")
+    _check(ctx, lib.h1w_ert_set_conductivity(ctx, _ptr(logsig)))
+
+
+def h1w_ert_sensitivities(ctx, src_node, pair, logsig=None, kgeo=None, g_out=None, J_out=None, U_out=None,
+                          rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True):
+    """Pole fields, voltages and sensitivities of an ERT context (see the
+    header); src_node: int32 (n_src,), pair: int32 (n_meas, 2) CUDA tensors."""
+    N, _ = h1w_get_sizes(ctx)
+    n_src = _ints(src_node, "src_node")
+    n_meas = _ints(pair, "pair", 2)
+    if logsig is not None:
+        _rows(logsig, N, "logsig")
+    _, ldj = _rows(J_out, N, "J_out")
+    _, ldu = _rows(U_out, N, "U_out")
+    o = h1w_solve_opts(float(rtol), int(maxit), 0, 0, 0, 0)
+    info = h1w_info()
+    st = lib.h1w_ert_sensitivities(ctx, _ptr(logsig), n_src, _ptr(src_node), n_meas, _ptr(pair), _ptr(kgeo),
+                                   _ptr(g_out), _ptr(J_out), ldj, _ptr(U_out), ldu, C.byref(o), C.byref(info))
+    if raise_on_error:
+        _check(ctx, st)
+        return info
+    return info, st
+
+
+def h1w_ert_vjp(ctx, pair, gbar, grad, U=None, n_src: int | None = None, src_node=None, kgeo=None):
+    """grad = J^T gbar for the current conductivity and the fields U (None:
+    the fields kept by the last h1w_ert_sensitivities call)."""
+    N, _ = h1w_get_sizes(ctx)
+    n_meas = _ints(pair, "pair", 2)
+    k, ldu = _rows(U, N, "U")
+    if U is None:
+        k = int(n_src if n_src is not None else _ints(src_node, "src_node"))
+    _rows(grad, N, "grad")
+    _check(ctx, lib.h1w_ert_vjp(ctx, k, _ptr(src_node), _ptr(U), ldu, n_meas, _ptr(pair), _ptr(kgeo),
+                                _ptr(gbar), _ptr(grad)))
+    return grad
 
 
 def h1w_set_kernel_timing(ctx, mask: int):

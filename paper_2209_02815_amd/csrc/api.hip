@@ -51,6 +51,41 @@ bool overlap(const void* a, int64_t lda, const void* b, int64_t ldb, int k, int6
 
 }  // namespace
 
+namespace {
+
+// copies a device int32 array of n entries to the host (synchronous)
+std::vector<int> fetch_ints(h1w::Ctx& c, const int* d, size_t n) {
+    std::vector<int> h(n);
+    if (n) {
+        H1W_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+    }
+    return h;
+}
+
+void check_sources(h1w::Ctx& c, int n_src, const int* src_node) {
+    require(n_src >= 1 && n_src <= 64, "n_src must be in [1, 64]");
+    need_ptr(src_node, 4, "src_node");
+    for (int v : fetch_ints(c, src_node, (size_t)n_src)) {
+        require(v >= 0 && v < c.N(), "src_node entry out of range");
+        require(!h1w::ert_on_dirichlet_host(c.lv[0], c.dmask, v), "a source node lies on a Dirichlet face");
+    }
+}
+
+void check_pairs(h1w::Ctx& c, int n_src, int n_meas, const int* pair) {
+    require(n_meas >= 0, "n_meas must be >= 0");
+    if (n_meas == 0) return;
+    need_ptr(pair, 4, "pair");
+    const std::vector<int> h = fetch_ints(c, pair, (size_t)2 * n_meas);
+    for (int i = 0; i < n_meas; ++i) {
+        const int a = h[2 * i], b = h[2 * i + 1];
+        require(a >= 0 && a < n_src && b >= 0 && b < n_src, "pair index out of [0, n_src)");
+        require(a != b, "a pair needs two different electrodes");
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* h1w_status_string(h1w_status s) {
@@ -120,6 +155,15 @@ h1w_status h1w_operator_apply(h1w_ctx* ctx, int k, const void* X, int64_t ldx, v
         need_ptr(Y, es, "Y");
         require(ldx >= n && ldy >= n, "leading dimensions must be >= N");
         require(!overlap(X, ldx, Y, ldy, k, n, es), "X and Y overlap");
+        if (c.ert) {
+            require(dtype == H1W_DT_F64, "an ERT context is FP64: dtype must be H1W_DT_F64");
+            if (!c.ert_ready) throw h1w::Error{H1W_ESTATE, "no conductivity set (h1w_ert_set_conductivity)"};
+            for (int r0 = 0; r0 < k; r0 += 65535) {
+                const int kk = std::min(65535, k - r0);
+                c.apply_A(kk, (const double*)X + (int64_t)r0 * ldx, ldx, (double*)Y + (int64_t)r0 * ldy, ldy);
+            }
+            return;
+        }
         for (int r0 = 0; r0 < k; r0 += 65535) {
             const int kk = std::min(65535, k - r0);
             if (dtype == H1W_DT_F64)
@@ -154,7 +198,10 @@ h1w_status h1w_poisson_solve_batched(h1w_ctx* ctx, int k, const void* F, int64_t
         need_ptr(X, es, "X");
         require(ldf >= n && ldx >= n, "leading dimensions must be >= N");
         require(!overlap(F, ldf, X, ldx, k, n, es), "F and X overlap");
-        if (mode == H1W_VCYCLE_ONCE) {
+        if (c.ert && !c.ert_ready) throw h1w::Error{H1W_ESTATE, "no conductivity set (h1w_ert_set_conductivity)"};
+        if (mode == H1W_VCYCLE_ONCE && c.ert) {
+            c.vcycle_B(k, (const double*)F, ldf, (double*)X, ldx);
+        } else if (mode == H1W_VCYCLE_ONCE) {
             if (c.fp32)
                 c.vcycle<float>(k, (const float*)F, ldf, (float*)X, ldx);
             else
@@ -176,6 +223,7 @@ h1w_status h1w_capacitance_build(h1w_ctx* ctx, int m, const double* J, int64_t l
     }
     return guarded(ctx, [&] {
         auto& c = ctx->c;
+        require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
         c.have_cap = false;
         require(m >= 1 && m <= 4096, "m must be in [1, 4096]");
@@ -214,6 +262,7 @@ h1w_status h1w_precond_apply(h1w_ctx* ctx, int k, const double* R, int64_t ldr, 
     if (!ctx) return H1W_EINVAL;
     return guarded(ctx, [&] {
         auto& c = ctx->c;
+        require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
         require(k >= 0, "k must be >= 0");
         if (k == 0) return;
@@ -234,6 +283,7 @@ h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
     }
     return guarded(ctx, [&] {
         auto& c = ctx->c;
+        require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
         require(m >= 0 && m <= 4096, "m must be in [0, 4096]");
         if (m > 0) {
@@ -269,6 +319,7 @@ h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
     if (!ctx) return H1W_EINVAL;
     return guarded(ctx, [&] {
         auto& c = ctx->c;
+        require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
         require(m >= 0, "m must be >= 0");
         if (m > 0) {
@@ -345,10 +396,114 @@ h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_bat
     return st;
 }
 
-h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double*, int, const int*, int, const int*, const double*,
-                                 double*, double*, int64_t, const h1w_solve_opts*, h1w_info*) {
-    if (ctx) ctx->c.err = "h1w_ert_sensitivities is not built in this version";
-    return H1W_ENOTIMPL;
+h1w_status h1w_ert_set_conductivity(h1w_ctx* ctx, const double* logsig) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        require(c.ert, "h1w_ert_set_conductivity needs an ERT context (op = H1W_OP_ERT)");
+        need_ptr(logsig, 8, "logsig");
+        c.ert_set_conductivity(logsig);
+    });
+}
+
+h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double* logsig, int n_src, const int* src_node, int n_meas,
+                                 const int* pair, const double* kgeo, double* g_out, double* J_out, int64_t ldj,
+                                 double* U_out, int64_t ldu, const h1w_solve_opts* opts, h1w_info* info) {
+    if (!ctx) return H1W_EINVAL;
+    if (info) {
+        *info = h1w_info{};
+        info->failed_pivot = -1;
+    }
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        require(c.ert, "h1w_ert_sensitivities needs an ERT context (op = H1W_OP_ERT)");
+        const int64_t n = c.N();
+        check_sources(c, n_src, src_node);
+        check_pairs(c, n_src, n_meas, pair);
+        if (kgeo && n_meas > 0) need_ptr(kgeo, 8, "kgeo");
+        if (g_out && n_meas > 0) need_ptr(g_out, 8, "g_out");
+        if (J_out && n_meas > 0) {
+            need_ptr(J_out, 8, "J_out");
+            require(ldj >= n, "ldj must be >= N");
+        }
+        if (U_out) {
+            need_ptr(U_out, 8, "U_out");
+            require(ldu >= n, "ldu must be >= N");
+            require(!(J_out && n_meas > 0 && overlap(U_out, ldu, J_out, ldj, std::min(n_src, n_meas), n, 8)),
+                    "U_out and J_out overlap");
+        }
+        h1w_solve_opts o{};
+        if (opts) o = *opts;
+        require(std::isfinite(o.rtol) && o.rtol >= 0.0, "rtol must be >= 0");
+        require(o.maxit >= 0, "maxit must be >= 0");
+        if (logsig) need_ptr(logsig, 8, "logsig");
+        c.ev_reserve();
+        c.ev_record(0);
+        if (logsig) c.ert_set_conductivity(logsig);
+        if (!c.ert_ready) throw h1w::Error{H1W_ESTATE, "no conductivity set: pass logsig"};
+        c.ev_record(1);
+        double* U = U_out;
+        int64_t lu = ldu;
+        if (!U) {
+            c.efield.reserve((size_t)n_src * c.pitch[0] * sizeof(double));
+            U = c.efield.as<double>();
+            lu = c.pitch[0];
+        }
+        c.efield_n = 0;
+        c.ert_fields(n_src, src_node, U, lu, o.rtol > 0.0 ? o.rtol : 1e-12, o.maxit > 0 ? o.maxit : 500, info);
+        if (!U_out) c.efield_n = n_src;
+        c.ev_record(2);
+        if (n_meas > 0 && (g_out || J_out)) {
+            const double* k = c.ert_kgeo(n_meas, pair, src_node, kgeo);
+            if (g_out) c.ert_measure(n_meas, pair, src_node, k, U, lu, g_out);
+            if (J_out) c.ert_sens(n_src, U, lu, n_meas, pair, k, J_out, ldj, nullptr, nullptr);
+        }
+        c.ev_record(3);
+        c.sync();
+        c.flush_timing();
+        if (info) {
+            info->t_zbuild_ms = c.ev_ms(0, 1);
+            info->t_cg_ms = c.ev_ms(1, 2);
+            info->t_gemm_ms = c.ev_ms(2, 3);
+            info->t_total_ms = c.ev_ms(0, 3);
+            info->nlevels = (int)c.lv.size();
+        }
+    });
+}
+
+h1w_status h1w_ert_vjp(h1w_ctx* ctx, int n_src, const int* src_node, const double* U, int64_t ldu, int n_meas,
+                       const int* pair, const double* kgeo, const double* gbar, double* grad) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        require(c.ert, "h1w_ert_vjp needs an ERT context (op = H1W_OP_ERT)");
+        if (!c.ert_ready) throw h1w::Error{H1W_ESTATE, "no conductivity set"};
+        const int64_t n = c.N();
+        require(n_src >= 1 && n_src <= 64, "n_src must be in [1, 64]");
+        check_pairs(c, n_src, n_meas, pair);
+        need_ptr(grad, 8, "grad");
+        if (!U) {
+            if (c.efield_n != n_src)
+                throw h1w::Error{H1W_ESTATE, "no kept pole fields with n_src rows (pass U)"};
+            U = c.efield.as<double>();
+            ldu = c.pitch[0];
+        } else {
+            need_ptr(U, 8, "U");
+            require(ldu >= n, "ldu must be >= N");
+        }
+        if (n_meas == 0) {
+            h1w::launch_fill(c.stream, n, 0.0, grad);
+            return;
+        }
+        need_ptr(gbar, 8, "gbar");
+        if (kgeo)
+            need_ptr(kgeo, 8, "kgeo");
+        else
+            check_sources(c, n_src, src_node);
+        const double* k = c.ert_kgeo(n_meas, pair, src_node, kgeo);
+        c.ert_sens(n_src, U, ldu, n_meas, pair, k, nullptr, 0, gbar, grad);
+        c.sync();
+    });
 }
 
 }  // extern "C"

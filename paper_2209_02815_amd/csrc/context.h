@@ -11,6 +11,11 @@
 
 namespace h1w {
 
+// coefficient arrays of one ERT level (each N_l long, pitch-aligned)
+struct ErtLevel {
+    double *sig, *D, *cx, *cy, *cz;
+};
+
 struct Ctx {
     h1w_grid_desc d{};
     int dim = 0;
@@ -84,6 +89,29 @@ struct Ctx {
     double exact_rtol = 1e-12;
     void mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, double rtol, int maxit,
                   h1w_info* info);
+    // Y = A X with the context's operator (FP64; the H1 Gram operator or the ERT one)
+    void apply_A(int k, const double* X, int64_t ldx, double* Y, int64_t ldy);
+
+    // ERT context (op = H1W_OP_ERT): conductivity operator, see ert.hip
+    bool ert = false;
+    unsigned dmask = 0;              // Dirichlet faces
+    bool ert_ready = false;          // a conductivity has been set
+    std::vector<int64_t> eoff;       // offset of each level's coefficient block in ecoef
+    DevBuf ecoef;                    // per level: sigma, D, cx, cy, cz
+    DevBuf efs, ekg, efield;         // unit loads, geometric factors, kept pole fields
+    int efield_n = 0;                // rows held by efield
+    ErtLevel ert_level(int l) const;
+    void ert_validate();
+    void ert_init();
+    void ert_set_conductivity(const double* logsig);
+    void ert_apply(int k, const double* X, int64_t ldx, double* Y, int64_t ldy);
+    void ert_vcycle_chunk(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
+    void ert_fields(int n_src, const int* src, double* U, int64_t ldu, double rtol, int maxit, h1w_info* info);
+    const double* ert_kgeo(int n_meas, const int* pair, const int* src, const double* kgeo);
+    void ert_measure(int n_meas, const int* pair, const int* src, const double* k, const double* U, int64_t ldu,
+                     double* g);
+    void ert_sens(int n_src, const double* U, int64_t ldu, int n_meas, const int* pair, const double* k, double* J,
+                  int64_t ldj, const double* gbar, double* grad);
 
     void capacitance_build(int m, const double* J, int64_t ldj, double alpha, int factor, h1w_info* info);
     void solve_S(double* x);

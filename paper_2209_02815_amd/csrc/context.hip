@@ -97,7 +97,10 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     require(dim == 2 || dim == 3, "dim must be 2 or 3");
     int n[3] = {d.n[0], d.n[1], dim == 3 ? d.n[2] : 1};
     for (int a = 0; a < dim; ++a) require(n[a] >= 2, "every n[d] must be >= 2");
-    require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
+    require(d.op == H1W_OP_H1GRAM || d.op == H1W_OP_ERT, "op must be H1W_OP_H1GRAM or H1W_OP_ERT");
+    ert = d.op == H1W_OP_ERT;
+    require(ert || d.dirichlet_mask == 0, "dirichlet_mask is for ERT contexts only");
+    if (!ert) require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
     require(d.precision == H1W_FP64 || d.precision == H1W_MIXED, "precision must be H1W_FP64 or H1W_MIXED");
     require(d.nu >= 0 && d.nu <= 16, "nu must be in [0, 16]");
     require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE)) == 0, "unknown bits in flags");
@@ -109,7 +112,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
         d.cheb_hi = 2.0;
     }
     require(d.cheb_lo > 0.0 && d.cheb_hi > d.cheb_lo && std::isfinite(d.cheb_hi), "need 0 < cheb_lo < cheb_hi");
-    if (d.coarse_max == 0) d.coarse_max = dim == 3 ? 729 : 289;
+    if (d.coarse_max == 0) d.coarse_max = ert ? 125 : (dim == 3 ? 729 : 289);
     fp32 = d.precision == H1W_MIXED;
     const int64_t N0 = (int64_t)n[0] * n[1] * n[2];
     require(N0 < (int64_t(1) << 31), "grid too large: N must be < 2^31");
@@ -118,7 +121,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     lv.clear();
     int cur[3] = {n[0], n[1], n[2]};
     for (;;) {
-        lv.push_back(make_geom(dim, cur, d.beta));
+        lv.push_back(make_geom(dim, cur, ert ? 0.0 : d.beta));
         const Geom& g = lv.back();
         if (g.N <= d.coarse_max) break;
         bool ok = true;
@@ -127,6 +130,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
         for (int a = 0; a < dim; ++a) cur[a] = (cur[a] - 1) / 2 + 1;
     }
     Nc = lv.back().N;
+    if (ert) ert_validate();
     require(Nc <= 4096, "coarsest level has " + std::to_string(Nc) +
                             " nodes (> 4096): use n_d = 2^k*c + 1 so the grid can be halved, or lower coarse_max");
 
@@ -135,6 +139,21 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     const double pi = 3.14159265358979323846;
     for (int k = 0; k < d.nu; ++k)
         w[k] = 1.0 / (0.5 * (d.cheb_hi + d.cheb_lo) + 0.5 * (d.cheb_hi - d.cheb_lo) * std::cos(pi * (2 * k + 1) / (2.0 * d.nu)));
+
+    pitch.resize(lv.size());
+    for (size_t l = 0; l < lv.size(); ++l) pitch[l] = cdiv(lv[l].N, 64) * 64;
+    chunk = d.rhs_chunk > 0 ? d.rhs_chunk : (int)std::clamp<int64_t>((int64_t(1) << 26) / N0, 1, 1024);
+    H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
+    scal.reserve(64 * sizeof(double));
+    iflag.reserve(16 * sizeof(int));
+    cpart_elems = coarse_part_elems(Nc);
+    if (cpart_elems) cpart.reserve(cpart_elems * sizeof(double));
+    if (ert) {
+        // the coarsest inverse depends on the conductivity: built on the device
+        // by h1w_ert_set_conductivity
+        ert_init();
+        return;
+    }
 
     // dense inverse of the coarsest operator, symmetrised so that the device
     // kernel may read it by columns
@@ -149,22 +168,13 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     std::vector<float> inv32(inv.begin(), inv.end());
     cinv32.reserve(inv32.size() * sizeof(float));
     H1W_HIP(hipMemcpy(cinv32.p, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
-    cpart_elems = coarse_part_elems(Nc);
-    if (cpart_elems) cpart.reserve(cpart_elems * sizeof(double));
 
     fused = dim == 3 && d.nu == 2 && lv.size() >= 2 && !(d.flags & H1W_FLAG_UNFUSED_VCYCLE);
     for (size_t l = 0; fused && l + 1 < lv.size(); ++l) fused = fused_levels_ok(lv[l], lv[l + 1]);
 
-    pitch.resize(lv.size());
-    for (size_t l = 0; l < lv.size(); ++l) pitch[l] = cdiv(lv[l].N, 64) * 64;
-    chunk = d.rhs_chunk > 0 ? d.rhs_chunk : (int)std::clamp<int64_t>((int64_t(1) << 26) / N0, 1, 1024);
-
     deflate = fp32;
     wsum = 1.0;
     for (int a = 0; a < dim; ++a) wsum *= double(n[a] - 1);  // sum of the trapezoid weights
-    H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
-    scal.reserve(64 * sizeof(double));
-    iflag.reserve(16 * sizeof(int));
 }
 
 Ctx::~Ctx() {
@@ -322,6 +332,13 @@ void Ctx::apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
 
 // y = B r for FP64 vectors in the context's V-cycle precision.
 void Ctx::vcycle_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
+    if (ert) {
+        for (int r0 = 0; r0 < k; r0 += chunk) {
+            const int kk = std::min(chunk, k - r0);
+            ert_vcycle_chunk(kk, F + (int64_t)r0 * ldf, ldf, X + (int64_t)r0 * ldx, ldx);
+        }
+        return;
+    }
     if (!fp32) {
         vcycle<double>(k, F, ldf, X, ldx);
         return;
@@ -359,6 +376,13 @@ void Ctx::vcycle_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) 
 }
 
 // ============================================================ MG-preconditioned CG (Poisson)
+
+void Ctx::apply_A(int k, const double* X, int64_t ldx, double* Y, int64_t ldy) {
+    if (ert)
+        ert_apply(k, X, ldx, Y, ldy);
+    else
+        launch_apply<double>(stream, dim, lv[0], k, X, ldx, Y, ldy, 1.0);
+}
 
 void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, double rtol, int maxit,
                    h1w_info* info) {
@@ -416,7 +440,7 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
                 if (info) info->iters = std::max(max_iters, it);
                 throw Error{H1W_ENOCONV, "MG-PCG did not converge in maxit iterations"};
             }
-            launch_apply<double>(stream, dim, lv[0], kk, Pv, P, Q, P, 1.0);
+            apply_A(kk, Pv, P, Q, P);
             launch_batched_dots(stream, kk, n, Pv, P, Q, P, pp, dpq);
             fetch(dpq, pq);
             for (int r = 0; r < kk; ++r) {
@@ -454,7 +478,7 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
             launch_batched_p(stream, kk, n, db, Zv, P, Pv, P, dact);
         }
         // verify with the true residual
-        launch_apply<double>(stream, dim, lv[0], kk, Xc, ldx, Q, P, 1.0);
+        apply_A(kk, Xc, ldx, Q, P);
         for (int r = 0; r < kk; ++r)
             launch_sub(stream, n, Fc + (int64_t)r * ldf, Q + (int64_t)r * P, R + (int64_t)r * P);
         launch_batched_dots(stream, kk, n, R, P, R, P, pp, dnrm);

@@ -1,0 +1,633 @@
+// ERT forward operator, its multigrid hierarchy and the pole-pole
+// sensitivities (Section 4: eq. (model), eqs. (ert_qoi2), (ert_qoi_scaling)
+// and (ert_qoi_derivative) with m = log sigma) on a structured 3D grid.
+//
+// Operator: vertex-centred finite volumes. Edge (p, q) along axis d carries
+// c_pq = (sigma_p + sigma_q)/2 * g_pq with g_pq = (dual-face area)/h_d, the
+// area being the product of the other two spacings, each halved when the edge
+// lies in a boundary face normal to that axis. Per level we store, for every
+// node p, the diagonal D_p = sum of the conductances of all its edges (1 on
+// a Dirichlet node) and the couplings cx_p, cy_p, cz_p of its edges to p+x,
+// p+y, p+z (0 when either end is a Dirichlet node or the edge leaves the
+// grid), so that (A u)_p = D_p u_p - sum_q c_pq u_q is symmetric and u stays
+// exactly 0 on the Dirichlet nodes.
+//
+// Multigrid: coarse conductivities are full-weighting averages of the finer
+// level's, recomputed at every conductivity update; each level is
+// rediscretised; restriction is P^T (the finite-volume scaling of the
+// operator is h^(d-2), so no 2^-d factor) with coarse Dirichlet nodes set to
+// zero; the coarsest level (at most kErtCoarseMax nodes) is inverted densely
+// by Gauss-Jordan elimination in LDS by one work-group.
+//
+// Sensitivities: for node j and the six edges (j, q) around it,
+// J[i, j] = -k_i sum_e w_e (u_a(j) - u_a(q)) (u_b(j) - u_b(q)),
+// w_e = sigma_j g_e / 2 (the derivative of c_jq with respect to m_j), for
+// measurement i = (a, b). A work-group stages the edge differences of every
+// source field for TN consecutive nodes in LDS and then writes TN consecutive
+// entries of each row of J (coalesced), or accumulates sum_i gbar_i J[i, j].
+#include <algorithm>
+#include <cmath>
+
+#include "context.h"
+
+namespace h1w {
+
+namespace {
+
+struct EG {  // level geometry for the ERT kernels
+    int nx, ny, nz;
+    int64_t N;
+    double hx, hy, hz;
+    unsigned mask;
+};
+
+EG make_eg(const Geom& g, unsigned mask) {
+    return EG{g.nx, g.ny, g.nz, g.N, 1.0 / (g.nx - 1), 1.0 / (g.ny - 1), 1.0 / (g.nz - 1), mask};
+}
+
+__device__ __forceinline__ bool on_dirichlet(const EG& g, int i, int j, int l) {
+    return ((g.mask & 1u) && i == 0) || ((g.mask & 2u) && i == g.nx - 1) || ((g.mask & 4u) && j == 0) ||
+           ((g.mask & 8u) && j == g.ny - 1) || ((g.mask & 16u) && l == 0) || ((g.mask & 32u) && l == g.nz - 1);
+}
+
+__device__ __forceinline__ double endw(int i, int n) { return (i == 0 || i == n - 1) ? 0.5 : 1.0; }
+
+// (dual-face area)/h of the x, y and z edges at node (i, j, l)
+__device__ __forceinline__ double geom_x(const EG& g, int j, int l) {
+    return g.hy * g.hz / g.hx * endw(j, g.ny) * endw(l, g.nz);
+}
+__device__ __forceinline__ double geom_y(const EG& g, int i, int l) {
+    return g.hx * g.hz / g.hy * endw(i, g.nx) * endw(l, g.nz);
+}
+__device__ __forceinline__ double geom_z(const EG& g, int i, int j) {
+    return g.hx * g.hy / g.hz * endw(i, g.nx) * endw(j, g.ny);
+}
+
+__device__ __forceinline__ void split(const EG& g, int64_t p, int& i, int& j, int& l) {
+    i = (int)(p % g.nx);
+    const int64_t t = p / g.nx;
+    j = (int)(t % g.ny);
+    l = (int)(t / g.ny);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ert_sigma(int64_t N, const double* __restrict__ logsig,
+                                                      double* __restrict__ sig, int* __restrict__ flag) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= N) return;
+    const double s = exp(logsig[p]);
+    sig[p] = s;
+    if (!(s > 0.0 && s <= 1.79e308)) flag[0] = 1;
+}
+
+// coarse node (I, J, L) <- weighted mean of the fine nodes around (2I, 2J, 2L)
+// with weights prod_d (1 or 1/2), normalised by the weights inside the grid
+__global__ __launch_bounds__(kBlock) void k_ert_coarsen(EG gf, EG gc, const double* __restrict__ sf,
+                                                        double* __restrict__ sc) {
+    const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (P >= gc.N) return;
+    int I, J, L;
+    split(gc, P, I, J, L);
+    double acc = 0.0, ws = 0.0;
+    for (int c = -1; c <= 1; ++c) {
+        const int l = 2 * L + c;
+        if (l < 0 || l >= gf.nz) continue;
+        for (int b = -1; b <= 1; ++b) {
+            const int j = 2 * J + b;
+            if (j < 0 || j >= gf.ny) continue;
+            for (int a = -1; a <= 1; ++a) {
+                const int i = 2 * I + a;
+                if (i < 0 || i >= gf.nx) continue;
+                const double w = (a ? 0.5 : 1.0) * (b ? 0.5 : 1.0) * (c ? 0.5 : 1.0);
+                acc += w * sf[i + (int64_t)gf.nx * (j + (int64_t)gf.ny * l)];
+                ws += w;
+            }
+        }
+    }
+    sc[P] = acc / ws;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ert_coeffs(EG g, const double* __restrict__ sig, double* __restrict__ D,
+                                                       double* __restrict__ cx, double* __restrict__ cy,
+                                                       double* __restrict__ cz) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= g.N) return;
+    int i, j, l;
+    split(g, p, i, j, l);
+    const int64_t PX = 1, PY = g.nx, PZ = (int64_t)g.nx * g.ny;
+    const bool dp = on_dirichlet(g, i, j, l);
+    const double s0 = sig[p];
+    double dsum = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
+    const double gx = geom_x(g, j, l), gy = geom_y(g, i, l), gz = geom_z(g, i, j);
+    if (i < g.nx - 1) {
+        const double c = 0.5 * (s0 + sig[p + PX]) * gx;
+        dsum += c;
+        vx = (dp || on_dirichlet(g, i + 1, j, l)) ? 0.0 : c;
+    }
+    if (i > 0) dsum += 0.5 * (s0 + sig[p - PX]) * gx;
+    if (j < g.ny - 1) {
+        const double c = 0.5 * (s0 + sig[p + PY]) * gy;
+        dsum += c;
+        vy = (dp || on_dirichlet(g, i, j + 1, l)) ? 0.0 : c;
+    }
+    if (j > 0) dsum += 0.5 * (s0 + sig[p - PY]) * gy;
+    if (l < g.nz - 1) {
+        const double c = 0.5 * (s0 + sig[p + PZ]) * gz;
+        dsum += c;
+        vz = (dp || on_dirichlet(g, i, j, l + 1)) ? 0.0 : c;
+    }
+    if (l > 0) dsum += 0.5 * (s0 + sig[p - PZ]) * gz;
+    D[p] = dp ? 1.0 : dsum;
+    cx[p] = vx;
+    cy[p] = vy;
+    cz[p] = vz;
+}
+
+enum { kErtApply = 0, kErtResidual = 1, kErtSmooth = 2, kErtFirst = 3 };
+
+// one pass over a batch: APPLY Y = A X; RESIDUAL Y = F - A X;
+// SMOOTH Y = X + w D^-1 (F - A X); FIRST Y = w D^-1 F
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_ert_step(EG g, ErtLevel c, const double* __restrict__ F, int64_t ldf,
+                                                     const double* __restrict__ X, int64_t ldx,
+                                                     double* __restrict__ Y, int64_t ldy, double w) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= g.N) return;
+    const int64_t r = blockIdx.y;
+    const double d = c.D[p];
+    if (MODE == kErtFirst) {
+        Y[r * ldy + p] = w * F[r * ldf + p] / d;
+        return;
+    }
+    int i, j, l;
+    split(g, p, i, j, l);
+    const int64_t PY = g.nx, PZ = (int64_t)g.nx * g.ny;
+    const double* x = X + r * ldx;
+    double s = 0.0;
+    if (i < g.nx - 1) s += c.cx[p] * x[p + 1];
+    if (i > 0) s += c.cx[p - 1] * x[p - 1];
+    if (j < g.ny - 1) s += c.cy[p] * x[p + PY];
+    if (j > 0) s += c.cy[p - PY] * x[p - PY];
+    if (l < g.nz - 1) s += c.cz[p] * x[p + PZ];
+    if (l > 0) s += c.cz[p - PZ] * x[p - PZ];
+    const double x0 = x[p];
+    const double ax = d * x0 - s;
+    if (MODE == kErtApply) {
+        Y[r * ldy + p] = ax;
+    } else if (MODE == kErtResidual) {
+        Y[r * ldy + p] = F[r * ldf + p] - ax;
+    } else {
+        Y[r * ldy + p] = x0 + w * (F[r * ldf + p] - ax) / d;
+    }
+}
+
+// Fc = P^T R on the coarse nodes that are not on a Dirichlet face (0 there)
+__global__ __launch_bounds__(kBlock) void k_ert_restrict(EG gf, EG gc, const double* __restrict__ R, int64_t ldr,
+                                                         double* __restrict__ Fc, int64_t ldc) {
+    const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (P >= gc.N) return;
+    const int64_t r = blockIdx.y;
+    int I, J, L;
+    split(gc, P, I, J, L);
+    double acc = 0.0;
+    if (!on_dirichlet(gc, I, J, L)) {
+        const double* rr = R + r * ldr;
+        for (int c = -1; c <= 1; ++c) {
+            const int l = 2 * L + c;
+            if (l < 0 || l >= gf.nz) continue;
+            for (int b = -1; b <= 1; ++b) {
+                const int j = 2 * J + b;
+                if (j < 0 || j >= gf.ny) continue;
+                double row = 0.0;
+                for (int a = -1; a <= 1; ++a) {
+                    const int i = 2 * I + a;
+                    if (i < 0 || i >= gf.nx) continue;
+                    row += (a ? 0.5 : 1.0) * rr[i + (int64_t)gf.nx * (j + (int64_t)gf.ny * l)];
+                }
+                acc += ((b ? 0.5 : 1.0) * (c ? 0.5 : 1.0)) * row;
+            }
+        }
+    }
+    Fc[r * ldc + P] = acc;
+}
+
+// Dense inverse of the coarsest operator by Gauss-Jordan elimination without
+// pivoting (the operator is symmetric positive definite), in LDS, one
+// work-group. Writes the symmetrised inverse; flag[0] = 1 on a non-positive
+// or non-finite pivot.
+constexpr int kErtCoarseMax = 128;
+constexpr int kGJThreads = 256;
+__global__ __launch_bounds__(kGJThreads) void k_ert_coarse_inverse(EG g, ErtLevel c, double* __restrict__ Cinv,
+                                                                   int* __restrict__ flag) {
+    __shared__ double a[kErtCoarseMax * kErtCoarseMax];
+    __shared__ double prow[kErtCoarseMax], pcol[kErtCoarseMax];
+    const int n = (int)g.N;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < n * n; t += kGJThreads) a[t] = 0.0;
+    __syncthreads();
+    const int PY = g.nx, PZ = g.nx * g.ny;
+    for (int p = tid; p < n; p += kGJThreads) {
+        int i, j, l;
+        split(g, p, i, j, l);
+        double* row = a + p * n;
+        row[p] = c.D[p];
+        if (i < g.nx - 1) row[p + 1] = -c.cx[p];
+        if (i > 0) row[p - 1] = -c.cx[p - 1];
+        if (j < g.ny - 1) row[p + PY] = -c.cy[p];
+        if (j > 0) row[p - PY] = -c.cy[p - PY];
+        if (l < g.nz - 1) row[p + PZ] = -c.cz[p];
+        if (l > 0) row[p - PZ] = -c.cz[p - PZ];
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        double piv = a[k * n + k];
+        if (!(piv > 0.0 && piv <= 1.79e308)) {
+            if (tid == 0) flag[1] = 1;
+            piv = 1.0;
+        }
+        const double inv = 1.0 / piv;
+        for (int t = tid; t < n; t += kGJThreads) {
+            prow[t] = a[k * n + t] * inv;
+            pcol[t] = a[t * n + k];
+        }
+        __syncthreads();
+        for (int t = tid; t < n * n; t += kGJThreads) {
+            const int i = t / n, j = t - i * n;
+            if (i == k)
+                a[t] = (j == k) ? inv : prow[j];
+            else
+                a[t] = (j == k) ? -pcol[i] * inv : a[t] - pcol[i] * prow[j];
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < n * n; t += kGJThreads) {
+        const int i = t / n, j = t - i * n;
+        Cinv[t] = 0.5 * (a[i * n + j] + a[j * n + i]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ert_unit_loads(int64_t N, const int* __restrict__ src,
+                                                           double* __restrict__ F, int64_t ldf) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= N) return;
+    const int r = blockIdx.y;
+    F[(int64_t)r * ldf + p] = (p == (int64_t)src[r]) ? 1.0 : 0.0;
+}
+
+// k_i = 2 pi |x_a - x_b| from the node coordinates of the two electrodes
+__global__ __launch_bounds__(kBlock) void k_ert_kgeo(EG g, int n_meas, const int* __restrict__ pair,
+                                                     const int* __restrict__ src, double* __restrict__ k) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_meas) return;
+    int ia, ja, la, ib, jb, lb;
+    split(g, src[pair[2 * t]], ia, ja, la);
+    split(g, src[pair[2 * t + 1]], ib, jb, lb);
+    const double dx = (ia - ib) * g.hx, dy = (ja - jb) * g.hy, dz = (la - lb) * g.hz;
+    k[t] = 2.0 * 3.14159265358979323846 * sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ert_meas(int n_meas, const int* __restrict__ pair,
+                                                     const int* __restrict__ src, const double* __restrict__ k,
+                                                     const double* __restrict__ U, int64_t ldu,
+                                                     double* __restrict__ gout) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_meas) return;
+    const int a = pair[2 * t], b = pair[2 * t + 1];
+    gout[t] = k[t] * U[(int64_t)a * ldu + src[b]];
+}
+
+// Pairwise-gradient sensitivities. TN nodes per work-group, NS sources at most
+// (NS * TN = 1024); the 6 x n_src x TN edge differences sit in LDS.
+constexpr int kSensThreads = 256;
+template <int TN, bool VJP>
+__global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* __restrict__ sig, int n_src,
+                                                           const double* __restrict__ U, int64_t ldu, int n_meas,
+                                                           const int* __restrict__ pair,
+                                                           const double* __restrict__ k, double* __restrict__ J,
+                                                           int64_t ldj, const double* __restrict__ gbar,
+                                                           double* __restrict__ grad) {
+    constexpr int NS = 1024 / TN;
+    constexpr int G = kSensThreads / TN;  // measurement groups
+    __shared__ double dl[6 * NS * TN];
+    __shared__ double we[6 * TN];
+    __shared__ double red[VJP ? G * TN : 1];
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * TN;
+    const int64_t PY = g.nx, PZ = (int64_t)g.nx * g.ny;
+
+    // edge differences of every field at the TN nodes
+    for (int q = tid; q < n_src * TN; q += kSensThreads) {
+        const int s = q / TN, t = q - s * TN;
+        const int64_t p = j0 + t;
+        double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (p < g.N) {
+            int i, j, l;
+            split(g, p, i, j, l);
+            const double* u = U + (int64_t)s * ldu;
+            const double u0 = u[p];
+            if (i < g.nx - 1) d[0] = u0 - u[p + 1];
+            if (i > 0) d[1] = u0 - u[p - 1];
+            if (j < g.ny - 1) d[2] = u0 - u[p + PY];
+            if (j > 0) d[3] = u0 - u[p - PY];
+            if (l < g.nz - 1) d[4] = u0 - u[p + PZ];
+            if (l > 0) d[5] = u0 - u[p - PZ];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) dl[(e * NS + s) * TN + t] = d[e];
+    }
+    if (tid < TN) {
+        const int64_t p = j0 + tid;
+        double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (p < g.N) {
+            int i, j, l;
+            split(g, p, i, j, l);
+            const double hs = 0.5 * sig[p];
+            const double gx = hs * geom_x(g, j, l), gy = hs * geom_y(g, i, l), gz = hs * geom_z(g, i, j);
+            if (i < g.nx - 1) w[0] = gx;
+            if (i > 0) w[1] = gx;
+            if (j < g.ny - 1) w[2] = gy;
+            if (j > 0) w[3] = gy;
+            if (l < g.nz - 1) w[4] = gz;
+            if (l > 0) w[5] = gz;
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) we[e * TN + tid] = w[e];
+    }
+    __syncthreads();
+
+    const int t = tid % TN, grp = tid / TN;
+    const int64_t p = j0 + t;
+    double w[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) w[e] = we[e * TN + t];
+    double acc_all = 0.0;
+    for (int i = grp; i < n_meas; i += G) {
+        const int a = pair[2 * i], b = pair[2 * i + 1];
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) acc += w[e] * dl[(e * NS + a) * TN + t] * dl[(e * NS + b) * TN + t];
+        if (VJP) {
+            acc_all += gbar[i] * k[i] * acc;
+        } else if (p < g.N) {
+            J[(int64_t)i * ldj + p] = -k[i] * acc;
+        }
+    }
+    if (VJP) {
+        red[grp * TN + t] = acc_all;
+        __syncthreads();
+        if (tid < TN && p < g.N) {
+            double s = 0.0;
+            for (int q = 0; q < G; ++q) s += red[q * TN + tid];
+            grad[p] = -s;
+        }
+    }
+}
+
+void launch_step(hipStream_t s, int mode, const EG& g, const ErtLevel& c, int k, const double* F, int64_t ldf,
+                 const double* X, int64_t ldx, double* Y, int64_t ldy, double w) {
+    if (k <= 0) return;
+    const dim3 grid((unsigned)cdiv(g.N, kBlock), (unsigned)k);
+    switch (mode) {
+        case kErtApply:
+            hipLaunchKernelGGL(k_ert_step<kErtApply>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+            break;
+        case kErtResidual:
+            hipLaunchKernelGGL(k_ert_step<kErtResidual>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+            break;
+        case kErtSmooth:
+            hipLaunchKernelGGL(k_ert_step<kErtSmooth>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+            break;
+        default:
+            hipLaunchKernelGGL(k_ert_step<kErtFirst>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+    }
+    H1W_LAUNCHED();
+}
+
+}  // namespace
+
+// ============================================================ context side
+
+ErtLevel Ctx::ert_level(int l) const {
+    double* b = ecoef.as<double>() + eoff[l];
+    const int64_t P = pitch[l];
+    return ErtLevel{b, b + P, b + 2 * P, b + 3 * P, b + 4 * P};
+}
+
+// host-only checks of an ERT description (before any device call)
+void Ctx::ert_validate() {
+    require(dim == 3, "ERT contexts are 3D");
+    require(d.precision == H1W_FP64, "ERT contexts are FP64");
+    require(d.flags == 0, "flags must be 0 for an ERT context");
+    require(std::isfinite(d.beta), "beta must be finite (it is ignored by ERT contexts)");
+    dmask = d.dirichlet_mask ? d.dirichlet_mask : 0x1Fu;
+    require((dmask & ~0x3Fu) == 0, "dirichlet_mask has bits above bit 5");
+    require(Nc <= kErtCoarseMax, "ERT coarsest level has " + std::to_string(Nc) + " nodes (> " +
+                                     std::to_string(kErtCoarseMax) +
+                                     "): use n_d = 2^k*c + 1 so the grid can be halved, or lower coarse_max");
+}
+
+void Ctx::ert_init() {
+    eoff.resize(lv.size());
+    int64_t tot = 0;
+    for (size_t l = 0; l < lv.size(); ++l) {
+        eoff[l] = tot;
+        tot += 5 * pitch[l];
+    }
+    ecoef.reserve((size_t)tot * sizeof(double));
+    cinv64.reserve((size_t)Nc * Nc * sizeof(double));
+}
+
+void Ctx::ert_set_conductivity(const double* logsig) {
+    const int L = (int)lv.size();
+    ert_ready = false;
+    H1W_HIP(hipMemsetAsync(iflag.p, 0, 2 * sizeof(int), stream));
+    {
+        const ErtLevel c0 = ert_level(0);
+        hipLaunchKernelGGL(k_ert_sigma, dim3((unsigned)cdiv(N(), kBlock)), dim3(kBlock), 0, stream, N(), logsig,
+                           c0.sig, iflag.as<int>());
+        H1W_LAUNCHED();
+    }
+    for (int l = 1; l < L; ++l) {
+        const EG gf = make_eg(lv[l - 1], dmask), gc = make_eg(lv[l], dmask);
+        hipLaunchKernelGGL(k_ert_coarsen, dim3((unsigned)cdiv(gc.N, kBlock)), dim3(kBlock), 0, stream, gf, gc,
+                           ert_level(l - 1).sig, ert_level(l).sig);
+        H1W_LAUNCHED();
+    }
+    for (int l = 0; l < L; ++l) {
+        const EG g = make_eg(lv[l], dmask);
+        const ErtLevel c = ert_level(l);
+        hipLaunchKernelGGL(k_ert_coeffs, dim3((unsigned)cdiv(g.N, kBlock)), dim3(kBlock), 0, stream, g, c.sig, c.D,
+                           c.cx, c.cy, c.cz);
+        H1W_LAUNCHED();
+    }
+    hipLaunchKernelGGL(k_ert_coarse_inverse, dim3(1), dim3(kGJThreads), 0, stream, make_eg(lv[L - 1], dmask),
+                       ert_level(L - 1), cinv64.as<double>(), iflag.as<int>());
+    H1W_LAUNCHED();
+    int hf[2] = {0, 0};
+    H1W_HIP(hipMemcpyAsync(hf, iflag.p, sizeof(hf), hipMemcpyDeviceToHost, stream));
+    sync();
+    if (hf[0]) throw Error{H1W_ENUMERIC, "conductivity exp(logsig) is not finite and positive at some node"};
+    if (hf[1]) throw Error{H1W_ENUMERIC, "coarsest ERT operator has a non-positive pivot"};
+    ert_ready = true;
+}
+
+void Ctx::ert_apply(int k, const double* X, int64_t ldx, double* Y, int64_t ldy) {
+    const EG g = make_eg(lv[0], dmask);
+    timed(H1W_K_ERT_STENCIL, 8.0 * (2.0 * k + 4.0) * g.N, 0.0,
+          [&] { launch_step(stream, kErtApply, g, ert_level(0), k, nullptr, 0, X, ldx, Y, ldy, 0.0); });
+}
+
+// One symmetric V(nu, nu) cycle from zero, like the unfused H1 cycle, on the
+// ERT levels.
+void Ctx::ert_vcycle_chunk(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
+    const int L = (int)lv.size();
+    const double ces = 8.0 * k;
+    auto coarse = [&](const double* f, int64_t lf, double* x, int64_t lx) {
+        timed(H1W_K_COARSE, ces * 2 * Nc + 8.0 * Nc * Nc, 2.0 * k * Nc * Nc, [&] {
+            launch_coarse_solve<double>(stream, Nc, cinv64.as<double>(), k, f, lf, x, lx, cpart.as<double>(),
+                                        cpart_elems);
+        });
+    };
+    if (L == 1) {
+        coarse(F, ldf, X, ldx);
+        return;
+    }
+    size_t need = (size_t)k * pitch[0];
+    for (int l = 1; l < L; ++l) need += (size_t)3 * k * pitch[l];
+    vws.reserve(need * sizeof(double));
+    double* base = vws.as<double>();
+    std::vector<double*> tb(L), fb(L), xb(L);
+    size_t off = 0;
+    tb[0] = base;
+    off += (size_t)k * pitch[0];
+    for (int l = 1; l < L; ++l) {
+        fb[l] = base + off;
+        off += (size_t)k * pitch[l];
+        xb[l] = base + off;
+        off += (size_t)k * pitch[l];
+        tb[l] = base + off;
+        off += (size_t)k * pitch[l];
+    }
+    auto fptr = [&](int l) { return l == 0 ? F : (const double*)fb[l]; };
+    auto fld = [&](int l) { return l == 0 ? ldf : pitch[l]; };
+    auto xptr = [&](int l) { return l == 0 ? X : xb[l]; };
+    auto xld = [&](int l) { return l == 0 ? ldx : pitch[l]; };
+    const int nu = d.nu;
+    std::vector<double*> cur(L), oth(L);
+    std::vector<int64_t> ldcur(L), ldoth(L);
+    auto step = [&](int mode, int l, const double* Xin, int64_t li, double* Y, int64_t ly, double wt) {
+        const EG g = make_eg(lv[l], dmask);
+        const double nl = (double)g.N;
+        const double bytes = mode == kErtFirst ? 8.0 * (2.0 * k + 1.0) * nl : 8.0 * (3.0 * k + 4.0) * nl;
+        timed(H1W_K_ERT_STENCIL, bytes, 0.0,
+              [&] { launch_step(stream, mode, g, ert_level(l), k, fptr(l), fld(l), Xin, li, Y, ly, wt); });
+    };
+    for (int l = 0; l < L - 1; ++l) {
+        // pre-smoothing from zero into t; with the residual written to the
+        // other buffer and the post-smoothing alternating between the two,
+        // the last post-smoothing step lands in x for every nu
+        double* a = tb[l];
+        int64_t la = pitch[l];
+        double* b = xptr(l);
+        int64_t lb = xld(l);
+        step(kErtFirst, l, nullptr, 0, a, la, w[0]);
+        for (int s = 1; s < nu; ++s) {
+            step(kErtSmooth, l, a, la, b, lb, w[s]);
+            std::swap(a, b);
+            std::swap(la, lb);
+        }
+        step(kErtResidual, l, a, la, b, lb, 0.0);
+        {
+            const EG gf = make_eg(lv[l], dmask), gc = make_eg(lv[l + 1], dmask);
+            timed(H1W_K_ERT_STENCIL, ces * (gf.N + gc.N), 0.0, [&] {
+                hipLaunchKernelGGL(k_ert_restrict, dim3((unsigned)cdiv(gc.N, kBlock), (unsigned)k), dim3(kBlock), 0,
+                                   stream, gf, gc, (const double*)b, lb, fb[l + 1], pitch[l + 1]);
+                H1W_LAUNCHED();
+            });
+        }
+        cur[l] = a;
+        ldcur[l] = la;
+        oth[l] = b;
+        ldoth[l] = lb;
+    }
+    coarse(fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
+    for (int l = L - 2; l >= 0; --l) {
+        const Geom& g = lv[l];
+        timed(H1W_K_PROLONG, ces * (2.0 * g.N + (double)lv[l + 1].N), 0.0, [&] {
+            launch_prolong_add<double>(stream, dim, g, lv[l + 1], k, xb[l + 1], pitch[l + 1], cur[l], ldcur[l]);
+        });
+        double* a = cur[l];
+        int64_t la = ldcur[l];
+        double* b = oth[l];
+        int64_t lb = ldoth[l];
+        for (int s = nu - 1; s >= 0; --s) {
+            step(kErtSmooth, l, a, la, b, lb, w[s]);
+            std::swap(a, b);
+            std::swap(la, lb);
+        }
+        if (a != xptr(l)) throw Error{H1W_EINVAL, "internal: ERT V-cycle buffer parity"};
+    }
+}
+
+void Ctx::ert_fields(int n_src, const int* src, double* U, int64_t ldu, double rtol, int maxit, h1w_info* info) {
+    const int64_t n = N();
+    efs.reserve((size_t)n_src * pitch[0] * sizeof(double));
+    hipLaunchKernelGGL(k_ert_unit_loads, dim3((unsigned)cdiv(n, kBlock), (unsigned)n_src), dim3(kBlock), 0, stream,
+                       n, src, efs.as<double>(), pitch[0]);
+    H1W_LAUNCHED();
+    mg_solve(n_src, efs.as<double>(), pitch[0], U, ldu, rtol, maxit, info);
+}
+
+const double* Ctx::ert_kgeo(int n_meas, const int* pair, const int* src, const double* kgeo) {
+    if (kgeo) return kgeo;
+    ekg.reserve((size_t)std::max(1, n_meas) * sizeof(double));
+    hipLaunchKernelGGL(k_ert_kgeo, dim3((unsigned)cdiv(n_meas, kBlock)), dim3(kBlock), 0, stream,
+                       make_eg(lv[0], dmask), n_meas, pair, src, ekg.as<double>());
+    H1W_LAUNCHED();
+    return ekg.as<double>();
+}
+
+void Ctx::ert_measure(int n_meas, const int* pair, const int* src, const double* k, const double* U, int64_t ldu,
+                      double* g) {
+    hipLaunchKernelGGL(k_ert_meas, dim3((unsigned)cdiv(n_meas, kBlock)), dim3(kBlock), 0, stream, n_meas, pair, src,
+                       k, U, ldu, g);
+    H1W_LAUNCHED();
+}
+
+void Ctx::ert_sens(int n_src, const double* U, int64_t ldu, int n_meas, const int* pair, const double* k, double* J,
+                   int64_t ldj, const double* gbar, double* grad) {
+    const EG g = make_eg(lv[0], dmask);
+    const double* sig = ert_level(0).sig;
+    const bool vjp = gbar != nullptr;
+    const int tn = n_src <= 32 ? 32 : 16;
+    const unsigned blocks = (unsigned)cdiv(g.N, tn);
+    const double nn = (double)g.N;
+    const double bytes = vjp ? 8.0 * nn * (n_src + 2.0) : 8.0 * nn * (n_src + 1.0 + n_meas);
+    timed(H1W_K_ERT_SENS, bytes, 12.0 * n_meas * nn, [&] {
+        if (tn == 32) {
+            if (vjp)
+                hipLaunchKernelGGL((k_ert_sens<32, true>), dim3(blocks), dim3(kSensThreads), 0, stream, g, sig, n_src,
+                                   U, ldu, n_meas, pair, k, J, ldj, gbar, grad);
+            else
+                hipLaunchKernelGGL((k_ert_sens<32, false>), dim3(blocks), dim3(kSensThreads), 0, stream, g, sig, n_src,
+                                   U, ldu, n_meas, pair, k, J, ldj, gbar, grad);
+        } else {
+            if (vjp)
+                hipLaunchKernelGGL((k_ert_sens<16, true>), dim3(blocks), dim3(kSensThreads), 0, stream, g, sig, n_src,
+                                   U, ldu, n_meas, pair, k, J, ldj, gbar, grad);
+            else
+                hipLaunchKernelGGL((k_ert_sens<16, false>), dim3(blocks), dim3(kSensThreads), 0, stream, g, sig, n_src,
+                                   U, ldu, n_meas, pair, k, J, ldj, gbar, grad);
+        }
+        H1W_LAUNCHED();
+    });
+}
+
+bool ert_on_dirichlet_host(const Geom& g, unsigned mask, int64_t p) {
+    const int i = (int)(p % g.nx);
+    const int64_t t = p / g.nx;
+    const int j = (int)(t % g.ny), l = (int)(t / g.ny);
+    return ((mask & 1u) && i == 0) || ((mask & 2u) && i == g.nx - 1) || ((mask & 4u) && j == 0) ||
+           ((mask & 8u) && j == g.ny - 1) || ((mask & 16u) && l == 0) || ((mask & 32u) && l == g.nz - 1);
+}
+
+}  // namespace h1w

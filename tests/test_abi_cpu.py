@@ -35,8 +35,11 @@ def test_status_strings_and_notimpl():
     from paper_2209_02815_amd import _native as nat
     assert nat.lib.h1w_status_string(nat.H1W_OK) == b"ok"
     assert nat.lib.h1w_status_string(nat.H1W_ENOTSPD).startswith(b"capacitance")
-    assert nat.lib.h1w_ert_sensitivities(None, None, 0, None, 0, None, None, None, None, 0, None, None) \
-        == nat.H1W_ENOTIMPL
+    assert nat.lib.h1w_status_string(nat.H1W_ENOTIMPL) == b"not implemented"
+    assert nat.lib.h1w_ert_sensitivities(None, None, 0, None, 0, None, None, None, None, 0, None, 0, None,
+                                         None) == nat.H1W_EINVAL
+    assert nat.lib.h1w_ert_set_conductivity(None, None) == nat.H1W_EINVAL
+    assert nat.lib.h1w_ert_vjp(None, 0, None, None, 0, 0, None, None, None, None) == nat.H1W_EINVAL
 
 
 @pytest.mark.parametrize("bad", [
@@ -58,6 +61,29 @@ def test_setup_rejects_invalid_arguments_on_host(bad):
     h = C.c_void_p()
     st = nat.lib.h1w_setup(C.byref(d), None, C.byref(h))
     assert st == nat.H1W_EINVAL
+    assert h.value is None
+    assert len(nat.lib.h1w_last_error(None)) > 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(op=2), dict(dim=2, n=(17, 17, 1)), dict(precision=1), dict(flags=1), dict(mask=0x40),
+    dict(n=(11, 11, 11)),  # coarsest level 6^3 = 216 nodes > 128 (the dense in-LDS inverse)
+    dict(op=0, mask=0x1F),  # a Dirichlet mask on an H1 Gram context
+])
+def test_ert_setup_rejects_invalid_arguments_on_host(bad):
+    from paper_2209_02815_amd import _native as nat
+    d = nat.h1w_grid_desc()
+    d.dim = bad.get("dim", 3)
+    for i, n in enumerate(bad.get("n", (17, 17, 17))):
+        d.n[i] = n
+    d.beta = 1e-2
+    d.precision = bad.get("precision", 0)
+    d.flags = bad.get("flags", 0)
+    d.op = bad.get("op", nat.H1W_OP_ERT)
+    d.dirichlet_mask = bad.get("mask", 0)
+    h = C.c_void_p()
+    st = nat.lib.h1w_setup(C.byref(d), None, C.byref(h))
+    assert st == nat.H1W_EINVAL, nat.lib.h1w_last_error(None)
     assert h.value is None
     assert len(nat.lib.h1w_last_error(None)) > 0
 

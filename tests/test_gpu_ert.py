@@ -1,0 +1,248 @@
+"""GPU: the ERT forward map and its sensitivities (Section 4) through the C ABI,
+against the CPU oracle (oracle/ert.py): the conductivity operator, the pole
+fields, the voltages, J and J^T gbar on small grids element by element; at the
+65^3 survey size (32 sources, 496 pairs) the fields' residual under the
+oracle's operator, the oracle's adjoint formula on sampled rows, the
+homogeneity identity, reciprocity, central finite differences on 20 random
+directions, and one Woodbury GN solve fed with the GPU's J."""
+import numpy as np
+import pytest
+
+import h1w_inputs as H
+from oracle import ert as OE
+from oracle import gn as OG
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2209_02815_amd as P
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+SMALL = [(9, 3, 2, 2, 0x1F), (17, 4, 2, 2, 0x1F), (17, 4, 2, 2, 0x15), (33, 8, 4, 2, 0x1F)]
+
+
+def _survey(n, nex, ney, s, mask, wid=41):
+    sv = H.ert_survey(n, nex, ney, s, wid=wid)
+    return sv, H.ert_logsig(sv), mask
+
+
+@pytest.mark.parametrize("n,nex,ney,s,mask", SMALL[:3])
+def test_operator_matches_oracle(P, n, nex, ney, s, mask):
+    sv, m, mask = _survey(n, nex, ney, s, mask)
+    print(f"ert operator n={n} mask={mask:#x}", flush=True)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs, dirichlet_mask=mask) as ec:
+        ec.set_conductivity(dev(m))
+        X = np.random.default_rng(1).standard_normal((3, sv.N))
+        Y = host(ec.operator_apply(dev(X)))
+    Af, free = OE.operator(sv.shape, m, mask)
+    on = OE.dirichlet_nodes(sv.shape, mask)
+    ref = (Af @ X[:, free].T).T
+    scale = np.abs(Af).max() * np.abs(X).max()
+    assert np.abs(Y[:, free] - ref).max() <= 1e-14 * scale * 8
+    assert np.array_equal(Y[:, on], X[:, on])     # identity rows on the Dirichlet faces
+
+
+@pytest.mark.parametrize("n,nex,ney,s,mask", SMALL)
+def test_fields_voltages_jacobian_match_oracle(P, n, nex, ney, s, mask):
+    sv, m, mask = _survey(n, nex, ney, s, mask)
+    print(f"ert sens n={n} mask={mask:#x} src={sv.n_src} meas={sv.n_meas}", flush=True)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs, dirichlet_mask=mask) as ec:
+        g, J, U, info = ec.forward(dev(m), jacobian=True, fields=True, rtol=1e-13)
+        g, J, U = host(g), host(J), host(U)
+    assert info.relres_true <= 1e-13 and info.iters > 0
+    Uo = OE.fields(sv.shape, m, mask, sv.electrodes)
+    k = OE.pole_pole_factors(sv.shape, sv.electrodes, sv.pairs)
+    go = OE.measurements(Uo, sv.electrodes, sv.pairs, k)
+    Jo = OE.jacobian(sv.shape, m, Uo, sv.pairs, k)
+    # fields: error <= cond(A) * rtol; the oracle's LU is exact to ~1e-15
+    assert np.abs(U - Uo).max() <= 1e-9 * np.abs(Uo).max()
+    assert np.abs(g - go).max() <= 1e-9 * np.abs(go).max()
+    assert np.abs(J - Jo).max() <= 1e-8 * np.abs(Jo).max()
+    on = OE.dirichlet_nodes(sv.shape, mask)
+    assert np.all(U[:, on] == 0.0)
+
+
+def test_default_geometric_factors_and_explicit_kgeo(P):
+    sv, m, mask = _survey(17, 4, 2, 2, 0x1F)
+    k = OE.pole_pole_factors(sv.shape, sv.electrodes, sv.pairs)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec:
+        g0, _, _, _ = ec.forward(dev(m))
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs, kgeo=2.0 * k) as ec:
+        g1, _, _, _ = ec.forward(dev(m))
+    assert np.allclose(host(g1), 2.0 * host(g0), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("n,nex,ney,s,mask", SMALL[1:3])
+def test_vjp_matches_transpose_product(P, n, nex, ney, s, mask):
+    sv, m, mask = _survey(n, nex, ney, s, mask)
+    gbar = np.random.default_rng(2).standard_normal(sv.n_meas)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs, dirichlet_mask=mask) as ec:
+        g, J, U, _ = ec.forward(dev(m), jacobian=True, fields=True)
+        v1 = host(ec.vjp(dev(gbar), U))
+        with pytest.raises(P.H1WError):       # fields went to U_out: none kept inside
+            ec.vjp(dev(gbar))
+    ref = host(J).T @ gbar
+    assert np.abs(v1 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_vjp_uses_kept_fields(P):
+    sv, m, mask = _survey(17, 4, 2, 2, 0x1F)
+    gbar = np.random.default_rng(3).standard_normal(sv.n_meas)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec:
+        _, J, _, _ = ec.forward(dev(m), jacobian=True)          # fields kept inside
+        v = host(ec.vjp(dev(gbar)))
+    ref = host(J).T @ gbar
+    assert np.abs(v - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_vcycle_is_symmetric_and_positive(P):
+    sv, m, mask = _survey(33, 8, 4, 2, 0x1F)
+    on = OE.dirichlet_nodes(sv.shape, mask)
+    rng = np.random.default_rng(4)
+    V = rng.standard_normal((4, sv.N))
+    V[:, on] = 0.0
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec:
+        ec.set_conductivity(dev(m))
+        BV = host(ec.vcycle(dev(V)))
+    G = V @ BV.T
+    assert np.abs(G - G.T).max() <= 1e-12 * np.abs(G).max()
+    assert np.all(np.diag(G) > 0.0)
+    assert np.all(BV[:, on] == 0.0)
+
+
+def test_mg_solve_contracts_like_multigrid(P):
+    # iterations to 1e-12 stay flat under refinement (17^3, 33^3, 65^3)
+    its = []
+    for n in (17, 33, 65):
+        sv = H.ert_survey(n, 4, 2, 2 * (n - 1) // 16, wid=42)
+        m = H.ert_logsig(sv)
+        with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec:
+            _, _, _, info = ec.forward(dev(m), rtol=1e-12)
+        its.append(info.iters)
+    assert max(its) <= 30 and max(its) - min(its) <= 6, its
+
+
+def test_autograd_gradcheck(P):
+    from paper_2209_02815_amd import ert_voltages
+    sv = H.ert_survey(7, 3, 2, 2, wid=43)
+    m = dev(H.ert_logsig(sv)).requires_grad_(True)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec:
+        assert torch.autograd.gradcheck(lambda x: ert_voltages(x, ec, 1e-14), (m,), eps=1e-6, atol=1e-7,
+                                        rtol=1e-5, nondet_tol=0.0)
+
+
+def test_errors(P):
+    from paper_2209_02815_amd import _native as nat
+    sv, m, mask = _survey(9, 3, 2, 2, 0x1F)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec:
+        X = dev(np.zeros((1, sv.N)))
+        with pytest.raises(P.H1WError) as e:
+            ec.operator_apply(X)                       # no conductivity yet
+        assert e.value.status == nat.H1W_ESTATE
+        bad = m.copy()
+        bad[5] = np.nan
+        with pytest.raises(P.H1WError) as e:
+            ec.set_conductivity(dev(bad))
+        assert e.value.status == nat.H1W_ENUMERIC
+        ec.set_conductivity(dev(m))
+        g = torch.empty(sv.n_meas, dtype=torch.float64, device="cuda:0")
+        for src, pair in [(np.array([0], np.int32), sv.pairs[:1]),                    # node on x = 0 face
+                          (sv.electrodes.astype(np.int32), np.array([[1, 1]], np.int32)),  # a == b
+                          (sv.electrodes.astype(np.int32), np.array([[0, 99]], np.int32)),  # out of range
+                          (np.zeros(0, np.int32), sv.pairs[:1])]:                      # no sources
+            st = nat.h1w_ert_sensitivities(ec.handle, dev(src), dev(pair.astype(np.int32)), None, None, g,
+                                           raise_on_error=False)[1]
+            assert st == nat.H1W_EINVAL
+        with pytest.raises(P.H1WError) as e:           # Gauss-Newton calls need an H1 context
+            nat.h1w_gn_solve(ec.handle, None, 1e-3, dev(np.zeros(sv.N)), b=dev(np.ones(sv.N)))
+        assert e.value.status == nat.H1W_EINVAL
+    with P.Context((9, 9, 9), 1e-2) as hc:             # ERT calls need an ERT context
+        with pytest.raises(P.H1WError) as e:
+            nat.h1w_ert_set_conductivity(hc.handle, dev(m))
+        assert e.value.status == nat.H1W_EINVAL
+
+
+# ---------------------------------------------------------------- full size (65^3, 32 sources, 496 pairs)
+
+@pytest.fixture(scope="module")
+def full(P):
+    sv = H.ert_survey()
+    m = H.ert_logsig(sv)
+    print(f"ert full size N={sv.N} src={sv.n_src} meas={sv.n_meas}", flush=True)
+    ec = P.ErtContext(sv.shape, sv.electrodes, sv.pairs)
+    g, J, U, info = ec.forward(dev(m), jacobian=True, fields=True, rtol=1e-12)
+    yield sv, m, ec, host(g), J, host(U), info
+    ec.close()
+
+
+def test_full_size_fields_residual_and_reciprocity(full):
+    sv, m, ec, g, J, U, info = full
+    assert info.relres_true <= 1e-12
+    Af, free = OE.operator(sv.shape, m, sv.mask)
+    pos = np.full(sv.N, -1)
+    pos[free] = np.arange(free.size)
+    E = np.zeros((free.size, sv.n_src))
+    E[pos[sv.electrodes], np.arange(sv.n_src)] = 1.0
+    R = Af @ U[:, free].T - E
+    assert np.linalg.norm(R, axis=0).max() <= 2e-12          # ||e_a|| = 1
+    V = U[:, sv.electrodes]
+    assert np.abs(V - V.T).max() <= 1e-9 * np.abs(V).max()
+    assert np.all(U[:, OE.dirichlet_nodes(sv.shape, sv.mask)] == 0.0)
+
+
+def test_full_size_jacobian_rows_and_homogeneity(full):
+    sv, m, ec, g, J, U, info = full
+    k = OE.pole_pole_factors(sv.shape, sv.electrodes, sv.pairs)
+    assert np.abs(g - OE.measurements(U, sv.electrodes, sv.pairs, k)).max() <= 1e-14 * np.abs(g).max()
+    rows = np.random.default_rng(6).choice(sv.n_meas, 24, replace=False)
+    Jo = OE.jacobian(sv.shape, m, U, sv.pairs[rows], k[rows])
+    Jg = host(J[torch.as_tensor(rows, device=J.device)])
+    assert np.abs(Jg - Jo).max() <= 1e-12 * np.abs(Jo).max()
+    row_sums = host(J.sum(dim=1))
+    assert np.abs(row_sums + g).max() <= 1e-9 * np.abs(g).max()
+
+
+def test_full_size_directional_finite_differences(full):
+    sv, m, ec, g, J, U, info = full
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    worst = 0.0
+    for q in range(20):
+        v = rng.standard_normal(sv.N)
+        gp, _, _, _ = ec.forward(dev(m + h * v), rtol=1e-13)
+        gm, _, _, _ = ec.forward(dev(m - h * v), rtol=1e-13)
+        fd = (host(gp) - host(gm)) / (2 * h)
+        jv = host(J @ dev(v))
+        worst = max(worst, np.linalg.norm(fd - jv) / np.linalg.norm(jv))
+    print(f"FD worst relative difference {worst:.3e}", flush=True)
+    assert worst <= 1e-6
+
+
+def test_full_size_gn_solve_with_ert_jacobian(P, full):
+    # paper-form right-hand side: m_ref = ln(1e-2), g_obs = g(m_ref), alpha = 1e-4,
+    # beta = 1e-2 on the same grid (the H^1 regulariser of the GN system)
+    sv, m, ec, g, J, U, info = full
+    m_ref = np.full(sv.N, np.log(1e-2))
+    g_obs, _, _, _ = ec.forward(dev(m_ref))
+    d = m - m_ref
+    res = g - host(g_obs)
+    with P.Context(sv.shape, 1e-2) as hc:
+        x = torch.zeros(sv.N, dtype=torch.float64, device="cuda:0")
+        gi = P.h1w_gn_solve(hc.handle, J, 1e-4, x, d=dev(d), res=dev(res), rtol=1e-10)
+    Jh = host(J)
+    b = OG.paper_rhs(sv.shape, 1e-2, Jh, 1e-4, d, res)
+    rr = OG.true_relres(sv.shape, 1e-2, Jh, 1e-4, b, host(x))
+    print(f"ERT GN solve: {gi.iters} iterations, relres {rr:.2e}", flush=True)
+    assert rr <= 1.01e-10
