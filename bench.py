@@ -37,6 +37,8 @@ def parse():
                     help="skip the batch of 256 uneven 2D instances (h1w_batch_solve)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison solve modes (Laplace-only and exact-B preconditioners)")
+    ap.add_argument("--no-ert", action="store_true",
+                    help="skip the ERT survey (65^3 forward map, J, GN solve and two Gauss-Newton steps)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of 1 GiB (a kernel of known size for PMC counter scaling)")
     return ap.parse_args()
@@ -55,6 +57,7 @@ KERNELS = {
     "jtv": ("hbm", "k_jt_u_t / k_jt_plain / k_z_stored", "blas.hip"), "factor": ("mfma", "k_blk_*", "blocked.hip"),
     "trsv": ("hbm", "k_blk_trsv", "blocked.hip"), "apply": ("hbm", "k_march<*, 3, 0> / k_apply_plus_dot", "stencil.hip"),
     "vdown": ("hbm", "k_down", "vfused.hip"), "vup": ("hbm", "k_up", "vfused.hip"),
+    "ert_stencil": ("hbm", "k_ert_step / k_ert_restrict", "ert.hip"), "ert_sens": ("hbm", "k_ert_sens", "ert.hip"),
 }
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix
@@ -145,6 +148,78 @@ def cpu_baseline(wl, J, b, threads):
                    f"({t_sample:.2f} s) + 1 DCT Poisson solve ({t_poisson:.3f} s) + 64x64 block of the "
                    f"capacitance product ({t_gemm_blk:.3f} s), scaled to one full solve: {t_full:.1f} s"),
     }
+
+
+def ert_bench(args):
+    """The ERT survey of Section 4 on the 65^3 grid (log10 sigma a Gaussian
+    random field, 32 pole electrodes on the top face, 496 pole-pole pairs):
+    the forward map with J (32 pole fields by batched MG-PCG to 1e-12, voltages,
+    the 496 x 274625 sensitivity matrix), one Woodbury GN solve fed with that J
+    (paper-form right-hand side, m_ref = ln 1e-2, g_obs = g(m_ref), alpha = 1e-4,
+    beta = 1e-2, rtol 1e-8), and two Gauss-Newton steps of Algorithm 2."""
+    import numpy as np
+    import torch
+    import h1w_inputs as H
+    import paper_2209_02815_amd as P
+    sv = H.ert_survey()
+    m = torch.from_numpy(H.ert_logsig(sv)).to("cuda:0")
+    out = {"workload": f"ERT {sv.shape[0]}^3, {sv.n_src} pole sources, {sv.n_meas} pole-pole pairs, "
+                       f"log10 sigma GRF (mean -2, std 0.5, corr 0.2)", "N": sv.N, "n_meas": sv.n_meas}
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec, P.Context(sv.shape, 1e-2) as hc:
+        J = torch.empty(sv.n_meas, sv.N, dtype=torch.float64, device="cuda:0")
+        ec.set_kernel_timing(["ert_sens", "ert_stencil"])
+        g, _, _, info = ec.forward(m, J_out=J)
+        ec.reset_kernel_timing()
+        reps = 5
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g, _, _, info = ec.forward(m, J_out=J)
+            infos.append(info)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        kt = ec.kernel_timing()
+        ec.set_kernel_timing([])
+        st = kt["ert_sens"]
+        out["forward_with_J"] = {
+            "per_s": 1.0 / dt, "ms": 1e3 * dt, "field_iters": info.iters, "field_relres": info.relres_true,
+            "t_conductivity_ms": float(np.median([i.t_zbuild_ms for i in infos])),
+            "t_fields_ms": float(np.median([i.t_cg_ms for i in infos])),
+            "t_voltages_and_J_ms": float(np.median([i.t_gemm_ms for i in infos])),
+            "sens_kernel": roofline("ert_sens", st),
+            "stencil_ms_per_forward": kt["ert_stencil"]["ms"] / reps,
+        }
+        log(f"ert forward: {out['forward_with_J']}")
+        m_ref = torch.full_like(m, float(np.log(1e-2)))
+        g_obs, _, _, _ = ec.forward(m_ref)
+        d = m - m_ref
+        res = g - g_obs
+        x = torch.zeros_like(m)
+        hc.gn_solve(J, 1e-4, d=d, res=res, x=x, rtol=args.rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            _, gi = hc.gn_solve(J, 1e-4, d=d, res=res, x=x, rtol=args.rtol)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 3
+        out["gn_solve"] = {"solves_per_s": 1.0 / dt, "ms": 1e3 * dt, "iters": gi.iters,
+                           "relres_true": gi.relres_true, "t_zbuild_ms": gi.t_zbuild_ms,
+                           "t_gemm_ms": gi.t_gemm_ms, "t_cg_ms": gi.t_cg_ms}
+        log(f"ert GN solve: {out['gn_solve']}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m_end, hist = P.ert_gauss_newton(ec, hc, m_ref, m_ref, g, 1e-4, steps=2, rtol=args.rtol)
+        g_end, _, _, _ = ec.forward(m_end)
+        torch.cuda.synchronize()
+        out["gauss_newton_2_steps"] = {
+            "ms": 1e3 * (time.perf_counter() - t0),
+            "misfit": [h[0] for h in hist] + [float(torch.linalg.norm(g_end - g))],
+            "gn_iters": [h[1] for h in hist]}
+        log(f"ert Gauss-Newton: {out['gauss_newton_2_steps']}")
+        del J
+    torch.cuda.empty_cache()
+    return out
 
 
 def batch_bench(args, threads):
@@ -272,6 +347,7 @@ def main():
     torch.cuda.empty_cache()
 
     batch = None if args.no_batch else batch_bench(args, threads)
+    ert = None if args.no_ert else ert_bench(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -292,6 +368,7 @@ def main():
         "mixed": results.get("mixed"),
         "comparison_modes": compare,
         "batch": batch,
+        "ert": ert,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

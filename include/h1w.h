@@ -405,6 +405,27 @@ h1w_status h1w_ert_vjp(h1w_ctx* ctx, int n_src, const int* src_node, const doubl
                        int64_t ldu, int n_meas, const int* pair, const double* kgeo,
                        const double* gbar, double* grad);
 
+/* One Gauss-Newton step of Algorithm 2 on an ERT survey: the voltages g(m)
+ * and the sensitivities J(m) on the ERT context (as h1w_ert_sensitivities),
+ * the step dm from the Woodbury-preconditioned GN system on the H1 context
+ * (as h1w_gn_solve with the paper-form right-hand side, d = m - m_ref and
+ * res = g(m) - g_obs, eq. (block_primal)), then m := m + dm.
+ * ert         ERT context; h1: H1 Gram context with the same n[3]
+ * m           N log-conductivities (in/out); m_ref: N reference values
+ * g_obs       n_meas observed voltages (1 <= n_meas <= 4096)
+ * J, ldj      n_meas x N workspace; holds J(m) of the old m on return
+ * dm          N workspace; holds the step on return
+ * g_out       n_meas, optional: g of the old m
+ * ert_opts    field solves (rtol 0 -> 1e-12); gn_opts: as for h1w_gn_solve
+ * info        the GN solve's diagnostics.
+ * m is updated only when every part succeeded. Errors are reported on h1
+ * (h1w_last_error(h1)). Blocks the host. */
+h1w_status h1w_ert_gn_step(h1w_ctx* ert, h1w_ctx* h1, double* m, const double* m_ref, int n_src,
+                           const int* src_node, int n_meas, const int* pair, const double* kgeo,
+                           const double* g_obs, double alpha, double* J, int64_t ldj, double* dm,
+                           double* g_out, const h1w_solve_opts* ert_opts,
+                           const h1w_solve_opts* gn_opts, h1w_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,4 +12,4 @@ marshalling with torch tensors that live on the GPU.
 from ._native import *  # noqa: F401,F403
 from ._native import H1WError, h1w_info, lib  # noqa: F401
 from .solver import Context  # noqa: F401
-from .ert import ErtContext, ert_voltages  # noqa: F401
+from .ert import ErtContext, ert_gauss_newton, ert_voltages  # noqa: F401

@@ -27,7 +27,7 @@ EXPORTED = [
     "h1w_operator_apply", "h1w_poisson_solve_batched", "h1w_capacitance_build",
     "h1w_precond_apply", "h1w_gn_solve", "h1w_gn_apply", "h1w_ert_sensitivities",
     "h1w_set_kernel_timing", "h1w_get_kernel_timing", "h1w_reset_kernel_timing", "h1w_batch_solve",
-    "h1w_ert_set_conductivity", "h1w_ert_vjp",
+    "h1w_ert_set_conductivity", "h1w_ert_vjp", "h1w_ert_gn_step",
 ]
 
 
@@ -112,6 +112,8 @@ def _load():
                                       C.POINTER(h1w_info)]),
         "h1w_ert_set_conductivity": (I, [P, P]),
         "h1w_ert_vjp": (I, [P, I, P, P, I64, I, P, P, P, P]),
+        "h1w_ert_gn_step": (I, [P, P, P, P, I, P, I, P, P, P, D, P, I64, P, P, C.POINTER(h1w_solve_opts),
+                                C.POINTER(h1w_solve_opts), C.POINTER(h1w_info)]),
         "h1w_set_kernel_timing": (I, [P, C.c_uint]),
         "h1w_get_kernel_timing": (I, [P, I, C.POINTER(h1w_kstat)]),
         "h1w_reset_kernel_timing": (I, [P]),
@@ -366,3 +368,22 @@ def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotun
     if raise_on_error and st != H1W_OK:
         raise H1WError(st, lib.h1w_last_error(None).decode())
     return out
+
+
+def h1w_ert_gn_step(ert, h1, m, m_ref, src_node, pair, g_obs, alpha: float, J, dm, g_out=None, kgeo=None,
+                    ert_rtol: float = 0.0, gn_rtol: float = 0.0, gn_maxit: int = 0):
+    """One Gauss-Newton step (see the header); m is updated in place. Errors are
+    reported on the H1 context h1."""
+    N, _ = h1w_get_sizes(h1)
+    n_src = _ints(src_node, "src_node")
+    n_meas = _ints(pair, "pair", 2)
+    _, ldj = _rows(J, N, "J")
+    for t, what in ((m, "m"), (m_ref, "m_ref"), (dm, "dm")):
+        _rows(t, N, what)
+    eo = h1w_solve_opts(float(ert_rtol), 0, 0, 0, 0, 0)
+    go = h1w_solve_opts(float(gn_rtol), int(gn_maxit), 0, 0, 0, 0)
+    info = h1w_info()
+    _check(h1, lib.h1w_ert_gn_step(ert, h1, _ptr(m), _ptr(m_ref), n_src, _ptr(src_node), n_meas, _ptr(pair),
+                                   _ptr(kgeo), _ptr(g_obs), float(alpha), _ptr(J), ldj, _ptr(dm), _ptr(g_out),
+                                   C.byref(eo), C.byref(go), C.byref(info)))
+    return info

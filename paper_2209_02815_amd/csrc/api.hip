@@ -72,6 +72,31 @@ void check_sources(h1w::Ctx& c, int n_src, const int* src_node) {
     }
 }
 
+// validated options of a Gauss-Newton solve on context c
+h1w_solve_opts gn_options(const h1w::Ctx& c, const h1w_solve_opts* opts) {
+    h1w_solve_opts o{};
+    if (opts) o = *opts;
+    require(std::isfinite(o.rtol) && o.rtol >= 0.0, "rtol must be >= 0");
+    require(o.maxit >= 0, "maxit must be >= 0");
+    require(o.zmode >= H1W_Z_AUTO && o.zmode <= H1W_Z_RECOMPUTE, "zmode must be AUTO, STORED or RECOMPUTE");
+    require(o.factor >= H1W_FACTOR_AUTO && o.factor <= H1W_FACTOR_LU, "factor must be AUTO, CHOL or LU");
+    require(o.check_every == 0, "check_every must be 0");
+    require((o.flags & ~(H1W_SOLVE_LAPLACE_ONLY | H1W_SOLVE_EXACT_B)) == 0, "unknown bits in flags");
+    require(o.flags != (H1W_SOLVE_LAPLACE_ONLY | H1W_SOLVE_EXACT_B), "LAPLACE_ONLY and EXACT_B exclude each other");
+    require(!(o.flags & H1W_SOLVE_EXACT_B) || !c.fp32, "EXACT_B needs an FP64 context");
+    return o;
+}
+
+h1w_solve_opts ert_options(const h1w_solve_opts* opts) {
+    h1w_solve_opts o{};
+    if (opts) o = *opts;
+    require(std::isfinite(o.rtol) && o.rtol >= 0.0, "rtol must be >= 0");
+    require(o.maxit >= 0, "maxit must be >= 0");
+    if (o.rtol == 0.0) o.rtol = 1e-12;
+    if (o.maxit == 0) o.maxit = 500;
+    return o;
+}
+
 void check_pairs(h1w::Ctx& c, int n_src, int n_meas, const int* pair) {
     require(n_meas >= 0, "n_meas must be >= 0");
     if (n_meas == 0) return;
@@ -300,17 +325,7 @@ h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
             if (m > 0) need_ptr(res, 8, "res (b is NULL)");
             require(!overlap(d, n, x, n, 1, n, 8), "d and x overlap");
         }
-        h1w_solve_opts o{};
-        if (opts) o = *opts;
-        require(std::isfinite(o.rtol) && o.rtol >= 0.0, "rtol must be >= 0");
-        require(o.maxit >= 0, "maxit must be >= 0");
-        require(o.zmode >= H1W_Z_AUTO && o.zmode <= H1W_Z_RECOMPUTE, "zmode must be AUTO, STORED or RECOMPUTE");
-        require(o.factor >= H1W_FACTOR_AUTO && o.factor <= H1W_FACTOR_LU, "factor must be AUTO, CHOL or LU");
-        require(o.check_every == 0, "check_every must be 0");
-        require((o.flags & ~(H1W_SOLVE_LAPLACE_ONLY | H1W_SOLVE_EXACT_B)) == 0, "unknown bits in flags");
-        require(o.flags != (H1W_SOLVE_LAPLACE_ONLY | H1W_SOLVE_EXACT_B), "LAPLACE_ONLY and EXACT_B exclude each other");
-        require(!(o.flags & H1W_SOLVE_EXACT_B) || !c.fp32, "EXACT_B needs an FP64 context");
-        c.gn_solve(m, J, ldj, alpha, b, d, res, x, o, info);
+        c.gn_solve(m, J, ldj, alpha, b, d, res, x, gn_options(c, opts), info);
     });
 }
 
@@ -432,10 +447,7 @@ h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double* logsig, int n_src, 
             require(!(J_out && n_meas > 0 && overlap(U_out, ldu, J_out, ldj, std::min(n_src, n_meas), n, 8)),
                     "U_out and J_out overlap");
         }
-        h1w_solve_opts o{};
-        if (opts) o = *opts;
-        require(std::isfinite(o.rtol) && o.rtol >= 0.0, "rtol must be >= 0");
-        require(o.maxit >= 0, "maxit must be >= 0");
+        const h1w_solve_opts o = ert_options(opts);
         if (logsig) need_ptr(logsig, 8, "logsig");
         c.ev_reserve();
         c.ev_record(0);
@@ -450,7 +462,7 @@ h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double* logsig, int n_src, 
             lu = c.pitch[0];
         }
         c.efield_n = 0;
-        c.ert_fields(n_src, src_node, U, lu, o.rtol > 0.0 ? o.rtol : 1e-12, o.maxit > 0 ? o.maxit : 500, info);
+        c.ert_fields(n_src, src_node, U, lu, o.rtol, o.maxit, info);
         if (!U_out) c.efield_n = n_src;
         c.ev_record(2);
         if (n_meas > 0 && (g_out || J_out)) {
@@ -503,6 +515,65 @@ h1w_status h1w_ert_vjp(h1w_ctx* ctx, int n_src, const int* src_node, const doubl
         const double* k = c.ert_kgeo(n_meas, pair, src_node, kgeo);
         c.ert_sens(n_src, U, ldu, n_meas, pair, k, nullptr, 0, gbar, grad);
         c.sync();
+    });
+}
+
+h1w_status h1w_ert_gn_step(h1w_ctx* ert, h1w_ctx* h1, double* m, const double* m_ref, int n_src,
+                           const int* src_node, int n_meas, const int* pair, const double* kgeo,
+                           const double* g_obs, double alpha, double* J, int64_t ldj, double* dm, double* g_out,
+                           const h1w_solve_opts* ert_opts, const h1w_solve_opts* gn_opts, h1w_info* info) {
+    if (!ert || !h1) return H1W_EINVAL;
+    if (info) {
+        *info = h1w_info{};
+        info->failed_pivot = -1;
+    }
+    return guarded(h1, [&] {
+        auto& E = ert->c;
+        auto& G = h1->c;
+        require(E.ert, "the first context must be an ERT context");
+        require(!G.ert, "the second context must be an H1 Gram context");
+        const h1w::Geom& ge = E.lv[0];
+        const h1w::Geom& gg = G.lv[0];
+        require(ge.nx == gg.nx && ge.ny == gg.ny && ge.nz == gg.nz, "the two contexts must share the grid");
+        const int64_t n = G.N();
+        require(n_meas >= 1 && n_meas <= 4096, "n_meas must be in [1, 4096]");
+        need_ptr(m, 8, "m");
+        need_ptr(m_ref, 8, "m_ref");
+        need_ptr(g_obs, 8, "g_obs");
+        need_ptr(J, 8, "J");
+        need_ptr(dm, 8, "dm");
+        require(ldj >= n, "ldj must be >= N");
+        require(std::isfinite(alpha) && alpha > 0.0, "alpha must be finite and > 0");
+        require(!overlap(m, n, dm, n, 1, n, 8), "m and dm overlap");
+        if (kgeo) need_ptr(kgeo, 8, "kgeo");
+        if (g_out) need_ptr(g_out, 8, "g_out");
+        check_sources(E, n_src, src_node);
+        check_pairs(E, n_src, n_meas, pair);
+        const h1w_solve_opts eo = ert_options(ert_opts);
+        const h1w_solve_opts go = gn_options(G, gn_opts);
+        // forward map and sensitivities at m (ERT context, its stream)
+        h1w_info finfo{};
+        E.ert_set_conductivity(m);
+        E.efield.reserve((size_t)n_src * E.pitch[0] * sizeof(double));
+        E.efield_n = 0;
+        E.ert_fields(n_src, src_node, E.efield.as<double>(), E.pitch[0], eo.rtol, eo.maxit, &finfo);
+        E.efield_n = n_src;
+        E.egn.reserve((size_t)(n + 2 * n_meas) * sizeof(double));
+        double* d = E.egn.as<double>();
+        double* g = d + n;
+        double* res = g + n_meas;
+        const double* k = E.ert_kgeo(n_meas, pair, src_node, kgeo);
+        E.ert_measure(n_meas, pair, src_node, k, E.efield.as<double>(), E.pitch[0], g);
+        E.ert_sens(n_src, E.efield.as<double>(), E.pitch[0], n_meas, pair, k, J, ldj, nullptr, nullptr);
+        E.sync();
+        E.flush_timing();
+        // GN step on the H1 context (its stream): d = m - m_ref, res = g - g_obs
+        h1w::launch_sub(G.stream, n, m, m_ref, d);
+        h1w::launch_sub(G.stream, n_meas, g, g_obs, res);
+        G.gn_solve(n_meas, J, ldj, alpha, nullptr, d, res, dm, go, info);
+        if (g_out) H1W_HIP(hipMemcpyAsync(g_out, g, n_meas * sizeof(double), hipMemcpyDeviceToDevice, G.stream));
+        h1w::launch_axpby(G.stream, n, 1.0, dm, 1.0, m);
+        G.sync();
     });
 }
 

@@ -99,6 +99,7 @@ struct Ctx {
     std::vector<int64_t> eoff;       // offset of each level's coefficient block in ecoef
     DevBuf ecoef;                    // per level: sigma, D, cx, cy, cz
     DevBuf efs, ekg, efield;         // unit loads, geometric factors, kept pole fields
+    DevBuf egn;                      // GN step: d = m - m_ref, g, res = g - g_obs
     int efield_n = 0;                // rows held by efield
     ErtLevel ert_level(int l) const;
     void ert_validate();

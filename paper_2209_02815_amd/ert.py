@@ -12,6 +12,9 @@ backward pass sets the conductivity again, which rebuilds it.
 from __future__ import annotations
 
 from . import _native as nat
+from .solver import Context
+
+__all__ = ["ErtContext", "ert_voltages", "ert_gauss_newton"]
 
 
 class ErtContext:
@@ -58,6 +61,11 @@ class ErtContext:
 
     def __exit__(self, *exc):
         self.close()
+
+    # per-kernel-class event timing, as for the H1 context
+    set_kernel_timing = Context.set_kernel_timing
+    kernel_timing = Context.kernel_timing
+    reset_kernel_timing = Context.reset_kernel_timing
 
     def set_conductivity(self, logsig):
         nat.h1w_ert_set_conductivity(self.handle, logsig)
@@ -133,3 +141,24 @@ def ert_voltages(logsig, ert: ErtContext, rtol: float = 1e-12):
     if _FN is None:
         _FN = _function()
     return _FN.apply(logsig, ert, rtol)
+
+
+def ert_gauss_newton(ert: ErtContext, h1, m0, m_ref, g_obs, alpha: float, steps: int = 2, rtol: float = 1e-10,
+                     maxit: int = 0):
+    """Gauss-Newton iterations of Algorithm 2 for the survey held by `ert`
+    with the H^1 regulariser of the Context `h1` (same grid): each step is one
+    h1w_ert_gn_step call (forward map, J, Woodbury-preconditioned GN solve,
+    update). Returns (m, history), history[k] = (misfit ||g(m_k) - g_obs||,
+    GN iterations, true relative residual of the GN solve)."""
+    import torch
+    m = m0.clone()
+    dev = m.device
+    J = torch.empty(ert.n_meas, ert.N, dtype=torch.float64, device=dev)
+    dm = torch.empty_like(m)
+    g = torch.empty(ert.n_meas, dtype=torch.float64, device=dev)
+    hist = []
+    for _ in range(steps):
+        info = nat.h1w_ert_gn_step(ert.handle, h1.handle, m, m_ref, ert.src, ert.pair, g_obs, alpha, J, dm, g,
+                                   ert.kgeo, gn_rtol=rtol, gn_maxit=maxit)
+        hist.append((float(torch.linalg.norm(g - g_obs)), info.iters, info.relres_true))
+    return m, hist

@@ -246,3 +246,48 @@ def test_full_size_gn_solve_with_ert_jacobian(P, full):
     rr = OG.true_relres(sv.shape, 1e-2, Jh, 1e-4, b, host(x))
     print(f"ERT GN solve: {gi.iters} iterations, relres {rr:.2e}", flush=True)
     assert rr <= 1.01e-10
+
+
+# ---------------------------------------------------------------- Gauss-Newton outer loop (Algorithm 2)
+
+def test_gn_steps_match_oracle(P):
+    # two GN steps from m_ref on a 17^3 survey with oracle data g_obs = g(m_true);
+    # the oracle takes the same steps with its own fields, J and the closed-form
+    # update of Section 3.1 (exact A^-1)
+    from paper_2209_02815_amd import ert_gauss_newton
+    sv = H.ert_survey(17, 4, 2, 2, wid=44)
+    m_true = H.ert_logsig(sv)
+    g_obs, _ = OE.forward(sv.shape, m_true, sv.mask, sv.electrodes, sv.pairs)
+    m_ref = np.full(sv.N, np.log(1e-2))
+    alpha, beta = 1e-4, 1e-2
+    k = OE.pole_pole_factors(sv.shape, sv.electrodes, sv.pairs)
+    m_o, mis_o = m_ref.copy(), []
+    for _ in range(2):
+        g, U = OE.forward(sv.shape, m_o, sv.mask, sv.electrodes, sv.pairs)
+        J = OE.jacobian(sv.shape, m_o, U, sv.pairs, k)
+        mis_o.append(np.linalg.norm(g - g_obs))
+        m_o = m_o + OG.paper_update(sv.shape, beta, J, alpha, m_o - m_ref, g - g_obs)
+    with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec, P.Context(sv.shape, beta) as hc:
+        m_g, hist = ert_gauss_newton(ec, hc, dev(m_ref), dev(m_ref), dev(g_obs), alpha, steps=2, rtol=1e-12)
+    m_g = host(m_g)
+    print(f"GN misfits GPU {[h[0] for h in hist]} oracle {mis_o}", flush=True)
+    assert np.allclose([h[0] for h in hist], mis_o, rtol=1e-7, atol=0)
+    assert all(h[2] <= 1e-12 for h in hist)
+    assert np.linalg.norm(m_g - m_o) <= 1e-6 * np.linalg.norm(m_o - m_ref)
+
+
+def test_full_size_gn_steps(P, full):
+    # Algorithm 2 at the 65^3 survey size: two steps from m_ref towards data
+    # generated at the random field (the GPU's own forward map: a property
+    # test, the misfit must drop at every step and every GN solve must reach
+    # its tolerance)
+    from paper_2209_02815_amd import ert_gauss_newton
+    sv, m, ec, g, J, U, info = full
+    m_ref = dev(np.full(sv.N, np.log(1e-2)))
+    with P.Context(sv.shape, 1e-2) as hc:
+        m_g, hist = ert_gauss_newton(ec, hc, m_ref, m_ref, dev(g), 1e-4, steps=2, rtol=1e-10)
+        g_end, _, _, _ = ec.forward(m_g)
+    mis = [h[0] for h in hist] + [float(np.linalg.norm(host(g_end) - g))]
+    print(f"GN misfits {mis}, iterations {[h[1] for h in hist]}", flush=True)
+    assert mis[0] > mis[1] > mis[2]
+    assert all(h[2] <= 1e-10 for h in hist)
