@@ -343,6 +343,33 @@ __global__ __launch_bounds__(kBlock) void k_batched_p(int64_t N, const double* _
     P[r * ldp + n] = Z[r * ldz + n] + b[r] * P[r * ldp + n];
 }
 
+// per-row CG step lengths a = rz / pq on the device (0 for finished rows);
+// flag[0] = 1 on a non-positive or non-finite p.q of an active row
+__global__ void k_pcg_alpha(int k, const double* __restrict__ rz, const double* __restrict__ pq,
+                            const int* __restrict__ active, double* __restrict__ a, int* __restrict__ flag) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    double v = 0.0;
+    if (active[r]) {
+        if (!(pq[r] > 0.0 && pq[r] <= 1.79e308)) flag[0] = 1;
+        else v = rz[r] / pq[r];
+    }
+    a[r] = v;
+}
+
+// per-row direction coefficients: b = rz_new / rz (or the flexible
+// Polak-Ribiere form -a z.q / rz when zq is given), then rz := rz_new
+__global__ void k_pcg_beta(int k, const double* __restrict__ rzn, double* __restrict__ rz,
+                           const double* __restrict__ zq, const double* __restrict__ a,
+                           const int* __restrict__ active, double* __restrict__ b) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    double v = 0.0;
+    if (active[r]) v = zq ? -a[r] * zq[r] / rz[r] : rzn[r] / rz[r];
+    b[r] = v;
+    rz[r] = rzn[r];
+}
+
 int dot_blocks(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, cdiv(N, kBlock * 4))); }
 
 }  // namespace
@@ -518,6 +545,18 @@ void launch_batched_cg_xr(hipStream_t s, int k, int64_t N, const double* a, cons
                           const int* active) {
     hipLaunchKernelGGL(k_batched_cg_xr, dim3((unsigned)cdiv(N, kBlock), k), dim3(kBlock), 0, s, N, a, P,
                        ldp, Q, ldq, X, ldx, R, ldr, active);
+    H1W_LAUNCHED();
+}
+
+void launch_pcg_alpha(hipStream_t s, int k, const double* rz, const double* pq, const int* active, double* a,
+                      int* flag) {
+    hipLaunchKernelGGL(k_pcg_alpha, dim3((unsigned)cdiv(k, 64)), dim3(64), 0, s, k, rz, pq, active, a, flag);
+    H1W_LAUNCHED();
+}
+
+void launch_pcg_beta(hipStream_t s, int k, const double* rzn, double* rz, const double* zq, const double* a,
+                     const int* active, double* b) {
+    hipLaunchKernelGGL(k_pcg_beta, dim3((unsigned)cdiv(k, 64)), dim3(64), 0, s, k, rzn, rz, zq, a, active, b);
     H1W_LAUNCHED();
 }
 

@@ -400,39 +400,45 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
         double* Q = Pv + (size_t)kk * P;
         mvec.reserve((size_t)8 * kk * sizeof(double) + 16 * kk * sizeof(int));
         double* dnrm = mvec.as<double>();       // kk
-        double* drz = dnrm + kk;                // kk
+        double* drz = dnrm + kk;                // kk: r.z of the current direction
         double* dpq = drz + kk;                 // kk
         double* da = dpq + kk;                  // kk
         double* db = da + kk;                   // kk
         double* dzq = db + kk;                  // kk
-        int* dact = (int*)(dzq + kk);           // kk
+        double* drzn = dzq + kk;                // kk: r.z after the new preconditioner apply
+        int* dact = (int*)(drzn + kk);          // kk
         part.reserve((size_t)kk * 64 * sizeof(double));
         double* pp = part.as<double>();
-        std::vector<double> nb(kk), rz(kk), pq(kk), a(kk, 0.0), bcoef(kk, 0.0), rr(kk), zq(kk);
+        std::vector<double> nb(kk), rr(kk);
         std::vector<int> act(kk, 1);
-        auto fetch = [&](const double* dsrc, std::vector<double>& dst) {
-            H1W_HIP(hipMemcpyAsync(dst.data(), dsrc, kk * sizeof(double), hipMemcpyDeviceToHost, stream));
+        int hflag = 0;
+        // one host round trip per iteration: the residual norms (and the
+        // breakdown flag); step lengths and direction coefficients stay on
+        // the device
+        auto fetch_norms = [&]() {
+            H1W_HIP(hipMemcpyAsync(rr.data(), dnrm, kk * sizeof(double), hipMemcpyDeviceToHost, stream));
+            H1W_HIP(hipMemcpyAsync(&hflag, iflag.as<int>() + 8, sizeof(int), hipMemcpyDeviceToHost, stream));
             sync();
         };
-        auto put = [&](double* ddst, const void* src, size_t bytes) {
-            H1W_HIP(hipMemcpyAsync(ddst, src, bytes, hipMemcpyHostToDevice, stream));
+        auto put_act = [&]() {
+            H1W_HIP(hipMemcpyAsync(dact, act.data(), kk * sizeof(int), hipMemcpyHostToDevice, stream));
         };
+        H1W_HIP(hipMemsetAsync(iflag.as<int>() + 8, 0, sizeof(int), stream));  // slot 8: PCG breakdown
         H1W_HIP(hipMemset2DAsync(Xc, ldx * sizeof(double), 0, n * sizeof(double), kk, stream));
         H1W_HIP(hipMemcpy2DAsync(R, P * sizeof(double), Fc, ldf * sizeof(double), n * sizeof(double), kk,
                                  hipMemcpyDeviceToDevice, stream));
         launch_batched_dots(stream, kk, n, R, P, R, P, pp, dnrm);
-        fetch(dnrm, nb);
+        fetch_norms();
         for (int r = 0; r < kk; ++r) {
-            if (!std::isfinite(nb[r])) throw Error{H1W_ENUMERIC, "non-finite right-hand side"};
-            nb[r] = std::sqrt(nb[r]);
+            if (!std::isfinite(rr[r])) throw Error{H1W_ENUMERIC, "non-finite right-hand side"};
+            nb[r] = std::sqrt(rr[r]);
             if (nb[r] == 0.0) act[r] = 0;
         }
-        put((double*)dact, act.data(), kk * sizeof(int));
+        put_act();
         vcycle_B(kk, R, P, Zv, P);
         H1W_HIP(hipMemcpy2DAsync(Pv, P * sizeof(double), Zv, P * sizeof(double), n * sizeof(double), kk,
                                  hipMemcpyDeviceToDevice, stream));
         launch_batched_dots(stream, kk, n, R, P, Zv, P, pp, drz);
-        fetch(drz, rz);
         int it = 0;
         bool done = std::none_of(act.begin(), act.end(), [](int v) { return v; });
         while (!done) {
@@ -442,15 +448,11 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
             }
             apply_A(kk, Pv, P, Q, P);
             launch_batched_dots(stream, kk, n, Pv, P, Q, P, pp, dpq);
-            fetch(dpq, pq);
-            for (int r = 0; r < kk; ++r) {
-                if (act[r] && !(pq[r] > 0.0)) throw Error{H1W_ENUMERIC, "MG-PCG breakdown (p.Ap <= 0 or NaN)"};
-                a[r] = act[r] ? rz[r] / pq[r] : 0.0;
-            }
-            put(da, a.data(), kk * sizeof(double));
+            launch_pcg_alpha(stream, kk, drz, dpq, dact, da, iflag.as<int>() + 8);
             launch_batched_cg_xr(stream, kk, n, da, Pv, P, Q, P, Xc, ldx, R, P, dact);
             launch_batched_dots(stream, kk, n, R, P, R, P, pp, dnrm);
-            fetch(dnrm, rr);
+            fetch_norms();
+            if (hflag) throw Error{H1W_ENUMERIC, "MG-PCG breakdown (p.Ap <= 0 or NaN)"};
             ++it;
             bool any = false;
             for (int r = 0; r < kk; ++r) {
@@ -459,22 +461,14 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
                 if (std::sqrt(rr[r]) <= rtol * nb[r]) act[r] = 0;
                 any = any || act[r];
             }
-            put((double*)dact, act.data(), kk * sizeof(int));
+            put_act();
             if (!any) break;
             vcycle_B(kk, R, P, Zv, P);
-            launch_batched_dots(stream, kk, n, R, P, Zv, P, pp, drz);
+            launch_batched_dots(stream, kk, n, R, P, Zv, P, pp, drzn);
+            // flexible (Polak-Ribiere) coefficient z.(r_new - r_old)/rz when B is an
+            // FP32 cycle, with r_new - r_old = -a q
             if (fp32) launch_batched_dots(stream, kk, n, Zv, P, Q, P, pp, dzq);
-            std::vector<double> rzn(kk);
-            fetch(drz, rzn);
-            if (fp32) fetch(dzq, zq);
-            for (int r = 0; r < kk; ++r) {
-                if (!act[r]) { bcoef[r] = 0.0; continue; }
-                // flexible (Polak-Ribiere) coefficient z.(r_new - r_old)/rz when B is an
-                // FP32 cycle, with r_new - r_old = -a q
-                bcoef[r] = fp32 ? -a[r] * zq[r] / rz[r] : rzn[r] / rz[r];
-                rz[r] = rzn[r];
-            }
-            put(db, bcoef.data(), kk * sizeof(double));
+            launch_pcg_beta(stream, kk, drzn, drz, fp32 ? dzq : nullptr, da, dact, db);
             launch_batched_p(stream, kk, n, db, Zv, P, Pv, P, dact);
         }
         // verify with the true residual
@@ -482,7 +476,7 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
         for (int r = 0; r < kk; ++r)
             launch_sub(stream, n, Fc + (int64_t)r * ldf, Q + (int64_t)r * P, R + (int64_t)r * P);
         launch_batched_dots(stream, kk, n, R, P, R, P, pp, dnrm);
-        fetch(dnrm, rr);
+        fetch_norms();
         double worst = 0.0;
         for (int r = 0; r < kk; ++r) worst = std::max(worst, nb[r] > 0 ? std::sqrt(rr[r]) / nb[r] : 0.0);
         if (info) info->relres_true = std::max(info->relres_true, worst);

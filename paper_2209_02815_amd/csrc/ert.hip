@@ -24,7 +24,9 @@
 // w_e = sigma_j g_e / 2 (the derivative of c_jq with respect to m_j), for
 // measurement i = (a, b). A work-group stages the edge differences of every
 // source field for TN consecutive nodes in LDS and then writes TN consecutive
-// entries of each row of J (coalesced), or accumulates sum_i gbar_i J[i, j].
+// entries of each row of J (coalesced), or accumulates sum_i gbar_i J[i, j];
+// the weighted differences of the first electrode stay in registers across
+// consecutive pairs that share it (pairs listed with a fixed first electrode).
 #include <algorithm>
 #include <cmath>
 
@@ -63,11 +65,14 @@ __device__ __forceinline__ double geom_z(const EG& g, int i, int j) {
     return g.hx * g.hy / g.hz * endw(i, g.nx) * endw(j, g.ny);
 }
 
+// node index -> (i, j, l) with two 32-bit divisions (N < 2^31)
 __device__ __forceinline__ void split(const EG& g, int64_t p, int& i, int& j, int& l) {
-    i = (int)(p % g.nx);
-    const int64_t t = p / g.nx;
-    j = (int)(t % g.ny);
-    l = (int)(t / g.ny);
+    const unsigned q = (unsigned)p;
+    const unsigned t = q / (unsigned)g.nx;
+    i = (int)(q - t * (unsigned)g.nx);
+    const unsigned z = t / (unsigned)g.ny;
+    j = (int)(t - z * (unsigned)g.ny);
+    l = (int)z;
 }
 
 __global__ __launch_bounds__(kBlock) void k_ert_sigma(int64_t N, const double* __restrict__ logsig,
@@ -144,39 +149,70 @@ __global__ __launch_bounds__(kBlock) void k_ert_coeffs(EG g, const double* __res
 
 enum { kErtApply = 0, kErtResidual = 1, kErtSmooth = 2, kErtFirst = 3 };
 
-// one pass over a batch: APPLY Y = A X; RESIDUAL Y = F - A X;
-// SMOOTH Y = X + w D^-1 (F - A X); FIRST Y = w D^-1 F
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_ert_step(EG g, ErtLevel c, const double* __restrict__ F, int64_t ldf,
-                                                     const double* __restrict__ X, int64_t ldx,
-                                                     double* __restrict__ Y, int64_t ldy, double w) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= g.N) return;
-    const int64_t r = blockIdx.y;
-    const double d = c.D[p];
-    if (MODE == kErtFirst) {
-        Y[r * ldy + p] = w * F[r * ldf + p] / d;
-        return;
+// One pass over a batch: APPLY Y = A X; RESIDUAL Y = F - A X;
+// SMOOTH Y = X + w D^-1 (F - A X); FIRST Y = w D^-1 F.
+// A thread owns one in-plane position and R right-hand sides and marches up a
+// chunk of zc planes (fewer on small levels, so that the launch still has
+// enough work-groups); every coefficient is read once for the R right-hand
+// sides. All loads are unconditional so that they issue together:
+// a neighbour outside the grid is replaced by a clamped in-range index whose
+// coupling is zero (the coupling of an edge that leaves the grid is stored as
+// 0, and so is that of the node before the first node of a row or plane), and
+// right-hand sides beyond k read row k - 1 and store nothing.
+constexpr int kErtZChunk = 8;
+constexpr int kErtRhs = 4;
+template <int MODE, int R>
+__global__ __launch_bounds__(kBlock) void k_ert_march(EG g, ErtLevel c, int k, int zc, const double* __restrict__ F,
+                                                      int64_t ldf, const double* __restrict__ X, int64_t ldx,
+                                                      double* __restrict__ Y, int64_t ldy, double w) {
+    const int PL = g.nx * g.ny;
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= PL) return;
+    const int r0 = blockIdx.z * R;
+    const int nr = min(R, k - r0);
+    const int z0 = blockIdx.y * zc, z1 = min(g.nz, z0 + zc);
+    const int64_t last = g.N - 1;
+    const double* xr[R];
+    const double* fr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = min(r0 + r, k - 1);
+        xr[r] = X + row * ldx;
+        fr[r] = F + row * ldf;
     }
-    int i, j, l;
-    split(g, p, i, j, l);
-    const int64_t PY = g.nx, PZ = (int64_t)g.nx * g.ny;
-    const double* x = X + r * ldx;
-    double s = 0.0;
-    if (i < g.nx - 1) s += c.cx[p] * x[p + 1];
-    if (i > 0) s += c.cx[p - 1] * x[p - 1];
-    if (j < g.ny - 1) s += c.cy[p] * x[p + PY];
-    if (j > 0) s += c.cy[p - PY] * x[p - PY];
-    if (l < g.nz - 1) s += c.cz[p] * x[p + PZ];
-    if (l > 0) s += c.cz[p - PZ] * x[p - PZ];
-    const double x0 = x[p];
-    const double ax = d * x0 - s;
-    if (MODE == kErtApply) {
-        Y[r * ldy + p] = ax;
-    } else if (MODE == kErtResidual) {
-        Y[r * ldy + p] = F[r * ldf + p] - ax;
-    } else {
-        Y[r * ldy + p] = x0 + w * (F[r * ldf + p] - ax) / d;
+    for (int l = z0; l < z1; ++l) {
+        const int64_t p = (int64_t)l * PL + q;
+        const double d = c.D[p];
+        if (MODE == kErtFirst) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nr) Y[(int64_t)(r0 + r) * ldy + p] = w * fr[r][p] / d;
+            continue;
+        }
+        const int64_t pxm = max(p - 1, (int64_t)0), pym = max(p - g.nx, (int64_t)0);
+        const int64_t pzm = max(p - PL, (int64_t)0);
+        const int64_t pxp = min(p + 1, last), pyp = min(p + g.nx, last), pzp = min(p + PL, last);
+        const double cxp = c.cx[p], cxm = c.cx[pxm] * (p > 0);
+        const double cyp = c.cy[p], cym = c.cy[pym] * (p >= g.nx);
+        const double czp = c.cz[p], czm = c.cz[pzm] * (p >= PL);
+        double v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double* x = xr[r];
+            const double x0 = x[p];
+            const double s = ((cxp * x[pxp] + cxm * x[pxm]) + (cyp * x[pyp] + cym * x[pym])) +
+                             (czp * x[pzp] + czm * x[pzm]);
+            const double ax = d * x0 - s;
+            if (MODE == kErtApply)
+                v[r] = ax;
+            else if (MODE == kErtResidual)
+                v[r] = fr[r][p] - ax;
+            else
+                v[r] = x0 + w * (fr[r][p] - ax) / d;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r < nr) Y[(int64_t)(r0 + r) * ldy + p] = v[r];
     }
 }
 
@@ -215,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_ert_restrict(EG gf, EG gc, const dou
 // work-group. Writes the symmetrised inverse; flag[0] = 1 on a non-positive
 // or non-finite pivot.
 constexpr int kErtCoarseMax = 128;
-constexpr int kGJThreads = 256;
+constexpr int kGJThreads = 1024;
 __global__ __launch_bounds__(kGJThreads) void k_ert_coarse_inverse(EG g, ErtLevel c, double* __restrict__ Cinv,
                                                                    int* __restrict__ flag) {
     __shared__ double a[kErtCoarseMax * kErtCoarseMax];
@@ -238,6 +274,9 @@ __global__ __launch_bounds__(kGJThreads) void k_ert_coarse_inverse(EG g, ErtLeve
         if (l > 0) row[p - PZ] = -c.cz[p - PZ];
     }
     __syncthreads();
+    // rows go to the waves, columns to the lanes (no index division)
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int kWaves = kGJThreads / 64;
     for (int k = 0; k < n; ++k) {
         double piv = a[k * n + k];
         if (!(piv > 0.0 && piv <= 1.79e308)) {
@@ -250,19 +289,20 @@ __global__ __launch_bounds__(kGJThreads) void k_ert_coarse_inverse(EG g, ErtLeve
             pcol[t] = a[t * n + k];
         }
         __syncthreads();
-        for (int t = tid; t < n * n; t += kGJThreads) {
-            const int i = t / n, j = t - i * n;
-            if (i == k)
-                a[t] = (j == k) ? inv : prow[j];
-            else
-                a[t] = (j == k) ? -pcol[i] * inv : a[t] - pcol[i] * prow[j];
+        for (int i = wv; i < n; i += kWaves) {
+            const double ci = pcol[i];
+            double* row = a + i * n;
+            for (int j = lane; j < n; j += 64) {
+                if (i == k)
+                    row[j] = (j == k) ? inv : prow[j];
+                else
+                    row[j] = (j == k) ? -ci * inv : row[j] - ci * prow[j];
+            }
         }
         __syncthreads();
     }
-    for (int t = tid; t < n * n; t += kGJThreads) {
-        const int i = t / n, j = t - i * n;
-        Cinv[t] = 0.5 * (a[i * n + j] + a[j * n + i]);
-    }
+    for (int i = wv; i < n; i += kWaves)
+        for (int j = lane; j < n; j += 64) Cinv[i * n + j] = 0.5 * (a[i * n + j] + a[j * n + i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ert_unit_loads(int64_t N, const int* __restrict__ src,
@@ -360,11 +400,22 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
 #pragma unroll
     for (int e = 0; e < 6; ++e) w[e] = we[e * TN + t];
     double acc_all = 0.0;
-    for (int i = grp; i < n_meas; i += G) {
+    // each group takes a contiguous range of measurements; w_e (u_a(j) - u_a(q))
+    // is kept in registers while consecutive pairs share their first electrode
+    const int per = (n_meas + G - 1) / G;
+    const int i0 = grp * per, i1 = min(n_meas, i0 + per);
+    int a_cur = -1;
+    double wa[6];
+    for (int i = i0; i < i1; ++i) {
         const int a = pair[2 * i], b = pair[2 * i + 1];
+        if (a != a_cur) {
+#pragma unroll
+            for (int e = 0; e < 6; ++e) wa[e] = w[e] * dl[(e * NS + a) * TN + t];
+            a_cur = a;
+        }
         double acc = 0.0;
 #pragma unroll
-        for (int e = 0; e < 6; ++e) acc += w[e] * dl[(e * NS + a) * TN + t] * dl[(e * NS + b) * TN + t];
+        for (int e = 0; e < 6; ++e) acc += wa[e] * dl[(e * NS + b) * TN + t];
         if (VJP) {
             acc_all += gbar[i] * k[i] * acc;
         } else if (p < g.N) {
@@ -385,19 +436,27 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
 void launch_step(hipStream_t s, int mode, const EG& g, const ErtLevel& c, int k, const double* F, int64_t ldf,
                  const double* X, int64_t ldx, double* Y, int64_t ldy, double w) {
     if (k <= 0) return;
-    const dim3 grid((unsigned)cdiv(g.N, kBlock), (unsigned)k);
+    const int64_t PL = (int64_t)g.nx * g.ny;
+    const int64_t base = cdiv(PL, kBlock) * cdiv(k, kErtRhs);
+    const int zc = (int)std::clamp<int64_t>(base * g.nz / 2048, 1, kErtZChunk);
+    const dim3 grid((unsigned)cdiv(PL, kBlock), (unsigned)cdiv(g.nz, zc), (unsigned)cdiv(k, kErtRhs));
+    require(grid.z <= 65535, "too many right-hand sides in one ERT launch");
     switch (mode) {
         case kErtApply:
-            hipLaunchKernelGGL(k_ert_step<kErtApply>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+            hipLaunchKernelGGL((k_ert_march<kErtApply, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X, ldx, Y,
+                               ldy, w);
             break;
         case kErtResidual:
-            hipLaunchKernelGGL(k_ert_step<kErtResidual>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+            hipLaunchKernelGGL((k_ert_march<kErtResidual, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X,
+                               ldx, Y, ldy, w);
             break;
         case kErtSmooth:
-            hipLaunchKernelGGL(k_ert_step<kErtSmooth>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+            hipLaunchKernelGGL((k_ert_march<kErtSmooth, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X, ldx,
+                               Y, ldy, w);
             break;
         default:
-            hipLaunchKernelGGL(k_ert_step<kErtFirst>, grid, dim3(kBlock), 0, s, g, c, F, ldf, X, ldx, Y, ldy, w);
+            hipLaunchKernelGGL((k_ert_march<kErtFirst, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X, ldx, Y,
+                               ldy, w);
     }
     H1W_LAUNCHED();
 }

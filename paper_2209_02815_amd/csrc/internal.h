@@ -180,6 +180,11 @@ void launch_batched_dots(hipStream_t s, int k, int64_t N, const double* X, int64
 void launch_batched_cg_xr(hipStream_t s, int k, int64_t N, const double* a, const double* P,
                           int64_t ldp, const double* Q, int64_t ldq, double* X, int64_t ldx,
                           double* R, int64_t ldr, const int* active);
+// device-side step lengths and direction coefficients of the batched PCG
+void launch_pcg_alpha(hipStream_t s, int k, const double* rz, const double* pq, const int* active, double* a,
+                      int* flag);
+void launch_pcg_beta(hipStream_t s, int k, const double* rzn, double* rz, const double* zq, const double* a,
+                     const int* active, double* b);
 void launch_batched_p(hipStream_t s, int k, int64_t N, const double* b, const double* Z,
                       int64_t ldz, double* P, int64_t ldp, const int* active);
 
