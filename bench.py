@@ -242,17 +242,21 @@ def batch_bench(args, threads):
     out = {"workload": f"{len(wls)} 2D instances, sides {H.BATCH_DEFAULT['sides']}, m in [16, 128], "
                        f"alpha log-uniform in [1e-5, 1e-2], beta 1e-2, rtol {args.rtol}",
            "rows": sum(w.m for w in wls), "nodes": sum(w.N for w in wls)}
-    for label, prec, nw, tune in (("fp64", nat.H1W_FP64, 4, True), ("mixed", nat.H1W_MIXED, 4, True),
-                                  ("fp64_one_worker", nat.H1W_FP64, 1, False)):
-        nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol)
+    for label, prec, nw, tune, gr in (("fp64", nat.H1W_FP64, 4, True, False),
+                                      ("mixed", nat.H1W_MIXED, 4, True, False),
+                                      ("fp64_graphs", nat.H1W_FP64, 4, True, True),
+                                      ("mixed_graphs", nat.H1W_MIXED, 4, True, True),
+                                      ("fp64_one_worker", nat.H1W_FP64, 1, False, False)):
+        nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol, graphs=gr)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        infos, stats, rep = nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol)
+        infos, stats, rep = nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol,
+                                                graphs=gr)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         worst = max(i.relres_true for i in infos)
         out[label] = {"instances_per_s": len(items) / dt, "ms": 1e3 * dt, "workers": rep.nworkers,
-                      "autotune": tune, "iters_total": int(sum(i.iters for i in infos)),
+                      "autotune": tune, "graphs": gr, "iters_total": int(sum(i.iters for i in infos)),
                       "worst_relres_true": worst,
                       "nu_chosen": sorted({rep.tuned[k].nu for k in range(rep.ntuned)}) if tune else None}
         log(f"batch {label}: {out[label]}")

@@ -101,6 +101,13 @@ typedef struct {
  * sequence of single-step stencil kernels instead of the fused down/up passes
  * (same cycle, same result up to rounding; more memory traffic). */
 #define H1W_FLAG_UNFUSED_VCYCLE 2u
+/* grid_desc.flags: replay V-cycles from HIP graphs. The kernel sequence of a
+ * V-cycle applied to the same (k, F, X) buffers is captured into a graph on
+ * its second use and replayed afterwards (the CG's preconditioner applies
+ * reuse the same context buffers at every iteration and across solves), which
+ * removes the per-kernel launch cost for small grids. Same results, bit for
+ * bit. Ignored while kernel timing is on. H1 contexts only. */
+#define H1W_FLAG_GRAPH_VCYCLE 4u
 
 /* Krylov options (h1w_gn_solve). A zeroed struct selects the defaults. */
 typedef struct {
@@ -317,6 +324,8 @@ typedef struct {
     int nu;              /* smoothing steps when not tuned (0 -> 2) */
     double rtol;         /* as h1w_solve_opts.rtol (0 -> 1e-10) */
     int maxit;           /* as h1w_solve_opts.maxit (0 -> 500) */
+    int graphs;          /* 1: contexts replay their V-cycles from HIP graphs
+                            (H1W_FLAG_GRAPH_VCYCLE) */
 } h1w_batch_opts;
 
 #define H1W_BATCH_MAX_KEYS 64

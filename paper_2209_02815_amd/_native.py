@@ -61,7 +61,7 @@ class h1w_batch_item(C.Structure):
 
 class h1w_batch_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("nworkers", C.c_int), ("autotune", C.c_int), ("nu", C.c_int),
-                ("rtol", C.c_double), ("maxit", C.c_int)]
+                ("rtol", C.c_double), ("maxit", C.c_int), ("graphs", C.c_int)]
 
 
 H1W_BATCH_MAX_KEYS = 64
@@ -168,6 +168,7 @@ def _dtype_code(t):
 # ------------------------------------------------------------------ entry points
 H1W_FLAG_STREAM_Z = 1
 H1W_FLAG_UNFUSED_VCYCLE = 2
+H1W_FLAG_GRAPH_VCYCLE = 4
 H1W_SOLVE_LAPLACE_ONLY = 1
 H1W_SOLVE_EXACT_B = 2
 H1W_OP_H1GRAM, H1W_OP_ERT = 0, 1
@@ -336,7 +337,7 @@ def h1w_reset_kernel_timing(ctx):
 
 
 def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotune: bool = False, nu: int = 0,
-                    rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True):
+                    rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True, graphs: bool = False):
     """items: list of dicts with shape, beta, alpha, J (CUDA (m, N) float64 or None), b, x.
     Returns (infos, statuses, report); raises on the first failing item unless raise_on_error is False."""
     arr = (h1w_batch_item * max(1, len(items)))()
@@ -359,7 +360,8 @@ def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotun
             if not t.is_cuda or t.dtype != __import__("torch").float64 or t.numel() != N or not t.is_contiguous():
                 raise ValueError(f"item {i}: {name} must be a contiguous float64 CUDA vector of N entries")
         e.b, e.x = it["b"].data_ptr(), it["x"].data_ptr()
-    opts = h1w_batch_opts(int(precision), int(nworkers), int(bool(autotune)), int(nu), float(rtol), int(maxit))
+    opts = h1w_batch_opts(int(precision), int(nworkers), int(bool(autotune)), int(nu), float(rtol), int(maxit),
+                          int(bool(graphs)))
     infos = (h1w_info * max(1, len(items)))()
     stats = (C.c_int * max(1, len(items)))()
     rep = h1w_batch_report()

@@ -381,6 +381,7 @@ h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_bat
                            h1w_info* infos, h1w_status* status, h1w_batch_report* report) {
     g_setup_error.clear();
     h1w_status st = H1W_OK;
+    std::string item_msg;
     try {
         require(count >= 0, "count must be >= 0");
         require(count == 0 || items != nullptr, "items is NULL");
@@ -389,13 +390,14 @@ h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_bat
         require(opts->nworkers >= 0 && opts->nu >= 0 && opts->nu <= 16 && opts->maxit >= 0,
                 "nworkers, nu and maxit must be >= 0 (nu <= 16)");
         require(std::isfinite(opts->rtol) && opts->rtol >= 0.0, "rtol must be >= 0");
+        require(opts->graphs == 0 || opts->graphs == 1, "graphs must be 0 or 1");
         std::vector<h1w_status> own;
         h1w_status* stp = status;
         if (!stp) {
             own.assign((size_t)count, H1W_OK);
             stp = own.data();
         }
-        h1w::batch_solve(count, items, *opts, infos, stp, report);
+        h1w::batch_solve(count, items, *opts, infos, stp, report, &item_msg);
         for (int i = 0; i < count && st == H1W_OK; ++i) st = stp[i];
     } catch (const h1w::Error& e) {
         g_setup_error = e.msg;
@@ -407,7 +409,8 @@ h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_bat
         g_setup_error = e.what();
         return H1W_EINVAL;
     }
-    if (st != H1W_OK) g_setup_error = std::string("a batch item failed: ") + h1w_status_string(st);
+    if (st != H1W_OK)
+        g_setup_error = std::string("a batch item failed: ") + h1w_status_string(st) + " (" + item_msg + ")";
     return st;
 }
 

@@ -72,7 +72,7 @@ struct Worker {
 }  // namespace
 
 void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
-                 h1w_status* status, h1w_batch_report* report) {
+                 h1w_status* status, h1w_batch_report* report, std::string* first_err) {
     int device = 0;
     H1W_HIP(hipGetDevice(&device));
     const int nworkers = std::clamp(o.nworkers > 0 ? o.nworkers : 4, 1, 16);
@@ -94,6 +94,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     std::atomic<int> next{0};
     std::vector<Worker> workers(nworkers);
     std::vector<std::string> worker_err(nworkers);
+    std::vector<std::string> item_err(count);
 
     auto choose_nu = [&](const TuneKey& tk, bool& tuning) -> int {
         tuning = false;
@@ -120,6 +121,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
         Worker& me = workers[w];
         try {
             H1W_HIP(hipSetDevice(device));
+            std::lock_guard<std::recursive_mutex> lk(capture_lock());
             H1W_HIP(hipStreamCreateWithFlags(&me.stream, hipStreamNonBlocking));
         } catch (const Error& e) {
             worker_err[w] = e.msg;
@@ -157,6 +159,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                     d.beta = it.beta;
                     d.precision = o.precision;
                     d.nu = nu;
+                    d.flags = o.graphs ? H1W_FLAG_GRAPH_VCYCLE : 0u;
                     auto c = std::make_unique<Ctx>();
                     c->init(d, me.stream);
                     slot = std::move(c);
@@ -175,10 +178,13 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 if (tuning) record(tk, nu, ms / work(i));
             } catch (const Error& e) {
                 st = e.st;
+                item_err[i] = e.msg;
             } catch (const std::bad_alloc&) {
                 st = H1W_ENOMEM;
-            } catch (const std::exception&) {
+                item_err[i] = "host allocation failed";
+            } catch (const std::exception& e) {
                 st = H1W_EINVAL;
+                item_err[i] = e.what();
             }
             if (infos) infos[i] = inf;
             if (status) status[i] = st;
@@ -199,6 +205,12 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     }
     for (const auto& e : worker_err)
         if (!e.empty()) throw Error{H1W_EHIP, "batch worker setup failed: " + e};
+    if (first_err) {
+        first_err->clear();
+        for (int q = 0; q < count && first_err->empty(); ++q)
+            if (!item_err[order[q]].empty())
+                *first_err = "item " + std::to_string(order[q]) + ": " + item_err[order[q]];
+    }
     if (report) {
         *report = h1w_batch_report{};
         report->t_total_ms = total_ms;

@@ -85,6 +85,29 @@ struct Ctx {
     // solve to exact_rtol while exact_b is set (the EXACT_B solve mode)
     void apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
     void vcycle_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
+    void vcycle_B_eager(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
+
+    // hipGraph replay of the V-cycle (H1W_FLAG_GRAPH_VCYCLE): the kernel
+    // sequence of vcycle_B for one (k, F, X) is captured on its second use
+    // and replayed afterwards; the graphs refer to the workspace buffers, so
+    // they are dropped whenever one of those is reallocated
+    struct VGraph {
+        int k;
+        const double* F;
+        int64_t ldf;
+        double* X;
+        int64_t ldx;
+        hipGraphExec_t exec;
+    };
+    bool graphs = false;
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;  // private stream the V-cycle graphs are captured on
+    std::vector<VGraph> vgraphs;
+    std::vector<const void*> vg_sig;
+    int64_t graph_launches = 0;
+    std::vector<const void*> workspace_signature() const;
+    void clear_graphs();
+    void vcycle_graph(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
     bool exact_b = false;
     double exact_rtol = 1e-12;
     void mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, double rtol, int maxit,

@@ -103,7 +103,9 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     if (!ert) require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
     require(d.precision == H1W_FP64 || d.precision == H1W_MIXED, "precision must be H1W_FP64 or H1W_MIXED");
     require(d.nu >= 0 && d.nu <= 16, "nu must be in [0, 16]");
-    require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE)) == 0, "unknown bits in flags");
+    require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE | H1W_FLAG_GRAPH_VCYCLE)) == 0,
+            "unknown bits in flags");
+    graphs = (d.flags & H1W_FLAG_GRAPH_VCYCLE) != 0;
     require(d.coarse_max >= 0, "coarse_max must be >= 0");
     require(d.rhs_chunk >= 0 && d.rhs_chunk <= 65535, "rhs_chunk must be in [0, 65535]");
     if (d.nu == 0) d.nu = 2;
@@ -143,7 +145,10 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     pitch.resize(lv.size());
     for (size_t l = 0; l < lv.size(); ++l) pitch[l] = cdiv(lv[l].N, 64) * 64;
     chunk = d.rhs_chunk > 0 ? d.rhs_chunk : (int)std::clamp<int64_t>((int64_t(1) << 26) / N0, 1, 1024);
-    H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
+    {
+        std::lock_guard<std::recursive_mutex> lk(capture_lock());
+        H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
+    }
     scal.reserve(64 * sizeof(double));
     iflag.reserve(16 * sizeof(int));
     cpart_elems = coarse_part_elems(Nc);
@@ -164,10 +169,13 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
             inv[(size_t)(i * Nc + j)] = inv[(size_t)(j * Nc + i)] = a;
         }
     cinv64.reserve(inv.size() * sizeof(double));
-    H1W_HIP(hipMemcpy(cinv64.p, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
     std::vector<float> inv32(inv.begin(), inv.end());
     cinv32.reserve(inv32.size() * sizeof(float));
-    H1W_HIP(hipMemcpy(cinv32.p, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
+    {
+        std::lock_guard<std::recursive_mutex> lk(capture_lock());
+        H1W_HIP(hipMemcpy(cinv64.p, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
+        H1W_HIP(hipMemcpy(cinv32.p, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
 
     fused = dim == 3 && d.nu == 2 && lv.size() >= 2 && !(d.flags & H1W_FLAG_UNFUSED_VCYCLE);
     for (size_t l = 0; fused && l + 1 < lv.size(); ++l) fused = fused_levels_ok(lv[l], lv[l + 1]);
@@ -178,6 +186,9 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
 }
 
 Ctx::~Ctx() {
+    std::lock_guard<std::recursive_mutex> lk(capture_lock());
+    clear_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hscal) (void)hipHostFree(hscal);
     for (auto& p : pending) {
         (void)hipEventDestroy(p.a);
@@ -332,6 +343,77 @@ void Ctx::apply_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
 
 // y = B r for FP64 vectors in the context's V-cycle precision.
 void Ctx::vcycle_B(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
+    if (graphs && !capturing && tmask == 0 && !ert) {
+        vcycle_graph(k, F, ldf, X, ldx);
+        return;
+    }
+    vcycle_B_eager(k, F, ldf, X, ldx);
+}
+
+std::vector<const void*> Ctx::workspace_signature() const {
+    return {vws.p, stage.p, part.p, jpart.p, scal.p, cpart.p, wvec.p, vdef.p, ones.p, cinv64.p, cinv32.p};
+}
+
+void Ctx::clear_graphs() {
+    for (auto& g : vgraphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    vgraphs.clear();
+}
+
+void Ctx::vcycle_graph(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
+    auto sig = workspace_signature();
+    if (sig != vg_sig) {
+        clear_graphs();
+        vg_sig = sig;
+    }
+    for (auto& g : vgraphs) {
+        if (g.k != k || g.F != F || g.ldf != ldf || g.X != X || g.ldx != ldx) continue;
+        if (!g.exec) {  // second use: capture the sequence, then replay it
+            // captured on a private stream (the context's stream may be the
+            // null stream, which cannot be captured); nothing runs during the
+            // capture, the graph is then launched on the context's stream
+            std::lock_guard<std::recursive_mutex> lk(capture_lock());
+            if (!cap_stream) H1W_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            hipGraph_t gr = nullptr;
+            const hipStream_t own = stream;
+            H1W_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+            capturing = true;
+            stream = cap_stream;
+            try {
+                vcycle_B_eager(k, F, ldf, X, ldx);
+            } catch (...) {
+                stream = own;
+                capturing = false;
+                (void)hipStreamEndCapture(cap_stream, &gr);
+                if (gr) (void)hipGraphDestroy(gr);
+                throw;
+            }
+            stream = own;
+            capturing = false;
+            H1W_HIP(hipStreamEndCapture(cap_stream, &gr));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            H1W_HIP(e);
+            g.exec = ex;
+            // the capture did not run the kernels
+        }
+        H1W_HIP(hipGraphLaunch(g.exec, stream));
+        ++graph_launches;
+        return;
+    }
+    // first use: run eagerly (this reserves the workspace) and remember the key
+    vcycle_B_eager(k, F, ldf, X, ldx);
+    sig = workspace_signature();
+    if (sig != vg_sig) {
+        clear_graphs();
+        vg_sig = sig;
+    }
+    if (vgraphs.size() >= 8) clear_graphs();
+    vgraphs.push_back(VGraph{k, F, ldf, X, ldx, nullptr});
+}
+
+void Ctx::vcycle_B_eager(int k, const double* F, int64_t ldf, double* X, int64_t ldx) {
     if (ert) {
         for (int r0 = 0; r0 < k; r0 += chunk) {
             const int kk = std::min(chunk, k - r0);

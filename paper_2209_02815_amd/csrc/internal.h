@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,17 @@ inline void require(bool ok, const std::string& msg) {
     if (!ok) throw Error{H1W_EINVAL, msg};
 }
 
+// ---------------------------------------------------------------- graph capture
+// Process-wide lock between stream captures (V-cycle graphs) and the runtime
+// calls that synchronise with every stream (allocation, release, blocking
+// copies): such a call made by another thread during a capture fails, so the
+// two never overlap. Recursive, so that a capture that had to allocate would
+// fail with the runtime's error instead of deadlocking.
+inline std::recursive_mutex& capture_lock() {
+    static std::recursive_mutex mu;
+    return mu;
+}
+
 // ---------------------------------------------------------------- device memory
 // Owning device buffer (the library's own workspace; caller arrays are raw pointers).
 struct DevBuf {
@@ -53,6 +65,7 @@ struct DevBuf {
     void release() {
         // work queued on any stream may still use the buffer
         if (p) {
+            std::lock_guard<std::recursive_mutex> lk(capture_lock());
             (void)hipDeviceSynchronize();
             (void)hipFree(p);
         }
@@ -63,6 +76,7 @@ struct DevBuf {
     void reserve(size_t need) {
         if (need <= bytes) return;
         release();
+        std::lock_guard<std::recursive_mutex> lk(capture_lock());
         hipError_t e = hipMalloc(&p, need);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -130,7 +144,7 @@ bool ert_on_dirichlet_host(const Geom& g, unsigned mask, int64_t p);
 // batch.hip: the executor behind h1w_batch_solve (throws Error on setup failures;
 // per-item failures go to status[])
 void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
-                 h1w_status* status, h1w_batch_report* report);
+                 h1w_status* status, h1w_batch_report* report, std::string* first_err);
 
 // blas.hip
 // partial dot products of npair vector pairs over N entries; returns #parts

@@ -98,3 +98,36 @@ def test_batch_bad_item_fails_alone(P):
     with pytest.raises(P.H1WError) as e:
         nat.h1w_batch_solve(items, nworkers=2, rtol=1e-10)
     assert e.value.status == nat.H1W_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replayed_vcycles_give_identical_solves(P, prec):
+    # the V-cycles of the CG replayed from HIP graphs: every solve of a
+    # sequence (different right-hand sides, row counts and grids, eager work
+    # and synchronisations in between) is bitwise the eager solve
+    rng = np.random.default_rng(9)
+    for shape, ms in (((65, 65), (24, 40, 24)), ((17, 17, 17), (12, 30))):
+        wl = H.workload("square129").with_(shape=shape, wid=900 + shape[0])
+        with P.Context(shape, 1e-2, precision=prec) as ce, P.Context(shape, 1e-2, precision=prec, graphs=True) as cg:
+            for m in ms:
+                J = dev(H.j_rows(wl.with_(m=m)))
+                b = dev(rng.standard_normal(wl.N))
+                xe, ie = ce.gn_solve(J, 1e-4, b=b, rtol=1e-8 if prec == "mixed" else 1e-10)
+                torch.cuda.synchronize()
+                _ = (b * 2.0).sum().item()              # eager work between the solves
+                xg, ig = cg.gn_solve(J, 1e-4, b=b, rtol=1e-8 if prec == "mixed" else 1e-10)
+                torch.cuda.synchronize()
+                assert ig.iters == ie.iters
+                assert torch.equal(xg, xe), (shape, m)
+
+
+def test_batch_with_graphs_matches_eager(P):
+    from paper_2209_02815_amd import _native as nat
+    wls = small_batch()
+    items_e, host = make_items(wls)
+    items_g, _ = make_items(wls)
+    nat.h1w_batch_solve(items_e, nworkers=3, rtol=1e-10)
+    infos, stats, _ = nat.h1w_batch_solve(items_g, nworkers=3, rtol=1e-10, graphs=True)
+    assert all(s == 0 for s in stats)
+    for a, b in zip(items_e, items_g):
+        assert torch.equal(a["x"], b["x"])
