@@ -152,25 +152,42 @@ enum { kErtApply = 0, kErtResidual = 1, kErtSmooth = 2, kErtFirst = 3 };
 // One pass over a batch: APPLY Y = A X; RESIDUAL Y = F - A X;
 // SMOOTH Y = X + w D^-1 (F - A X); FIRST Y = w D^-1 F.
 // A thread owns one in-plane position and R right-hand sides and marches up a
-// chunk of zc planes (fewer on small levels, so that the launch still has
-// enough work-groups); every coefficient is read once for the R right-hand
-// sides. All loads are unconditional so that they issue together:
-// a neighbour outside the grid is replaced by a clamped in-range index whose
-// coupling is zero (the coupling of an edge that leaves the grid is stored as
-// 0, and so is that of the node before the first node of a row or plane), and
-// right-hand sides beyond k read row k - 1 and store nothing.
-constexpr int kErtZChunk = 8;
+// chunk of zc planes, keeping x on the planes below and at the current one in
+// registers (each x is loaded once per chunk, plus one plane below it); the
+// in-plane neighbours come from cache. Work items (in-plane tile of kBlock
+// positions, z-chunk, group of R right-hand sides) are numbered with the
+// right-hand-side group fastest and dealt to the 8 XCDs in contiguous
+// ranges, so that the groups sharing a tile's coefficients, and neighbouring
+// tiles, run behind the same L2. All loads are unconditional so that they
+// issue together: a neighbour outside the grid is replaced by a clamped
+// in-range index whose coupling is zero (the coupling of an edge that leaves
+// the grid is stored as 0, and so is that of the node before the first node
+// of a row or plane), and right-hand sides beyond k read row k - 1 and store
+// nothing.
+constexpr int kErtZChunk = 16;
 constexpr int kErtRhs = 4;
+struct MarchGrid {
+    int ntile, nzc, ngrp, zc, total;
+};
 template <int MODE, int R>
-__global__ __launch_bounds__(kBlock) void k_ert_march(EG g, ErtLevel c, int k, int zc, const double* __restrict__ F,
-                                                      int64_t ldf, const double* __restrict__ X, int64_t ldx,
+__global__ __launch_bounds__(kBlock) void k_ert_march(EG g, ErtLevel c, int k, MarchGrid mg,
+                                                      const double* __restrict__ F, int64_t ldf,
+                                                      const double* __restrict__ X, int64_t ldx,
                                                       double* __restrict__ Y, int64_t ldy, double w) {
+    const int bid = blockIdx.x;
+    const int per = (mg.total + 7) >> 3;
+    const int wi = (bid & 7) * per + (bid >> 3);
+    if (wi >= mg.total) return;
+    const int grp = wi % mg.ngrp;
+    const int rest = wi / mg.ngrp;
+    const int tile = rest % mg.ntile;
+    const int zr = rest / mg.ntile;
     const int PL = g.nx * g.ny;
-    const int q = blockIdx.x * kBlock + threadIdx.x;
+    const int q = tile * kBlock + threadIdx.x;
     if (q >= PL) return;
-    const int r0 = blockIdx.z * R;
+    const int r0 = grp * R;
     const int nr = min(R, k - r0);
-    const int z0 = blockIdx.y * zc, z1 = min(g.nz, z0 + zc);
+    const int z0 = zr * mg.zc, z1 = min(g.nz, z0 + mg.zc);
     const int64_t last = g.N - 1;
     const double* xr[R];
     const double* fr[R];
@@ -179,6 +196,16 @@ __global__ __launch_bounds__(kBlock) void k_ert_march(EG g, ErtLevel c, int k, i
         const int64_t row = min(r0 + r, k - 1);
         xr[r] = X + row * ldx;
         fr[r] = F + row * ldf;
+    }
+    double xb[R], x0[R];
+    if (MODE != kErtFirst) {
+        const int64_t p0 = (int64_t)z0 * PL + q;
+        const int64_t pb = max(p0 - PL, (int64_t)0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            xb[r] = xr[r][pb];
+            x0[r] = xr[r][p0];
+        }
     }
     for (int l = z0; l < z1; ++l) {
         const int64_t p = (int64_t)l * PL + q;
@@ -195,24 +222,27 @@ __global__ __launch_bounds__(kBlock) void k_ert_march(EG g, ErtLevel c, int k, i
         const double cxp = c.cx[p], cxm = c.cx[pxm] * (p > 0);
         const double cyp = c.cy[p], cym = c.cy[pym] * (p >= g.nx);
         const double czp = c.cz[p], czm = c.cz[pzm] * (p >= PL);
-        double v[R];
+        double v[R], xa[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double* x = xr[r];
-            const double x0 = x[p];
+            xa[r] = x[pzp];
             const double s = ((cxp * x[pxp] + cxm * x[pxm]) + (cyp * x[pyp] + cym * x[pym])) +
-                             (czp * x[pzp] + czm * x[pzm]);
-            const double ax = d * x0 - s;
+                             (czp * xa[r] + czm * xb[r]);
+            const double ax = d * x0[r] - s;
             if (MODE == kErtApply)
                 v[r] = ax;
             else if (MODE == kErtResidual)
                 v[r] = fr[r][p] - ax;
             else
-                v[r] = x0 + w * (fr[r][p] - ax) / d;
+                v[r] = x0[r] + w * (fr[r][p] - ax) / d;
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r) {
             if (r < nr) Y[(int64_t)(r0 + r) * ldy + p] = v[r];
+            xb[r] = x0[r];
+            x0[r] = xa[r];
+        }
     }
 }
 
@@ -436,27 +466,33 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
 void launch_step(hipStream_t s, int mode, const EG& g, const ErtLevel& c, int k, const double* F, int64_t ldf,
                  const double* X, int64_t ldx, double* Y, int64_t ldy, double w) {
     if (k <= 0) return;
-    const int64_t PL = (int64_t)g.nx * g.ny;
-    const int64_t base = cdiv(PL, kBlock) * cdiv(k, kErtRhs);
-    const int zc = (int)std::clamp<int64_t>(base * g.nz / 2048, 1, kErtZChunk);
-    const dim3 grid((unsigned)cdiv(PL, kBlock), (unsigned)cdiv(g.nz, zc), (unsigned)cdiv(k, kErtRhs));
-    require(grid.z <= 65535, "too many right-hand sides in one ERT launch");
+    MarchGrid mg{};
+    mg.ntile = (int)cdiv((int64_t)g.nx * g.ny, kBlock);
+    mg.ngrp = (int)cdiv(k, kErtRhs);
+    // planes per work item: as many as keep >= ~2048 work-groups in the launch
+    const int64_t base = (int64_t)mg.ntile * mg.ngrp;
+    mg.zc = (int)std::clamp<int64_t>(base * g.nz / 2048, 1, kErtZChunk);
+    mg.nzc = (int)cdiv(g.nz, mg.zc);
+    require(base * mg.nzc < (int64_t(1) << 31), "ERT launch too large");
+    mg.total = (int)(base * mg.nzc);
+    // 8 equal ranges of items, one per XCD (block ids go round-robin over the XCDs)
+    const dim3 grid((unsigned)(8 * cdiv(mg.total, 8)));
     switch (mode) {
         case kErtApply:
-            hipLaunchKernelGGL((k_ert_march<kErtApply, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X, ldx, Y,
-                               ldy, w);
-            break;
-        case kErtResidual:
-            hipLaunchKernelGGL((k_ert_march<kErtResidual, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X,
+            hipLaunchKernelGGL((k_ert_march<kErtApply, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, mg, F, ldf, X,
                                ldx, Y, ldy, w);
             break;
+        case kErtResidual:
+            hipLaunchKernelGGL((k_ert_march<kErtResidual, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, mg, F, ldf,
+                               X, ldx, Y, ldy, w);
+            break;
         case kErtSmooth:
-            hipLaunchKernelGGL((k_ert_march<kErtSmooth, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X, ldx,
-                               Y, ldy, w);
+            hipLaunchKernelGGL((k_ert_march<kErtSmooth, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, mg, F, ldf, X,
+                               ldx, Y, ldy, w);
             break;
         default:
-            hipLaunchKernelGGL((k_ert_march<kErtFirst, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, zc, F, ldf, X, ldx, Y,
-                               ldy, w);
+            hipLaunchKernelGGL((k_ert_march<kErtFirst, kErtRhs>), grid, dim3(kBlock), 0, s, g, c, k, mg, F, ldf, X,
+                               ldx, Y, ldy, w);
     }
     H1W_LAUNCHED();
 }
