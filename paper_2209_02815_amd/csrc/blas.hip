@@ -271,9 +271,11 @@ __global__ __launch_bounds__(kBlock) void k_p_stored(int m, int64_t N, const TZ*
 }
 
 __global__ __launch_bounds__(kBlock) void k_axpby(int64_t N, double a, const double* __restrict__ x,
-                                                  double b, double* __restrict__ y) {
+                                                  double b, const double* __restrict__ bdev,
+                                                  double* __restrict__ y) {
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (n < N) y[n] = a * x[n] + (b == 0.0 ? 0.0 : b * y[n]);
+    const double bb = bdev ? *bdev : b;
+    if (n < N) y[n] = a * x[n] + (bb == 0.0 ? 0.0 : bb * y[n]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sub(int64_t N, const double* __restrict__ b,
@@ -284,11 +286,12 @@ __global__ __launch_bounds__(kBlock) void k_sub(int64_t N, const double* __restr
 }
 
 // x += a p ; r -= a q ; partial sums of r.r
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, double a, const double* __restrict__ p,
-                                                      const double* __restrict__ q,
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, double a0, const double* __restrict__ adev,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                       double* __restrict__ x, double* __restrict__ r,
                                                       double* __restrict__ partial) {
     __shared__ double sh[kBlock / 64];
+    const double a = adev ? *adev : a0;
     double acc = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x; n < N;
          n += (int64_t)gridDim.x * kBlock) {
@@ -515,7 +518,63 @@ void launch_p_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, 
 }
 
 void launch_axpby(hipStream_t s, int64_t N, double a, const double* x, double b, double* y) {
-    hipLaunchKernelGGL(k_axpby, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, a, x, b, y);
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, a, x, b, (const double*)nullptr,
+                       y);
+    H1W_LAUNCHED();
+}
+
+void launch_axpby_dev(hipStream_t s, int64_t N, double a, const double* x, const double* bdev, double* y) {
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, a, x, 0.0, bdev, y);
+    H1W_LAUNCHED();
+}
+
+// Scalars of the Gauss-Newton CG kept on the device (dsc = scal + kGnScal):
+// dsc[0] = r.z, [1] = step length a, [2] = direction coefficient beta,
+// [3] = p.q, [4] = r.r, [5] = 1 if r.z <= 0 at the last preconditioner step,
+// [6] = 1 if p.q <= 0, [7] = 1 if p.q is not finite.
+// beta from the dot products s[0], s[1] of the preconditioner step:
+// mode 0 (recompute form) r.z = (s0 - s1) / alpha; mode 1 (stored Z)
+// r.z = s0, z.q = s1; mode 2 (no Woodbury correction) r.z = s0 / alpha,
+// z.q = s1 / alpha. beta = 0 on a first step, else z.(r_new - r_old)/r.z
+// (flexible, with r_new - r_old = -a q) or r.z_new / r.z.
+__global__ void k_gn_beta(const double* __restrict__ sdot, double ia, int mode, int first, int flexible,
+                          double* __restrict__ dsc) {
+    if (threadIdx.x != 0) return;
+    double rzn, zq = 0.0;
+    if (mode == 0) {
+        rzn = (sdot[0] - sdot[1]) * ia;
+    } else if (mode == 1) {
+        rzn = sdot[0];
+        zq = sdot[1];
+    } else {
+        rzn = sdot[0] * ia;
+        zq = sdot[1] * ia;
+    }
+    const bool ok = rzn > 0.0;
+    double beta = 0.0;
+    if (ok && !first) beta = flexible ? -dsc[1] * zq / dsc[0] : rzn / dsc[0];
+    dsc[2] = beta;
+    if (ok) dsc[0] = rzn;
+    dsc[5] = ok ? 0.0 : 1.0;
+}
+
+// a = r.z / p.q, or 0 when the step must not be taken
+__global__ void k_gn_alpha(double* __restrict__ dsc) {
+    if (threadIdx.x != 0) return;
+    const double pq = dsc[3];
+    const bool finite = pq >= -1.79e308 && pq <= 1.79e308;
+    dsc[7] = finite ? 0.0 : 1.0;
+    dsc[6] = (finite && !(pq > 0.0)) ? 1.0 : 0.0;
+    dsc[1] = (dsc[5] == 0.0 && finite && pq > 0.0) ? dsc[0] / pq : 0.0;
+}
+
+void launch_gn_beta(hipStream_t s, const double* sdot, double ia, int mode, bool first, bool flexible, double* dsc) {
+    hipLaunchKernelGGL(k_gn_beta, dim3(1), dim3(64), 0, s, sdot, ia, mode, (int)first, (int)flexible, dsc);
+    H1W_LAUNCHED();
+}
+
+void launch_gn_alpha(hipStream_t s, double* dsc) {
+    hipLaunchKernelGGL(k_gn_alpha, dim3(1), dim3(64), 0, s, dsc);
     H1W_LAUNCHED();
 }
 
@@ -527,7 +586,15 @@ void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, doub
 void launch_cg_update(hipStream_t s, int64_t N, double a, const double* p, const double* q, double* x,
                       double* r, double* partial, int* nparts) {
     const int nb = dot_blocks(N);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, a, p, q, x, r, partial);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, a, (const double*)nullptr, p, q, x, r, partial);
+    H1W_LAUNCHED();
+    *nparts = nb;
+}
+
+void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
+                          double* x, double* r, double* partial, int* nparts) {
+    const int nb = dot_blocks(N);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, 0.0, adev, p, q, x, r, partial);
     H1W_LAUNCHED();
     *nparts = nb;
 }

@@ -67,6 +67,7 @@ struct Ctx {
     DevBuf nvec, mvec, part, jpart, gpart, scal, iflag;
     int mstride = 1;                 // m-vector slot stride (grows only)
     double* hscal = nullptr;         // pinned host copy of device scalars
+    static constexpr int kGnScal = 32;  // slots of the GN CG's device scalars in scal
     hipEvent_t ev[8] = {};
 
     ~Ctx();

@@ -921,7 +921,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     if (!std::isfinite(bnorm)) throw Error{H1W_ENUMERIC, "non-finite right-hand side"};
 
     int it = 0, restarts = 0;
-    double rz = 0.0, a = 0.0, relres_rec = 0.0, relres_true = 0.0;
+    double relres_rec = 0.0, relres_true = 0.0;
     // Recompute form: the Jz recurrence Jz = (Jy - (S - alpha I) w) / alpha
     // assumes B (J^T w) = Z^T w, but the two come from separate V-cycles whose
     // rounding differs; amplified by 1/alpha, the recursive residual drifts
@@ -933,19 +933,17 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     bool replaced = false;
     h1w_status status = H1W_OK;
 
-    // z = P^{-1} r, p = z + beta p, t = J^T Jp; returns false if r.z <= 0 (converged to rounding)
-    auto precond_step = [&](bool first) -> bool {
+    // z = P^{-1} r, p = z + beta p, t = J^T Jp. The scalars stay on the device
+    // (dsc, see launch_gn_beta); r.z <= 0 (converged to rounding) is flagged
+    // there and read with the residual norm after the next update.
+    double* dsc = scal.as<double>() + kGnScal;
+    auto precond_step = [&](bool first) {
         apply_B(1, r, n, y, n);
         if (m == 0 || laplace) {
             // z = B r / alpha (no Woodbury correction); t = J^T (J p) by two passes
             dots(n, {{r, y}, {y, q}}, 0);
-            read_scal(2);
-            const double rzn = hscal[0] * ia;
-            const double zq = hscal[1] * ia;
-            if (!(rzn > 0.0)) return false;
-            const double beta = first ? 0.0 : (flexible ? -a * zq / rz : rzn / rz);
-            rz = rzn;
-            launch_axpby(stream, n, ia, y, beta, p);
+            launch_gn_beta(stream, scal.as<double>(), ia, 2, first, flexible, dsc);
+            launch_axpby_dev(stream, n, ia, y, dsc + 2, p);
             if (m == 0) {
                 H1W_HIP(hipMemsetAsync(t, 0, n * sizeof(double), stream));
             } else {
@@ -953,23 +951,19 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                 timed(H1W_K_JTV, 8.0 * m * n + 8.0 * n, 2.0 * m * n,
                       [&] { launch_jt_plain(stream, m, n, J, ldj, Jp, t, nullptr, 0.0); });
             }
-            return true;
+            return;
         }
         woodbury_mspace(y, Jy, w);
-        double beta = 0.0;
         if (zm == H1W_Z_RECOMPUTE) {
+            // r.z = (r.y - w.Jy) / alpha with z = B(r - J^T w)/alpha
             dots(n, {{r, y}}, 0);
             dots(m, {{w, Jy}}, 1);
-            read_scal(2);
-            const double rzn = (hscal[0] - hscal[1]) * ia;  // r.z with z = B(r - J^T w)/alpha
-            if (!(rzn > 0.0)) return false;
-            beta = first ? 0.0 : rzn / rz;
-            rz = rzn;
-            launch_jz_update(stream, m, Sbuf.as<double>(), alpha, Jy, w, beta, Jz, Jp);
+            launch_gn_beta(stream, scal.as<double>(), ia, 0, first, false, dsc);
+            launch_jz_update_dev(stream, m, Sbuf.as<double>(), alpha, Jy, w, dsc + 2, Jz, Jp);
             timed(H1W_K_JTV, 8.0 * m * n + 24.0 * n, 4.0 * m * n,
                   [&] { launch_jt_u_t(stream, m, n, J, ldj, w, Jp, r, ia, u, t); });
             apply_B(1, u, n, z, n);
-            launch_axpby(stream, n, 1.0, z, beta, p);
+            launch_axpby_dev(stream, n, 1.0, z, dsc + 2, p);
         } else {
             timed(H1W_K_JTV, (fp32 ? 4.0 : 8.0) * m * n + 16.0 * n, 2.0 * m * n, [&] {
                 if (fp32) {
@@ -981,17 +975,12 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                 }
             });
             dots(n, {{z, r}, {z, q}}, 0);
-            read_scal(2);
-            const double rzn = hscal[0], zq = hscal[1];
-            if (!(rzn > 0.0)) return false;
-            beta = first ? 0.0 : (flexible ? -a * zq / rz : rzn / rz);
-            rz = rzn;
-            launch_jz_update(stream, m, Sbuf.as<double>(), alpha, Jy, w, beta, Jz, Jp);
-            launch_axpby(stream, n, 1.0, z, beta, p);
+            launch_gn_beta(stream, scal.as<double>(), ia, 1, first, flexible, dsc);
+            launch_jz_update_dev(stream, m, Sbuf.as<double>(), alpha, Jy, w, dsc + 2, Jz, Jp);
+            launch_axpby_dev(stream, n, 1.0, z, dsc + 2, p);
             timed(H1W_K_JTV, 8.0 * m * n + 8.0 * n, 2.0 * m * n,
                   [&] { launch_jt_plain(stream, m, n, J, ldj, Jp, t, nullptr, 0.0); });
         }
-        return true;
     };
     auto true_relres = [&]() -> double {
         gn_apply(m, J, ldj, alpha, x, z);  // z is free here; gn_apply uses tmp internally
@@ -1004,32 +993,31 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     if (bnorm == 0.0) {
         relres_true = 0.0;
     } else {
-        bool ok = precond_step(true);
+        precond_step(true);
         for (;;) {
-            if (ok) {
-                int np = 0;
-                timed(H1W_K_APPLY, 24.0 * n, 0.0,
-                      [&] { launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np); });
-                launch_reduce_parts(stream, 1, np, part.as<double>(), scal.as<double>());
-                read_scal(1);
-                const double pq = hscal[0];
-                if (!std::isfinite(pq)) {
-                    status = H1W_ENUMERIC;
-                    break;
-                }
-                if (pq <= 0.0) ok = false;
+            // q = alpha A p + t, p.q, a = r.z / p.q (0 when r.z <= 0 or p.q <= 0
+            // was flagged), x += a p, r -= a q, r.r: one host round trip
+            int np = 0;
+            timed(H1W_K_APPLY, 24.0 * n, 0.0,
+                  [&] { launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np); });
+            launch_reduce_parts(stream, 1, np, part.as<double>(), dsc + 3);
+            launch_gn_alpha(stream, dsc);
+            launch_cg_update_dev(stream, n, dsc + 1, p, q, x, r, part.as<double>(), &np);
+            launch_reduce_parts(stream, 1, np, part.as<double>(), dsc + 4);
+            H1W_HIP(hipMemcpyAsync(hscal + kGnScal, dsc, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+            sync();
+            const double* hs = hscal + kGnScal;
+            if (hs[7] != 0.0) {
+                status = H1W_ENUMERIC;
+                break;
             }
+            const bool ok = hs[5] == 0.0 && hs[6] == 0.0;
             if (ok) {
-                a = rz / hscal[0];
-                int np = 0;
-                launch_cg_update(stream, n, a, p, q, x, r, part.as<double>(), &np);
-                launch_reduce_parts(stream, 1, np, part.as<double>(), scal.as<double>());
-                read_scal(1);
-                if (!std::isfinite(hscal[0])) {
+                if (!std::isfinite(hs[4])) {
                     status = H1W_ENUMERIC;
                     break;
                 }
-                relres_rec = std::sqrt(hscal[0]) / bnorm;
+                relres_rec = std::sqrt(hs[4]) / bnorm;
                 ++it;
             }
             if (!ok || relres_rec <= rtol) {
@@ -1043,13 +1031,10 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                     status = H1W_ENOCONV;
                     break;
                 }
-                // restart from the true residual
+                // restart from the true residual (a restart whose r.z <= 0 is
+                // seen by the next check and ends in ENOCONV after 8 restarts)
                 H1W_HIP(hipMemcpyAsync(r, u, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
-                ok = precond_step(true);
-                if (!ok) {  // r.z <= 0 while the true residual is above tolerance
-                    status = H1W_ENOCONV;
-                    break;
-                }
+                precond_step(true);
                 continue;
             }
             if (!replaced && relres_rec <= replace_tol && it < maxit) {
@@ -1062,7 +1047,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                 if (relres_true <= rtol) break;
                 ++restarts;
                 H1W_HIP(hipMemcpyAsync(r, u, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
-                ok = precond_step(true);
+                precond_step(true);
                 continue;
             }
             if (it >= maxit) {
@@ -1070,7 +1055,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                 status = relres_true <= rtol ? H1W_OK : H1W_ENOCONV;
                 break;
             }
-            ok = precond_step(false);
+            precond_step(false);
         }
     }
     ev_record(6);

@@ -187,7 +187,9 @@ __global__ __launch_bounds__(kDense) void k_lu_solve(int m, const double* __rest
 // One wave per row.
 __global__ __launch_bounds__(kBlock) void k_jz_update(int m, const double* __restrict__ S, double alpha,
                                                       const double* __restrict__ Jy, const double* __restrict__ w,
-                                                      double beta, double* __restrict__ Jz, double* __restrict__ Jp) {
+                                                      double beta0, const double* __restrict__ bdev,
+                                                      double* __restrict__ Jz, double* __restrict__ Jp) {
+    const double beta = bdev ? *bdev : beta0;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= m) return;
@@ -253,7 +255,14 @@ void launch_lu_solve(hipStream_t s, int m, const double* LUt, const double* /*LU
 void launch_jz_update(hipStream_t s, int m, const double* S, double alpha, const double* Jy, const double* w,
                       double beta, double* Jz, double* Jp) {
     hipLaunchKernelGGL(k_jz_update, dim3((unsigned)cdiv(m, kBlock / 64)), dim3(kBlock), 0, s, m, S, alpha, Jy, w,
-                       beta, Jz, Jp);
+                       beta, (const double*)nullptr, Jz, Jp);
+    H1W_LAUNCHED();
+}
+
+void launch_jz_update_dev(hipStream_t s, int m, const double* S, double alpha, const double* Jy, const double* w,
+                          const double* bdev, double* Jz, double* Jp) {
+    hipLaunchKernelGGL(k_jz_update, dim3((unsigned)cdiv(m, kBlock / 64)), dim3(kBlock), 0, s, m, S, alpha, Jy, w,
+                       0.0, bdev, Jz, Jp);
     H1W_LAUNCHED();
 }
 

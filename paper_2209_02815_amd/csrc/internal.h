@@ -185,6 +185,14 @@ void launch_node_weights(hipStream_t s, int dim, const Geom& g, double* out);
 void launch_convert_deflate(hipStream_t s, int64_t N, int k, const double* X, int64_t ldx, const double* sv,
                             const double* wv, float* Y, int64_t ldy);
 void launch_axpby(hipStream_t s, int64_t N, double a, const double* x, double b, double* y);
+// y = a x + b y with b read from device memory
+void launch_axpby_dev(hipStream_t s, int64_t N, double a, const double* x, const double* bdev, double* y);
+// device-side scalars of the GN CG (see blas.hip): beta from the preconditioner
+// step's dot products, then the step length
+void launch_gn_beta(hipStream_t s, const double* sdot, double ia, int mode, bool first, bool flexible, double* dsc);
+void launch_gn_alpha(hipStream_t s, double* dsc);
+void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
+                          double* x, double* r, double* partial, int* nparts);
 void launch_cg_update(hipStream_t s, int64_t N, double a, const double* p, const double* q,
                       double* x, double* r, double* partial, int* nparts);
 void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, double* out);
@@ -225,6 +233,8 @@ void launch_lu_solve(hipStream_t s, int m, const double* LUt, const double* LU, 
                      double* x);
 void launch_jz_update(hipStream_t s, int m, const double* S, double alpha, const double* Jy,
                       const double* w, double beta, double* Jz, double* Jp);
+void launch_jz_update_dev(hipStream_t s, int m, const double* S, double alpha, const double* Jy, const double* w,
+                          const double* bdev, double* Jz, double* Jp);
 void launch_asym(hipStream_t s, int m, const double* S, double* out);
 // blocked.hip: right-looking blocked Cholesky (mode 0, upper) or LU without
 // pivoting (mode 1) in place, with diagonal-block inverses; triangular solves
