@@ -381,7 +381,14 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
     __shared__ double we[6 * TN];
     __shared__ double red[VJP ? G * TN : 1];
     const int tid = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * TN;
+    // node tiles in contiguous ranges per XCD (block ids go round-robin over
+    // the 8 XCDs), so the neighbour rows and planes a tile reads were mostly
+    // brought into the same L2 by the tiles next to it
+    const int ntile = (int)((g.N + TN - 1) / TN);
+    const int per = (ntile + 7) >> 3;
+    const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (tile >= ntile) return;
+    const int64_t j0 = (int64_t)tile * TN;
     const int64_t PY = g.nx, PZ = (int64_t)g.nx * g.ny;
 
     // edge differences of every field at the TN nodes
@@ -432,12 +439,26 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
     double acc_all = 0.0;
     // each group takes a contiguous range of measurements; w_e (u_a(j) - u_a(q))
     // is kept in registers while consecutive pairs share their first electrode
-    const int per = (n_meas + G - 1) / G;
-    const int i0 = grp * per, i1 = min(n_meas, i0 + per);
+    const int mper = (n_meas + G - 1) / G;
+    const int i0 = grp * mper, i1 = min(n_meas, i0 + mper);
     int a_cur = -1;
     double wa[6];
+    // the pair and factor of the next measurement are loaded one iteration ahead
+    int a_nx = 0, b_nx = 0;
+    double k_nx = 0.0;
+    if (i0 < i1) {
+        a_nx = pair[2 * i0];
+        b_nx = pair[2 * i0 + 1];
+        k_nx = k[i0];
+    }
     for (int i = i0; i < i1; ++i) {
-        const int a = pair[2 * i], b = pair[2 * i + 1];
+        const int a = a_nx, b = b_nx;
+        const double ki = k_nx;
+        if (i + 1 < i1) {
+            a_nx = pair[2 * i + 2];
+            b_nx = pair[2 * i + 3];
+            k_nx = k[i + 1];
+        }
         if (a != a_cur) {
 #pragma unroll
             for (int e = 0; e < 6; ++e) wa[e] = w[e] * dl[(e * NS + a) * TN + t];
@@ -447,9 +468,9 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
 #pragma unroll
         for (int e = 0; e < 6; ++e) acc += wa[e] * dl[(e * NS + b) * TN + t];
         if (VJP) {
-            acc_all += gbar[i] * k[i] * acc;
+            acc_all += gbar[i] * ki * acc;
         } else if (p < g.N) {
-            J[(int64_t)i * ldj + p] = -k[i] * acc;
+            J[(int64_t)i * ldj + p] = -ki * acc;
         }
     }
     if (VJP) {
@@ -694,7 +715,7 @@ void Ctx::ert_sens(int n_src, const double* U, int64_t ldu, int n_meas, const in
     const double* sig = ert_level(0).sig;
     const bool vjp = gbar != nullptr;
     const int tn = n_src <= 32 ? 32 : 16;
-    const unsigned blocks = (unsigned)cdiv(g.N, tn);
+    const unsigned blocks = (unsigned)(8 * cdiv(cdiv(g.N, tn), 8));
     const double nn = (double)g.N;
     const double bytes = vjp ? 8.0 * nn * (n_src + 2.0) : 8.0 * nn * (n_src + 1.0 + n_meas);
     timed(H1W_K_ERT_SENS, bytes, 12.0 * n_meas * nn, [&] {
