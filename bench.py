@@ -225,8 +225,10 @@ def ert_bench(args):
 def batch_bench(args, threads):
     """256 independent 2D instances of uneven size (sides {65,129,193,257}, m in
     [16,128], log-uniform alpha in [1e-5,1e-2]) solved by h1w_batch_solve: FP64
-    and mixed with the executor's 4 workers and the autotuner, and FP64 with one
-    worker (no overlap) for reference. One warmup pass, then the batch is timed."""
+    and mixed with 8 workers, with the autotuner (choices made in the warmup
+    call, or again inside the timed call) and with nu = 2 fixed, FP64 with the
+    V-cycles replayed from HIP graphs, and FP64 with one worker (no overlap)
+    for reference. One warmup pass, then the batch is timed."""
     import torch
     import h1w_inputs as H
     from paper_2209_02815_amd import _native as nat
@@ -242,11 +244,15 @@ def batch_bench(args, threads):
     out = {"workload": f"{len(wls)} 2D instances, sides {H.BATCH_DEFAULT['sides']}, m in [16, 128], "
                        f"alpha log-uniform in [1e-5, 1e-2], beta 1e-2, rtol {args.rtol}",
            "rows": sum(w.m for w in wls), "nodes": sum(w.N for w in wls)}
-    for label, prec, nw, tune, gr in (("fp64", nat.H1W_FP64, 4, True, False),
-                                      ("mixed", nat.H1W_MIXED, 4, True, False),
-                                      ("fp64_graphs", nat.H1W_FP64, 4, True, True),
-                                      ("mixed_graphs", nat.H1W_MIXED, 4, True, True),
-                                      ("fp64_one_worker", nat.H1W_FP64, 1, False, False)):
+    # autotune 1: keys tuned by the warmup call are reused by the timed one;
+    # autotune 2: the timed call tunes every key again (tuning cost included)
+    for label, prec, nw, tune, gr in (("fp64", nat.H1W_FP64, 8, 1, False),
+                                      ("mixed", nat.H1W_MIXED, 8, 1, False),
+                                      ("fp64_fixed_nu", nat.H1W_FP64, 8, 0, False),
+                                      ("mixed_fixed_nu", nat.H1W_MIXED, 8, 0, False),
+                                      ("fp64_tuning_in_timed_call", nat.H1W_FP64, 8, 2, False),
+                                      ("fp64_graphs", nat.H1W_FP64, 8, 1, True),
+                                      ("fp64_one_worker", nat.H1W_FP64, 1, 0, False)):
         nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol, graphs=gr)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -294,11 +294,12 @@ h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx);
  * The items are ordered by decreasing work N * (m + 1) and pulled from one
  * queue by opts.nworkers host threads; each thread owns a HIP stream (default
  * priority) and one context per (grid, precision, smoothing steps) it meets,
- * reused by later items of that key. With opts.autotune, the first items of
- * each (grid, precision, ceil(log2 m)) key are solved with nu = 2, 1 and 3
- * smoothing steps per side and the later items of the key use the one with
- * the smallest wall time per N * (m + 1) (the tuning solves are kept as
- * results). Items of one grid must share beta. All pointers are device
+ * reused by later items of that key. With opts.autotune, the first item of
+ * each (grid, precision, ceil(log2 m)) key is solved with nu = 1, 3 and 2
+ * smoothing steps per side back to back by one worker, and the later items
+ * of the key use the nu with the shortest wall time (the nu = 2 solve is the
+ * item's result; until a key is tuned its items use nu = 2, or opts.nu).
+ * Items of one grid must share beta. All pointers are device
  * pointers owned by the caller; J, b, x follow h1w_gn_solve (J m x N with
  * leading dimension ldj, x receives the solution). infos and status (count
  * entries each, may be NULL) receive each item's diagnostics and status;
@@ -319,8 +320,10 @@ typedef struct {
 
 typedef struct {
     int precision;       /* H1W_FP64 or H1W_MIXED, for every item */
-    int nworkers;        /* host threads / streams (0 -> 4, at most 16) */
-    int autotune;        /* 1: choose the smoothing steps per key as described above */
+    int nworkers;        /* host threads / streams (0 -> 8, at most 16) */
+    int autotune;        /* 1: choose the smoothing steps per key as described above,
+                            reusing the keys tuned by earlier batches of the process;
+                            2: tune every key again (and keep the new choice); 0: off */
     int nu;              /* smoothing steps when not tuned (0 -> 2) */
     double rtol;         /* as h1w_solve_opts.rtol (0 -> 1e-10) */
     int maxit;           /* as h1w_solve_opts.maxit (0 -> 500) */
@@ -335,6 +338,7 @@ typedef struct {
     int m_bucket;        /* ceil(log2 m) */
     int nu;              /* chosen smoothing steps */
     double ms_per_unit;  /* its wall time per N * (m + 1), in ms */
+    int reused;          /* 1: the choice of an earlier batch */
 } h1w_batch_tuned;
 
 typedef struct {

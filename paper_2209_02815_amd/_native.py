@@ -69,7 +69,7 @@ H1W_BATCH_MAX_KEYS = 64
 
 class h1w_batch_tuned(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("m_bucket", C.c_int), ("nu", C.c_int),
-                ("ms_per_unit", C.c_double)]
+                ("ms_per_unit", C.c_double), ("reused", C.c_int)]
 
 
 class h1w_batch_report(C.Structure):
@@ -336,7 +336,7 @@ def h1w_reset_kernel_timing(ctx):
     _check(ctx, lib.h1w_reset_kernel_timing(ctx))
 
 
-def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotune: bool = False, nu: int = 0,
+def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotune: int = 0, nu: int = 0,
                     rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True, graphs: bool = False):
     """items: list of dicts with shape, beta, alpha, J (CUDA (m, N) float64 or None), b, x.
     Returns (infos, statuses, report); raises on the first failing item unless raise_on_error is False."""
@@ -360,7 +360,7 @@ def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotun
             if not t.is_cuda or t.dtype != __import__("torch").float64 or t.numel() != N or not t.is_contiguous():
                 raise ValueError(f"item {i}: {name} must be a contiguous float64 CUDA vector of N entries")
         e.b, e.x = it["b"].data_ptr(), it["x"].data_ptr()
-    opts = h1w_batch_opts(int(precision), int(nworkers), int(bool(autotune)), int(nu), float(rtol), int(maxit),
+    opts = h1w_batch_opts(int(precision), int(nworkers), int(autotune), int(nu), float(rtol), int(maxit),
                           int(bool(graphs)))
     infos = (h1w_info * max(1, len(items)))()
     stats = (C.c_int * max(1, len(items)))()

@@ -11,11 +11,16 @@
 // threads' streams let the small kernels and host round trips of different
 // instances overlap.
 //
-// Autotuner: for each (grid, precision, row bucket ceil(log2 m)) key the first
-// instances are solved with nu = 2, 1 and 3 smoothing steps per side; the
-// wall time of each, divided by N * (m + 1), ranks the candidates, and the
-// later instances of the key use the fastest. Tuning instances are ordinary
-// solves (their results are kept).
+// Autotuner: for each (grid, precision, row bucket ceil(log2 m)) key, the
+// worker that meets the key first solves that instance with nu = 1, 3 and
+// then 2 smoothing steps per side, back to back on its own stream, and the
+// later instances of the key use the nu with the shortest wall time (the
+// candidates are compared on the same system, so differences in m, alpha and
+// iteration count between instances do not enter). The last tuning solve
+// (nu = 2) is the instance's result; while a key is being tuned, other
+// workers solve its instances with the default nu. Tuned keys are kept for
+// the process: a later batch reuses them (autotune = 1) or tunes them again
+// (autotune = 2).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -32,7 +37,7 @@ namespace h1w {
 
 namespace {
 
-constexpr int kTuneCandidates[] = {2, 1, 3};
+constexpr int kTuneCandidates[] = {1, 3, 2};  // the default last: its solution is kept
 constexpr int kNumCandidates = 3;
 
 struct GridKey {
@@ -58,11 +63,16 @@ int row_bucket(int m) {
 
 // Candidate choice for one tuning key, shared by all workers.
 struct TuneState {
-    int issued = 0;                          // tuning solves handed out
-    double best = -1.0;                      // best normalised time so far
-    int best_nu = kTuneCandidates[0];
-    int done = 0;                            // tuning solves finished
+    bool claimed = false;                    // a worker is tuning (or has tuned) the key
+    bool done = false;
+    bool reused = false;                     // taken from an earlier batch of the process
+    double best = -1.0;                      // wall time per N (m + 1) of the best candidate
+    int best_nu = 2;
 };
+
+// tuning results of earlier batches in this process
+std::mutex g_tuned_mu;
+std::map<TuneKey, TuneState> g_tuned;
 
 struct Worker {
     hipStream_t stream = nullptr;
@@ -75,7 +85,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                  h1w_status* status, h1w_batch_report* report, std::string* first_err) {
     int device = 0;
     H1W_HIP(hipGetDevice(&device));
-    const int nworkers = std::clamp(o.nworkers > 0 ? o.nworkers : 4, 1, 16);
+    const int nworkers = std::clamp(o.nworkers > 0 ? o.nworkers : 8, 1, 16);
     const int nu_fixed = o.nu > 0 ? o.nu : 2;
 
     // decreasing work first, so the long solves do not finish last
@@ -90,31 +100,39 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
 
     std::mutex tune_mu;
-    std::map<TuneKey, TuneState> tune;
+    std::map<TuneKey, TuneState> tune;  // the keys met by this batch
     std::atomic<int> next{0};
     std::vector<Worker> workers(nworkers);
     std::vector<std::string> worker_err(nworkers);
     std::vector<std::string> item_err(count);
 
+    // nu for an instance of key tk; tuning = this worker tunes the key now
     auto choose_nu = [&](const TuneKey& tk, bool& tuning) -> int {
         tuning = false;
         if (!o.autotune) return nu_fixed;
         std::lock_guard<std::mutex> lk(tune_mu);
         TuneState& ts = tune[tk];
-        if (ts.issued < kNumCandidates) {
-            tuning = true;
-            return kTuneCandidates[ts.issued++];
+        if (!ts.claimed && o.autotune == 1) {  // a choice of an earlier batch
+            std::lock_guard<std::mutex> lg(g_tuned_mu);
+            auto f = g_tuned.find(tk);
+            if (f != g_tuned.end()) {
+                ts = f->second;
+                ts.reused = true;
+            }
         }
-        return ts.best_nu;
+        if (!ts.claimed) {
+            ts.claimed = true;
+            tuning = true;
+            return nu_fixed;
+        }
+        return ts.done ? ts.best_nu : nu_fixed;
     };
-    auto record = [&](const TuneKey& tk, int nu, double t_norm) {
+    auto finish_tuning = [&](const TuneKey& tk, int nu, double t_norm) {
         std::lock_guard<std::mutex> lk(tune_mu);
         TuneState& ts = tune[tk];
-        ++ts.done;
-        if (ts.best < 0.0 || t_norm < ts.best) {
-            ts.best = t_norm;
-            ts.best_nu = nu;
-        }
+        ts.best = t_norm;
+        ts.best_nu = nu;
+        ts.done = true;
     };
 
     auto run = [&](int w) {
@@ -142,40 +160,63 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 const int n2 = it.dim == 3 ? it.n[2] : 1;
                 TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision, row_bucket(it.m)};
                 bool tuning = false;
-                // a later instance whose key is still being tuned uses the default
-                int nu = choose_nu(tk, tuning);
-                if (!tuning && o.autotune) {
-                    std::lock_guard<std::mutex> lk(tune_mu);
-                    if (tune[tk].done < kNumCandidates) nu = nu_fixed;
-                }
-                GridKey gk{it.dim, it.n[0], it.n[1], n2, o.precision, nu};
-                auto& slot = me.ctxs[gk];
-                if (!slot) {
-                    h1w_grid_desc d{};
-                    d.dim = it.dim;
-                    d.n[0] = it.n[0];
-                    d.n[1] = it.n[1];
-                    d.n[2] = n2;
-                    d.beta = it.beta;
-                    d.precision = o.precision;
-                    d.nu = nu;
-                    d.flags = o.graphs ? H1W_FLAG_GRAPH_VCYCLE : 0u;
-                    auto c = std::make_unique<Ctx>();
-                    c->init(d, me.stream);
-                    slot = std::move(c);
-                }
-                require(std::isfinite(it.beta) && it.beta == slot->d.beta,
-                        "items of one grid must share beta within a batch");
+                const int nu = choose_nu(tk, tuning);
+                auto ctx_for = [&](int nu_c) -> Ctx& {
+                    GridKey gk{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c};
+                    auto& slot = me.ctxs[gk];
+                    if (!slot) {
+                        h1w_grid_desc d{};
+                        d.dim = it.dim;
+                        d.n[0] = it.n[0];
+                        d.n[1] = it.n[1];
+                        d.n[2] = n2;
+                        d.beta = it.beta;
+                        d.precision = o.precision;
+                        d.nu = nu_c;
+                        d.flags = o.graphs ? H1W_FLAG_GRAPH_VCYCLE : 0u;
+                        auto c = std::make_unique<Ctx>();
+                        c->init(d, me.stream);
+                        slot = std::move(c);
+                    }
+                    require(std::isfinite(it.beta) && it.beta == slot->d.beta,
+                            "items of one grid must share beta within a batch");
+                    return *slot;
+                };
                 require(std::isfinite(it.alpha) && it.alpha > 0.0, "item alpha must be finite and > 0");
-                require(it.m == 0 || it.ldj >= slot->N(), "item ldj must be >= N");
+                require(it.m == 0 || it.ldj >= ctx_for(nu).N(), "item ldj must be >= N");
                 h1w_solve_opts so{};
                 so.rtol = o.rtol;
                 so.maxit = o.maxit;
-                const auto t0 = std::chrono::steady_clock::now();
-                slot->gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
-                const double ms =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                if (tuning) record(tk, nu, ms / work(i));
+                if (!tuning) {
+                    ctx_for(nu).gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
+                } else {
+                    // the candidates on this instance, the default last (its x is the result)
+                    int best_nu = nu_fixed;
+                    double best = -1.0;
+                    for (int c = 0; c < kNumCandidates; ++c) {
+                        const int nu_c = c + 1 == kNumCandidates ? nu_fixed : kTuneCandidates[c];
+                        if (c + 1 < kNumCandidates && nu_c == nu_fixed) continue;
+                        Ctx& cx = ctx_for(nu_c);
+                        cx.sync();
+                        const auto t0 = std::chrono::steady_clock::now();
+                        if (nu_c == nu_fixed) {
+                            cx.gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
+                        } else {
+                            try {  // a candidate that fails (e.g. no convergence) is skipped
+                                cx.gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
+                            } catch (const Error&) {
+                                continue;
+                            }
+                        }
+                        const double ms =
+                            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                        if (best < 0.0 || ms < best) {
+                            best = ms;
+                            best_nu = nu_c;
+                        }
+                    }
+                    finish_tuning(tk, best_nu, best / work(i));
+                }
             } catch (const Error& e) {
                 st = e.st;
                 item_err[i] = e.msg;
@@ -211,6 +252,11 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
             if (!item_err[order[q]].empty())
                 *first_err = "item " + std::to_string(order[q]) + ": " + item_err[order[q]];
     }
+    if (o.autotune) {
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        for (const auto& [tk, ts] : tune)
+            if (ts.done && !ts.reused) g_tuned[tk] = ts;
+    }
     if (report) {
         *report = h1w_batch_report{};
         report->t_total_ms = total_ms;
@@ -226,6 +272,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
             r.m_bucket = tk.bucket;
             r.nu = ts.best_nu;
             r.ms_per_unit = ts.best;
+            r.reused = ts.reused ? 1 : 0;
         }
         report->ntuned = k;
     }

@@ -7,6 +7,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
 
 namespace h1w {
 
@@ -90,6 +94,29 @@ static std::vector<double> spd_inverse(std::vector<double> A, int64_t n) {
     return X;
 }
 
+// Symmetrised dense inverse of the coarsest operator of grid g. Coarsest
+// levels of up to 1024 nodes are computed once per (dimension, grid, beta) in
+// the process and shared (contexts of a batch mostly end on the same few).
+static std::shared_ptr<const std::vector<double>> coarsest_inverse(int dim, const Geom& g) {
+    auto compute = [&] {
+        const int64_t n = g.N;
+        auto v = std::make_shared<std::vector<double>>(spd_inverse(dense_operator(dim, g), n));
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                const double a = 0.5 * ((*v)[(size_t)(i * n + j)] + (*v)[(size_t)(j * n + i)]);
+                (*v)[(size_t)(i * n + j)] = (*v)[(size_t)(j * n + i)] = a;
+            }
+        return std::shared_ptr<const std::vector<double>>(v);
+    };
+    if (g.N > 1024) return compute();
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, double>, std::shared_ptr<const std::vector<double>>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto& slot = cache[std::make_tuple(dim, g.nx, g.ny, g.nz, g.beta)];
+    if (!slot) slot = compute();
+    return slot;
+}
+
 void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     d = desc;
     stream = s;
@@ -161,13 +188,10 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     }
 
     // dense inverse of the coarsest operator, symmetrised so that the device
-    // kernel may read it by columns
-    std::vector<double> inv = spd_inverse(dense_operator(dim, lv.back()), Nc);
-    for (int64_t i = 0; i < Nc; ++i)
-        for (int64_t j = i + 1; j < Nc; ++j) {
-            const double a = 0.5 * (inv[(size_t)(i * Nc + j)] + inv[(size_t)(j * Nc + i)]);
-            inv[(size_t)(i * Nc + j)] = inv[(size_t)(j * Nc + i)] = a;
-        }
+    // kernel may read it by columns; it depends only on the coarsest grid and
+    // beta, so contexts share it through a process-wide cache
+    const auto inv_ptr = coarsest_inverse(dim, lv.back());
+    const std::vector<double>& inv = *inv_ptr;
     cinv64.reserve(inv.size() * sizeof(double));
     std::vector<float> inv32(inv.begin(), inv.end());
     cinv32.reserve(inv32.size() * sizeof(float));

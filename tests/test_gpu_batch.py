@@ -77,11 +77,18 @@ def test_batch_autotune_reports_choices(P):
     from paper_2209_02815_amd import _native as nat
     wls = H.batch_workloads(count=14, batch_id=8, sides=(33, 65), m_lo=20, m_hi=30)
     items, host = make_items(wls)
-    infos, stats, rep = nat.h1w_batch_solve(items, nworkers=2, autotune=True, rtol=1e-10)
+    infos, stats, rep = nat.h1w_batch_solve(items, nworkers=2, autotune=2, rtol=1e-10)   # tune every key
     assert all(s == 0 for s in stats)
     keys = {(rep.tuned[k].n[0], rep.tuned[k].m_bucket) for k in range(rep.ntuned)}
     assert keys == {(wl.shape[0], int(np.ceil(np.log2(wl.m)))) for wl in wls}
     assert all(rep.tuned[k].nu in (1, 2, 3) and rep.tuned[k].ms_per_unit > 0 for k in range(rep.ntuned))
+    assert all(rep.tuned[k].reused == 0 for k in range(rep.ntuned))
+    chosen = {(rep.tuned[k].n[0], rep.tuned[k].m_bucket): rep.tuned[k].nu for k in range(rep.ntuned)}
+    # a second batch of the process reuses the choices (autotune = 1)
+    _, stats2, rep2 = nat.h1w_batch_solve(items, nworkers=2, autotune=1, rtol=1e-10)
+    assert all(s == 0 for s in stats2)
+    assert all(rep2.tuned[k].reused == 1 for k in range(rep2.ntuned))
+    assert {(rep2.tuned[k].n[0], rep2.tuned[k].m_bucket): rep2.tuned[k].nu for k in range(rep2.ntuned)} == chosen
     for wl, it, (J, b) in zip(wls, items, host):
         rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy())
         assert rr <= 1.01e-10

@@ -317,3 +317,27 @@ def test_noncubic_anisotropic_grid_matches_oracle(P):
     assert np.abs(U - Uo).max() <= 1e-9 * np.abs(Uo).max()
     assert np.abs(g - OE.measurements(Uo, src, pairs, k)).max() <= 1e-9 * np.abs(g).max()
     assert np.abs(J - Jo).max() <= 1e-8 * np.abs(Jo).max()
+
+
+def test_more_than_32_sources_uses_the_narrow_tile(P):
+    # 40 sources (the sensitivity kernel's 16-node tiles for 33..64 sources),
+    # all 780 pairs, J and J^T gbar against the oracle
+    shape = (17, 17, 17)
+    ex, ey = np.tile(np.arange(1, 16, 2), 5), np.repeat(np.arange(3, 12, 2), 8)
+    src = ex + 17 * (ey + 17 * 16)
+    a, b = np.triu_indices(len(src), k=1)
+    pairs = np.stack([a, b], 1).astype(np.int32)
+    sv = H.ert_survey(17, 4, 2, 2, wid=45)
+    m = H.ert_logsig(sv)
+    gbar = np.random.default_rng(13).standard_normal(len(pairs))
+    with P.ErtContext(shape, src, pairs) as ec:
+        g, J, U, _ = ec.forward(dev(m), jacobian=True, fields=True, rtol=1e-13)
+        v = host(ec.vjp(dev(gbar), U))
+        g, J = host(g), host(J)
+    Uo = OE.fields(shape, m, 0x1F, src)
+    k = OE.pole_pole_factors(shape, src, pairs)
+    Jo = OE.jacobian(shape, m, Uo, pairs, k)
+    assert np.abs(g - OE.measurements(Uo, src, pairs, k)).max() <= 1e-9 * np.abs(g).max()
+    assert np.abs(J - Jo).max() <= 1e-8 * np.abs(Jo).max()
+    ref = J.T @ gbar
+    assert np.abs(v - ref).max() <= 1e-12 * np.abs(ref).max()
