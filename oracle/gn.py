@@ -51,6 +51,20 @@ def true_relres(shape, beta, J, alpha, b, x) -> float:
     return float(np.linalg.norm(b - gn_apply(shape, beta, J, alpha, x)) / np.linalg.norm(b))
 
 
+def residual_rounding_floor(shape, beta, J, alpha, b, x) -> float:
+    """Rounding level of an FP64 evaluation of ||b - G x|| / ||b||: with the
+    componentwise bound |fl(G x) - G x| <~ u |alpha A| |x| + u |J|^T (|J| |x|)
+    per accumulated term and errors that add like a random walk over the
+    sqrt(N) terms of the longest sums, two independent evaluations (on the CPU
+    and on the GPU) of the relative residual differ by about
+    4 sqrt(N) u || |alpha A||x| + |J|^T (|J||x|) || / ||b||."""
+    u = np.finfo(np.float64).eps / 2
+    A = abs(op.gram_operator(shape, beta))
+    ax = np.abs(x)
+    mag = alpha * (A @ ax) + (np.abs(J).T @ (np.abs(J) @ ax) if J.shape[0] else 0.0)
+    return float(4.0 * np.sqrt(x.size) * u * np.linalg.norm(mag) / np.linalg.norm(b))
+
+
 def gn_dense(shape, beta, J, alpha) -> np.ndarray:
     A = op.gram_operator(shape, beta).toarray()
     return alpha * A + J.T @ J

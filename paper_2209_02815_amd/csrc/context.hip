@@ -201,8 +201,9 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
         H1W_HIP(hipMemcpy(cinv32.p, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
     }
 
-    fused = dim == 3 && d.nu == 2 && lv.size() >= 2 && !(d.flags & H1W_FLAG_UNFUSED_VCYCLE);
-    for (size_t l = 0; fused && l + 1 < lv.size(); ++l) fused = fused_levels_ok(lv[l], lv[l + 1]);
+    fused = d.nu == 2 && lv.size() >= 2 && !(d.flags & H1W_FLAG_UNFUSED_VCYCLE);
+    for (size_t l = 0; fused && l + 1 < lv.size(); ++l)
+        fused = dim == 3 ? fused_levels_ok(lv[l], lv[l + 1]) : fused2_levels_ok(lv[l], lv[l + 1]);
 
     deflate = fp32;
     wsum = 1.0;
@@ -274,21 +275,30 @@ void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
     auto xld = [&](int l) { return l == 0 ? ldx : pitch[l]; };
 
     if (fused) {
-        // 3D, two smoothing steps per side: one pass down and one pass up per
-        // level; the pre-smoothed iterate of level l is kept in tb[l]
+        // two smoothing steps per side: one pass down and one pass up per
+        // level (3D z-march or 2D tiles in LDS); the pre-smoothed iterate of
+        // level l is kept in tb[l]
         for (int l = 0; l < L - 1; ++l) {
             const double nl = (double)lv[l].N, nc = (double)lv[l + 1].N;
             timed(H1W_K_VDOWN, ces * (2 * nl + nc), 0.0, [&] {
-                launch_vdown<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], fb[l + 1],
-                                pitch[l + 1], w[0], w[1]);
+                if (dim == 3)
+                    launch_vdown<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], fb[l + 1],
+                                    pitch[l + 1], w[0], w[1]);
+                else
+                    launch_vdown2<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], fb[l + 1],
+                                     pitch[l + 1], w[0], w[1]);
             });
         }
         coarse(fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
         for (int l = L - 2; l >= 0; --l) {
             const double nl = (double)lv[l].N, nc = (double)lv[l + 1].N;
             timed(H1W_K_VUP, ces * (3 * nl + nc), 0.0, [&] {
-                launch_vup<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], xb[l + 1],
-                              pitch[l + 1], xptr(l), xld(l), w[1], w[0]);
+                if (dim == 3)
+                    launch_vup<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], xb[l + 1],
+                                  pitch[l + 1], xptr(l), xld(l), w[1], w[0]);
+                else
+                    launch_vup2<T>(stream, lv[l], lv[l + 1], k, fptr(l), fld(l), tb[l], pitch[l], xb[l + 1],
+                                   pitch[l + 1], xptr(l), xld(l), w[1], w[0]);
             });
         }
         return;

@@ -141,6 +141,15 @@ void launch_vup(hipStream_t s, const Geom& gf, const Geom& gc, int k, const T* F
 // ert.hip: host check of a node against the Dirichlet faces of an ERT grid
 bool ert_on_dirichlet_host(const Geom& g, unsigned mask, int64_t p);
 
+// vfused2d.hip: fused passes of the 2D V-cycle (two smoothing steps per side)
+bool fused2_levels_ok(const Geom& gf, const Geom& gc);
+template <typename T>
+void launch_vdown2(hipStream_t s, const Geom& gf, const Geom& gc, int k, const T* F, int64_t ldf, T* X, int64_t ldx,
+                   T* Fc, int64_t ldc, double w0, double w1);
+template <typename T>
+void launch_vup2(hipStream_t s, const Geom& gf, const Geom& gc, int k, const T* F, int64_t ldf, const T* X0,
+                 int64_t ldx0, const T* Ec, int64_t ldc, T* Y, int64_t ldy, double wa, double wb);
+
 // batch.hip: the executor behind h1w_batch_solve (throws Error on setup failures;
 // per-item failures go to status[])
 void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,

@@ -118,14 +118,18 @@ def test_vcycle_fp32_matches_oracle(P, shape, cmax, nu):
     assert rel_rows(X, Xref).max() < 2e-5
 
 
-# 3D, two smoothing steps per side: the fused down/up passes against the
-# sequence of single-step kernels (same cycle; the fused passes multiply by
-# 1/D where the single-step kernels divide by D, so the two agree to rounding
-# amplified at most like the oracle comparison above). Shapes: non-cubic with
-# nz > nx > ny, several right-hand-side chunks, padded leading dimensions, a
-# 65^3 grid whose tiles are ragged in x, y and z.
+# Two smoothing steps per side: the fused down/up passes (3D z-march, 2D
+# tiles in LDS) against the sequence of single-step kernels (same cycle; the
+# fused passes multiply by 1/D where the single-step kernels divide by D, so
+# the two agree to rounding amplified at most like the oracle comparison
+# above). Shapes: non-cubic with nz > nx > ny, several right-hand-side chunks,
+# padded leading dimensions, a 65^3 grid whose tiles are ragged in x, y and z;
+# 2D grids with one tile, ragged tiles, a 193^2 grid with a 13^2 coarsest
+# level, and an anisotropic 257 x 65 grid.
 @pytest.mark.parametrize("shape,cmax,k,chunk", [((17, 17, 17), 27, 3, 2), ((33, 17, 65), 0, 5, 2),
-                                                ((65, 65, 65), 0, 3, 0), ((9, 17, 5), 1, 4, 1)])
+                                                ((65, 65, 65), 0, 3, 0), ((9, 17, 5), 1, 4, 1),
+                                                ((17, 17), 25, 3, 2), ((65, 129), 289, 5, 2),
+                                                ((193, 193), 289, 3, 0), ((257, 65), 81, 4, 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_vcycle_fused_matches_unfused(P, shape, cmax, k, chunk, prec):
     beta = 1e-2
@@ -279,7 +283,7 @@ def test_gn_solve_square33(P, prec, zmode, rtol):
         x = host(x)
     rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
     assert rr <= rtol * 1.01, (rr, info.as_dict())
-    assert abs(rr - info.relres_true) <= 1e-3 * rtol + 1e-15
+    assert abs(rr - info.relres_true) <= 1e-3 * rtol + gn.residual_rounding_floor(wl.shape, wl.beta, J, wl.alpha, b, x)
     xs = gn.solve_dense(wl.shape, wl.beta, J, wl.alpha, b)
     kappa = _cond_bound(wl, J)
     assert np.linalg.norm(x - xs) <= 1.01 * kappa * rr * np.linalg.norm(xs)
@@ -400,7 +404,8 @@ def test_laplace_only_mode_matches_oracle(P, name, prec, rtol):
     assert info.zmode_used == 0 and info.t_gemm_ms == 0.0
     assert info.iters > 2 * infow.iters
     rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
-    assert rr <= 1.01 * rtol and abs(rr - info.relres_true) <= 1e-3 * rtol + 1e-14
+    assert rr <= 1.01 * rtol
+    assert abs(rr - info.relres_true) <= 1e-3 * rtol + gn.residual_rounding_floor(wl.shape, wl.beta, J, wl.alpha, b, x)
     if wl.N <= 1100:  # against the oracle's direct solution (dense cond is cheap here)
         xs = gn.solve_dense(wl.shape, wl.beta, J, wl.alpha, b)
         assert np.linalg.norm(x - xs) <= 1.01 * _cond_bound(wl, J) * rr * np.linalg.norm(xs)
