@@ -493,6 +493,59 @@ __global__ __launch_bounds__(kBlock) void k_undeflate(int64_t N, const float* __
     if (n < N) y[n] = double(x[n]) - cm[1] + cm[0] * v[n];
 }
 
+// Deflation steps of the single-vector FP32 V-cycle with the partial sums
+// reduced inside the kernel (the same fixed order as k_reduce_parts, so every
+// block gets the same value): c = inv_w * sum(part) and Y = float(F - c w)
+// (cm[0] = c); then mu = inv_w * sum(part) and y = x - mu + c v (cm[1] = mu).
+__device__ __forceinline__ double reduce_parts_block(int nparts, const double* __restrict__ part, double* sh,
+                                                     double* bc) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) acc += part[b];
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) *bc = s;
+    __syncthreads();
+    return *bc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_deflate_in(int64_t N, const double* __restrict__ F,
+                                                       const double* __restrict__ part, int nparts, double inv_w,
+                                                       const double* __restrict__ wv, float* __restrict__ Y,
+                                                       double* __restrict__ cm) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double bc;
+    const double c = reduce_parts_block(nparts, part, sh, &bc) * inv_w;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cm[0] = c;
+    if (p < N) Y[p] = float(F[p] - c * wv[p]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_deflate_out(int64_t N, const float* __restrict__ x,
+                                                        const double* __restrict__ part, int nparts, double inv_w,
+                                                        double* __restrict__ cm, const double* __restrict__ v,
+                                                        double* __restrict__ y) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double bc;
+    const double mu = reduce_parts_block(nparts, part, sh, &bc) * inv_w;
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const double c = cm[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) cm[1] = mu;
+    if (n < N) y[n] = double(x[n]) - mu + c * v[n];
+}
+
+void launch_deflate_in(hipStream_t s, int64_t N, const double* F, const double* part, int nparts, double inv_w,
+                       const double* wv, float* Y, double* cm) {
+    hipLaunchKernelGGL(k_deflate_in, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, F, part, nparts, inv_w,
+                       wv, Y, cm);
+    H1W_LAUNCHED();
+}
+
+void launch_deflate_out(hipStream_t s, int64_t N, const float* x, const double* part, int nparts, double inv_w,
+                        double* cm, const double* v, double* y) {
+    hipLaunchKernelGGL(k_deflate_out, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, x, part, nparts, inv_w,
+                       cm, v, y);
+    H1W_LAUNCHED();
+}
+
 void launch_undeflate(hipStream_t s, int64_t N, const float* x, const double* cm, const double* v, double* y) {
     hipLaunchKernelGGL(k_undeflate, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, x, cm, v, y);
     H1W_LAUNCHED();

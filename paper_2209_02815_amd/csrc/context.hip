@@ -470,14 +470,15 @@ void Ctx::vcycle_B_eager(int k, const double* F, int64_t ldf, double* X, int64_t
         float* fin = stage.as<float>();
         float* fout = fin + pitch[0];
         double* cm = scal.as<double>() + 12;  // cm[0] = c, cm[1] = mu
-        dots(n, {{ones.as<double>(), F}}, 14);
-        launch_scale(stream, 1, 1.0 / wsum, scal.as<double>() + 14, cm);
-        launch_convert_deflate(stream, n, 1, F, ldf, cm, wvec.as<double>(), fin, pitch[0]);
+        {
+            const double* X1[1] = {ones.as<double>()};
+            const double* Y1[1] = {F};
+            const int nb = launch_dots_partial(stream, n, 1, X1, Y1, part.as<double>());
+            launch_deflate_in(stream, n, F, part.as<double>(), nb, 1.0 / wsum, wvec.as<double>(), fin, cm);
+        }
         vcycle_chunk<float>(1, fin, pitch[0], fout, pitch[0]);
         const int nch = launch_rows_dot_partial_f32(stream, 1, n, fout, pitch[0], wvec.as<double>(), jpart.as<double>());
-        launch_reduce_parts(stream, 1, nch, jpart.as<double>(), scal.as<double>() + 15);
-        launch_scale(stream, 1, 1.0 / wsum, scal.as<double>() + 15, cm + 1);
-        launch_undeflate(stream, n, fout, cm, vdef.as<double>(), X);
+        launch_deflate_out(stream, n, fout, jpart.as<double>(), nch, 1.0 / wsum, cm, vdef.as<double>(), X);
         return;
     }
     for (int r0 = 0; r0 < k; r0 += chunk) {

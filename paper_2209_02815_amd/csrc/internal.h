@@ -186,6 +186,11 @@ void launch_rank2_add(hipStream_t s, int m, const double* a, const double* b, co
 int launch_rows_dot_partial_f32(hipStream_t s, int m, int64_t N, const float* M, int64_t ldm, const double* v,
                                 double* partial);
 void launch_undeflate(hipStream_t s, int64_t N, const float* x, const double* cm, const double* v, double* y);
+// deflation steps of the single-vector FP32 V-cycle, partial sums reduced in the kernel
+void launch_deflate_in(hipStream_t s, int64_t N, const double* F, const double* part, int nparts, double inv_w,
+                       const double* wv, float* Y, double* cm);
+void launch_deflate_out(hipStream_t s, int64_t N, const float* x, const double* part, int nparts, double inv_w,
+                        double* cm, const double* v, double* y);
 void launch_scale(hipStream_t s, int m, double a, const double* x, double* y);
 void launch_fill(hipStream_t s, int64_t N, double v, double* y);
 void launch_zout_deflated(hipStream_t s, int m, int64_t N, const float* Z1, int64_t ldz, const double* sv,
