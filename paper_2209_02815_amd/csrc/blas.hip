@@ -286,12 +286,14 @@ __global__ __launch_bounds__(kBlock) void k_sub(int64_t N, const double* __restr
 }
 
 // x += a p ; r -= a q ; partial sums of r.r
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, double a0, const double* __restrict__ adev,
+// x += a p, r -= a q with the step length a read from device memory;
+// partial sums of r.r
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, const double* __restrict__ adev,
                                                       const double* __restrict__ p, const double* __restrict__ q,
                                                       double* __restrict__ x, double* __restrict__ r,
                                                       double* __restrict__ partial) {
     __shared__ double sh[kBlock / 64];
-    const double a = adev ? *adev : a0;
+    const double a = *adev;
     double acc = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x; n < N;
          n += (int64_t)gridDim.x * kBlock) {
@@ -487,12 +489,6 @@ void launch_zout_deflated(hipStream_t s, int m, int64_t N, const float* Z1, int6
 }
 
 // y = x - mu + c v  (FP64 result of a deflated FP32 V-cycle: x converted from float)
-__global__ __launch_bounds__(kBlock) void k_undeflate(int64_t N, const float* __restrict__ x, const double* __restrict__ cm,
-                                                      const double* __restrict__ v, double* __restrict__ y) {
-    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (n < N) y[n] = double(x[n]) - cm[1] + cm[0] * v[n];
-}
-
 // Deflation steps of the single-vector FP32 V-cycle with the partial sums
 // reduced inside the kernel (the same fixed order as k_reduce_parts, so every
 // block gets the same value): c = inv_w * sum(part) and Y = float(F - c w)
@@ -543,11 +539,6 @@ void launch_deflate_out(hipStream_t s, int64_t N, const float* x, const double* 
                         double* cm, const double* v, double* y) {
     hipLaunchKernelGGL(k_deflate_out, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, x, part, nparts, inv_w,
                        cm, v, y);
-    H1W_LAUNCHED();
-}
-
-void launch_undeflate(hipStream_t s, int64_t N, const float* x, const double* cm, const double* v, double* y) {
-    hipLaunchKernelGGL(k_undeflate, dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, N, x, cm, v, y);
     H1W_LAUNCHED();
 }
 
@@ -636,18 +627,10 @@ void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, doub
     H1W_LAUNCHED();
 }
 
-void launch_cg_update(hipStream_t s, int64_t N, double a, const double* p, const double* q, double* x,
-                      double* r, double* partial, int* nparts) {
-    const int nb = dot_blocks(N);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, a, (const double*)nullptr, p, q, x, r, partial);
-    H1W_LAUNCHED();
-    *nparts = nb;
-}
-
 void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
                           double* x, double* r, double* partial, int* nparts) {
     const int nb = dot_blocks(N);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, 0.0, adev, p, q, x, r, partial);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, adev, p, q, x, r, partial);
     H1W_LAUNCHED();
     *nparts = nb;
 }

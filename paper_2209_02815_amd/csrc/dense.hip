@@ -1,7 +1,8 @@
 // Dense m x m kernels for the capacitance system (Algorithm 3, third step and
-// the two triangular solves of the preconditioner apply): Cholesky, LU with
-// partial pivoting, triangular solves and the J-space update of the CG
-// recurrences. One work-group of 1024 threads walks the columns; m is at most
+// the two triangular solves of the preconditioner apply): the LU with partial
+// pivoting used when the blocked factorisation meets a vanishing pivot, its
+// triangular solves, the transpose, the asymmetry measure and the J-space
+// update of the CG recurrences. One work-group of 1024 threads walks the columns; m is at most
 // a few thousand, so these are latency-bound and small next to the V-cycles
 // and the GEMM. All matrices are row-major with leading dimension m.
 #include <algorithm>
@@ -15,38 +16,6 @@ namespace {
 
 constexpr int kDense = 1024;
 constexpr int kMaxSolveM = 4096;  // x is staged in LDS (32 KB)
-
-// Right-looking Cholesky S = U^T U on the upper triangle, in place.
-// info[0] = -1 on success, else the first column whose pivot is not positive
-// (or not finite).
-__global__ __launch_bounds__(kDense) void k_cholesky_upper(int m, double* __restrict__ U, int* __restrict__ info) {
-    __shared__ double sdiag;
-    __shared__ int sfail;
-    if (threadIdx.x == 0) sfail = -1;
-    for (int k = 0; k < m; ++k) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const double d = U[(int64_t)k * m + k];
-            if (!(d > 0.0) || !isfinite(d)) sfail = k;
-            sdiag = sqrt(d);
-        }
-        __syncthreads();
-        if (sfail >= 0) break;
-        const double s = sdiag;
-        double* rowk = U + (int64_t)k * m;
-        for (int j = k + 1 + threadIdx.x; j < m; j += kDense) rowk[j] /= s;
-        __syncthreads();
-        if (threadIdx.x == 0) rowk[k] = s;
-        // trailing update of the upper triangle: U[i][j] -= U[k][i] U[k][j], k < i <= j
-        for (int i = k + 1; i < m; ++i) {
-            const double uki = rowk[i];
-            double* rowi = U + (int64_t)i * m;
-            for (int j = i + threadIdx.x; j < m; j += kDense) rowi[j] -= uki * rowk[j];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) info[0] = sfail;
-}
 
 // LU with partial pivoting, in place: P A = L U with unit-lower L below the
 // diagonal. piv[k] = row swapped with k at step k. info[0] = -1 on success,
@@ -152,17 +121,6 @@ __device__ void trsv_cols(int m, const double* __restrict__ C, bool lower, bool 
     __syncthreads();
 }
 
-// S = U^T U: solve U^T y = b (lower, columns of U^T = rows of U), then U x = y
-// (upper, columns of U = rows of L = U^T).
-__global__ __launch_bounds__(kDense) void k_chol_solve(int m, const double* __restrict__ U,
-                                                       const double* __restrict__ L, double* __restrict__ x) {
-    __shared__ double sx[kMaxSolveM];
-    for (int i = threadIdx.x; i < m; i += kDense) sx[i] = x[i];
-    trsv_cols(m, U, true, false, sx);
-    trsv_cols(m, L, false, false, sx);
-    for (int i = threadIdx.x; i < m; i += kDense) x[i] = sx[i];
-}
-
 // P S = L U (LU in place, LUt its transpose = the factors stored column-major).
 __global__ __launch_bounds__(kDense) void k_lu_solve(int m, const double* __restrict__ LUt,
                                                      const int* __restrict__ piv, double* __restrict__ x) {
@@ -187,9 +145,9 @@ __global__ __launch_bounds__(kDense) void k_lu_solve(int m, const double* __rest
 // One wave per row.
 __global__ __launch_bounds__(kBlock) void k_jz_update(int m, const double* __restrict__ S, double alpha,
                                                       const double* __restrict__ Jy, const double* __restrict__ w,
-                                                      double beta0, const double* __restrict__ bdev,
+                                                      const double* __restrict__ bdev,
                                                       double* __restrict__ Jz, double* __restrict__ Jp) {
-    const double beta = bdev ? *bdev : beta0;
+    const double beta = *bdev;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= m) return;
@@ -224,11 +182,6 @@ __global__ __launch_bounds__(kDense) void k_asym(int m, const double* __restrict
 
 }  // namespace
 
-void launch_cholesky_upper(hipStream_t s, int m, double* U, int* info) {
-    hipLaunchKernelGGL(k_cholesky_upper, dim3(1), dim3(kDense), 0, s, m, U, info);
-    H1W_LAUNCHED();
-}
-
 void launch_lu(hipStream_t s, int m, double* A, int* piv, int* info) {
     hipLaunchKernelGGL(k_lu, dim3(1), dim3(kDense), 0, s, m, A, piv, info);
     H1W_LAUNCHED();
@@ -240,29 +193,16 @@ void launch_transpose(hipStream_t s, int m, const double* A, double* At) {
     H1W_LAUNCHED();
 }
 
-void launch_chol_solve(hipStream_t s, int m, const double* U, const double* L, double* x) {
-    if (m > kMaxSolveM) throw Error{H1W_EINVAL, "m too large for the triangular solve"};
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(kDense), 0, s, m, U, L, x);
-    H1W_LAUNCHED();
-}
-
 void launch_lu_solve(hipStream_t s, int m, const double* LUt, const double* /*LU*/, const int* piv, double* x) {
     if (m > kMaxSolveM) throw Error{H1W_EINVAL, "m too large for the triangular solve"};
     hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kDense), 0, s, m, LUt, piv, x);
     H1W_LAUNCHED();
 }
 
-void launch_jz_update(hipStream_t s, int m, const double* S, double alpha, const double* Jy, const double* w,
-                      double beta, double* Jz, double* Jp) {
-    hipLaunchKernelGGL(k_jz_update, dim3((unsigned)cdiv(m, kBlock / 64)), dim3(kBlock), 0, s, m, S, alpha, Jy, w,
-                       beta, (const double*)nullptr, Jz, Jp);
-    H1W_LAUNCHED();
-}
-
 void launch_jz_update_dev(hipStream_t s, int m, const double* S, double alpha, const double* Jy, const double* w,
                           const double* bdev, double* Jz, double* Jp) {
     hipLaunchKernelGGL(k_jz_update, dim3((unsigned)cdiv(m, kBlock / 64)), dim3(kBlock), 0, s, m, S, alpha, Jy, w,
-                       0.0, bdev, Jz, Jp);
+                       bdev, Jz, Jp);
     H1W_LAUNCHED();
 }
 

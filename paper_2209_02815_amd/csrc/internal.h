@@ -185,7 +185,6 @@ void launch_rank2_add(hipStream_t s, int m, const double* a, const double* b, co
                       double* S);
 int launch_rows_dot_partial_f32(hipStream_t s, int m, int64_t N, const float* M, int64_t ldm, const double* v,
                                 double* partial);
-void launch_undeflate(hipStream_t s, int64_t N, const float* x, const double* cm, const double* v, double* y);
 // deflation steps of the single-vector FP32 V-cycle, partial sums reduced in the kernel
 void launch_deflate_in(hipStream_t s, int64_t N, const double* F, const double* part, int nparts, double inv_w,
                        const double* wv, float* Y, double* cm);
@@ -207,8 +206,6 @@ void launch_gn_beta(hipStream_t s, const double* sdot, double ia, int mode, bool
 void launch_gn_alpha(hipStream_t s, double* dsc);
 void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
                           double* x, double* r, double* partial, int* nparts);
-void launch_cg_update(hipStream_t s, int64_t N, double a, const double* p, const double* q,
-                      double* x, double* r, double* partial, int* nparts);
 void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, double* out);
 // batched (per-row coefficient) helpers for MG-PCG
 void launch_batched_dots(hipStream_t s, int k, int64_t N, const double* X, int64_t ldx,
@@ -239,14 +236,10 @@ void launch_mirror_lower(hipStream_t s, int m, double* S);
 size_t gemm_partial_elems(int m, int m2, int64_t N);
 
 // dense.hip (single-workgroup factorisations for m <= a few thousand)
-void launch_cholesky_upper(hipStream_t s, int m, double* U, int* info);
 void launch_lu(hipStream_t s, int m, double* A, int* piv, int* info);
 void launch_transpose(hipStream_t s, int m, const double* A, double* At);
-void launch_chol_solve(hipStream_t s, int m, const double* U, const double* L, double* x);
 void launch_lu_solve(hipStream_t s, int m, const double* LUt, const double* LU, const int* piv,
                      double* x);
-void launch_jz_update(hipStream_t s, int m, const double* S, double alpha, const double* Jy,
-                      const double* w, double beta, double* Jz, double* Jp);
 void launch_jz_update_dev(hipStream_t s, int m, const double* S, double alpha, const double* Jy, const double* w,
                           const double* bdev, double* Jz, double* Jp);
 void launch_asym(hipStream_t s, int m, const double* S, double* out);
