@@ -63,14 +63,38 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix
 
 
+# functions whose source text decides the PMC traffic recorded for a class
+TRAFFIC_SOURCES = {"jv": ("blas.hip", ["k_rows_dot", "launch_rows_dot_partial"])}
+
+
+def _function_text(src: str, name: str) -> str:
+    """Text of the first definition of function `name` in a source file: from
+    the start of its line (with a preceding template line) to its closing brace."""
+    import re
+    m = re.search(r"^(template <[^\n]*>\n)?[^\n]*\b" + re.escape(name) + r"\(", src, re.M)
+    if not m:
+        raise KeyError(name)
+    i = src.index("{", m.end())
+    depth = 0
+    for j in range(i, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[j], 0)
+        if depth == 0:
+            return src[m.start():j + 1]
+    raise ValueError(name)
+
+
 def source_sha(cls: str) -> str:
-    """Hash of the source file holding the kernel class (and the device helpers
-    it includes): PMC traffic recorded for a kernel stays valid while it is unchanged."""
+    """Hash of the source text of the class's kernel and launcher (and of the
+    device helpers every kernel includes): PMC traffic recorded for a kernel
+    stays valid while that text is unchanged."""
     import hashlib
-    h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2209_02815_amd", "csrc")
-    for f in (KERNELS[cls][2], "devutil.h"):
-        h.update(open(os.path.join(d, f), "rb").read())
+    fname, funcs = TRAFFIC_SOURCES[cls]
+    src = open(os.path.join(d, fname)).read()
+    h = hashlib.sha256()
+    for f in funcs:
+        h.update(_function_text(src, f).encode())
+    h.update(open(os.path.join(d, "devutil.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -87,7 +111,7 @@ def roofline(cls: str, st: dict) -> dict:
     tp = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tp):
         t = json.load(open(tp))
-        if t.get("class") == cls and t.get("source_sha") == source_sha(cls):
+        if cls in TRAFFIC_SOURCES and t.get("class") == cls and t.get("source_sha") == source_sha(cls):
             traffic = t.get("traffic_bytes_per_launch")
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": traffic, "kernel": cls, "symbol": KERNELS[cls][1], "launches": st["launches"],
