@@ -2,9 +2,10 @@
 // third step) and the triangular solves of the preconditioner apply.
 //
 // Right-looking, block size NB = 64, three launches per block column kb:
-//   diag   one work-group factors the NB x NB diagonal block in LDS
-//          (Cholesky S_kk = U^T U, or LU without pivoting) and writes the
-//          explicit inverses of its triangular factors (Dinv_fwd, Dinv_bwd)
+//   diag   one work-group of 16 waves factors the NB x NB diagonal block
+//          held in registers (Cholesky S_kk = U^T U, or LU without pivoting)
+//          and writes the explicit inverses of its triangular factors
+//          (Dinv_fwd, Dinv_bwd)
 //   panel  Cholesky: U[kb, jb] = U_kk^{-T} A[kb, jb]                (jb > kb)
 //          LU:       U[kb, jb] = L_kk^{-1} A[kb, jb], L[ib, kb] = A[ib, kb] U_kk^{-1}
 //   update Cholesky: A[ib, jb] -= U[kb, ib]^T U[kb, jb]             (kb < ib <= jb)
@@ -69,88 +70,174 @@ __device__ __forceinline__ void quad_pos(int i, int j, int v, int& r, int& c) {
     c = (wave & 1) * 32 + 16 * j + (lane & 15);
 }
 
+// v of lane `lane` (wave-uniform) of the calling wave
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 // ---------------------------------------------------------------- diag
 // mode 0: Cholesky (upper), mode 1: LU without pivoting.
-__global__ __launch_bounds__(256) void k_blk_diag(int m, double* __restrict__ A, int kb, int mode,
+// Lane j of wave w (16 waves) holds column j of the block rows w, w + 16,
+// w + 32, w + 48 in registers (d[q] = row w + 16q) for the whole kernel; four
+// waves share each SIMD, so one wave's read and FMA latencies hide behind
+// the others' work. At elimination step k
+// the wave that holds row k publishes it in LDS (Cholesky: already divided
+// by u_kk; LU: with column k of every row, from lane k of each wave), one
+// barrier makes it visible, and every thread updates its 16 entries with
+// broadcast reads and selects (no branch, no per-row division). The explicit
+// inverses of the triangular factors are computed the same way, by back (and,
+// for LU, forward) substitution on all NB columns of the identity at once,
+// with the factors read from an LDS copy.
+constexpr int kDiagThreads = 1024;
+constexpr int kDiagWaves = kDiagThreads / 64;
+constexpr int kRowsPerWave = NB / kDiagWaves;
+
+__global__ __launch_bounds__(kDiagThreads) void k_blk_diag(int m, double* __restrict__ A, int kb, int mode,
                                                   double* __restrict__ Dfwd, double* __restrict__ Dbwd,
                                                   int* __restrict__ info) {
-    __shared__ double D[NB][NB + 1];
-    __shared__ double X[NB][NB + 1];
-    __shared__ int fail;
+    static_assert(NB == 64, "one column per lane");
+    __shared__ double row[2][NB];
+    __shared__ double col[2][NB];
+    __shared__ double F[NB][NB + 1];   // the factored block
+    __shared__ double X[NB][NB + 1];   // an inverse, for coalesced stores
     if (info[0] >= 0) return;
     const int o = kb * NB;
     const int tid = threadIdx.x;
-    if (tid == 0) fail = -1;
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int r = e / NB, c = e % NB;
-        D[r][c] = (o + r < m && o + c < m) ? A[(int64_t)(o + r) * m + o + c] : (r == c ? 1.0 : 0.0);
+    const int j = tid & 63, w = tid >> 6;
+    double d[kRowsPerWave];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+        const int i = w + kDiagWaves * q;
+        d[q] = (o + i < m && o + j < m) ? A[(int64_t)(o + i) * m + o + j] : (i == j ? 1.0 : 0.0);
     }
-    __syncthreads();
+    // the held entry of row k (called by its holder only), and its replacement
+    auto get = [&](const double (&v)[kRowsPerWave], int k) {
+        double r = 0.0;
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q)
+            if (kDiagWaves * q + w == k) r = v[q];
+        return r;
+    };
+    auto put = [&](double (&v)[kRowsPerWave], int k, double x) {
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q)
+            if (kDiagWaves * q + w == k) v[q] = x;
+    };
+    // Cholesky S = U^T U: u_kk = sqrt(p), u_kj = d_kj / u_kk, and the upper
+    // trailing entries lose u_ki u_kj (p = d_kk before step k); the lower
+    // triangle is left as it was. LU: l_ik = d_ik / p in place of d_ik, and
+    // d_ij -= l_ik d_kj for i, j > k. The pivot goes
+    // through LDS to every thread, so all of them stop together on a bad one.
+    int fail = -1;
     for (int k = 0; k < NB; ++k) {
-        if (tid == 0) {
-            const double p = D[k][k];
-            const bool bad = mode == 0 ? !(p > 0.0) || !isfinite(p) : !(p != 0.0) || !isfinite(p);
-            if (bad) fail = o + k;
-            if (mode == 0) D[k][k] = sqrt(p);
-        }
-        __syncthreads();
-        if (fail >= 0) break;
-        const double p = D[k][k];
-        if (mode == 0) {
-            for (int j = k + 1 + tid; j < NB; j += 256) D[k][j] /= p;
-        } else {
-            for (int i = k + 1 + tid; i < NB; i += 256) D[i][k] /= p;
-        }
-        __syncthreads();
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int i = e / NB, j = e % NB;
-            if (i > k && j > k) {
-                if (mode == 0) {
-                    if (j >= i) D[i][j] -= D[k][i] * D[k][j];
-                } else {
-                    D[i][j] -= D[i][k] * D[k][j];
-                }
+        double* rk = row[k & 1];
+        double* ck = col[k & 1];
+        if (w == (k % kDiagWaves)) {
+            const double dk = get(d, k);
+            if (mode == 0) {
+                const double p = lane_value(dk, k);
+                const double sk = sqrt(p);
+                const double u = dk / sk;
+                rk[j] = j == k ? p : u;
+                if (j >= k) put(d, k, j == k ? sk : u);
+            } else {
+                rk[j] = dk;
             }
         }
+        if (mode == 1 && j == k) {
+#pragma unroll
+            for (int q = 0; q < kRowsPerWave; ++q) ck[w + kDiagWaves * q] = d[q];
+        }
         __syncthreads();
+        const double p = rk[k];
+        const bool bad = mode == 0 ? !(p > 0.0) || !isfinite(p) : !(p != 0.0) || !isfinite(p);
+        if (bad) {
+            fail = o + k;
+            break;
+        }
+        const double rkj = rk[j];
+        if (mode == 0) {
+#pragma unroll
+            for (int q = 0; q < kRowsPerWave; ++q) {
+                const int i = w + kDiagWaves * q;
+                const double nv = d[q] - rk[i] * rkj;
+                d[q] = (i > k && i <= j) ? nv : d[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kRowsPerWave; ++q) {
+                const int i = w + kDiagWaves * q;
+                const double l = ck[i] / p;
+                const double nv = j > k ? d[q] - l * rkj : (j == k ? l : d[q]);
+                d[q] = i > k ? nv : d[q];
+            }
+        }
     }
     if (fail >= 0) {
         if (tid == 0) info[0] = fail;
         return;
     }
-    // inverse of the upper factor: solve U X = I (one column per thread)
-    if (tid < NB) {
-        const int j = tid;
-        for (int i = NB - 1; i >= 0; --i) {
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int l = i + 1; l <= j; ++l) s -= D[i][l] * X[l][j];
-            X[i][j] = (i <= j) ? s / D[i][i] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) F[w + kDiagWaves * q][j] = d[q];
+    __syncthreads();
+    // U X = I by back substitution: x_kj = b_kj / u_kk, then b_ij -= u_ik x_kj
+    // for the rows i < k
+    double x[kRowsPerWave];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) x[q] = (w + kDiagWaves * q == j) ? 1.0 : 0.0;
+    for (int k = NB - 1; k >= 0; --k) {
+        double* rk = row[k & 1];
+        if (w == (k % kDiagWaves)) {
+            const double xk = get(x, k) / F[k][k];
+            rk[j] = xk;
+            put(x, k, xk);
+        }
+        __syncthreads();
+        const double xk = rk[j];
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            const int i = w + kDiagWaves * q;
+            const double nv = x[q] - F[i][k] * xk;
+            x[q] = i < k ? nv : x[q];
         }
     }
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) X[w + kDiagWaves * q][j] = x[q];
     __syncthreads();
     double* Fw = Dfwd + (int64_t)kb * NB * NB;
     double* Bw = Dbwd + (int64_t)kb * NB * NB;
-    for (int e = tid; e < NB * NB; e += 256) {
+    for (int e = tid; e < NB * NB; e += kDiagThreads) {
         const int r = e / NB, c = e % NB;
-        Bw[e] = X[r][c];
-        if (mode == 0) Fw[e] = X[c][r];  // (U^T)^{-1} = (U^{-1})^T
+        Bw[e] = r <= c ? X[r][c] : 0.0;
+        if (mode == 0) Fw[e] = c <= r ? X[c][r] : 0.0;  // (U^T)^{-1} = (U^{-1})^T
     }
-    __syncthreads();
-    if (mode == 1) {  // inverse of the unit-lower factor: L X = I
-        if (tid < NB) {
-            const int j = tid;
-            for (int i = 0; i < NB; ++i) {
-                double s = (i == j) ? 1.0 : 0.0;
-                for (int l = j; l < i; ++l) s -= D[i][l] * X[l][j];
-                X[i][j] = (i >= j) ? s : 0.0;
+    if (mode == 1) {  // L X = I by forward substitution (unit diagonal): b_ij -= l_ik x_kj, i > k
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) x[q] = (w + kDiagWaves * q == j) ? 1.0 : 0.0;
+        for (int k = 0; k < NB; ++k) {
+            double* rk = row[k & 1];
+            if (w == (k % kDiagWaves)) rk[j] = get(x, k);
+            __syncthreads();
+            const double xk = rk[j];
+#pragma unroll
+            for (int q = 0; q < kRowsPerWave; ++q) {
+                const int i = w + kDiagWaves * q;
+                const double nv = x[q] - F[i][k] * xk;
+                x[q] = i > k ? nv : x[q];
             }
         }
-        __syncthreads();
-        for (int e = tid; e < NB * NB; e += 256) Fw[e] = X[e / NB][e % NB];
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            const int i = w + kDiagWaves * q;
+            Fw[i * NB + j] = i >= j ? x[q] : 0.0;
+        }
     }
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int r = e / NB, c = e % NB;
-        if (o + r < m && o + c < m) A[(int64_t)(o + r) * m + o + c] = D[r][c];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+        const int i = w + kDiagWaves * q;
+        if (o + i < m && o + j < m) A[(int64_t)(o + i) * m + o + j] = d[q];
     }
 }
 
@@ -326,7 +413,7 @@ void launch_blocked_factor(hipStream_t s, int m, double* A, int mode, double* Df
     H1W_HIP(hipMemsetAsync(info, 0xff, sizeof(int), s));  // info = -1
     const int nb = (m + NB - 1) / NB;
     for (int kb = 0; kb < nb; ++kb) {
-        hipLaunchKernelGGL(k_blk_diag, dim3(1), dim3(256), 0, s, m, A, kb, mode, Dfwd, Dbwd, info);
+        hipLaunchKernelGGL(k_blk_diag, dim3(1), dim3(kDiagThreads), 0, s, m, A, kb, mode, Dfwd, Dbwd, info);
         H1W_LAUNCHED();
         const int rest = nb - kb - 1;
         if (rest == 0) break;

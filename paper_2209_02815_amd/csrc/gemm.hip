@@ -169,20 +169,37 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
 // S[i][j] (block of m x m2 at S, leading dimension lds) = sum over splits of
 // the partials (+ alpha on the block diagonal i == j). lower: the square
 // product was computed on and below the diagonal only; S[i][j] for i < j is
-// taken from the partial at (j, i).
+// taken from the partial at (j, i). A work-group takes kRedOut consecutive
+// outputs; its kRedGroups thread groups sum the splits g, g + kRedGroups, ...
+// and the group sums are added in group order (a fixed order, so the result
+// does not depend on timing).
+constexpr int kRedGroups = 8;
+constexpr int kRedOut = kBlock / kRedGroups;
+
 __global__ __launch_bounds__(kBlock) void k_cap_reduce(int m, int m2, int splits, const double* __restrict__ partial,
                                                        int lower, double alpha, double* __restrict__ S,
                                                        int64_t lds) {
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= (int64_t)m * m2) return;
-    const int i = (int)(idx / m2), j = (int)(idx - (int64_t)i * m2);
-    const int si = (lower && i < j) ? j : i;
-    const int sj = (lower && i < j) ? i : j;
-    const double* p = partial + (int64_t)si * m2 + sj;
+    __shared__ double sh[kRedGroups][kRedOut];
+    const int g = threadIdx.x / kRedOut, q = threadIdx.x % kRedOut;
+    const int64_t idx = (int64_t)blockIdx.x * kRedOut + q;
+    const bool ok = idx < (int64_t)m * m2;
+    const int i = ok ? (int)(idx / m2) : 0, j = ok ? (int)(idx - (int64_t)i * m2) : 0;
     double acc = 0.0;
-    for (int s = 0; s < splits; ++s) acc += p[(int64_t)s * m * m2];
-    if (i == j) acc += alpha;
-    S[(int64_t)i * lds + j] = acc;
+    if (ok) {
+        const int si = (lower && i < j) ? j : i;
+        const int sj = (lower && i < j) ? i : j;
+        const double* p = partial + (int64_t)si * m2 + sj;
+        for (int s = g; s < splits; s += kRedGroups) acc += p[(int64_t)s * m * m2];
+    }
+    sh[g][q] = acc;
+    __syncthreads();
+    if (g == 0 && ok) {
+        double t = sh[0][q];
+#pragma unroll
+        for (int h = 1; h < kRedGroups; ++h) t += sh[h][q];
+        if (i == j) t += alpha;
+        S[(int64_t)i * lds + j] = t;
+    }
 }
 
 // S[i][j] = S[j][i] for i < j (upper triangle from the lower one)
@@ -239,7 +256,7 @@ int launch_capacitance_partial(hipStream_t s, int m, int m2, int64_t N, const do
 void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const double* partial, bool lower_only,
                                double alpha, double* S, int64_t lds) {
     if (m <= 0 || m2 <= 0) return;
-    hipLaunchKernelGGL(k_cap_reduce, dim3((unsigned)cdiv((int64_t)m * m2, kBlock)), dim3(kBlock), 0, s, m, m2,
+    hipLaunchKernelGGL(k_cap_reduce, dim3((unsigned)cdiv((int64_t)m * m2, kRedOut)), dim3(kBlock), 0, s, m, m2,
                        splits, partial, (int)lower_only, alpha, S, lds);
     H1W_LAUNCHED();
 }
