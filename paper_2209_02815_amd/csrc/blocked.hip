@@ -79,99 +79,100 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 
 // ---------------------------------------------------------------- diag
 // mode 0: Cholesky (upper), mode 1: LU without pivoting.
-// Lane j of wave w (16 waves) holds column j of the block rows w, w + 16,
-// w + 32, w + 48 in registers (d[q] = row w + 16q) for the whole kernel; four
-// waves share each SIMD, so one wave's read and FMA latencies hide behind
-// the others' work. At elimination step k
-// the wave that holds row k publishes it in LDS (Cholesky: already divided
-// by u_kk; LU: with column k of every row, from lane k of each wave), one
-// barrier makes it visible, and every thread updates its 16 entries with
-// broadcast reads and selects (no branch, no per-row division). The explicit
-// inverses of the triangular factors are computed the same way, by back (and,
-// for LU, forward) substitution on all NB columns of the identity at once,
-// with the factors read from an LDS copy.
+// Lane j of wave w (16 waves) holds column j of the block rows 4w .. 4w + 3
+// in registers (d[t] = row 4w + t) for the whole kernel. The elimination
+// runs in 16 panel steps of 4 columns: the wave holding the panel's 4 rows
+// eliminates them among themselves (pivots and multipliers from lane k by
+// readlane), publishes them in LDS, and after one barrier every later wave
+// applies the 4 eliminations to its rows in the same order. Each entry sees
+// the same operations in the same order as in column-by-column elimination.
+// The explicit inverses of the triangular factors are computed the same way
+// by back (and, for LU, forward) substitution on all NB columns of the
+// identity at once.
 constexpr int kDiagThreads = 1024;
-constexpr int kDiagWaves = kDiagThreads / 64;
-constexpr int kRowsPerWave = NB / kDiagWaves;
+constexpr int kPanel = 4;   // rows per wave = columns per panel step
+static_assert(kDiagThreads / 64 * kPanel == NB, "16 waves of 4 rows");
+
+__device__ __forceinline__ bool bad_pivot(int mode, double p) {
+    return mode == 0 ? !(p > 0.0) || !isfinite(p) : !(p != 0.0) || !isfinite(p);
+}
 
 __global__ __launch_bounds__(kDiagThreads) void k_blk_diag(int m, double* __restrict__ A, int kb, int mode,
-                                                  double* __restrict__ Dfwd, double* __restrict__ Dbwd,
-                                                  int* __restrict__ info) {
-    static_assert(NB == 64, "one column per lane");
-    __shared__ double row[2][NB];
-    __shared__ double col[2][NB];
-    __shared__ double F[NB][NB + 1];   // the factored block
-    __shared__ double X[NB][NB + 1];   // an inverse, for coalesced stores
+                                                           double* __restrict__ Dfwd, double* __restrict__ Dbwd,
+                                                           int* __restrict__ info) {
+    __shared__ double pan[2][kPanel][NB];
+    __shared__ int pfail[2];
+    __shared__ double X[NB][NB + 1];
     if (info[0] >= 0) return;
     const int o = kb * NB;
     const int tid = threadIdx.x;
     const int j = tid & 63, w = tid >> 6;
-    double d[kRowsPerWave];
+    const int r0 = kPanel * w;  // first row of this wave
+    double d[kPanel];
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) {
-        const int i = w + kDiagWaves * q;
-        d[q] = (o + i < m && o + j < m) ? A[(int64_t)(o + i) * m + o + j] : (i == j ? 1.0 : 0.0);
+    for (int t = 0; t < kPanel; ++t) {
+        const int i = r0 + t;
+        d[t] = (o + i < m && o + j < m) ? A[(int64_t)(o + i) * m + o + j] : (i == j ? 1.0 : 0.0);
     }
-    // the held entry of row k (called by its holder only), and its replacement
-    auto get = [&](const double (&v)[kRowsPerWave], int k) {
-        double r = 0.0;
-#pragma unroll
-        for (int q = 0; q < kRowsPerWave; ++q)
-            if (kDiagWaves * q + w == k) r = v[q];
-        return r;
-    };
-    auto put = [&](double (&v)[kRowsPerWave], int k, double x) {
-#pragma unroll
-        for (int q = 0; q < kRowsPerWave; ++q)
-            if (kDiagWaves * q + w == k) v[q] = x;
-    };
     // Cholesky S = U^T U: u_kk = sqrt(p), u_kj = d_kj / u_kk, and the upper
     // trailing entries lose u_ki u_kj (p = d_kk before step k); the lower
     // triangle is left as it was. LU: l_ik = d_ik / p in place of d_ik, and
-    // d_ij -= l_ik d_kj for i, j > k. The pivot goes
-    // through LDS to every thread, so all of them stop together on a bad one.
+    // d_ij -= l_ik d_kj for i, j > k. The first bad pivot goes through LDS
+    // to every thread, so all of them stop together.
     int fail = -1;
-    for (int k = 0; k < NB; ++k) {
-        double* rk = row[k & 1];
-        double* ck = col[k & 1];
-        if (w == (k % kDiagWaves)) {
-            const double dk = get(d, k);
-            if (mode == 0) {
-                const double p = lane_value(dk, k);
-                const double sk = sqrt(p);
-                const double u = dk / sk;
-                rk[j] = j == k ? p : u;
-                if (j >= k) put(d, k, j == k ? sk : u);
-            } else {
-                rk[j] = dk;
-            }
-        }
-        if (mode == 1 && j == k) {
+    for (int kp = 0; kp < NB / kPanel; ++kp) {
+        const int k0 = kPanel * kp;
+        double (*P)[NB] = pan[kp & 1];
+        if (w == kp) {
+            int f = -1;
 #pragma unroll
-            for (int q = 0; q < kRowsPerWave; ++q) ck[w + kDiagWaves * q] = d[q];
+            for (int t = 0; t < kPanel; ++t) {
+                const int k = k0 + t;
+                const double p = lane_value(d[t], k);
+                if (f < 0 && bad_pivot(mode, p)) f = o + k;
+                if (mode == 0) {
+                    const double sk = sqrt(p);
+                    const double u = d[t] / sk;
+#pragma unroll
+                    for (int t2 = t + 1; t2 < kPanel; ++t2) {
+                        const double ui = lane_value(u, k0 + t2);
+                        if (j >= k0 + t2) d[t2] -= ui * u;
+                    }
+                    P[t][j] = u;
+                    if (j >= k) d[t] = j == k ? sk : u;
+                } else {
+#pragma unroll
+                    for (int t2 = t + 1; t2 < kPanel; ++t2) {
+                        const double l = lane_value(d[t2], k) / p;
+                        d[t2] = j > k ? d[t2] - l * d[t] : (j == k ? l : d[t2]);
+                    }
+                    P[t][j] = d[t];
+                }
+            }
+            if (j == 0) pfail[kp & 1] = f;
         }
         __syncthreads();
-        const double p = rk[k];
-        const bool bad = mode == 0 ? !(p > 0.0) || !isfinite(p) : !(p != 0.0) || !isfinite(p);
-        if (bad) {
-            fail = o + k;
-            break;
-        }
-        const double rkj = rk[j];
-        if (mode == 0) {
+        fail = pfail[kp & 1];
+        if (fail >= 0) break;
+        if (w > kp) {
 #pragma unroll
-            for (int q = 0; q < kRowsPerWave; ++q) {
-                const int i = w + kDiagWaves * q;
-                const double nv = d[q] - rk[i] * rkj;
-                d[q] = (i > k && i <= j) ? nv : d[q];
-            }
-        } else {
+            for (int t = 0; t < kPanel; ++t) {
+                const int k = k0 + t;
+                const double ukj = P[t][j];
+                if (mode == 0) {
 #pragma unroll
-            for (int q = 0; q < kRowsPerWave; ++q) {
-                const int i = w + kDiagWaves * q;
-                const double l = ck[i] / p;
-                const double nv = j > k ? d[q] - l * rkj : (j == k ? l : d[q]);
-                d[q] = i > k ? nv : d[q];
+                    for (int q = 0; q < kPanel; ++q) {
+                        const double nv = d[q] - P[t][r0 + q] * ukj;
+                        d[q] = j >= r0 + q ? nv : d[q];
+                    }
+                } else {
+                    const double p = P[t][k];
+#pragma unroll
+                    for (int q = 0; q < kPanel; ++q) {
+                        const double l = lane_value(d[q], k) / p;
+                        d[q] = j > k ? d[q] - l * ukj : (j == k ? l : d[q]);
+                    }
+                }
             }
         }
     }
@@ -179,32 +180,38 @@ __global__ __launch_bounds__(kDiagThreads) void k_blk_diag(int m, double* __rest
         if (tid == 0) info[0] = fail;
         return;
     }
-#pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) F[w + kDiagWaves * q][j] = d[q];
-    __syncthreads();
+    __syncthreads();  // the last panel's readers are done before pan[1] is reused
     // U X = I by back substitution: x_kj = b_kj / u_kk, then b_ij -= u_ik x_kj
-    // for the rows i < k
-    double x[kRowsPerWave];
+    // for the rows i < k, k descending
+    double x[kPanel];
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) x[q] = (w + kDiagWaves * q == j) ? 1.0 : 0.0;
-    for (int k = NB - 1; k >= 0; --k) {
-        double* rk = row[k & 1];
-        if (w == (k % kDiagWaves)) {
-            const double xk = get(x, k) / F[k][k];
-            rk[j] = xk;
-            put(x, k, xk);
+    for (int t = 0; t < kPanel; ++t) x[t] = (r0 + t == j) ? 1.0 : 0.0;
+    for (int kp = NB / kPanel - 1; kp >= 0; --kp) {
+        const int k0 = kPanel * kp;
+        double (*P)[NB] = pan[kp & 1];
+        if (w == kp) {
+#pragma unroll
+            for (int t = kPanel - 1; t >= 0; --t) {
+                const int k = k0 + t;
+                x[t] = x[t] / lane_value(d[t], k);
+#pragma unroll
+                for (int t2 = 0; t2 < t; ++t2) x[t2] -= lane_value(d[t2], k) * x[t];
+            }
+#pragma unroll
+            for (int t = 0; t < kPanel; ++t) P[t][j] = x[t];
         }
         __syncthreads();
-        const double xk = rk[j];
+        if (w < kp) {
 #pragma unroll
-        for (int q = 0; q < kRowsPerWave; ++q) {
-            const int i = w + kDiagWaves * q;
-            const double nv = x[q] - F[i][k] * xk;
-            x[q] = i < k ? nv : x[q];
+            for (int t = kPanel - 1; t >= 0; --t) {
+                const double xk = P[t][j];
+#pragma unroll
+                for (int q = 0; q < kPanel; ++q) x[q] -= lane_value(d[q], k0 + t) * xk;
+            }
         }
     }
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) X[w + kDiagWaves * q][j] = x[q];
+    for (int t = 0; t < kPanel; ++t) X[r0 + t][j] = x[t];
     __syncthreads();
     double* Fw = Dfwd + (int64_t)kb * NB * NB;
     double* Bw = Dbwd + (int64_t)kb * NB * NB;
@@ -215,29 +222,38 @@ __global__ __launch_bounds__(kDiagThreads) void k_blk_diag(int m, double* __rest
     }
     if (mode == 1) {  // L X = I by forward substitution (unit diagonal): b_ij -= l_ik x_kj, i > k
 #pragma unroll
-        for (int q = 0; q < kRowsPerWave; ++q) x[q] = (w + kDiagWaves * q == j) ? 1.0 : 0.0;
-        for (int k = 0; k < NB; ++k) {
-            double* rk = row[k & 1];
-            if (w == (k % kDiagWaves)) rk[j] = get(x, k);
-            __syncthreads();
-            const double xk = rk[j];
+        for (int t = 0; t < kPanel; ++t) x[t] = (r0 + t == j) ? 1.0 : 0.0;
+        for (int kp = 0; kp < NB / kPanel; ++kp) {
+            const int k0 = kPanel * kp;
+            double (*P)[NB] = pan[kp & 1];
+            if (w == kp) {
 #pragma unroll
-            for (int q = 0; q < kRowsPerWave; ++q) {
-                const int i = w + kDiagWaves * q;
-                const double nv = x[q] - F[i][k] * xk;
-                x[q] = i > k ? nv : x[q];
+                for (int t = 0; t < kPanel; ++t) {
+#pragma unroll
+                    for (int t2 = t + 1; t2 < kPanel; ++t2) x[t2] -= lane_value(d[t2], k0 + t) * x[t];
+                    P[t][j] = x[t];
+                }
+            }
+            __syncthreads();
+            if (w > kp) {
+#pragma unroll
+                for (int t = 0; t < kPanel; ++t) {
+                    const double xk = P[t][j];
+#pragma unroll
+                    for (int q = 0; q < kPanel; ++q) x[q] -= lane_value(d[q], k0 + t) * xk;
+                }
             }
         }
 #pragma unroll
-        for (int q = 0; q < kRowsPerWave; ++q) {
-            const int i = w + kDiagWaves * q;
-            Fw[i * NB + j] = i >= j ? x[q] : 0.0;
+        for (int t = 0; t < kPanel; ++t) {
+            const int i = r0 + t;
+            Fw[i * NB + j] = i >= j ? x[t] : 0.0;
         }
     }
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) {
-        const int i = w + kDiagWaves * q;
-        if (o + i < m && o + j < m) A[(int64_t)(o + i) * m + o + j] = d[q];
+    for (int t = 0; t < kPanel; ++t) {
+        const int i = r0 + t;
+        if (o + i < m && o + j < m) A[(int64_t)(o + i) * m + o + j] = d[t];
     }
 }
 
