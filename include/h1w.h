@@ -292,9 +292,14 @@ h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx);
  * multigrid Poisson solver): a native executor overlaps them on one GPU.
  *
  * The items are ordered by decreasing work N * (m + 1) and pulled from one
- * queue by opts.nworkers host threads; each thread owns a HIP stream (default
- * priority) and one context per (grid, precision, smoothing steps) it meets,
- * reused by later items of that key. With opts.autotune, the first item of
+ * queue by opts.nworkers host threads; each thread drives a worker that owns
+ * a HIP stream (default priority) and one context per (grid, precision,
+ * smoothing steps, beta, graph replay) it meets, reused by later items of
+ * that key. Workers are kept for the process and reused by later batches
+ * (at most 12 contexts each, the least recently used dropped beyond that; a
+ * context whose item failed is dropped), so their device memory stays
+ * allocated until the process ends; a batch on grids met before allocates
+ * no device memory. With opts.autotune, the first item of
  * each (grid, precision, ceil(log2 m)) key is solved with nu = 1, 3 and 2
  * smoothing steps per side back to back by one worker, and the later items
  * of the key use the nu with the shortest wall time (the nu = 2 solve is the

@@ -3,13 +3,16 @@
 // that overlaps the instances on the GPU, and a small autotuner.
 //
 // Executor: the instances are sorted by decreasing work (N * (m + 1)) and
-// pulled from a shared queue by nworkers host threads. Each thread owns one
-// HIP stream (default priority) and keeps one context per (grid, precision,
-// smoother steps) it has met, so the hierarchy, the coarsest inverse and the
-// device workspace are set up once per key and reused by later instances.
-// The solve of one instance is the library's own h1w_gn_solve path; the
-// threads' streams let the small kernels and host round trips of different
-// instances overlap.
+// pulled from a shared queue by nworkers host threads. Each thread drives one
+// worker: a HIP stream (default priority) and one context per (grid,
+// precision, smoother steps, beta, graph replay) it has met, so the
+// hierarchy, the coarsest inverse and the device workspace are set up once
+// per key and reused by later instances. Workers are kept for the process
+// (per device, at most kMaxCtxPerWorker contexts each, the least recently
+// used one dropped beyond that) and handed to later batches, so a batch on
+// grids seen before allocates and frees no device memory. The solve of one
+// instance is the library's own h1w_gn_solve path; the workers' streams let
+// the small kernels and host round trips of different instances overlap.
 //
 // Autotuner: for each (grid, precision, row bucket ceil(log2 m)) key, the
 // worker that meets the key first solves that instance with nu = 1, 3 and
@@ -42,10 +45,23 @@ constexpr int kNumCandidates = 3;
 
 struct GridKey {
     int dim, n0, n1, n2, precision, nu;
+    double beta;
+    bool graphs;
     bool operator<(const GridKey& o) const {
-        return std::tie(dim, n0, n1, n2, precision, nu) < std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu);
+        return std::tie(dim, n0, n1, n2, precision, nu, beta, graphs) <
+               std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu, o.beta, o.graphs);
     }
 };
+
+// a grid within one batch (its items must share beta)
+struct ShapeKey {
+    int dim, n0, n1, n2;
+    bool operator<(const ShapeKey& o) const {
+        return std::tie(dim, n0, n1, n2) < std::tie(o.dim, o.n0, o.n1, o.n2);
+    }
+};
+
+constexpr int kMaxCtxPerWorker = 12;
 
 struct TuneKey {
     int dim, n0, n1, n2, precision, bucket;
@@ -77,7 +93,21 @@ std::map<TuneKey, TuneState> g_tuned;
 struct Worker {
     hipStream_t stream = nullptr;
     std::map<GridKey, std::unique_ptr<Ctx>> ctxs;
+    std::map<GridKey, uint64_t> last_use;
+    uint64_t clock = 0;
 };
+
+// Idle workers per device. Never destroyed: the workers' streams and device
+// buffers are reclaimed with the process, so no HIP call runs during exit.
+struct WorkerPool {
+    std::mutex mu;
+    std::map<int, std::vector<Worker*>> idle;
+};
+
+WorkerPool& worker_pool() {
+    static WorkerPool* p = new WorkerPool();
+    return *p;
+}
 
 }  // namespace
 
@@ -102,7 +132,26 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     std::mutex tune_mu;
     std::map<TuneKey, TuneState> tune;  // the keys met by this batch
     std::atomic<int> next{0};
-    std::vector<Worker> workers(nworkers);
+    std::vector<Worker*> workers(nworkers, nullptr);
+    {
+        std::lock_guard<std::mutex> lk(worker_pool().mu);
+        auto& idle = worker_pool().idle[device];
+        for (int w = 0; w < nworkers; ++w) {
+            if (!idle.empty()) {
+                workers[w] = idle.back();
+                idle.pop_back();
+            } else {
+                workers[w] = new Worker();
+            }
+        }
+    }
+    // each item's grid must keep the beta of the first item of that grid
+    std::map<ShapeKey, double> grid_beta;
+    for (int i = 0; i < count; ++i) {
+        const h1w_batch_item& it = items[i];
+        if (it.dim != 2 && it.dim != 3) continue;  // reported per item below
+        grid_beta.emplace(ShapeKey{it.dim, it.n[0], it.n[1], it.dim == 3 ? it.n[2] : 1}, it.beta);
+    }
     std::vector<std::string> worker_err(nworkers);
     std::vector<std::string> item_err(count);
 
@@ -136,11 +185,13 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     };
 
     auto run = [&](int w) {
-        Worker& me = workers[w];
+        Worker& me = *workers[w];
         try {
             H1W_HIP(hipSetDevice(device));
-            std::lock_guard<std::recursive_mutex> lk(capture_lock());
-            H1W_HIP(hipStreamCreateWithFlags(&me.stream, hipStreamNonBlocking));
+            if (!me.stream) {
+                std::lock_guard<std::recursive_mutex> lk(capture_lock());
+                H1W_HIP(hipStreamCreateWithFlags(&me.stream, hipStreamNonBlocking));
+            }
         } catch (const Error& e) {
             worker_err[w] = e.msg;
             return;
@@ -152,6 +203,11 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
             const h1w_batch_item& it = items[i];
             h1w_info inf{};
             h1w_status st = H1W_OK;
+            std::vector<GridKey> used;  // contexts this item ran on (dropped if it fails)
+            auto drop = [&](const GridKey& gk) {
+                me.ctxs.erase(gk);
+                me.last_use.erase(gk);
+            };
             try {
                 require(it.dim == 2 || it.dim == 3, "item dim must be 2 or 3");
                 require(it.m >= 0, "item m must be >= 0");
@@ -161,10 +217,27 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision, row_bucket(it.m)};
                 bool tuning = false;
                 const int nu = choose_nu(tk, tuning);
+                require(std::isfinite(it.beta) && it.beta == grid_beta[ShapeKey{it.dim, it.n[0], it.n[1], n2}],
+                        "items of one grid must share beta within a batch");
                 auto ctx_for = [&](int nu_c) -> Ctx& {
-                    GridKey gk{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c};
+                    GridKey gk{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c, it.beta, o.graphs != 0};
+                    me.last_use[gk] = ++me.clock;
+                    used.push_back(gk);
                     auto& slot = me.ctxs[gk];
                     if (!slot) {
+                        // beyond the cap, drop the least recently used context
+                        while ((int)me.ctxs.size() > kMaxCtxPerWorker) {
+                            auto victim = me.ctxs.end();
+                            uint64_t oldest = UINT64_MAX;
+                            for (auto c = me.ctxs.begin(); c != me.ctxs.end(); ++c)
+                                if (c->second && me.last_use[c->first] < oldest) {
+                                    oldest = me.last_use[c->first];
+                                    victim = c;
+                                }
+                            if (victim == me.ctxs.end()) break;
+                            me.last_use.erase(victim->first);
+                            me.ctxs.erase(victim);
+                        }
                         h1w_grid_desc d{};
                         d.dim = it.dim;
                         d.n[0] = it.n[0];
@@ -176,11 +249,9 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                         d.flags = o.graphs ? H1W_FLAG_GRAPH_VCYCLE : 0u;
                         auto c = std::make_unique<Ctx>();
                         c->init(d, me.stream);
-                        slot = std::move(c);
+                        me.ctxs[gk] = std::move(c);
                     }
-                    require(std::isfinite(it.beta) && it.beta == slot->d.beta,
-                            "items of one grid must share beta within a batch");
-                    return *slot;
+                    return *me.ctxs[gk];
                 };
                 require(std::isfinite(it.alpha) && it.alpha > 0.0, "item alpha must be finite and > 0");
                 require(it.m == 0 || it.ldj >= ctx_for(nu).N(), "item ldj must be >= N");
@@ -205,6 +276,9 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                             try {  // a candidate that fails (e.g. no convergence) is skipped
                                 cx.gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
                             } catch (const Error&) {
+                                used.pop_back();
+                                drop(GridKey{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c, it.beta,
+                                             o.graphs != 0});
                                 continue;
                             }
                         }
@@ -227,6 +301,8 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 st = H1W_EINVAL;
                 item_err[i] = e.what();
             }
+            if (st != H1W_OK)  // a context left by a failed solve is not reused
+                for (const GridKey& gk : used) drop(gk);
             if (infos) infos[i] = inf;
             if (status) status[i] = st;
         }
@@ -239,10 +315,11 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     for (auto& t : threads) t.join();
     const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 
-    // tear down after every worker has stopped (buffer release synchronises the device)
-    for (auto& w : workers) {
-        w.ctxs.clear();
-        if (w.stream) (void)hipStreamDestroy(w.stream);
+    // the workers go back to the pool with their streams and contexts
+    {
+        std::lock_guard<std::mutex> lk(worker_pool().mu);
+        auto& idle = worker_pool().idle[device];
+        for (Worker* w : workers) idle.push_back(w);
     }
     for (const auto& e : worker_err)
         if (!e.empty()) throw Error{H1W_EHIP, "batch worker setup failed: " + e};
