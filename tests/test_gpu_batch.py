@@ -139,3 +139,24 @@ def test_batch_with_graphs_matches_eager(P):
     assert all(s == 0 for s in stats)
     for a, b in zip(items_e, items_g):
         assert torch.equal(a["x"], b["x"])
+
+
+def test_batch_workers_reused_across_batches(P):
+    # The executor keeps its workers' contexts for the process: a second batch
+    # on the same grids with another beta gets contexts of its own, an item
+    # that fails inside its solve (a NaN right-hand side) does not leave a
+    # broken context behind, and every solve is still right against the oracle.
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads(count=6, batch_id=8, sides=(17, 33), m_lo=4, m_hi=24)
+    for beta in (1e-2, 3e-2, 1e-2):
+        ws = [wl.with_(beta=beta) for wl in wls]
+        items, host = make_items(ws)
+        nanb = items[0]["b"].clone()
+        nanb[3] = float("nan")
+        bad = dict(items[0], b=nanb, x=torch.zeros_like(items[0]["x"]))
+        infos, stats, _ = nat.h1w_batch_solve(items + [bad], precision=nat.H1W_FP64, nworkers=2, rtol=1e-10,
+                                              raise_on_error=False)
+        assert stats[-1] == nat.H1W_ENUMERIC and all(s == 0 for s in stats[:-1]), stats
+        for wl, it, (J, b) in zip(ws, items, host):
+            rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy())
+            assert rr <= 1.01e-10, (wl.name, beta, rr)

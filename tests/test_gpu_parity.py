@@ -473,17 +473,20 @@ def test_gn_solve_deterministic(P):
         assert torch.equal(x1, x2)
 
 
-@pytest.mark.parametrize("m", [24, 130])
-def test_forced_lu_fp64(P, m):
-    # the blocked LU (no pivoting) of the symmetric FP64 capacitance matrix
+@pytest.mark.parametrize("m", [24, 64, 65, 130])
+@pytest.mark.parametrize("factor", [1, 2])
+def test_blocked_factor_fp64(P, m, factor):
+    # the blocked Cholesky and LU (no pivoting) of the FP64 capacitance matrix:
+    # one partial block, exactly one block, one block plus one row, and three
+    # blocks with a ragged last one
     wl, J, b = _bump_problem("square33", m)
     R = rng(9).standard_normal((1, wl.N))
     with P.Context(wl.shape, wl.beta) as ctx:
         Jd = dev(J)
-        _, _, info = ctx.capacitance_build(Jd, wl.alpha, factor=2)
-        assert info.factor_used == 2
+        _, _, info = ctx.capacitance_build(Jd, wl.alpha, factor=factor)
+        assert info.factor_used == factor
         Zp = host(ctx.precond_apply(dev(R), zmode=1))
-        x, info = ctx.gn_solve(Jd, wl.alpha, b=dev(b), rtol=1e-10, factor=2)
+        x, info = ctx.gn_solve(Jd, wl.alpha, b=dev(b), rtol=1e-10, factor=factor)
         x = host(x)
     V = mg.VCycle(wl.shape, wl.beta)
     ref = gn.woodbury_precond(V.apply, J, wl.alpha, R)
