@@ -171,7 +171,10 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
 
     pitch.resize(lv.size());
     for (size_t l = 0; l < lv.size(); ++l) pitch[l] = cdiv(lv[l].N, 64) * 64;
-    chunk = d.rhs_chunk > 0 ? d.rhs_chunk : (int)std::clamp<int64_t>((int64_t(1) << 26) / N0, 1, 1024);
+    // right-hand sides per batched V-cycle: about 2^28 values per fine-level
+    // array (the workspace holds about 1.43 of them: 3 GB in FP64), so the
+    // coarse levels of a large grid still launch enough work-groups
+    chunk = d.rhs_chunk > 0 ? d.rhs_chunk : (int)std::clamp<int64_t>((int64_t(1) << 28) / N0, 1, 1024);
     {
         std::lock_guard<std::recursive_mutex> lk(capture_lock());
         H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
