@@ -581,18 +581,45 @@ void launch_axpby_dev(hipStream_t s, int64_t N, double a, const double* x, const
 // r.z = s0, z.q = s1; mode 2 (no Woodbury correction) r.z = s0 / alpha,
 // z.q = s1 / alpha. beta = 0 on a first step, else z.(r_new - r_old)/r.z
 // (flexible, with r_new - r_old = -a q) or r.z_new / r.z.
-__global__ void k_gn_beta(const double* __restrict__ sdot, double ia, int mode, int first, int flexible,
-                          double* __restrict__ dsc) {
+// Partial sums reduced in the order of k_reduce_parts: out[v] = sum over b
+// of partial[v * nparts + b] (block-strided, then the waves in order).
+__device__ void reduce_rows_block(const double* __restrict__ partial, int nvec, int nparts, double* out, double* sh) {
+    for (int v = 0; v < nvec; ++v) {
+        const double* p = partial + (int64_t)v * nparts;
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += kBlock) acc += p[b];
+        const double s = block_sum<kBlock>(acc, sh);
+        if (threadIdx.x == 0) out[v] = s;
+    }
+}
+
+// The dot products of a CG step, reduced here from their partial sums (na
+// vectors of nba parts in pa, then nb vectors of nbb parts in pb) into
+// sdot[0 .. na + nb - 1], then beta and r.z:
+//   mode 0 (recompute form): r.z = (r.y - w.Jy) / alpha;
+//   mode 1 (stored Z, flexible): r.z = sdot[0], z.q = sdot[1] (Polak-Ribiere);
+//   mode 2 (B / alpha only):    r.z = r.y / alpha, z.q = y.q / alpha.
+// dsc: [0] r.z, [2] beta, [5] 1 when r.z <= 0 (converged to rounding).
+__global__ __launch_bounds__(kBlock) void k_gn_beta(const double* __restrict__ pa, int na, int nba,
+                                                    const double* __restrict__ pb, int nb, int nbb, double ia,
+                                                    int mode, int first, int flexible, double* __restrict__ sdot,
+                                                    double* __restrict__ dsc) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double sd[4];
+    reduce_rows_block(pa, na, nba, sd, sh);
+    reduce_rows_block(pb, nb, nbb, sd + na, sh);
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    for (int v = 0; v < na + nb; ++v) sdot[v] = sd[v];
     double rzn, zq = 0.0;
     if (mode == 0) {
-        rzn = (sdot[0] - sdot[1]) * ia;
+        rzn = (sd[0] - sd[1]) * ia;
     } else if (mode == 1) {
-        rzn = sdot[0];
-        zq = sdot[1];
+        rzn = sd[0];
+        zq = sd[1];
     } else {
-        rzn = sdot[0] * ia;
-        zq = sdot[1] * ia;
+        rzn = sd[0] * ia;
+        zq = sd[1] * ia;
     }
     const bool ok = rzn > 0.0;
     double beta = 0.0;
@@ -602,23 +629,33 @@ __global__ void k_gn_beta(const double* __restrict__ sdot, double ia, int mode, 
     dsc[5] = ok ? 0.0 : 1.0;
 }
 
-// a = r.z / p.q, or 0 when the step must not be taken
-__global__ void k_gn_alpha(double* __restrict__ dsc) {
+// p.q reduced here from its nparts partial sums into dsc[3]; then the step
+// a = r.z / p.q in dsc[1], or 0 when the step must not be taken
+__global__ __launch_bounds__(kBlock) void k_gn_alpha(const double* __restrict__ partial, int nparts,
+                                                     double* __restrict__ dsc) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double spq;
+    reduce_rows_block(partial, 1, nparts, &spq, sh);
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    const double pq = dsc[3];
+    const double pq = spq;
+    dsc[3] = pq;
     const bool finite = pq >= -1.79e308 && pq <= 1.79e308;
     dsc[7] = finite ? 0.0 : 1.0;
     dsc[6] = (finite && !(pq > 0.0)) ? 1.0 : 0.0;
     dsc[1] = (dsc[5] == 0.0 && finite && pq > 0.0) ? dsc[0] / pq : 0.0;
 }
 
-void launch_gn_beta(hipStream_t s, const double* sdot, double ia, int mode, bool first, bool flexible, double* dsc) {
-    hipLaunchKernelGGL(k_gn_beta, dim3(1), dim3(64), 0, s, sdot, ia, mode, (int)first, (int)flexible, dsc);
+void launch_gn_beta(hipStream_t s, const double* pa, int na, int nba, const double* pb, int nb, int nbb, double ia,
+                    int mode, bool first, bool flexible, double* sdot, double* dsc) {
+    if (na + nb > 4) throw Error{H1W_EINVAL, "internal: at most 4 dot products"};
+    hipLaunchKernelGGL(k_gn_beta, dim3(1), dim3(kBlock), 0, s, pa, na, nba, pb, nb, nbb, ia, mode, (int)first,
+                       (int)flexible, sdot, dsc);
     H1W_LAUNCHED();
 }
 
-void launch_gn_alpha(hipStream_t s, double* dsc) {
-    hipLaunchKernelGGL(k_gn_alpha, dim3(1), dim3(64), 0, s, dsc);
+void launch_gn_alpha(hipStream_t s, const double* partial, int nparts, double* dsc) {
+    hipLaunchKernelGGL(k_gn_alpha, dim3(1), dim3(kBlock), 0, s, partial, nparts, dsc);
     H1W_LAUNCHED();
 }
 

@@ -367,22 +367,17 @@ __global__ __launch_bounds__(256) void k_blk_update(int m, double* __restrict__ 
 }
 
 // ---------------------------------------------------------------- solves
-// Solve T x = b in place (x has m entries) for block-triangular T given by
-// C[j][i] = T[i][j] (row-major, ld m) and the inverses Dinv of its diagonal
-// blocks. lower: forward substitution, else backward.
+// Solve T x = b in place on the LDS vector sx (m entries) for block-triangular
+// T given by C[j][i] = T[i][j] (row-major, ld m) and the inverses Dinv of its
+// diagonal blocks; lower: forward substitution, else backward. All threads of
+// the group take part; sx is final at return.
 constexpr int kSolveThreads = 1024;
 constexpr int kMaxM = 4096;
 
-__global__ __launch_bounds__(kSolveThreads) void k_blk_trsv(int m, const double* __restrict__ C,
-                                                            const double* __restrict__ Dinv, int lower,
-                                                            double* __restrict__ x) {
-    __shared__ double sx[kMaxM];
-    __shared__ double part[16][NB + 1];
-    __shared__ double tvec[NB];
+__device__ void blk_trsv_lds(int m, const double* __restrict__ C, const double* __restrict__ Dinv, bool lower,
+                             double* sx, double (*part)[NB + 1], double* tvec) {
     const int tid = threadIdx.x;
     const int li = tid & 63, grp = tid >> 6;  // 64 entries x 16 groups
-    for (int i = tid; i < m; i += kSolveThreads) sx[i] = x[i];
-    __syncthreads();
     const int nb = (m + NB - 1) / NB;
     for (int s = 0; s < nb; ++s) {
         const int kb = lower ? s : nb - 1 - s;
@@ -418,7 +413,23 @@ __global__ __launch_bounds__(kSolveThreads) void k_blk_trsv(int m, const double*
         }
         __syncthreads();
     }
-    for (int i = tid; i < m; i += kSolveThreads) x[i] = sx[i];
+}
+
+// out = T2^{-1} T1^{-1} in: the two triangular solves of S = T1 T2 in one
+// launch, the vector staying in LDS between them (out may equal in)
+__global__ __launch_bounds__(kSolveThreads) void k_blk_solve2(int m, const double* __restrict__ C1,
+                                                              const double* __restrict__ D1, int lower1,
+                                                              const double* __restrict__ C2,
+                                                              const double* __restrict__ D2, int lower2,
+                                                              const double* in, double* out) {
+    __shared__ double sx[kMaxM];
+    __shared__ double part[16][NB + 1];
+    __shared__ double tvec[NB];
+    for (int i = threadIdx.x; i < m; i += kSolveThreads) sx[i] = in[i];
+    __syncthreads();
+    blk_trsv_lds(m, C1, D1, lower1 != 0, sx, part, tvec);
+    blk_trsv_lds(m, C2, D2, lower2 != 0, sx, part, tvec);
+    for (int i = threadIdx.x; i < m; i += kSolveThreads) out[i] = sx[i];
 }
 
 }  // namespace
@@ -442,9 +453,11 @@ void launch_blocked_factor(hipStream_t s, int m, double* A, int mode, double* Df
     }
 }
 
-void launch_blocked_trsv(hipStream_t s, int m, const double* C, const double* Dinv, bool lower, double* x) {
+void launch_blocked_solve2(hipStream_t s, int m, const double* C1, const double* D1, bool lower1, const double* C2,
+                           const double* D2, bool lower2, const double* in, double* out) {
     if (m > kMaxM) throw Error{H1W_EINVAL, "m too large for the triangular solve"};
-    hipLaunchKernelGGL(k_blk_trsv, dim3(1), dim3(kSolveThreads), 0, s, m, C, Dinv, (int)lower, x);
+    hipLaunchKernelGGL(k_blk_solve2, dim3(1), dim3(kSolveThreads), 0, s, m, C1, D1, (int)lower1, C2, D2,
+                       (int)lower2, in, out);
     H1W_LAUNCHED();
 }
 

@@ -139,11 +139,13 @@ struct Ctx {
                   int64_t ldj, const double* gbar, double* grad);
 
     void capacitance_build(int m, const double* J, int64_t ldj, double alpha, int factor, h1w_info* info);
-    void solve_S(double* x);
+    void solve_S(const double* in, double* x);  // x = S^{-1} in (x may equal in)
     void ensure_cg_ws(int mneed);
     double* nv(int i);
     double* mv(int i);
     void dots(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs, int slot);
+    // partial sums only (launch_dots_partial layout) into dst; returns the parts per pair
+    int dots_parts(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs, double* dst);
     void woodbury_mspace(const double* y, double* Jy, double* w);
     void rows_dot(int mm, const double* M, int64_t ldm, const double* v, double* out);
     void precond_one(const double* r, double* z, int zmode);

@@ -608,6 +608,10 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
     }
 }
 
+// offset in `part` of a second set of dot-product partials (the first set
+// holds at most 2 x 1024 of them; `part` holds at least 4 x 1024)
+constexpr int kPartB = 2048;
+
 // ============================================================ capacitance
 
 void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha_, int factor_, h1w_info* info) {
@@ -789,18 +793,19 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     }
 }
 
-void Ctx::solve_S(double* x) {
-    const double tb = 4.0 * m * m + 8.0 * blocked_inv_elems(m), tf = (double)m * m;
-    auto trsv = [&](const double* C, const double* D, bool lower) {
-        timed(H1W_K_TRSV, tb, tf, [&] { launch_blocked_trsv(stream, m, C, D, lower, x); });
+void Ctx::solve_S(const double* in, double* x) {
+    const double tb = 2.0 * (4.0 * m * m + 8.0 * blocked_inv_elems(m)), tf = 2.0 * m * m;
+    auto solve2 = [&](const double* C1, const double* C2) {
+        timed(H1W_K_TRSV, tb, tf, [&] {
+            launch_blocked_solve2(stream, m, C1, Dfwd.as<double>(), true, C2, Dbwd.as<double>(), false, in, x);
+        });
     };
-    if (factor == H1W_FACTOR_CHOL) {  // S = U^T U: U^T y = x, then U x = y
-        trsv(F1.as<double>(), Dfwd.as<double>(), true);
-        trsv(F2.as<double>(), Dbwd.as<double>(), false);
+    if (factor == H1W_FACTOR_CHOL) {  // S = U^T U: U^T y = in, then U x = y
+        solve2(F1.as<double>(), F2.as<double>());
     } else if (!lu_pivoted) {  // S = L U
-        trsv(F2.as<double>(), Dfwd.as<double>(), true);
-        trsv(F2.as<double>(), Dbwd.as<double>(), false);
+        solve2(F2.as<double>(), F2.as<double>());
     } else {
+        if (x != in) H1W_HIP(hipMemcpyAsync(x, in, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, stream));
         launch_lu_solve(stream, m, F2.as<double>(), F1.as<double>(), pivb.as<int>(), x);
     }
 }
@@ -822,6 +827,19 @@ double* Ctx::mv(int i) { return mvec.as<double>() + (size_t)i * mstride; }
 
 // out[slot..] = dot products of the given pairs (device); returns after the
 // values are in hscal[slot..] when fetch is true.
+int Ctx::dots_parts(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs,
+                    double* dst) {
+    const double* X[4];
+    const double* Y[4];
+    int q = 0;
+    for (auto& pr : pairs) {
+        X[q] = pr.first;
+        Y[q] = pr.second;
+        ++q;
+    }
+    return launch_dots_partial(stream, len, q, X, Y, dst);
+}
+
 void Ctx::dots(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs, int slot) {
     const double* X[4];
     const double* Y[4];
@@ -838,8 +856,7 @@ void Ctx::dots(int64_t len, std::initializer_list<std::pair<const double*, const
 // w = S^{-1} J y and the J-space update Jz, Jp (Jp = Jz + beta Jp)
 void Ctx::woodbury_mspace(const double* y, double* Jy, double* w) {
     rows_dot(m, J, ldj, y, Jy);
-    H1W_HIP(hipMemcpyAsync(w, Jy, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, stream));
-    solve_S(w);
+    solve_S(Jy, w);
 }
 
 // one preconditioner apply z = P^{-1} r without CG bookkeeping (h1w_precond_apply)
@@ -979,8 +996,9 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         apply_B(1, r, n, y, n);
         if (m == 0 || laplace) {
             // z = B r / alpha (no Woodbury correction); t = J^T (J p) by two passes
-            dots(n, {{r, y}, {y, q}}, 0);
-            launch_gn_beta(stream, scal.as<double>(), ia, 2, first, flexible, dsc);
+            const int nb1 = dots_parts(n, {{r, y}, {y, q}}, part.as<double>());
+            launch_gn_beta(stream, part.as<double>(), 2, nb1, nullptr, 0, 0, ia, 2, first, flexible,
+                           scal.as<double>(), dsc);
             launch_axpby_dev(stream, n, ia, y, dsc + 2, p);
             if (m == 0) {
                 H1W_HIP(hipMemsetAsync(t, 0, n * sizeof(double), stream));
@@ -994,9 +1012,10 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         woodbury_mspace(y, Jy, w);
         if (zm == H1W_Z_RECOMPUTE) {
             // r.z = (r.y - w.Jy) / alpha with z = B(r - J^T w)/alpha
-            dots(n, {{r, y}}, 0);
-            dots(m, {{w, Jy}}, 1);
-            launch_gn_beta(stream, scal.as<double>(), ia, 0, first, false, dsc);
+            const int nb1 = dots_parts(n, {{r, y}}, part.as<double>());
+            const int nb2 = dots_parts(m, {{w, Jy}}, part.as<double>() + kPartB);
+            launch_gn_beta(stream, part.as<double>(), 1, nb1, part.as<double>() + kPartB, 1, nb2, ia, 0, first,
+                           false, scal.as<double>(), dsc);
             launch_jz_update_dev(stream, m, Sbuf.as<double>(), alpha, Jy, w, dsc + 2, Jz, Jp);
             timed(H1W_K_JTV, 8.0 * m * n + 24.0 * n, 4.0 * m * n,
                   [&] { launch_jt_u_t(stream, m, n, J, ldj, w, Jp, r, ia, u, t); });
@@ -1012,8 +1031,9 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                     launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, ia, nullptr, nullptr, z);
                 }
             });
-            dots(n, {{z, r}, {z, q}}, 0);
-            launch_gn_beta(stream, scal.as<double>(), ia, 1, first, flexible, dsc);
+            const int nb1 = dots_parts(n, {{z, r}, {z, q}}, part.as<double>());
+            launch_gn_beta(stream, part.as<double>(), 2, nb1, nullptr, 0, 0, ia, 1, first, flexible,
+                           scal.as<double>(), dsc);
             launch_jz_update_dev(stream, m, Sbuf.as<double>(), alpha, Jy, w, dsc + 2, Jz, Jp);
             launch_axpby_dev(stream, n, 1.0, z, dsc + 2, p);
             timed(H1W_K_JTV, 8.0 * m * n + 8.0 * n, 2.0 * m * n,
@@ -1038,8 +1058,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
             int np = 0;
             timed(H1W_K_APPLY, 24.0 * n, 0.0,
                   [&] { launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np); });
-            launch_reduce_parts(stream, 1, np, part.as<double>(), dsc + 3);
-            launch_gn_alpha(stream, dsc);
+            launch_gn_alpha(stream, part.as<double>(), np, dsc);
             launch_cg_update_dev(stream, n, dsc + 1, p, q, x, r, part.as<double>(), &np);
             launch_reduce_parts(stream, 1, np, part.as<double>(), dsc + 4);
             H1W_HIP(hipMemcpyAsync(hscal + kGnScal, dsc, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));

@@ -202,8 +202,13 @@ void launch_axpby(hipStream_t s, int64_t N, double a, const double* x, double b,
 void launch_axpby_dev(hipStream_t s, int64_t N, double a, const double* x, const double* bdev, double* y);
 // device-side scalars of the GN CG (see blas.hip): beta from the preconditioner
 // step's dot products, then the step length
-void launch_gn_beta(hipStream_t s, const double* sdot, double ia, int mode, bool first, bool flexible, double* dsc);
-void launch_gn_alpha(hipStream_t s, double* dsc);
+// CG scalars on the device from dot-product partial sums (reduced in the
+// kernel, in the order of launch_reduce_parts): beta and r.z from na vectors
+// of nba parts in pa and nb vectors of nbb parts in pb (sdot receives the
+// na + nb dot products); the step length from the nparts partials of p.q
+void launch_gn_beta(hipStream_t s, const double* pa, int na, int nba, const double* pb, int nb, int nbb, double ia,
+                    int mode, bool first, bool flexible, double* sdot, double* dsc);
+void launch_gn_alpha(hipStream_t s, const double* partial, int nparts, double* dsc);
 void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
                           double* x, double* r, double* partial, int* nparts);
 void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, double* out);
@@ -247,6 +252,9 @@ void launch_asym(hipStream_t s, int m, const double* S, double* out);
 // pivoting (mode 1) in place, with diagonal-block inverses; triangular solves
 size_t blocked_inv_elems(int m);
 void launch_blocked_factor(hipStream_t s, int m, double* A, int mode, double* Dfwd, double* Dbwd, int* info);
-void launch_blocked_trsv(hipStream_t s, int m, const double* C, const double* Dinv, bool lower, double* x);
+// out = T2^{-1} T1^{-1} in with T1, T2 block-triangular (given as C[j][i] =
+// T[i][j] and the diagonal-block inverses D); one launch, out may equal in
+void launch_blocked_solve2(hipStream_t s, int m, const double* C1, const double* D1, bool lower1, const double* C2,
+                           const double* D2, bool lower2, const double* in, double* out);
 
 }  // namespace h1w
