@@ -646,6 +646,72 @@ __global__ __launch_bounds__(kBlock) void k_gn_alpha(const double* __restrict__ 
     dsc[1] = (dsc[5] == 0.0 && finite && pq > 0.0) ? dsc[0] / pq : 0.0;
 }
 
+// r.r reduced from its partial sums into dsc[4] (order of k_reduce_parts);
+// then the eight scalars dsc[0..7] written to host-visible memory, so the
+// host reads them after a stream synchronisation without a copy.
+__global__ __launch_bounds__(kBlock) void k_gn_report(const double* __restrict__ partial, int nparts,
+                                                      double* __restrict__ dsc, double* __restrict__ host) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double srr;
+    reduce_rows_block(partial, 1, nparts, &srr, sh);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t == 4) dsc[4] = srr;
+    if (t < 8) host[t] = t == 4 ? srr : dsc[t];
+}
+
+// out[v] = sum_b partial[v * nparts + b] (order of k_reduce_parts), written
+// to host-visible memory; one block.
+__global__ __launch_bounds__(kBlock) void k_reduce_host(int nvec, int nparts, const double* __restrict__ partial,
+                                                        double* __restrict__ host) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double sv[4];
+    reduce_rows_block(partial, nvec, nparts, sv, sh);
+    __syncthreads();
+    if ((int)threadIdx.x < nvec) host[threadIdx.x] = sv[threadIdx.x];
+}
+
+// Start of CG from x = 0: x = 0, r = b, p = q = 0, Jp = 0 (m values), and
+// the partial sums of b.b with the grid and order of k_dots_partial<1>.
+__global__ __launch_bounds__(kBlock) void k_cg_init(int64_t N, const double* __restrict__ b, double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ p,
+                                                    double* __restrict__ q, int m, double* __restrict__ Jp,
+                                                    double* __restrict__ partial) {
+    __shared__ double sh[kBlock / 64];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += stride) {
+        const double v = b[i];
+        acc += v * v;
+        x[i] = 0.0;
+        r[i] = v;
+        p[i] = 0.0;
+        q[i] = 0.0;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) Jp[i] = 0.0;
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+void launch_gn_report(hipStream_t s, const double* partial, int nparts, double* dsc, double* host) {
+    hipLaunchKernelGGL(k_gn_report, dim3(1), dim3(kBlock), 0, s, partial, nparts, dsc, host);
+    H1W_LAUNCHED();
+}
+
+void launch_reduce_host(hipStream_t s, int nvec, int nparts, const double* partial, double* host) {
+    if (nvec < 1 || nvec > 4) throw Error{H1W_EINVAL, "internal: 1 to 4 reductions"};
+    hipLaunchKernelGGL(k_reduce_host, dim3(1), dim3(kBlock), 0, s, nvec, nparts, partial, host);
+    H1W_LAUNCHED();
+}
+
+int launch_cg_init(hipStream_t s, int64_t N, const double* b, double* x, double* r, double* p, double* q, int m,
+                   double* Jp, double* partial) {
+    const int nb = dot_blocks(N);
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kBlock), 0, s, N, b, x, r, p, q, m, Jp, partial);
+    H1W_LAUNCHED();
+    return nb;
+}
+
 void launch_gn_beta(hipStream_t s, const double* pa, int na, int nba, const double* pb, int nb, int nbb, double ia,
                     int mode, bool first, bool flexible, double* sdot, double* dsc) {
     if (na + nb > 4) throw Error{H1W_EINVAL, "internal: at most 4 dot products"};

@@ -67,6 +67,8 @@ struct Ctx {
     DevBuf nvec, mvec, part, jpart, gpart, scal, iflag;
     int mstride = 1;                 // m-vector slot stride (grows only)
     double* hscal = nullptr;         // pinned host copy of device scalars
+    double* hrep = nullptr;          // coherent pinned host memory written by kernels (CG scalars, norms)
+    double* drep = nullptr;          // hrep as seen by the device
     static constexpr int kGnScal = 32;  // slots of the GN CG's device scalars in scal
     hipEvent_t ev[8] = {};
 

@@ -178,6 +178,8 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     {
         std::lock_guard<std::recursive_mutex> lk(capture_lock());
         H1W_HIP(hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault));
+        H1W_HIP(hipHostMalloc((void**)&hrep, 16 * sizeof(double), hipHostMallocCoherent));
+        H1W_HIP(hipHostGetDevicePointer((void**)&drep, hrep, 0));
     }
     scal.reserve(64 * sizeof(double));
     iflag.reserve(16 * sizeof(int));
@@ -218,6 +220,7 @@ Ctx::~Ctx() {
     clear_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hscal) (void)hipHostFree(hscal);
+    if (hrep) (void)hipHostFree(hrep);
     for (auto& p : pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -965,14 +968,14 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         launch_axpby(stream, n, -1.0, bb, 0.0, bb);
         b = bb;
     }
-    H1W_HIP(hipMemsetAsync(x, 0, n * sizeof(double), stream));
-    H1W_HIP(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
-    H1W_HIP(hipMemsetAsync(p, 0, n * sizeof(double), stream));
-    H1W_HIP(hipMemsetAsync(q, 0, n * sizeof(double), stream));
-    if (m > 0) H1W_HIP(hipMemsetAsync(Jp, 0, (size_t)m * sizeof(double), stream));
-    dots(n, {{b, b}}, 0);
-    read_scal(1);
-    const double bnorm = std::sqrt(hscal[0]);
+    // x = 0, r = b, p = q = 0, Jp = 0 and b.b in two launches; the norm is
+    // written to host-visible memory
+    {
+        const int nb = launch_cg_init(stream, n, b, x, r, p, q, m, Jp, part.as<double>());
+        launch_reduce_host(stream, 1, nb, part.as<double>(), drep);
+        sync();
+    }
+    const double bnorm = std::sqrt(hrep[0]);
     if (!std::isfinite(bnorm)) throw Error{H1W_ENUMERIC, "non-finite right-hand side"};
 
     int it = 0, restarts = 0;
@@ -1043,9 +1046,10 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
     auto true_relres = [&]() -> double {
         gn_apply(m, J, ldj, alpha, x, z);  // z is free here; gn_apply uses tmp internally
         launch_sub(stream, n, b, z, u);
-        dots(n, {{u, u}}, 0);
-        read_scal(1);
-        return bnorm > 0 ? std::sqrt(hscal[0]) / bnorm : 0.0;
+        const int nb = dots_parts(n, {{u, u}}, part.as<double>());
+        launch_reduce_host(stream, 1, nb, part.as<double>(), drep);
+        sync();
+        return bnorm > 0 ? std::sqrt(hrep[0]) / bnorm : 0.0;
     };
 
     if (bnorm == 0.0) {
@@ -1060,10 +1064,9 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                   [&] { launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np); });
             launch_gn_alpha(stream, part.as<double>(), np, dsc);
             launch_cg_update_dev(stream, n, dsc + 1, p, q, x, r, part.as<double>(), &np);
-            launch_reduce_parts(stream, 1, np, part.as<double>(), dsc + 4);
-            H1W_HIP(hipMemcpyAsync(hscal + kGnScal, dsc, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+            launch_gn_report(stream, part.as<double>(), np, dsc, drep);
             sync();
-            const double* hs = hscal + kGnScal;
+            const double* hs = hrep;
             if (hs[7] != 0.0) {
                 status = H1W_ENUMERIC;
                 break;

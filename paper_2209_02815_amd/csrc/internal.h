@@ -209,6 +209,13 @@ void launch_axpby_dev(hipStream_t s, int64_t N, double a, const double* x, const
 void launch_gn_beta(hipStream_t s, const double* pa, int na, int nba, const double* pb, int nb, int nbb, double ia,
                     int mode, bool first, bool flexible, double* sdot, double* dsc);
 void launch_gn_alpha(hipStream_t s, const double* partial, int nparts, double* dsc);
+// r.r from its partials into dsc[4], then dsc[0..7] to host-visible memory
+void launch_gn_report(hipStream_t s, const double* partial, int nparts, double* dsc, double* host);
+// nvec (<= 4) sums of nparts partials each, written to host-visible memory
+void launch_reduce_host(hipStream_t s, int nvec, int nparts, const double* partial, double* host);
+// x = 0, r = b, p = q = 0, Jp[0..m) = 0 and the partials of b.b (returns their count)
+int launch_cg_init(hipStream_t s, int64_t N, const double* b, double* x, double* r, double* p, double* q, int m,
+                   double* Jp, double* partial);
 void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
                           double* x, double* r, double* partial, int* nparts);
 void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, double* out);
