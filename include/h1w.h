@@ -109,6 +109,12 @@ typedef struct {
  * removes the per-kernel launch cost for small grids. Same results, bit for
  * bit. Ignored while kernel timing is on. H1 contexts only. */
 #define H1W_FLAG_GRAPH_VCYCLE 4u
+/* grid_desc.flags: in 2D fused V-cycles (two smoothing steps per side), run
+ * every level as its own down and up pass. Without the flag the levels from
+ * the first one that fits one work-group's LDS (with every coarser level)
+ * down to the coarsest, and back, run in one launch per V-cycle: the same
+ * cycle with the same arithmetic, so the result is the same bit for bit. */
+#define H1W_FLAG_NO_VTAIL 8u
 
 /* Krylov options (h1w_gn_solve). A zeroed struct selects the defaults. */
 typedef struct {
@@ -273,7 +279,8 @@ typedef enum {
     H1W_K_VUP = 13,        /* fused 3D pass: interpolation, two post-smoothing steps */
     H1W_K_ERT_STENCIL = 14,/* ERT operator: apply, residual, smoothing steps, restriction */
     H1W_K_ERT_SENS = 15,   /* ERT pairwise-gradient sensitivities (J) and their transpose product */
-    H1W_K_NCLASS = 16
+    H1W_K_VTAIL = 16,      /* 2D coarse levels and coarsest solve of a V-cycle in one launch */
+    H1W_K_NCLASS = 17
 } h1w_kclass;
 
 typedef struct {

@@ -20,7 +20,7 @@ H1W_Z_AUTO, H1W_Z_STORED, H1W_Z_RECOMPUTE = 0, 1, 2
 H1W_FACTOR_AUTO, H1W_FACTOR_CHOL, H1W_FACTOR_LU = 0, 1, 2
 
 KCLASS = ["smooth", "smooth_first", "residual", "restrict", "prolong", "coarse", "gemm", "jv", "jtv",
-          "factor", "trsv", "apply", "vdown", "vup", "ert_stencil", "ert_sens"]
+          "factor", "trsv", "apply", "vdown", "vup", "ert_stencil", "ert_sens", "vtail"]
 
 EXPORTED = [
     "h1w_setup", "h1w_destroy", "h1w_last_error", "h1w_status_string", "h1w_get_sizes",
@@ -169,6 +169,7 @@ def _dtype_code(t):
 H1W_FLAG_STREAM_Z = 1
 H1W_FLAG_UNFUSED_VCYCLE = 2
 H1W_FLAG_GRAPH_VCYCLE = 4
+H1W_FLAG_NO_VTAIL = 8
 H1W_SOLVE_LAPLACE_ONLY = 1
 H1W_SOLVE_EXACT_B = 2
 H1W_OP_H1GRAM, H1W_OP_ERT = 0, 1

@@ -26,6 +26,8 @@ struct Ctx {
     std::vector<int64_t> pitch;      // workspace row pitch per level (elements)
     std::vector<double> w;           // Chebyshev step weights
     bool fused = false;              // V-cycles as fused down/up passes (3D, nu = 2)
+    int tail_l0 = 0;                 // 2D fused: first level of the one-launch coarse tail (L: none)
+    TailGeo tail{};                  // its levels and LDS layout
     int64_t Nc = 0;                  // nodes on the coarsest level
     DevBuf cinv64, cinv32;           // dense inverse of the coarsest operator
     DevBuf cpart;                    // partial sums of the coarsest solve (split over j)

@@ -130,7 +130,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     if (!ert) require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
     require(d.precision == H1W_FP64 || d.precision == H1W_MIXED, "precision must be H1W_FP64 or H1W_MIXED");
     require(d.nu >= 0 && d.nu <= 16, "nu must be in [0, 16]");
-    require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE | H1W_FLAG_GRAPH_VCYCLE)) == 0,
+    require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE | H1W_FLAG_GRAPH_VCYCLE | H1W_FLAG_NO_VTAIL)) == 0,
             "unknown bits in flags");
     graphs = (d.flags & H1W_FLAG_GRAPH_VCYCLE) != 0;
     require(d.coarse_max >= 0, "coarse_max must be >= 0");
@@ -209,6 +209,8 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     fused = d.nu == 2 && lv.size() >= 2 && !(d.flags & H1W_FLAG_UNFUSED_VCYCLE);
     for (size_t l = 0; fused && l + 1 < lv.size(); ++l)
         fused = dim == 3 ? fused_levels_ok(lv[l], lv[l + 1]) : fused2_levels_ok(lv[l], lv[l + 1]);
+    tail_l0 = (int)lv.size();
+    if (fused && dim == 2 && !(d.flags & H1W_FLAG_NO_VTAIL)) tail2_plan(lv.data(), (int)lv.size(), tail_l0, tail);
 
     deflate = fp32;
     wsum = 1.0;
@@ -284,7 +286,9 @@ void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
         // two smoothing steps per side: one pass down and one pass up per
         // level (3D z-march or 2D tiles in LDS); the pre-smoothed iterate of
         // level l is kept in tb[l]
-        for (int l = 0; l < L - 1; ++l) {
+        // 2D: the levels from tail_l0 on run in one launch
+        const int lt = std::min(tail_l0, L - 1);
+        for (int l = 0; l < lt; ++l) {
             const double nl = (double)lv[l].N, nc = (double)lv[l + 1].N;
             timed(H1W_K_VDOWN, ces * (2 * nl + nc), 0.0, [&] {
                 if (dim == 3)
@@ -295,8 +299,17 @@ void Ctx::vcycle_chunk(int k, const T* F, int64_t ldf, T* X, int64_t ldx) {
                                      pitch[l + 1], w[0], w[1]);
             });
         }
-        coarse(fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
-        for (int l = L - 2; l >= 0; --l) {
+        if (lt < L - 1) {
+            const double nt = (double)lv[lt].N;
+            TailGeo tg = tail;
+            tg.csplit = cpart_elems ? coarse_splits(Nc, k, cpart_elems) : 1;
+            timed(H1W_K_VTAIL, ces * 2 * nt + (double)es * Nc * Nc, 2.0 * k * Nc * Nc, [&] {
+                launch_vtail2<T>(stream, tg, fp_cinv<T>(), k, fptr(lt), fld(lt), xptr(lt), xld(lt), w[0], w[1]);
+            });
+        } else {
+            coarse(fb[L - 1], pitch[L - 1], xb[L - 1], pitch[L - 1]);
+        }
+        for (int l = lt - 1; l >= 0; --l) {
             const double nl = (double)lv[l].N, nc = (double)lv[l + 1].N;
             timed(H1W_K_VUP, ces * (3 * nl + nc), 0.0, [&] {
                 if (dim == 3)

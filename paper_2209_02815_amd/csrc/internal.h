@@ -120,6 +120,8 @@ template <typename T>
 void launch_coarse_solve(hipStream_t s, int64_t Nc, const T* Cinv, int k, const T* F,
                          int64_t ldf, T* X, int64_t ldx, T* part, size_t part_elems);
 size_t coarse_part_elems(int64_t Nc);
+// j-range splits of the coarsest solve for k right-hand sides (1 .. ceil(Nc / 32))
+int coarse_splits(int64_t Nc, int k, size_t part_elems);
 template <typename TI, typename TO>
 void launch_convert(hipStream_t s, int64_t N, int k, const TI* X, int64_t ldx, TO* Y,
                     int64_t ldy, double scale);
@@ -143,6 +145,23 @@ bool ert_on_dirichlet_host(const Geom& g, unsigned mask, int64_t p);
 
 // vfused2d.hip: fused passes of the 2D V-cycle (two smoothing steps per side)
 bool fused2_levels_ok(const Geom& gf, const Geom& gc);
+// The coarse end of a 2D fused V-cycle in one launch (one work-group per
+// right-hand side, every level in LDS): levels l0 .. L-1 of the hierarchy.
+constexpr int kTailLevels = 6;
+constexpr int kTailElems = 19712;  // LDS values per work-group (FP64: 154 KiB)
+constexpr int kTailMaxNc = 289;    // largest coarsest level it solves
+struct TailGeo {
+    int L;                    // levels in the tail; the last is the coarsest
+    Geom g[kTailLevels];
+    int off[kTailLevels];     // LDS offset of level q's f, x, t (g[q].N values each)
+    int red;                  // LDS offset of the coarse solve's partial sums
+    int csplit;               // j-range splits of the coarsest solve (those of the separate solve)
+};
+// l0 = first level of the tail and its layout; false (l0 = L) when no tail fits
+bool tail2_plan(const Geom* lv, int L, int& l0, TailGeo& tg);
+template <typename T>
+void launch_vtail2(hipStream_t s, const TailGeo& tg, const T* Cinv, int k, const T* F, int64_t ldf, T* X,
+                   int64_t ldx, double w0, double w1);
 template <typename T>
 void launch_vdown2(hipStream_t s, const Geom& gf, const Geom& gc, int k, const T* F, int64_t ldf, T* X, int64_t ldx,
                    T* Fc, int64_t ldc, double w0, double w1);

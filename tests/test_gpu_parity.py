@@ -148,11 +148,51 @@ def test_vcycle_fused_matches_unfused(P, shape, cmax, k, chunk, prec):
             kt = ctx.kernel_timing()
             ctx.set_kernel_timing([])
             out.append(host(Xd))
-            assert (kt["vdown"]["launches"] > 0) == fused and (kt["smooth"]["launches"] > 0) == (not fused)
+            nfused = kt["vdown"]["launches"] + kt["vtail"]["launches"]
+            assert (nfused > 0) == fused and (kt["smooth"]["launches"] > 0) == (not fused)
     V = mg.VCycle(shape, beta, coarse_max=cmax or 729)
     tol = 100 * EPS64 * np.linalg.cond(V.Acoarse) if prec == "fp64" else 2e-5
     assert rel_rows(out[0], out[1]).max() < tol
     if N <= 40000:  # and both against the oracle
+        Xref = V.apply(F if prec == "fp64" else F.astype(np.float32).astype(np.float64))
+        assert rel_rows(out[0], Xref).max() < tol
+
+
+# 2D: the coarse levels of the fused cycle in one launch (one work-group per
+# right-hand side, every level in LDS) against the same cycle run level by
+# level: the same expressions stage by stage and the same decomposition of
+# the coarsest solve, so the two agree bit for bit. Shapes:
+# every level in the tail (17^2 and 65^2), tails starting at level 1
+# (65 x 129), at level 2 (193^2), five levels of an anisotropic grid
+# (257 x 65), and a grid whose coarsest level is too large for a tail
+# (coarse_max 1089 > the tail's limit).
+@pytest.mark.parametrize("shape,cmax,k,chunk,tail", [((17, 17), 25, 3, 2, True), ((65, 65), 0, 4, 0, True),
+                                                     ((65, 129), 289, 5, 2, True), ((193, 193), 289, 3, 0, True),
+                                                     ((257, 65), 81, 4, 1, True), ((129, 129), 1089, 2, 0, False)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vcycle_tail_matches_per_level(P, shape, cmax, k, chunk, tail, prec):
+    beta = 1e-2
+    N = int(np.prod(shape))
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    F = rng(14).standard_normal((k, N))
+    out = []
+    for vt in (True, False):
+        with P.Context(shape, beta, precision="fp64" if prec == "fp64" else "mixed", coarse_max=cmax,
+                       rhs_chunk=chunk, vtail=vt) as ctx:
+            Fd = padded(k, N, dtype=tdt)
+            Fd.copy_(dev(F, tdt))
+            Xd = padded(k, N, pad=3, dtype=tdt)
+            ctx.set_kernel_timing("all")
+            ctx.vcycle(Fd, Xd)
+            kt = ctx.kernel_timing()
+            ctx.set_kernel_timing([])
+            out.append(host(Xd))
+            assert (kt["vtail"]["launches"] > 0) == (vt and tail)
+            assert (kt["coarse"]["launches"] == 0) == (vt and tail)
+    assert np.array_equal(out[0], out[1])
+    V = mg.VCycle(shape, beta, coarse_max=cmax or 289)
+    tol = 100 * EPS64 * np.linalg.cond(V.Acoarse) if prec == "fp64" else 2e-5
+    if N <= 40000:
         Xref = V.apply(F if prec == "fp64" else F.astype(np.float32).astype(np.float64))
         assert rel_rows(out[0], Xref).max() < tol
 
