@@ -56,8 +56,9 @@ KERNELS = {
     "gemm": ("mfma", "k_cap_gemm", "gemm.hip"), "jv": ("hbm", "k_rows_dot", "blas.hip"),
     "jtv": ("hbm", "k_jt_u_t / k_jt_plain / k_z_stored", "blas.hip"), "factor": ("mfma", "k_blk_*", "blocked.hip"),
     "trsv": ("hbm", "k_blk_trsv", "blocked.hip"), "apply": ("hbm", "k_march<*, 3, 0> / k_apply_plus_dot", "stencil.hip"),
-    "vdown": ("hbm", "k_down", "vfused.hip"), "vup": ("hbm", "k_up", "vfused.hip"),
+    "vdown": ("hbm", "k_down / k_down2", "vfused.hip"), "vup": ("hbm", "k_up / k_up2", "vfused.hip"),
     "ert_stencil": ("hbm", "k_ert_step / k_ert_restrict", "ert.hip"), "ert_sens": ("hbm", "k_ert_sens", "ert.hip"),
+    "vtail": ("hbm", "k_vtail2", "vfused2d.hip"),
 }
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix
@@ -309,6 +310,13 @@ def batch_bench(args, threads):
     return out
 
 
+def grid_text(shape) -> str:
+    """'3D 129^3' for a cube, '2D 129x65' otherwise."""
+    if len(set(shape)) == 1:
+        return f"{len(shape)}D {shape[0]}^{len(shape)}"
+    return f"{len(shape)}D " + "x".join(str(n) for n in shape)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -410,8 +418,10 @@ def main():
         "value": r64["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r64["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{wl.name}: 3D {wl.shape[0]}^3 H1 Gram (beta={wl.beta}), m={wl.m} bump rows, "
-                               f"alpha={wl.alpha}, rtol={args.rtol}", "N": wl.N, "m": wl.m,
+        "config": {"workload": f"{wl.name}: {grid_text(wl.shape)} H1 Gram (beta={wl.beta}), m={wl.m} "
+                               f"{'bump' if wl.j_kind == 'bumps' else 'Gaussian'} rows, alpha={wl.alpha}, "
+                               f"rtol={args.rtol}",
+                   "N": wl.N, "m": wl.m,
                    "parallelism": "single GPU"},
         "roofline": r64["roofline"],
         "fp64": r64,
