@@ -27,7 +27,8 @@ namespace h1w {
 
 namespace {
 
-constexpr int kF2Threads = 256;
+constexpr int kF2Threads = 256;       // threads per work-group when the launch fills the GPU
+constexpr int kF2ThreadsFew = 1024;   // ... and when it has fewer work-groups than 2 per CU
 constexpr int kDownTC = 16;                   // coarse nodes per tile side (down pass)
 constexpr int kDownRW = 2 * kDownTC + 5;      // region: fine columns 2 cX0 - 3 .. 2 (cX0 + TC) + 1
 constexpr int kUpT = 32;                      // fine nodes per tile side (up pass)
@@ -61,8 +62,8 @@ __device__ __forceinline__ T nsum2(const Coef2<T>& c, const T* P, int p, int RW)
     return fma(c.cy, P[p - RW] + P[p + RW], c.cx * (P[p - 1] + P[p + 1]));
 }
 
-template <typename T>
-__global__ __launch_bounds__(kF2Threads) void k_down2(Geom gf, Geom gc, int ntx, const T* __restrict__ F,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_down2(Geom gf, Geom gc, int ntx, const T* __restrict__ F,
                                                       int64_t ldf, T* __restrict__ X, int64_t ldx,
                                                       T* __restrict__ Fc, int64_t ldc, T w0, T w1) {
     constexpr int RW = kDownRW, RN = RW * RW;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kF2Threads) void k_down2(Geom gf, Geom gc, int ntx,
     const T* f = F + r * ldf;
     T* x = X + r * ldx;
     // stage 1: f and x1 = w0 D^-1 f on the whole region (0 outside the grid)
-    for (int p = threadIdx.x; p < RN; p += kF2Threads) {
+    for (int p = threadIdx.x; p < RN; p += NT) {
         const int a = p % RW, b = p / RW;
         const int i = i0 + a, j = j0 + b;
         const Coef2<T> c = coef2<T>(gf, i, j);
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(kF2Threads) void k_down2(Geom gf, Geom gc, int ntx,
     }
     __syncthreads();
     // stage 2: x2 one ring in; written for the fine nodes this tile owns
-    for (int p = threadIdx.x; p < RN; p += kF2Threads) {
+    for (int p = threadIdx.x; p < RN; p += NT) {
         const int a = p % RW, b = p / RW;
         if (a < 1 || a > RW - 2 || b < 1 || b > RW - 2) continue;
         const int i = i0 + a, j = j0 + b;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(kF2Threads) void k_down2(Geom gf, Geom gc, int ntx,
     }
     __syncthreads();
     // stage 3: r = f - A x2 two rings in
-    for (int p = threadIdx.x; p < RN; p += kF2Threads) {
+    for (int p = threadIdx.x; p < RN; p += NT) {
         const int a = p % RW, b = p / RW;
         if (a < 2 || a > RW - 3 || b < 2 || b > RW - 3) continue;
         const int i = i0 + a, j = j0 + b;
@@ -125,8 +126,8 @@ __global__ __launch_bounds__(kF2Threads) void k_down2(Geom gf, Geom gc, int ntx,
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kF2Threads) void k_up2(Geom gf, Geom gc, int ntx, const T* __restrict__ F, int64_t ldf,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_up2(Geom gf, Geom gc, int ntx, const T* __restrict__ F, int64_t ldf,
                                                     const T* __restrict__ X0, int64_t ldx0,
                                                     const T* __restrict__ Ec, int64_t ldc, T* __restrict__ Y,
                                                     int64_t ldy, T wa, T wb) {
@@ -142,13 +143,13 @@ __global__ __launch_bounds__(kF2Threads) void k_up2(Geom gf, Geom gc, int ntx, c
     const T* e = Ec + r * ldc;
     T* y = Y + r * ldy;
     // the coarse correction under the region (0 outside the coarse grid)
-    for (int q = threadIdx.x; q < CW * CW; q += kF2Threads) {
+    for (int q = threadIdx.x; q < CW * CW; q += NT) {
         const int I = cI0 + q % CW, J = cJ0 + q / CW;
         se[q] = (I >= 0 && I < gc.nx && J >= 0 && J < gc.ny) ? e[(int64_t)J * gc.nx + I] : T(0);
     }
     __syncthreads();
     // stage 1: f and y0 = x2 + P e on the whole region
-    for (int p = threadIdx.x; p < RN; p += kF2Threads) {
+    for (int p = threadIdx.x; p < RN; p += NT) {
         const int a = p % RW, b = p / RW;
         const int i = i0 + a, j = j0 + b;
         const bool ing = i >= 0 && i < gf.nx && j >= 0 && j < gf.ny;
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(kF2Threads) void k_up2(Geom gf, Geom gc, int ntx, c
     }
     __syncthreads();
     // stage 2: y1 one ring in
-    for (int p = threadIdx.x; p < RN; p += kF2Threads) {
+    for (int p = threadIdx.x; p < RN; p += NT) {
         const int a = p % RW, b = p / RW;
         if (a < 1 || a > RW - 2 || b < 1 || b > RW - 2) continue;
         const Coef2<T> c = coef2<T>(gf, i0 + a, j0 + b);
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(kF2Threads) void k_up2(Geom gf, Geom gc, int ntx, c
     }
     __syncthreads();
     // stage 3: y on the tile
-    for (int q = threadIdx.x; q < kUpT * kUpT; q += kF2Threads) {
+    for (int q = threadIdx.x; q < kUpT * kUpT; q += NT) {
         const int a = 2 + q % kUpT, b = 2 + q / kUpT;
         const int i = i0 + a, j = j0 + b;
         const Coef2<T> c = coef2<T>(gf, i, j);
@@ -428,8 +429,13 @@ void launch_vdown2(hipStream_t st, const Geom& gf, const Geom& gc, int k, const 
     require(fused2_levels_ok(gf, gc), "internal: fused 2D pass on non-nested levels");
     require(k <= 65535, "internal: too many rows in one fused 2D launch");
     const int ntx = (int)cdiv(gc.nx, kDownTC), nty = (int)cdiv(gc.ny, kDownTC);
-    hipLaunchKernelGGL((k_down2<T>), dim3((unsigned)(ntx * nty), (unsigned)k), dim3(kF2Threads), 0, st, gf, gc, ntx,
-                       F, ldf, X, ldx, Fc, ldc, T(w0), T(w1));
+    const dim3 grid((unsigned)(ntx * nty), (unsigned)k);
+    if ((int64_t)ntx * nty * k < 512)  // few groups: more threads each, shorter stages
+        hipLaunchKernelGGL((k_down2<T, kF2ThreadsFew>), grid, dim3(kF2ThreadsFew), 0, st, gf, gc, ntx, F, ldf, X, ldx,
+                           Fc, ldc, T(w0), T(w1));
+    else
+        hipLaunchKernelGGL((k_down2<T, kF2Threads>), grid, dim3(kF2Threads), 0, st, gf, gc, ntx, F, ldf, X, ldx, Fc,
+                           ldc, T(w0), T(w1));
     H1W_LAUNCHED();
 }
 
@@ -440,8 +446,13 @@ void launch_vup2(hipStream_t st, const Geom& gf, const Geom& gc, int k, const T*
     require(fused2_levels_ok(gf, gc), "internal: fused 2D pass on non-nested levels");
     require(k <= 65535, "internal: too many rows in one fused 2D launch");
     const int ntx = (int)cdiv(gf.nx, kUpT), nty = (int)cdiv(gf.ny, kUpT);
-    hipLaunchKernelGGL((k_up2<T>), dim3((unsigned)(ntx * nty), (unsigned)k), dim3(kF2Threads), 0, st, gf, gc, ntx, F,
-                       ldf, X0, ldx0, Ec, ldc, Y, ldy, T(wa), T(wb));
+    const dim3 grid((unsigned)(ntx * nty), (unsigned)k);
+    if ((int64_t)ntx * nty * k < 512)
+        hipLaunchKernelGGL((k_up2<T, kF2ThreadsFew>), grid, dim3(kF2ThreadsFew), 0, st, gf, gc, ntx, F, ldf, X0, ldx0,
+                           Ec, ldc, Y, ldy, T(wa), T(wb));
+    else
+        hipLaunchKernelGGL((k_up2<T, kF2Threads>), grid, dim3(kF2Threads), 0, st, gf, gc, ntx, F, ldf, X0, ldx0, Ec,
+                           ldc, Y, ldy, T(wa), T(wb));
     H1W_LAUNCHED();
 }
 
