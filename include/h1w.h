@@ -81,7 +81,7 @@ typedef struct {
     double cheb_lo;      /* Chebyshev interval for eig(D^-1 A): [lo, hi] */
     double cheb_hi;      /* (0, 0) -> [0.3, 2.0] */
     int64_t coarse_max;  /* coarsest level: first level with <= coarse_max nodes
-                            (or that cannot be halved); 0 -> 729 (3D) / 289 (2D) */
+                            (or that cannot be halved); 0 -> 729 (3D) / 81 (2D) */
     int rhs_chunk;       /* right-hand sides per batched V-cycle launch (0 -> auto:
                             2^28 / N, clamped to [1, 1024]) */
     unsigned flags;      /* H1W_FLAG_* bits, other bits must be 0 */

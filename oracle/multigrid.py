@@ -33,7 +33,10 @@ DEFAULT_HI = 2.0
 
 
 def default_coarse_max(dim: int) -> int:
-    return 729 if dim == 3 else 289
+    # The coarsest level is a parameter of the multigrid Poisson solver, which
+    # Section 3 leaves open: 9^3 nodes in 3D and 9^2 in 2D (the default of
+    # the GPU contexts too, so that both build the same hierarchy).
+    return 729 if dim == 3 else 81
 
 
 def level_shapes(shape, coarse_max: int):

@@ -194,15 +194,42 @@ __global__ __launch_bounds__(kBlock) void k_jt_plain(int m, int64_t N, const dou
     if (n < N) out[n] = add ? acc + add_coef * add[n] : acc;
 }
 
-// z = (y - Z^T w) * inv_alpha
+// z = (y - Z^T w - (c0 v - c1)) * inv_alpha, the last term only with v
+// (the rank-one parts of a deflated FP32 Z). c0, c1 = s.w, mu.w are read
+// from cptr, or, with sd and md given (m <= kBlock * 4), computed here by
+// every work-group in the order of k_dots_partial<2> (one block) followed by
+// k_reduce_parts, so the values are the same as from those two kernels.
 template <typename TZ>
 __global__ __launch_bounds__(kBlock) void k_z_stored(int m, int64_t N, const TZ* __restrict__ Z,
                                                      int64_t ldz, const double* __restrict__ w,
                                                      const double* __restrict__ y, double inv_alpha,
                                                      const double* __restrict__ v, const double* __restrict__ cptr,
+                                                     const double* __restrict__ sd, const double* __restrict__ md,
                                                      double* __restrict__ z) {
     __shared__ double sw[kTile];
+    __shared__ double sh[kBlock / 64];
+    __shared__ double sc[2];
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double c0 = 0.0, c1 = 0.0;
+    if (v && sd) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int i = threadIdx.x; i < m; i += kBlock) {
+            a0 += sd[i] * w[i];
+            a1 += md[i] * w[i];
+        }
+        const double s0 = block_sum<kBlock>(a0, sh);
+        const double s1 = block_sum<kBlock>(a1, sh);
+        if (threadIdx.x == 0) {
+            sc[0] = s0;
+            sc[1] = s1;
+        }
+        __syncthreads();
+        c0 = sc[0];
+        c1 = sc[1];
+    } else if (v) {
+        c0 = cptr[0];
+        c1 = cptr[1];
+    }
     double acc = 0.0;
     for (int i0 = 0; i0 < m; i0 += kTile) {
         const int cnt = std::min(kTile, m - i0);
@@ -215,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_z_stored(int m, int64_t N, const TZ*
             for (int q = 0; q < cnt; ++q) acc += double(col[(int64_t)q * ldz]) * sw[q];
         }
     }
-    if (n < N) z[n] = (y[n] - acc - (v ? cptr[0] * v[n] - cptr[1] : 0.0)) * inv_alpha;
+    if (n < N) z[n] = (y[n] - acc - (v ? c0 * v[n] - c1 : 0.0)) * inv_alpha;
 }
 
 // S[i][j] += a[i] b[j] + c[i] d[j]  (m x m, row-major)
@@ -441,9 +468,11 @@ void launch_jt_plain(hipStream_t s, int m, int64_t N, const double* J, int64_t l
 
 template <typename TZ>
 void launch_z_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
-                     const double* y, double inv_alpha, const double* v, const double* cptr, double* z) {
+                     const double* y, double inv_alpha, const double* v, const double* cptr, double* z,
+                     const double* sd, const double* md) {
+    if (sd && m > kBlock * 4) throw Error{H1W_EINVAL, "internal: in-kernel rank-one dots need m <= 1024"};
     hipLaunchKernelGGL((k_z_stored<TZ>), dim3((unsigned)cdiv(N, kBlock)), dim3(kBlock), 0, s, m, N, Z,
-                       ldz, w, y, inv_alpha, v, cptr, z);
+                       ldz, w, y, inv_alpha, v, cptr, sd, md, z);
     H1W_LAUNCHED();
 }
 
@@ -774,9 +803,11 @@ void launch_batched_p(hipStream_t s, int k, int64_t N, const double* b, const do
 }
 
 template void launch_z_stored<double>(hipStream_t, int, int64_t, const double*, int64_t, const double*,
-                                      const double*, double, const double*, const double*, double*);
+                                      const double*, double, const double*, const double*, double*, const double*,
+                                      const double*);
 template void launch_z_stored<float>(hipStream_t, int, int64_t, const float*, int64_t, const double*,
-                                     const double*, double, const double*, const double*, double*);
+                                     const double*, double, const double*, const double*, double*, const double*,
+                                     const double*);
 template void launch_p_stored<double>(hipStream_t, int, int64_t, const double*, int64_t, const double*,
                                       const double*, int64_t, const double*, const double*, double,
                                       double, double*, double*);

@@ -152,6 +152,7 @@ struct Ctx {
     int dots_parts(int64_t len, std::initializer_list<std::pair<const double*, const double*>> pairs, double* dst);
     void woodbury_mspace(const double* y, double* Jy, double* w);
     void rows_dot(int mm, const double* M, int64_t ldm, const double* v, double* out);
+    void z_stored_fp32(const double* w, const double* y, double ia, double* z);
     void precond_one(const double* r, double* z, int zmode);
     void precond_apply(int k, const double* R, int64_t ldr, double* Zout, int64_t ldz, int zmode);
     void gn_apply(int m, const double* J, int64_t ldj, double alpha, const double* x, double* y);

@@ -141,7 +141,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
         d.cheb_hi = 2.0;
     }
     require(d.cheb_lo > 0.0 && d.cheb_hi > d.cheb_lo && std::isfinite(d.cheb_hi), "need 0 < cheb_lo < cheb_hi");
-    if (d.coarse_max == 0) d.coarse_max = ert ? 125 : (dim == 3 ? 729 : 289);
+    if (d.coarse_max == 0) d.coarse_max = ert ? 125 : (dim == 3 ? 729 : 81);
     fp32 = d.precision == H1W_MIXED;
     const int64_t N0 = (int64_t)n[0] * n[1] * n[2];
     require(N0 < (int64_t(1) << 31), "grid too large: N must be < 2^31");
@@ -875,6 +875,20 @@ void Ctx::woodbury_mspace(const double* y, double* Jy, double* w) {
     solve_S(Jy, w);
 }
 
+// z = (y - Z~^T w) / alpha with the deflated FP32 Z~ and its rank-one parts
+// (s.w, mu.w reduced inside the kernel when m allows, else by two launches)
+void Ctx::z_stored_fp32(const double* w, const double* y, double ia, double* z) {
+    const int64_t n = N();
+    if (m <= 1024) {
+        launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, vdef.as<double>(), nullptr, z,
+                               sdef.as<double>(), mudef.as<double>());
+    } else {
+        dots(m, {{sdef.as<double>(), w}, {mudef.as<double>(), w}}, 8);  // s.w, mu.w for the rank-1 parts of Z
+        launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, vdef.as<double>(),
+                               scal.as<double>() + 8, z);
+    }
+}
+
 // one preconditioner apply z = P^{-1} r without CG bookkeeping (h1w_precond_apply)
 void Ctx::precond_one(const double* r, double* z, int zm) {
     const int64_t n = N();
@@ -886,9 +900,7 @@ void Ctx::precond_one(const double* r, double* z, int zm) {
     woodbury_mspace(y, Jy, w);
     if (zm == H1W_Z_STORED) {
         if (fp32) {
-            dots(m, {{sdef.as<double>(), w}, {mudef.as<double>(), w}}, 8);  // s.w, mu.w for the rank-1 parts of Z
-            launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, 1.0 / alpha, vdef.as<double>(),
-                                   scal.as<double>() + 8, z);
+            z_stored_fp32(w, y, 1.0 / alpha, z);
         } else {
             launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, 1.0 / alpha, nullptr, nullptr, z);
         }
@@ -1040,9 +1052,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         } else {
             timed(H1W_K_JTV, (fp32 ? 4.0 : 8.0) * m * n + 16.0 * n, 2.0 * m * n, [&] {
                 if (fp32) {
-                    dots(m, {{sdef.as<double>(), w}, {mudef.as<double>(), w}}, 8);
-                    launch_z_stored<float>(stream, m, n, Zbuf.as<float>(), ldz, w, y, ia, vdef.as<double>(),
-                                           scal.as<double>() + 8, z);
+                    z_stored_fp32(w, y, ia, z);
                 } else {
                     launch_z_stored<double>(stream, m, n, Zbuf.as<double>(), ldz, w, y, ia, nullptr, nullptr, z);
                 }

@@ -194,10 +194,12 @@ template <typename TZ>
 void launch_p_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
                      const double* J, int64_t ldj, const double* jp, const double* y,
                      double inv_alpha, double beta, double* p, double* t);
-// z = (y - Z^T w - c0 v + c1) * inv_alpha with (c0, c1) = cptr[0..1] (v may be null: no extra terms)
+// z = (y - Z^T w - c0 v + c1) * inv_alpha with (c0, c1) = cptr[0..1] (v may be null: no extra terms);
+// with sd and md given (m <= 1024), c0 = sd.w and c1 = md.w are computed in the kernel (cptr unused)
 template <typename TZ>
 void launch_z_stored(hipStream_t s, int m, int64_t N, const TZ* Z, int64_t ldz, const double* w,
-                     const double* y, double inv_alpha, const double* v, const double* cptr, double* z);
+                     const double* y, double inv_alpha, const double* v, const double* cptr, double* z,
+                     const double* sd = nullptr, const double* md = nullptr);
 int launch_rows_dot2_partial(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm, const double* v1,
                              const double* v2, double* part1, double* part2);
 void launch_rank2_add(hipStream_t s, int m, const double* a, const double* b, const double* c, const double* d,

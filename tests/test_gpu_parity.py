@@ -190,7 +190,7 @@ def test_vcycle_tail_matches_per_level(P, shape, cmax, k, chunk, tail, prec):
             assert (kt["vtail"]["launches"] > 0) == (vt and tail)
             assert (kt["coarse"]["launches"] == 0) == (vt and tail)
     assert np.array_equal(out[0], out[1])
-    V = mg.VCycle(shape, beta, coarse_max=cmax or 289)
+    V = mg.VCycle(shape, beta, coarse_max=cmax or 81)
     tol = 100 * EPS64 * np.linalg.cond(V.Acoarse) if prec == "fp64" else 2e-5
     if N <= 40000:
         Xref = V.apply(F if prec == "fp64" else F.astype(np.float32).astype(np.float64))
