@@ -315,22 +315,29 @@ __global__ __launch_bounds__(kBlock) void k_sub(int64_t N, const double* __restr
 // x += a p ; r -= a q ; partial sums of r.r
 // x += a p, r -= a q with the step length a read from device memory;
 // partial sums of r.r
+// x += a p, r -= a q and the partial sums of r.r; with psum, also those of
+// sum(r) (the grid and order of k_dots_partial<1> against a vector of ones)
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t N, const double* __restrict__ adev,
                                                       const double* __restrict__ p, const double* __restrict__ q,
                                                       double* __restrict__ x, double* __restrict__ r,
-                                                      double* __restrict__ partial) {
+                                                      double* __restrict__ partial, double* __restrict__ psum) {
     __shared__ double sh[kBlock / 64];
     const double a = *adev;
-    double acc = 0.0;
+    double acc = 0.0, acs = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x; n < N;
          n += (int64_t)gridDim.x * kBlock) {
         x[n] += a * p[n];
         const double rn = r[n] - a * q[n];
         r[n] = rn;
         acc += rn * rn;
+        acs += rn;
     }
     const double s = block_sum<kBlock>(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (psum) {
+        const double t = block_sum<kBlock>(acs, sh);
+        if (threadIdx.x == 0) psum[blockIdx.x] = t;
+    }
 }
 
 // per-row dot products of a batch: partial[r*nb + b]
@@ -760,9 +767,9 @@ void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, doub
 }
 
 void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
-                          double* x, double* r, double* partial, int* nparts) {
+                          double* x, double* r, double* partial, int* nparts, double* psum) {
     const int nb = dot_blocks(N);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, adev, p, q, x, r, partial);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, s, N, adev, p, q, x, r, partial, psum);
     H1W_LAUNCHED();
     *nparts = nb;
 }

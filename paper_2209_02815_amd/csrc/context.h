@@ -70,6 +70,9 @@ struct Ctx {
     int mstride = 1;                 // m-vector slot stride (grows only)
     double* hscal = nullptr;         // pinned host copy of device scalars
     double* hrep = nullptr;          // coherent pinned host memory written by kernels (CG scalars, norms)
+    const double* rsum_of = nullptr; // vector whose sum(.) partials are at rsum_part (mixed GN-CG residual)
+    const double* rsum_part = nullptr;
+    int rsum_nb = 0;
     double* drep = nullptr;          // hrep as seen by the device
     static constexpr int kGnScal = 32;  // slots of the GN CG's device scalars in scal
     hipEvent_t ev[8] = {};

@@ -489,12 +489,16 @@ void Ctx::vcycle_B_eager(int k, const double* F, int64_t ldf, double* X, int64_t
         float* fin = stage.as<float>();
         float* fout = fin + pitch[0];
         double* cm = scal.as<double>() + 12;  // cm[0] = c, cm[1] = mu
-        {
+        if (F == rsum_of && rsum_part && !graphs) {
+            // the GN-CG update left the partial sums of F = r (same order)
+            launch_deflate_in(stream, n, F, rsum_part, rsum_nb, 1.0 / wsum, wvec.as<double>(), fin, cm);
+        } else {
             const double* X1[1] = {ones.as<double>()};
             const double* Y1[1] = {F};
             const int nb = launch_dots_partial(stream, n, 1, X1, Y1, part.as<double>());
             launch_deflate_in(stream, n, F, part.as<double>(), nb, 1.0 / wsum, wvec.as<double>(), fin, cm);
         }
+        rsum_of = nullptr;
         vcycle_chunk<float>(1, fin, pitch[0], fout, pitch[0]);
         const int nch = launch_rows_dot_partial_f32(stream, 1, n, fout, pitch[0], wvec.as<double>(), jpart.as<double>());
         launch_deflate_out(stream, n, fout, jpart.as<double>(), nch, 1.0 / wsum, cm, vdef.as<double>(), X);
@@ -956,6 +960,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         }
     } exact_scope(*this, (o.flags & H1W_SOLVE_EXACT_B) != 0);
     ev_reserve();
+    rsum_of = nullptr;
     H1W_HIP(hipEventRecord(ev[5], stream));
     if (m_ > 0 && !laplace) {
         capacitance_build(m_, J_, ldj_, alpha_, o.factor, info);
@@ -1067,6 +1072,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
         }
     };
     auto true_relres = [&]() -> double {
+        rsum_of = nullptr;  // r is replaced after a true-residual check
         gn_apply(m, J, ldj, alpha, x, z);  // z is free here; gn_apply uses tmp internally
         launch_sub(stream, n, b, z, u);
         const int nb = dots_parts(n, {{u, u}}, part.as<double>());
@@ -1086,7 +1092,16 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
             timed(H1W_K_APPLY, 24.0 * n, 0.0,
                   [&] { launch_apply_plus_dot(stream, dim, lv[0], alpha, p, t, q, part.as<double>(), &np); });
             launch_gn_alpha(stream, part.as<double>(), np, dsc);
-            launch_cg_update_dev(stream, n, dsc + 1, p, q, x, r, part.as<double>(), &np);
+            // mixed: the update also leaves the partial sums of r for the
+            // constant-mode deflation of the next preconditioner apply
+            // (not with V-cycle graphs: a captured cycle must not depend on it)
+            double* psum = (fp32 && deflate && !graphs) ? part.as<double>() + kPartB : nullptr;
+            launch_cg_update_dev(stream, n, dsc + 1, p, q, x, r, part.as<double>(), &np, psum);
+            if (psum) {
+                rsum_of = r;
+                rsum_part = psum;
+                rsum_nb = np;
+            }
             launch_gn_report(stream, part.as<double>(), np, dsc, drep);
             sync();
             const double* hs = hrep;
@@ -1141,6 +1156,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
             precond_step(false);
         }
     }
+    rsum_of = nullptr;
     ev_record(6);
     sync();
     flush_timing();

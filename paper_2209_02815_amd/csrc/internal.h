@@ -237,8 +237,9 @@ void launch_reduce_host(hipStream_t s, int nvec, int nparts, const double* parti
 // x = 0, r = b, p = q = 0, Jp[0..m) = 0 and the partials of b.b (returns their count)
 int launch_cg_init(hipStream_t s, int64_t N, const double* b, double* x, double* r, double* p, double* q, int m,
                    double* Jp, double* partial);
+// x += a p, r -= a q, partials of r.r (and of sum(r) into psum when given)
 void launch_cg_update_dev(hipStream_t s, int64_t N, const double* adev, const double* p, const double* q,
-                          double* x, double* r, double* partial, int* nparts);
+                          double* x, double* r, double* partial, int* nparts, double* psum = nullptr);
 void launch_sub(hipStream_t s, int64_t N, const double* b, const double* v, double* out);
 // batched (per-row coefficient) helpers for MG-PCG
 void launch_batched_dots(hipStream_t s, int k, int64_t N, const double* X, int64_t ldx,
