@@ -16,10 +16,13 @@
 //
 // Autotuner: for each (grid, precision, row bucket ceil(log2 m)) key, the
 // worker that meets the key first solves that instance with nu = 1, 3 and
-// then 2 smoothing steps per side, back to back on its own stream, and the
-// later instances of the key use the nu with the shortest wall time (the
-// candidates are compared on the same system, so differences in m, alpha and
-// iteration count between instances do not enter). The last tuning solve
+// then 2 smoothing steps per side, back to back on its own stream, twice over
+// (the faster of each candidate's two runs counts), and the later instances
+// of the key use nu = 1 or 3 only if its wall time is below 0.75 times that
+// of the default (the candidates are compared on the same
+// system, so differences in m, alpha and iteration count between instances
+// do not enter; the margin covers the launches that a single solve's wall
+// time undercounts and the batch pays for). The last tuning solve
 // (nu = 2) is the instance's result; while a key is being tuned, other
 // workers solve its instances with the default nu. Tuned keys are kept for
 // the process: a later batch reuses them (autotune = 1) or tunes them again
@@ -42,6 +45,8 @@ namespace {
 
 constexpr int kTuneCandidates[] = {1, 3, 2};  // the default last: its solution is kept
 constexpr int kNumCandidates = 3;
+constexpr double kTuneMargin = 0.75;  // another nu is kept only below 0.75 x the default's time
+constexpr int kTuneReps = 2;         // timed solves per candidate (the faster counts)
 
 struct GridKey {
     int dim, n0, n1, n2, precision, nu;
@@ -263,10 +268,15 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 } else {
                     // the candidates on this instance, the default last (its x is the result)
                     int best_nu = nu_fixed;
-                    double best = -1.0;
-                    for (int c = 0; c < kNumCandidates; ++c) {
+                    double best = -1.0, t_alt = -1.0, t_def = -1.0;
+                    int alt_nu = nu_fixed;
+                    bool failed[kNumCandidates] = {};
+                    // every candidate twice (the faster run counts: the first run
+                    // of a new context also sets it up); the default solves last
+                    for (int cc = 0; cc < kTuneReps * kNumCandidates; ++cc) {
+                        const int c = cc % kNumCandidates;
                         const int nu_c = c + 1 == kNumCandidates ? nu_fixed : kTuneCandidates[c];
-                        if (c + 1 < kNumCandidates && nu_c == nu_fixed) continue;
+                        if ((c + 1 < kNumCandidates && nu_c == nu_fixed) || failed[c]) continue;
                         Ctx& cx = ctx_for(nu_c);
                         cx.sync();
                         const auto t0 = std::chrono::steady_clock::now();
@@ -276,6 +286,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                             try {  // a candidate that fails (e.g. no convergence) is skipped
                                 cx.gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
                             } catch (const Error&) {
+                                failed[c] = true;
                                 used.pop_back();
                                 drop(GridKey{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c, it.beta,
                                              o.graphs != 0});
@@ -284,10 +295,22 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                         }
                         const double ms =
                             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                        if (best < 0.0 || ms < best) {
-                            best = ms;
-                            best_nu = nu_c;
+                        if (nu_c == nu_fixed) {
+                            t_def = t_def < 0.0 ? ms : std::min(t_def, ms);
+                        } else if (t_alt < 0.0 || ms < t_alt) {
+                            t_alt = ms;
+                            alt_nu = nu_c;
                         }
+                    }
+                    // another nu must beat the default by kTuneMargin: one solve's
+                    // wall time undercounts what the batch pays for the extra
+                    // launches of the unfused candidates (the default nu = 2 has
+                    // the fused passes)
+                    best_nu = nu_fixed;
+                    best = t_def;
+                    if (t_alt >= 0.0 && (t_def < 0.0 || t_alt < kTuneMargin * t_def)) {
+                        best_nu = alt_nu;
+                        best = t_alt;
                     }
                     finish_tuning(tk, best_nu, best / work(i));
                 }
