@@ -1,14 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the Woodbury-preconditioned Gauss-Newton linear solve on one MI355X.
 
-Workload (default "cube129"): 3D unit cube, 129^3 nodes, H^1 Gram operator
-A = K + beta*M (beta = 1e-2, Neumann), alpha = 1e-4, J dense 512 x 2146689
-FP64 (each row four Gaussian bumps of width 0.05 plus 1e-3 white noise),
-one right-hand side b ~ N(0,1). A step is one complete solve
-(h1w_gn_solve: 512 batched V-cycles for Z, capacitance GEMM, factorisation,
-preconditioned CG to a true relative residual of 1e-8), with J and b already
-resident in HBM. The FP64 path (FP64 V-cycles and GEMM) gives `value`; the
-mixed FP32/FP64 path is timed the same way and reported beside it.
+Workload (default "cube257", the precision workload): 3D unit cube, 257^3
+nodes (N = 16,974,593), H^1 Gram operator A = K + beta*M (beta = 1e-2,
+Neumann), alpha = 1e-5, J dense 1024 x N FP64 (139 GB; each row four Gaussian
+bumps of width 0.05 plus 1e-3 white noise), one right-hand side b ~ N(0,1).
+A step is one complete solve (h1w_gn_solve: 1024 batched V-cycles for Z, the
+capacitance GEMM, its factorisation and preconditioned CG to a true relative
+residual of 1e-8), with J and b already resident in HBM. Both precision forms
+are timed the same way: plain FP64 (FP64 V-cycles, Z streamed in row chunks
+against J, recompute form of the Woodbury apply, Cholesky) and mixed (FP32
+V-cycles and stored FP32 Z, FP64 capacitance, LU and flexible CG). `value` is
+the FP64 form's solves/s; the mixed form and the ratio mixed / FP64 are
+reported beside it (the metric compares the two).
+
+The timed solves carry no instrumentation. The roofline of the dominant kernel
+class comes from a separate pass of solves after the timed ones, with HIP
+events around that class's launches on the library's stream.
 
 Prints one JSON line (see the keys below).
 """
@@ -27,12 +35,18 @@ sys.path.insert(0, ROOT)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cube129")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cube257")
+    ap.add_argument("--compare-workload", default="cube129",
+                    help="workload of the comparison solve modes (Laplace-only, exact-B)")
+    ap.add_argument("--profile-steps", type=int, default=2,
+                    help="solves after the timed ones with event timing of the dominant kernel class")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="also time the oracle's complete solve (J must fit in host memory: 129^3)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch of 256 uneven 2D instances (h1w_batch_solve)")
     ap.add_argument("--no-compare", action="store_true",
@@ -120,18 +134,17 @@ def roofline(cls: str, st: dict) -> dict:
             "algorithmic_flops_per_launch": st["flops"] / st["launches"]}
 
 
-def time_solves(ctx, Jd, alpha, bd, xd, steps, warmup, rtol):
-    """Warmup (all kernel classes timed, to find the dominant one), then `steps`
-    timed solves with event timing of the dominant class only."""
+def time_solves(ctx, Jd, alpha, bd, xd, steps, warmup, profile_steps, rtol):
+    """`warmup` untimed solves, then `steps` timed solves with no
+    instrumentation (wall clock, synchronised on both sides). Afterwards, for
+    the roofline and the kernel-time shares: `profile_steps` solves with every
+    kernel class timed by HIP events (shares and the dominant class), then as
+    many with events around the dominant class's launches only (its average
+    launch duration)."""
     import torch
-    ctx.set_kernel_timing("all")
-    for _ in range(max(1, warmup)):
+    for _ in range(warmup):
         ctx.gn_solve(Jd, alpha, b=bd, x=xd, rtol=rtol)
     torch.cuda.synchronize()
-    kt = ctx.kernel_timing()
-    dominant = max(kt, key=lambda c: kt[c]["ms"])
-    ctx.reset_kernel_timing()
-    ctx.set_kernel_timing([dominant])
     infos = []
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -139,23 +152,40 @@ def time_solves(ctx, Jd, alpha, bd, xd, steps, warmup, rtol):
         infos.append(info.as_dict())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ctx.set_kernel_timing("all")
+    for _ in range(max(1, profile_steps)):
+        ctx.gn_solve(Jd, alpha, b=bd, x=xd, rtol=rtol)
+    torch.cuda.synchronize()
+    kt = ctx.kernel_timing()
+    dominant = max(kt, key=lambda c: kt[c]["ms"])
+    ctx.reset_kernel_timing()
+    ctx.set_kernel_timing([dominant])
+    for _ in range(max(1, profile_steps)):
+        ctx.gn_solve(Jd, alpha, b=bd, x=xd, rtol=rtol)
+    torch.cuda.synchronize()
     st = ctx.kernel_timing()[dominant]
     ctx.set_kernel_timing([])
+    ctx.reset_kernel_timing()
     shares = {c: round(v["ms"] / max(1e-9, sum(x["ms"] for x in kt.values())), 4) for c, v in kt.items()}
     return dt, infos, roofline(dominant, st), shares
 
 
-def cpu_baseline(wl, J, b, threads):
+def cpu_baseline(wl, J, b, threads, full=False):
     """Oracle (DCT-Woodbury + refinement, FP64 numpy/scipy) timed on a bounded sample.
 
-    Sample: the oracle's Woodbury solve on the same grid with the first 8 rows
-    of J, one extra exact Poisson solve, and a 64 x 64 block of the capacitance
-    product (the first 64 rows of J against themselves); scaled to one full
-    solve as t_sample + (m - 8) * t_poisson + (m / 64)^2 * t_gemm_block.
-    J holds at least the first 64 rows.
+    Sample: the oracle's Woodbury solve on the same grid with the first ms rows
+    of J (8, or 2 on grids above 4M nodes, where one exact Poisson solve takes
+    about a second), one extra exact Poisson solve, and a 64 x 64 block of the
+    capacitance product (the first 64 rows of J against themselves); scaled to
+    one full solve as t_sample + (m - ms) * t_poisson + (m / 64)^2 * t_gemm_block
+    (the Woodbury route's cost: one Poisson solve per row of J for Z = A^-1 J^T
+    and the m x m product J Z^T; the refinement steps are in t_sample).
+    J holds at least the first 64 rows. full=True also times the oracle's
+    complete solve with all m rows (J must be the whole matrix) to check that
+    model; that takes about a minute at 129^3 and is not part of the default run.
     """
     from oracle import gn, poisson
-    ms = 8
+    ms = 8 if wl.N <= (4 << 20) else 2
     t0 = time.perf_counter()
     gn.solve_woodbury(wl.shape, wl.beta, J[:ms], wl.alpha, b)
     t_sample = time.perf_counter() - t0
@@ -167,12 +197,21 @@ def cpu_baseline(wl, J, b, threads):
     _ = blk @ blk.T
     t_gemm_blk = time.perf_counter() - t0
     t_full = t_sample + (wl.m - ms) * t_poisson + (wl.m / 64) ** 2 * t_gemm_blk
-    return {
+    out = {
         "value": 1.0 / t_full, "unit": "solves/s", "cores": threads, "kind": "oracle",
-        "sample": (f"oracle Woodbury solve on the {'x'.join(map(str, wl.shape))} grid with 8 of {wl.m} rows "
+        "sample": (f"oracle Woodbury solve on the {'x'.join(map(str, wl.shape))} grid with {ms} of {wl.m} rows "
                    f"({t_sample:.2f} s) + 1 DCT Poisson solve ({t_poisson:.3f} s) + 64x64 block of the "
                    f"capacitance product ({t_gemm_blk:.3f} s), scaled to one full solve: {t_full:.1f} s"),
     }
+    if full:
+        assert J.shape[0] == wl.m
+        t0 = time.perf_counter()
+        x = gn.solve_woodbury(wl.shape, wl.beta, J, wl.alpha, b)
+        t_meas = time.perf_counter() - t0
+        out["full_solve"] = {"s": t_meas, "model_s": t_full,
+                             "relres": gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)}
+        log(f"oracle full solve: {t_meas:.1f} s (model {t_full:.1f} s)")
+    return out
 
 
 def ert_bench(args):
@@ -325,6 +364,36 @@ def grid_text(shape) -> str:
     return f"{len(shape)}D " + "x".join(str(n) for n in shape)
 
 
+def make_inputs(wl, threads):
+    """J on the device (row chunks straight from the generator when it is
+    large, never whole on the host), b on the host and device, and the first
+    64 rows of J on the host (the CPU baseline's sample)."""
+    import torch
+    import h1w_inputs as H
+    log(f"{wl.name}: generating J ({wl.m} x {wl.N}) and b on {threads} threads")
+    t0 = time.perf_counter()
+    b = H.rhs_b(wl)
+    if wl.m * wl.N * 8 <= (16 << 30):
+        J = H.j_rows(wl, threads=threads)
+        Jd = torch.from_numpy(J).to("cuda:0")
+        Jhead = J
+    else:
+        Jd = torch.empty((wl.m, wl.N), dtype=torch.float64, device="cuda:0")
+        step = 64
+        Jhead = None
+        for i0 in range(0, wl.m, step):
+            rows = H.j_rows(wl, i0, min(wl.m, i0 + step), threads=threads)
+            Jd[i0:i0 + rows.shape[0]].copy_(torch.from_numpy(rows))
+            if Jhead is None:
+                Jhead = rows[:64].copy()
+            if (i0 // step) % 4 == 0:
+                log(f"  rows {i0}..{i0 + rows.shape[0]} on the GPU ({time.perf_counter() - t0:.0f} s)")
+    bd = torch.from_numpy(b).to("cuda:0")
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+    return Jd, Jhead, b, bd
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -349,34 +418,20 @@ def main():
 
     wl = H.workload(args.workload)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log(f"generating J ({wl.m} x {wl.N}) and b on {threads} threads")
-    t0 = time.perf_counter()
-    b = H.rhs_b(wl)
-    if wl.m * wl.N * 8 <= (16 << 30):
-        J = H.j_rows(wl, threads=threads)
-        Jd = torch.from_numpy(J).to("cuda:0")
-    else:  # large J: generate row chunks straight into the device copy
-        Jd = torch.empty((wl.m, wl.N), dtype=torch.float64, device="cuda:0")
-        step = 32
-        for i0 in range(0, wl.m, step):
-            rows = H.j_rows(wl, i0, min(wl.m, i0 + step), threads=threads)
-            Jd[i0:i0 + rows.shape[0]].copy_(torch.from_numpy(rows))
-            if i0 == 0:
-                J = rows[:64].copy() if rows.shape[0] >= 64 else H.j_rows(wl, 0, 64, threads=threads)
-            if (i0 // step) % 8 == 0:
-                log(f"  rows {i0}..{i0 + rows.shape[0]} on the GPU")
-    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
-    bd = torch.from_numpy(b).to("cuda:0")
+    Jd, J, b, bd = make_inputs(wl, threads)
     xd = torch.empty_like(bd)
-    torch.cuda.synchronize()
 
     results = {}
     modes = ["fp64"] + ([] if args.no_mixed else ["mixed"])
     for mode in modes:
         with P.Context(wl.shape, wl.beta, precision=mode) as ctx:
-            log(f"{mode}: warmup {args.warmup}, timing {args.steps} solves")
-            dt, infos, roof, shares = time_solves(ctx, Jd, wl.alpha, bd, xd, args.steps, args.warmup, args.rtol)
-            # independent FP64 check of the last solution: ||b - G x|| / ||b|| via the library's GN apply
+            log(f"{mode}: warmup {args.warmup}, timing {args.steps} solves, then {args.profile_steps} + "
+                f"{args.profile_steps} profiled solves")
+            dt, infos, roof, shares = time_solves(ctx, Jd, wl.alpha, bd, xd, args.steps, args.warmup,
+                                                  args.profile_steps, args.rtol)
+            # FP64 recomputation of the last solution's relative residual by the
+            # library's GN apply (the oracle checks this configuration in the
+            # GPU tests; it is not called here)
             y = ctx.gn_apply(Jd, wl.alpha, xd)
             rr = float(torch.linalg.norm(bd - y) / torch.linalg.norm(bd))
         med = lambda k: float(np.median([i[k] for i in infos]))
@@ -385,32 +440,39 @@ def main():
             "iters": int(np.median([i["iters"] for i in infos])), "relres_true": rr,
             "t_zbuild_ms": med("t_zbuild_ms"), "t_gemm_ms": med("t_gemm_ms"), "t_factor_ms": med("t_factor_ms"),
             "t_cg_ms": med("t_cg_ms"), "t_total_ms": med("t_total_ms"), "factor": infos[-1]["factor_used"],
-            "roofline": roof, "kernel_time_share": shares,
+            "zmode": infos[-1]["zmode_used"], "roofline": roof, "kernel_time_share": shares,
         }
         log(f"{mode}: {results[mode]}")
-    # comparison modes on the same system (FP64): the Laplace-only preconditioner
-    # (B / alpha, no Woodbury correction) and the exact Woodbury inverse with
-    # B = A^-1 by MG-PCG; context for the Woodbury preconditioner's robustness
+    del Jd, xd
+    torch.cuda.empty_cache()
+
+    # comparison modes (FP64) on their own workload: the Laplace-only
+    # preconditioner (B / alpha, no Woodbury correction) and the exact Woodbury
+    # inverse with B = A^-1 by MG-PCG; context for the Woodbury preconditioner's
+    # robustness
     compare = None
     if not args.no_compare:
-        compare = {}
-        with P.Context(wl.shape, wl.beta, precision="fp64") as ctx:
-            for mode, warm, steps in (("exact", 1, 2), ("laplace", 0, 1)):
+        cwl = H.workload(args.compare_workload)
+        cJd, _, _, cbd = make_inputs(cwl, threads)
+        cxd = torch.empty_like(cbd)
+        compare = {"workload": f"{cwl.name}: {grid_text(cwl.shape)}, m={cwl.m}, alpha={cwl.alpha}"}
+        with P.Context(cwl.shape, cwl.beta, precision="fp64") as ctx:
+            for mode, warm, steps in (("woodbury", 1, 3), ("exact", 1, 2), ("laplace", 0, 1)):
                 log(f"comparison mode {mode}: warmup {warm}, timing {steps} solve(s)")
                 for _ in range(warm):
-                    ctx.gn_solve(Jd, wl.alpha, b=bd, x=xd, rtol=args.rtol, mode=mode, maxit=20000)
+                    ctx.gn_solve(cJd, cwl.alpha, b=cbd, x=cxd, rtol=args.rtol, mode=mode, maxit=20000)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 for _ in range(steps):
-                    _, info = ctx.gn_solve(Jd, wl.alpha, b=bd, x=xd, rtol=args.rtol, mode=mode, maxit=20000)
+                    _, info = ctx.gn_solve(cJd, cwl.alpha, b=cbd, x=cxd, rtol=args.rtol, mode=mode, maxit=20000)
                 torch.cuda.synchronize()
                 dt = (time.perf_counter() - t0) / steps
                 compare[mode] = {"solves_per_s": 1.0 / dt, "ms_per_solve": 1e3 * dt, "iters": info.iters,
                                  "relres_true": info.relres_true, "t_zbuild_ms": info.t_zbuild_ms,
                                  "t_cg_ms": info.t_cg_ms}
                 log(f"{mode}: {compare[mode]}")
-    del Jd
-    torch.cuda.empty_cache()
+        del cJd, cxd
+        torch.cuda.empty_cache()
 
     batch = None if args.no_batch else batch_bench(args, threads)
     ert = None if args.no_ert else ert_bench(args)
@@ -418,9 +480,12 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl, J, b, threads)
+        if args.cpu_baseline_full and J.shape[0] < wl.m:
+            J = H.j_rows(wl, threads=threads)
+        cpu = cpu_baseline(wl, J, b, threads, full=args.cpu_baseline_full)
 
     r64 = results["fp64"]
+    rmx = results.get("mixed")
     out = {
         "metric": "GN-system solves/s at 1e-8 rel. residual: mixed FP32/FP64 vs plain FP64, 1 GPU",
         "value": r64["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -429,11 +494,12 @@ def main():
         "config": {"workload": f"{wl.name}: {grid_text(wl.shape)} H1 Gram (beta={wl.beta}), m={wl.m} "
                                f"{'bump' if wl.j_kind == 'bumps' else 'Gaussian'} rows, alpha={wl.alpha}, "
                                f"rtol={args.rtol}",
-                   "N": wl.N, "m": wl.m,
+                   "N": wl.N, "m": wl.m, "form": "plain FP64 (value); mixed FP32/FP64 beside it",
                    "parallelism": "single GPU"},
         "roofline": r64["roofline"],
         "fp64": r64,
-        "mixed": results.get("mixed"),
+        "mixed": rmx,
+        "mixed_over_fp64": (rmx["solves_per_s"] / r64["solves_per_s"]) if rmx else None,
         "comparison_modes": compare,
         "batch": batch,
         "ert": ert,

@@ -51,6 +51,47 @@ def true_relres(shape, beta, J, alpha, b, x) -> float:
     return float(np.linalg.norm(b - gn_apply(shape, beta, J, alpha, x)) / np.linalg.norm(b))
 
 
+def gn_apply_streamed(shape, beta, row_blocks, alpha, X):
+    """G X = alpha*A X + J^T (J X) with J supplied as an iterable of row blocks
+    (arrays of shape (rows, N); every row of J exactly once, in any order),
+    consumed once: J^T J X is the sum over the blocks of J_b^T (J_b X), so J is
+    never held whole (a 1024 x 257^3 J is 139 GB). X: (N,) or (k, N); the
+    result has the shape of X."""
+    X = np.asarray(X, dtype=np.float64)
+    X2 = X.reshape(1, -1) if X.ndim == 1 else X
+    out = alpha * op.apply(shape, beta, X2)
+    for Jb in row_blocks:
+        out += (Jb.T @ (Jb @ X2.T)).T
+    return out.reshape(X.shape)
+
+
+def relres_streamed(shape, beta, row_blocks, alpha, b, X):
+    """(relres, floor) for each row x of X (or the single vector X), with J
+    streamed as in gn_apply_streamed:
+      relres = ||b - G x||_2 / ||b||_2 (the paper's stopping quantity);
+      floor  = u || alpha |A||x| + |J|^T (|J||x|) ||_2 / ||b||_2, u = 2^-53,
+               the componentwise rounding level of one FP64 product G x, i.e.
+               the smallest relative residual an FP64 solve can be expected to
+               reach (residual_rounding_floor is 4 sqrt(N) times it).
+    Both come from the same single pass over the blocks."""
+    X = np.asarray(X, dtype=np.float64)
+    X2 = X.reshape(1, -1) if X.ndim == 1 else X
+    A = op.gram_operator(shape, beta)
+    Gx = alpha * (A @ X2.T).T
+    mag = alpha * (abs(A) @ np.abs(X2).T).T
+    for Jb in row_blocks:
+        Gx += (Jb.T @ (Jb @ X2.T)).T
+        aJ = np.abs(Jb)
+        mag += (aJ.T @ (aJ @ np.abs(X2).T)).T
+    nb = np.linalg.norm(b)
+    u = np.finfo(np.float64).eps / 2
+    rr = np.linalg.norm(b[None, :] - Gx, axis=1) / nb
+    fl = u * np.linalg.norm(mag, axis=1) / nb
+    if X.ndim == 1:
+        return float(rr[0]), float(fl[0])
+    return rr, fl
+
+
 def residual_rounding_floor(shape, beta, J, alpha, b, x) -> float:
     """Rounding level of an FP64 evaluation of ||b - G x|| / ||b||: with the
     componentwise bound |fl(G x) - G x| <~ u |alpha A| |x| + u |J|^T (|J| |x|)

@@ -36,6 +36,8 @@ struct Ctx {
     DevBuf vws;                      // V-cycle level workspace
     DevBuf stage;                    // FP32 staging (mixed precision)
     DevBuf pcg;                      // MG-PCG batch vectors
+    DevBuf mgvec, mgpart;            // MG-PCG per-RHS scalars and dot partials (its own: the
+                                     // V-cycle of a MIXED context may grow the GN-CG buffers)
 
     // capacitance state (valid when have_cap)
     bool have_cap = false;

@@ -538,8 +538,11 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
         double* Zv = R + (size_t)kk * P;
         double* Pv = Zv + (size_t)kk * P;
         double* Q = Pv + (size_t)kk * P;
-        mvec.reserve((size_t)8 * kk * sizeof(double) + 16 * kk * sizeof(int));
-        double* dnrm = mvec.as<double>();       // kk
+        // scratch of its own: vcycle_B may reserve (and so reallocate) the
+        // GN-CG workspace (mvec, part) of a MIXED context, and an EXACT_B
+        // solve runs inside the GN-CG, whose m-vectors live in mvec
+        mgvec.reserve((size_t)8 * kk * sizeof(double) + 16 * kk * sizeof(int));
+        double* dnrm = mgvec.as<double>();      // kk
         double* drz = dnrm + kk;                // kk: r.z of the current direction
         double* dpq = drz + kk;                 // kk
         double* da = dpq + kk;                  // kk
@@ -547,8 +550,8 @@ void Ctx::mg_solve(int k, const double* F, int64_t ldf, double* X, int64_t ldx, 
         double* dzq = db + kk;                  // kk
         double* drzn = dzq + kk;                // kk: r.z after the new preconditioner apply
         int* dact = (int*)(drzn + kk);          // kk
-        part.reserve((size_t)kk * 64 * sizeof(double));
-        double* pp = part.as<double>();
+        mgpart.reserve((size_t)kk * 64 * sizeof(double));
+        double* pp = mgpart.as<double>();
         std::vector<double> nb(kk), rr(kk);
         std::vector<int> act(kk, 1);
         int hflag = 0;

@@ -228,6 +228,29 @@ def test_mg_solve(P, shape, prec):
     assert np.all(np.linalg.norm(X - Xs, axis=1) <= 1.01 * bound + 1e-12)
 
 
+@pytest.mark.parametrize("shape", [(33, 33), (17, 17, 17)])
+def test_mg_solve_one_rhs_mixed(P, shape):
+    # Regression: on a MIXED context a single right-hand side takes the
+    # constant-mode deflated FP32 cycle, which reserves the GN-CG workspace;
+    # the MG-PCG kept pointers into that workspace and then wrote through them
+    # after it had grown (a fresh context, and one whose capacitance was built
+    # with m = 130 first). The MG-PCG scratch is now its own.
+    beta = 1e-2
+    N = int(np.prod(shape))
+    F = rng(5).standard_normal((1, N))
+    A = op.gram_operator(shape, beta)
+    J = rng(6).standard_normal((130, N)) / np.sqrt(N)
+    with P.Context(shape, beta, precision="mixed") as ctx:
+        X1, info1 = ctx.mg_solve(dev(F), rtol=1e-10)
+        X1 = host(X1)
+        ctx.capacitance_build(dev(J), 1e-3)
+        X2, info2 = ctx.mg_solve(dev(F), rtol=1e-10)
+        X2 = host(X2)
+    for X, info in ((X1, info1), (X2, info2)):
+        rr = np.linalg.norm(F - (A @ X.T).T) / np.linalg.norm(F)
+        assert rr <= 1e-10 * 1.01 and info.relres_true <= 1e-10 * 1.01
+
+
 # ------------------------------------------------------------------ capacitance
 def _bump_problem(name, m=None):
     wl = H.workload(name)
@@ -577,21 +600,23 @@ def test_streamed_z_capacitance_and_solve(P):
     assert gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x) <= 1.01e-10
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_full_size_cube129(P, prec):
-    # The benchmark workload at its full size (129^3, m = 512, 8.8 GB J) in the
-    # launch configuration bench.py times; checked through the oracle's FP64
-    # true residual of the GPU's solution (the direct solution is too costly here).
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-8), ("mixed", 1e-8), ("fp64", 1e-10)])
+def test_full_size_cube129(P, prec, rtol):
+    # The 129^3 workload at its full size (m = 512, 8.8 GB J) in the launch
+    # configuration bench.py times, at the shared 1e-8 and at the FP64
+    # tolerance 1e-10; checked through the oracle's FP64 true residual of the
+    # GPU's solution (the direct solution is too costly here).
     wl = H.workload("cube129")
     J, b = H.j_rows(wl), H.rhs_b(wl)
-    rtol = 1e-8
     with P.Context(wl.shape, wl.beta, precision=prec) as ctx:
         Jd = dev(J)
         x, info = ctx.gn_solve(Jd, wl.alpha, b=dev(b), rtol=rtol)
         x = host(x)
         del Jd
-    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
-    print(f"cube129 {prec}: iters={info.iters} relres(oracle)={rr:.3e} relres(GPU)={info.relres_true:.3e}")
+    rr, fl = gn.relres_streamed(wl.shape, wl.beta, [J], wl.alpha, b, x)
+    print(f"cube129 {prec} rtol={rtol:g}: iters={info.iters} relres(oracle)={rr:.3e} "
+          f"relres(GPU)={info.relres_true:.3e} FP64 floor={fl:.2e}")
     assert rr <= rtol * 1.01
-    assert abs(rr - info.relres_true) <= 1e-3 * rtol
-    assert info.iters <= 12
+    assert abs(rr - info.relres_true) <= 1e-3 * rtol + 4.0 * np.sqrt(wl.N) * fl
+    assert fl <= 1e-2 * rtol
+    assert info.iters <= (12 if rtol >= 1e-8 else 16)
