@@ -10,9 +10,13 @@
 // per key and reused by later instances. Workers are kept for the process
 // (per device, at most kMaxCtxPerWorker contexts each, the least recently
 // used one dropped beyond that) and handed to later batches, so a batch on
-// grids seen before allocates and frees no device memory. The solve of one
-// instance is the library's own h1w_gn_solve path; the workers' streams let
-// the small kernels and host round trips of different instances overlap.
+// grids seen before allocates and frees no device memory. A worker's two
+// streams (its work stream and the stream its contexts capture V-cycle graphs
+// on) are created once, one thread at a time, and never destroyed, so no
+// stream is created or destroyed while other workers synchronise theirs. The
+// solve of one instance is the library's own h1w_gn_solve path; the workers'
+// streams let the small kernels and host round trips of different instances
+// overlap.
 //
 // Autotuner: for each (grid, precision, row bucket ceil(log2 m)) key, the
 // worker that meets the key first solves that instance with nu = 1, 3 and
@@ -97,6 +101,7 @@ std::map<TuneKey, TuneState> g_tuned;
 
 struct Worker {
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // lent to its contexts for V-cycle graph captures
     std::map<GridKey, std::unique_ptr<Ctx>> ctxs;
     std::map<GridKey, uint64_t> last_use;
     uint64_t clock = 0;
@@ -197,6 +202,10 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 std::lock_guard<std::recursive_mutex> lk(capture_lock());
                 H1W_HIP(hipStreamCreateWithFlags(&me.stream, hipStreamNonBlocking));
             }
+            if (o.graphs && !me.cap_stream) {
+                std::lock_guard<std::recursive_mutex> lk(capture_lock());
+                H1W_HIP(hipStreamCreateWithFlags(&me.cap_stream, hipStreamNonBlocking));
+            }
         } catch (const Error& e) {
             worker_err[w] = e.msg;
             return;
@@ -254,6 +263,10 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                         d.flags = o.graphs ? H1W_FLAG_GRAPH_VCYCLE : 0u;
                         auto c = std::make_unique<Ctx>();
                         c->init(d, me.stream);
+                        if (o.graphs) {  // no stream is created or destroyed with a batch context
+                            c->cap_stream = me.cap_stream;
+                            c->own_cap_stream = false;
+                        }
                         me.ctxs[gk] = std::move(c);
                     }
                     return *me.ctxs[gk];

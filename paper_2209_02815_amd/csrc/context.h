@@ -112,6 +112,8 @@ struct Ctx {
     bool graphs = false;
     bool capturing = false;
     hipStream_t cap_stream = nullptr;  // private stream the V-cycle graphs are captured on
+    bool own_cap_stream = true;        // destroyed with the context (false: lent by a batch worker,
+                                       // which keeps it for the process)
     std::vector<VGraph> vgraphs;
     std::vector<const void*> vg_sig;
     int64_t graph_launches = 0;

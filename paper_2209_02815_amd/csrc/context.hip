@@ -220,7 +220,7 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
 Ctx::~Ctx() {
     std::lock_guard<std::recursive_mutex> lk(capture_lock());
     clear_graphs();
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (cap_stream && own_cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hscal) (void)hipHostFree(hscal);
     if (hrep) (void)hipHostFree(hrep);
     for (auto& p : pending) {
