@@ -189,13 +189,16 @@ def cpu_baseline(wl, J, b, threads, full=False):
     t0 = time.perf_counter()
     gn.solve_woodbury(wl.shape, wl.beta, J[:ms], wl.alpha, b)
     t_sample = time.perf_counter() - t0
+    log(f"cpu baseline: oracle Woodbury solve with {ms} rows {t_sample:.1f} s")
     t0 = time.perf_counter()
     poisson.dct_solve(wl.shape, wl.beta, b, workers=threads)
     t_poisson = time.perf_counter() - t0
+    log(f"cpu baseline: one DCT Poisson solve {t_poisson:.2f} s")
     blk = J[:64]
     t0 = time.perf_counter()
     _ = blk @ blk.T
     t_gemm_blk = time.perf_counter() - t0
+    log(f"cpu baseline: 64 x 64 capacitance block {t_gemm_blk:.2f} s")
     t_full = t_sample + (wl.m - ms) * t_poisson + (wl.m / 64) ** 2 * t_gemm_blk
     out = {
         "value": 1.0 / t_full, "unit": "solves/s", "cores": threads, "kind": "oracle",
@@ -365,9 +368,9 @@ def grid_text(shape) -> str:
 
 
 def make_inputs(wl, threads):
-    """J on the device (row chunks straight from the generator when it is
-    large, never whole on the host), b on the host and device, and the first
-    64 rows of J on the host (the CPU baseline's sample)."""
+    """J on the device (large J in row blocks through pinned host buffers,
+    never whole on the host), b on the host and device, and the first 64 rows
+    of J on the host (the CPU baseline's sample)."""
     import torch
     import h1w_inputs as H
     log(f"{wl.name}: generating J ({wl.m} x {wl.N}) and b on {threads} threads")
@@ -379,15 +382,8 @@ def make_inputs(wl, threads):
         Jhead = J
     else:
         Jd = torch.empty((wl.m, wl.N), dtype=torch.float64, device="cuda:0")
-        step = 64
-        Jhead = None
-        for i0 in range(0, wl.m, step):
-            rows = H.j_rows(wl, i0, min(wl.m, i0 + step), threads=threads)
-            Jd[i0:i0 + rows.shape[0]].copy_(torch.from_numpy(rows))
-            if Jhead is None:
-                Jhead = rows[:64].copy()
-            if (i0 // step) % 4 == 0:
-                log(f"  rows {i0}..{i0 + rows.shape[0]} on the GPU ({time.perf_counter() - t0:.0f} s)")
+        H.upload_j(wl, Jd, threads=threads, log=log)
+        Jhead = H.j_rows(wl, 0, min(64, wl.m), threads=threads)
     bd = torch.from_numpy(b).to("cuda:0")
     torch.cuda.synchronize()
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s")

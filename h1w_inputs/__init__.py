@@ -35,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "WORKLOADS", "workload", "grid_shape", "num_nodes", "axis_coords",
-    "j_rows", "rhs_b", "paper_data", "rng_for", "batch_workloads",
+    "j_rows", "j_row_blocks", "upload_j", "rhs_b", "paper_data", "rng_for", "batch_workloads",
     "ErtSurvey", "ert_survey", "ert_logsig", "ERT_DIRICHLET_DEFAULT",
 ]
 
@@ -130,49 +130,113 @@ def rng_for(wid: int, stream: int, row: int = 0) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([wid, stream, row])))
 
 
-def _one_row(wl: Workload, i: int) -> np.ndarray:
+def _one_row(wl: Workload, i: int, out: np.ndarray | None = None) -> np.ndarray:
+    """Row i of J, written into `out` (length N) when given.
+
+    Bump rows: out = noise * xi + sum_k a_k g_k, with g_k the separable
+    Gaussian prod_d exp(-(x_d - c_kd)^2 / (2 w^2)). The bump sum is formed as a
+    product with inner dimension nbumps: (slowest-axis factors, n_slow x K)
+    times (a_k times the outer product of the other axes' factors, K x rest),
+    added slab by slab of the slowest axis, so no N-sized temporary is made."""
     N = wl.N
+    if out is None:
+        out = np.empty(N, dtype=np.float64)
     if wl.j_kind == "gauss":
-        return rng_for(wl.wid, 0, i).standard_normal(N) / np.sqrt(N)
+        rng_for(wl.wid, 0, i).standard_normal(N, out=out)
+        out /= np.sqrt(N)
+        return out
     if wl.j_kind != "bumps":
         raise ValueError(f"unknown j_kind {wl.j_kind!r}")
     prm = rng_for(wl.wid, 2, i)
     centres = prm.random((wl.nbumps, wl.dim))
     amps = prm.standard_normal(wl.nbumps)
-    row = wl.noise * rng_for(wl.wid, 0, i).standard_normal(N)
-    # reshape to (nz, ny, nx) / (ny, nx): x fastest in memory
-    grid = row.reshape(tuple(reversed(wl.shape)))
+    rng_for(wl.wid, 0, i).standard_normal(N, out=out)
+    out *= wl.noise
     s2 = 2.0 * wl.width ** 2
+    g = [[np.exp(-(axis_coords(wl.shape[ax]) - centres[k, ax]) ** 2 / s2) for ax in range(wl.dim)]
+         for k in range(wl.nbumps)]
+    slow = wl.dim - 1                     # x fastest in memory: the last axis is the slowest
+    F = np.stack([g[k][slow] for k in range(wl.nbumps)], axis=1)       # (n_slow, K)
+    R = []
     for k in range(wl.nbumps):
-        # separable Gaussian: prod_d exp(-(x_d - c_d)^2 / (2 w^2))
         f = None
-        for ax in reversed(range(wl.dim)):   # slowest axis first
-            g = np.exp(-(axis_coords(wl.shape[ax]) - centres[k, ax]) ** 2 / s2)
-            f = g if f is None else np.multiply.outer(f, g)
-        grid += amps[k] * f
-    return row
+        for ax in reversed(range(slow)):  # the remaining axes, slowest first
+            f = g[k][ax] if f is None else np.multiply.outer(f, g[k][ax])
+        R.append(amps[k] * f.ravel())
+    R = np.stack(R)                                                     # (K, rest)
+    grid = out.reshape(wl.shape[slow], -1)
+    step = max(1, (1 << 20) // grid.shape[1])
+    for s0 in range(0, grid.shape[0], step):
+        grid[s0:s0 + step] += F[s0:s0 + step] @ R
+    return out
 
 
 def j_rows(wl: Workload, i0: int = 0, i1: int | None = None, dtype=np.float64,
            threads: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
-    """Rows i0..i1-1 of J as a C-contiguous (i1-i0, N) array (row i = sensitivity i)."""
+    """Rows i0..i1-1 of J as a C-contiguous (i1-i0, N) array (row i = sensitivity i).
+    `out`, if given, is filled in place (FP64 rows, or any dtype through a
+    per-row FP64 buffer). The rows are drawn in parallel on `threads` threads
+    with the BLAS of each thread's small products kept single-threaded."""
     i1 = wl.m if i1 is None else i1
     if not (0 <= i0 <= i1 <= wl.m):
         raise ValueError("row range out of bounds")
     if out is None:
         out = np.empty((i1 - i0, wl.N), dtype=dtype)
     threads = threads or min(16, os.cpu_count() or 1)
+    direct = out.dtype == np.float64
 
     def fill(i):
-        out[i - i0] = _one_row(wl, i)
+        if direct:
+            _one_row(wl, i, out[i - i0])
+        else:
+            out[i - i0] = _one_row(wl, i)
 
-    if threads > 1 and i1 - i0 > 1:
-        with ThreadPoolExecutor(threads) as ex:
-            list(ex.map(fill, range(i0, i1)))
-    else:
-        for i in range(i0, i1):
-            fill(i)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"):
+        if threads > 1 and i1 - i0 > 1:
+            with ThreadPoolExecutor(threads) as ex:
+                list(ex.map(fill, range(i0, i1)))
+        else:
+            for i in range(i0, i1):
+                fill(i)
     return out
+
+
+def j_row_blocks(wl: Workload, block: int = 32, threads: int | None = None):
+    """Yield (i0, rows) for consecutive blocks of `block` rows of J, every row
+    once, in order. The rows are written into one host buffer that is reused
+    for every block, so a consumer must be done with a block before it asks
+    for the next (J of the 257^3 workload is 139 GB and is never held whole)."""
+    buf = np.empty((min(block, wl.m), wl.N), dtype=np.float64)
+    for i0 in range(0, wl.m, block):
+        i1 = min(wl.m, i0 + block)
+        yield i0, j_rows(wl, i0, i1, threads=threads, out=buf[:i1 - i0])
+
+
+def upload_j(wl: Workload, Jd, threads: int | None = None, block: int = 32, log=None):
+    """Fill the device tensor Jd (m x N, FP64, row-major) with J, block by
+    block through two pinned host buffers: a block is drawn into one buffer
+    while the previous one is copied to the device, so J is never held whole
+    on the host. Returns nothing; the copies have finished on return."""
+    import time
+    import torch
+    rows = min(block, wl.m)
+    bufs = [torch.empty((rows, wl.N), dtype=torch.float64, pin_memory=True) for _ in range(2)]
+    done = [None, None]
+    t0 = time.perf_counter()
+    for n, i0 in enumerate(range(0, wl.m, block)):
+        i1 = min(wl.m, i0 + block)
+        k = n % 2
+        if done[k] is not None:
+            done[k].synchronize()
+        j_rows(wl, i0, i1, threads=threads, out=bufs[k].numpy()[:i1 - i0])
+        Jd[i0:i1].copy_(bufs[k][:i1 - i0], non_blocking=True)
+        done[k] = torch.cuda.Event()
+        done[k].record()
+        if log is not None and n % 8 == 0:
+            log(f"J rows {i0}..{i1} on the device ({time.perf_counter() - t0:.0f} s)")
+    torch.cuda.synchronize()
+    del bufs
 
 
 def rhs_b(wl: Workload, k: int = 1) -> np.ndarray:

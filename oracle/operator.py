@@ -18,6 +18,8 @@ condition of Section 2.2 leaves constants in the kernel of the gradient part).
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -56,7 +58,15 @@ def lumped_mass(shape) -> sp.csr_matrix:
 
 
 def gram_operator(shape, beta: float) -> sp.csr_matrix:
-    """A = sum_d (K1 on axis d, W1 on the other axes) + beta*W  (CSR, float64)."""
+    """A = sum_d (K1 on axis d, W1 on the other axes) + beta*W  (CSR, float64).
+
+    The assembled matrix of the last few (shape, beta) pairs is kept (a 257^3
+    assembly takes tens of seconds); callers must not modify it."""
+    return _gram_operator(tuple(int(n) for n in shape), float(beta))
+
+
+@functools.lru_cache(maxsize=3)
+def _gram_operator(shape, beta):
     hs = spacing(shape)
     A = beta * lumped_mass(shape)
     for d in range(len(shape)):
