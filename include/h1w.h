@@ -115,6 +115,16 @@ typedef struct {
  * down to the coarsest, and back, run in one launch per V-cycle: the same
  * cycle with the same arithmetic, so the result is the same bit for bit. */
 #define H1W_FLAG_NO_VTAIL 8u
+/* grid_desc.flags, MIXED contexts only (EINVAL otherwise): form the product
+ * J Z^T of the capacitance (Algorithm 3, second step) on the FP32 matrix cores
+ * with FP32 operands (J rounded to FP32 as it is read) and FP32 accumulation
+ * over each K split of the GEMM, the splits then summed in FP64; the
+ * constant-mode terms and alpha*I stay FP64. Its error, about
+ * eps32 * sqrt(K / splits) * |J| |Z| per entry, breaks the consistency
+ * J (I - Z S^{-1} J) = alpha S^{-1} J that the Woodbury correction needs once
+ * ||S|| / alpha is large, so flexible CG slows down or stops converging as
+ * alpha falls. Off by default: S is accumulated in FP64. */
+#define H1W_FLAG_CAP_FP32_GEMM 16u
 
 /* Krylov options (h1w_gn_solve). A zeroed struct selects the defaults. */
 typedef struct {

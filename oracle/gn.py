@@ -166,6 +166,20 @@ def paper_update(shape, beta, J, alpha, d, res):
     return -d + Z.T @ np.linalg.solve(S, J @ d - res)
 
 
+def woodbury_operator(B, J, alpha, Z=None):
+    """The preconditioner apply r -> (1/alpha)(B r - Z S^{-1} J B r) as a
+    callable on (N,) vectors, with Z = B J^T (M x N; computed here unless
+    given: Z does not depend on alpha) and S = alpha*I + J Z^T factored once."""
+    Z = B(J) if Z is None else Z
+    S = alpha * np.eye(J.shape[0]) + J @ Z.T
+    lu = sla.lu_factor(S)
+
+    def apply(r):
+        y = B(r)
+        return (y - Z.T @ sla.lu_solve(lu, J @ y)) / alpha
+    return apply
+
+
 def woodbury_precond(B, J, alpha, R):
     """z = (1/alpha)(B r - Z S^{-1} J B r), Z = B J^T, S = alpha*I + J Z^T.
 

@@ -170,6 +170,7 @@ H1W_FLAG_STREAM_Z = 1
 H1W_FLAG_UNFUSED_VCYCLE = 2
 H1W_FLAG_GRAPH_VCYCLE = 4
 H1W_FLAG_NO_VTAIL = 8
+H1W_FLAG_CAP_FP32_GEMM = 16
 H1W_SOLVE_LAPLACE_ONLY = 1
 H1W_SOLVE_EXACT_B = 2
 H1W_OP_H1GRAM, H1W_OP_ERT = 0, 1

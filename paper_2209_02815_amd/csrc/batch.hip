@@ -23,7 +23,9 @@
 // then 2 smoothing steps per side, back to back on its own stream, twice over
 // (the faster of each candidate's two runs counts), and the later instances
 // of the key use nu = 1 or 3 only if its wall time is below 0.75 times that
-// of the default (the candidates are compared on the same
+// of the default; the losing candidates' contexts are dropped at once, so
+// that they do not push the contexts later batches use out of the worker's
+// cache (the candidates are compared on the same
 // system, so differences in m, alpha and iteration count between instances
 // do not enter; the margin covers the launches that a single solve's wall
 // time undercounts and the batch pays for). The last tuning solve
@@ -326,6 +328,15 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                         best = t_alt;
                     }
                     finish_tuning(tk, best_nu, best / work(i));
+                    // the losing candidates' contexts are not used again by
+                    // this key: dropped now (in the tuning call) rather than
+                    // by the LRU cap later, when a timed batch would pay for
+                    // re-creating what they pushed out
+                    for (int c = 0; c + 1 < kNumCandidates; ++c) {
+                        const int nu_c = kTuneCandidates[c];
+                        if (nu_c != best_nu && nu_c != nu_fixed)
+                            drop(GridKey{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c, it.beta, o.graphs != 0});
+                    }
                 }
             } catch (const Error& e) {
                 st = e.st;

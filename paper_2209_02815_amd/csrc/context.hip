@@ -130,8 +130,11 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     if (!ert) require(std::isfinite(d.beta) && d.beta > 0.0, "beta must be finite and > 0");
     require(d.precision == H1W_FP64 || d.precision == H1W_MIXED, "precision must be H1W_FP64 or H1W_MIXED");
     require(d.nu >= 0 && d.nu <= 16, "nu must be in [0, 16]");
-    require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE | H1W_FLAG_GRAPH_VCYCLE | H1W_FLAG_NO_VTAIL)) == 0,
+    require((d.flags & ~(H1W_FLAG_STREAM_Z | H1W_FLAG_UNFUSED_VCYCLE | H1W_FLAG_GRAPH_VCYCLE | H1W_FLAG_NO_VTAIL |
+                         H1W_FLAG_CAP_FP32_GEMM)) == 0,
             "unknown bits in flags");
+    require(!(d.flags & H1W_FLAG_CAP_FP32_GEMM) || d.precision == H1W_MIXED,
+            "H1W_FLAG_CAP_FP32_GEMM needs a MIXED context");
     graphs = (d.flags & H1W_FLAG_GRAPH_VCYCLE) != 0;
     require(d.coarse_max >= 0, "coarse_max must be >= 0");
     require(d.rhs_chunk >= 0 && d.rhs_chunk <= 65535, "rhs_chunk must be in [0, 65535]");
@@ -696,6 +699,9 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
             if (!fp32)
                 splits = launch_capacitance_partial<double>(stream, m, m, n, J, ldj, Zbuf.as<double>(), ldz, lower,
                                                             gpart.as<double>(), pe);
+            else if (d.flags & H1W_FLAG_CAP_FP32_GEMM)
+                splits = launch_capacitance_partial_f32acc(stream, m, m, n, J, ldj, Zbuf.as<float>(), ldz,
+                                                           gpart.as<double>(), pe);
             else
                 splits = launch_capacitance_partial<float>(stream, m, m, n, J, ldj, Zbuf.as<float>(), ldz, lower,
                                                            gpart.as<double>(), pe);

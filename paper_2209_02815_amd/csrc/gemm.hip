@@ -166,6 +166,124 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
             }
 }
 
+// FP32-accumulated variant (opt-in, MIXED contexts): the same work items and
+// K splits, but the operands are FP32 (J rounded to FP32 as it is loaded, Z
+// stored FP32) and the product runs on the FP32 matrix cores,
+// v_mfma_f32_16x16x4_f32, accumulating in FP32 over the work-group's whole K
+// range; only the split partials are summed in FP64 (k_cap_reduce). The
+// result differs from J Z^T by about eps32 * sqrt(K range) * |J||Z| per entry,
+// which the Woodbury correction cannot absorb when ||S|| / alpha is large:
+// the mode exists to measure that, the FP64-accumulated product is the default.
+// Accumulator layout of the FP32 16x16 block: lane l, element v holds row
+// 4 (l/16) + v, column l%16 (the FP64 block above has row (l/16) + 4v).
+// K is consumed in chunks of 32 (one 128-byte FP32 row segment); loader
+// mapping: thread t owns column k = t % 32 of rows t/32 + 8u (u = 0..15).
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int KB32 = 32;
+constexpr int LDT32 = KB32 + 1;  // LDS row stride (floats)
+
+__global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm32(int m, int m2, int64_t N,
+                                                                const double* __restrict__ J, int64_t ldj,
+                                                                const float* __restrict__ Z, int64_t ldz, int T2,
+                                                                int ntile, int total, int64_t kper,
+                                                                double* __restrict__ partial) {
+    __shared__ float sA[2][kTileMN * LDT32];
+    __shared__ float sB[2][kTileMN * LDT32];
+    const int bid = blockIdx.x;
+    const int per = (total + 7) / 8;
+    const int u = (bid & 7) * per + (bid >> 3);
+    if (u >= total) return;
+    const int split = u / ntile;
+    const int tile = u - split * ntile;
+    const int tr = tile / T2, tc = tile - (tile / T2) * T2;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int arow0 = tr * kTileMN, brow0 = tc * kTileMN;
+
+    const int lk = tid & 31, lr = tid >> 5;
+    const double* pa[16];
+    const float* pb[16];
+    bool va[16], vb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = arow0 + lr + 8 * q;
+        va[q] = r < m;
+        pa[q] = J + (int64_t)(va[q] ? r : 0) * ldj;
+        const int c = brow0 + lr + 8 * q;
+        vb[q] = c < m2;
+        pb[q] = Z + (int64_t)(vb[q] ? c : 0) * ldz;
+    }
+    const int64_t k0 = (int64_t)split * kper;
+    const int64_t k1 = std::min<int64_t>(N, k0 + kper);
+    const int nchunk = (int)((k1 - k0 + KB32 - 1) / KB32);
+    float ra[16], rb[16];
+    auto gload = [&](int c) {
+        const int64_t k = k0 + (int64_t)c * KB32 + lk;
+        const bool in = k < k1;
+        const int64_t kc = in ? k : k0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const float x = (float)pa[q][kc];
+            ra[q] = (va[q] && in) ? x : 0.0f;
+            const float y = pb[q][kc];
+            rb[q] = (vb[q] && in) ? y : 0.0f;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            sA[buf][(lr + 8 * q) * LDT32 + lk] = ra[q];
+            sB[buf][(lr + 8 * q) * LDT32 + lk] = rb[q];
+        }
+    };
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (nchunk > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunk) gload(c + 1);
+        const float* A = sA[buf];
+        const float* B = sB[buf];
+#pragma unroll
+        for (int s4 = 0; s4 < KB32 / 4; ++s4) {
+            const int kk = 4 * s4 + g;
+            float a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a[r] = A[(wr + 16 * r + l16) * LDT32 + kk];
+                b[r] = B[(wc + 16 * r + l16) * LDT32 + kk];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc)
+                    acc[r][cc] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b[cc], acc[r][cc], 0, 0, 0);
+        }
+        if (c + 1 < nchunk) lstore(buf ^ 1);
+        __syncthreads();
+    }
+    double* P = partial + (int64_t)split * m * m2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = arow0 + wr + r * 16 + 4 * g + v;
+                const int col = brow0 + wc + c * 16 + l16;
+                if (row < m && col < m2) P[(int64_t)row * m2 + col] = (double)acc[r][c][v];
+            }
+}
+
 // S[i][j] (block of m x m2 at S, leading dimension lds) = sum over splits of
 // the partials (+ alpha on the block diagonal i == j). lower: the square
 // product was computed on and below the diagonal only; S[i][j] for i < j is
@@ -249,6 +367,19 @@ int launch_capacitance_partial(hipStream_t s, int m, int m2, int64_t N, const do
     const int grid = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL((k_cap_gemm<TZ>), dim3(grid), dim3(kGemmThreads), 0, s, m, m2, N, J, ldj, Z, ldz, p.T, p.T2,
                        p.ntile, (int)lower_only, total, p.kper, partial);
+    H1W_LAUNCHED();
+    return p.splits;
+}
+
+int launch_capacitance_partial_f32acc(hipStream_t s, int m, int m2, int64_t N, const double* J, int64_t ldj,
+                                      const float* Z, int64_t ldz, double* partial, size_t partial_elems) {
+    if (m <= 0 || m2 <= 0) return 0;
+    const GemmPlan p = plan(m, m2, N, false);
+    if ((size_t)p.splits * m * m2 > partial_elems) throw Error{H1W_EINVAL, "internal: GEMM partial buffer too small"};
+    const int total = p.ntile * p.splits;
+    const int grid = 8 * ((total + 7) / 8);
+    hipLaunchKernelGGL(k_cap_gemm32, dim3(grid), dim3(kGemmThreads), 0, s, m, m2, N, J, ldj, Z, ldz, p.T2, p.ntile,
+                       total, p.kper, partial);
     H1W_LAUNCHED();
     return p.splits;
 }

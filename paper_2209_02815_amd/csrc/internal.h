@@ -264,6 +264,11 @@ template <typename TZ>
 int launch_capacitance_partial(hipStream_t s, int m, int m2, int64_t N, const double* J, int64_t ldj,
                                const TZ* Z, int64_t ldz, bool lower_only, double* partial,
                                size_t partial_elems);
+// the same product with FP32 operands (J rounded on load) on the FP32 matrix
+// cores, FP32 accumulation within each K split, splits summed in FP64 by the
+// reduce kernel (opt-in H1W_FLAG_CAP_FP32_GEMM)
+int launch_capacitance_partial_f32acc(hipStream_t s, int m, int m2, int64_t N, const double* J, int64_t ldj,
+                                      const float* Z, int64_t ldz, double* partial, size_t partial_elems);
 void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const double* partial, bool lower_only,
                                double alpha, double* S, int64_t lds);
 void launch_mirror_lower(hipStream_t s, int m, double* S);

