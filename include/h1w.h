@@ -264,6 +264,20 @@ h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
 h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha,
                         const double* x, double* y);
 
+/* y = G x as h1w_gn_apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no allocation, no memset and no host synchronisation happen in
+ * the call. Its scratch (the m-vector J x and the partial sums of the J x
+ * pass) lives in a static device array of 32 MiB that the library holds on
+ * every GPU it runs on until the process ends; sizes that need more,
+ * m * ceil(N / 2048) + (m rounded up to 32) > 4194304 doubles, return EINVAL
+ * (m <= 3994 at 129^3, m <= 505 at 257^3). Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU race. The work is enqueued on the
+ * context's stream and y is valid once that stream has synchronised. Arguments
+ * and errors as h1w_gn_apply; J and y must not overlap. */
+h1w_status h1w_gn_apply_noalloc(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha,
+                                const double* x, double* y);
+
 /* ---------------------------------------------------------------- kernel timing
  * Optional per-kernel-class timing with HIP events recorded on the context's
  * stream around every launch of the selected classes (bit (1 << class) in

@@ -27,7 +27,7 @@ EXPORTED = [
     "h1w_operator_apply", "h1w_poisson_solve_batched", "h1w_capacitance_build",
     "h1w_precond_apply", "h1w_gn_solve", "h1w_gn_apply", "h1w_ert_sensitivities",
     "h1w_set_kernel_timing", "h1w_get_kernel_timing", "h1w_reset_kernel_timing", "h1w_batch_solve",
-    "h1w_ert_set_conductivity", "h1w_ert_vjp", "h1w_ert_gn_step",
+    "h1w_ert_set_conductivity", "h1w_ert_vjp", "h1w_ert_gn_step", "h1w_gn_apply_noalloc",
 ]
 
 
@@ -108,6 +108,7 @@ def _load():
         "h1w_precond_apply": (I, [P, I, P, I64, P, I64, I]),
         "h1w_gn_solve": (I, [P, I, P, I64, D, P, P, P, P, C.POINTER(h1w_solve_opts), C.POINTER(h1w_info)]),
         "h1w_gn_apply": (I, [P, I, P, I64, D, P, P]),
+        "h1w_gn_apply_noalloc": (I, [P, I, P, I64, D, P, P]),
         "h1w_ert_sensitivities": (I, [P, P, I, P, I, P, P, P, P, I64, P, I64, C.POINTER(h1w_solve_opts),
                                       C.POINTER(h1w_info)]),
         "h1w_ert_set_conductivity": (I, [P, P]),
@@ -269,6 +270,15 @@ def h1w_gn_apply(ctx, J, alpha: float, x, y):
     N, _ = h1w_get_sizes(ctx)
     m, ldj = (0, N) if J is None else _rows(J, N, "J")
     _check(ctx, lib.h1w_gn_apply(ctx, m, _ptr(J), ldj, float(alpha), _ptr(x), _ptr(y)))
+    return y
+
+
+def h1w_gn_apply_noalloc(ctx, J, alpha: float, x, y):
+    """y = G x with the library's static device scratch (no allocation, no
+    synchronisation: y is valid once the context's stream has synchronised)."""
+    N, _ = h1w_get_sizes(ctx)
+    m, ldj = (0, N) if J is None else _rows(J, N, "J")
+    _check(ctx, lib.h1w_gn_apply_noalloc(ctx, m, _ptr(J), ldj, float(alpha), _ptr(x), _ptr(y)))
     return y
 
 

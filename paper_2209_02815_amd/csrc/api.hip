@@ -148,6 +148,9 @@ h1w_status h1w_setup(const h1w_grid_desc* desc, void* hip_stream, h1w_ctx** out)
         delete ctx;
         return st;
     }
+    // the address of the static scratch of h1w_gn_apply_noalloc on this
+    // device (a failure here is reported by that entry point's first call)
+    h1w::noalloc_init_device();
     *out = ctx;
     return H1W_OK;
 }
@@ -348,6 +351,33 @@ h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
         c.ensure_cg_ws(m);
         c.gn_apply(m, J, ldj, alpha, x, y);
         c.sync();
+    });
+}
+
+h1w_status h1w_gn_apply_noalloc(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha, const double* x,
+                                double* y) {
+    if (!ctx) return H1W_EINVAL;
+    return guarded(ctx, [&] {
+        auto& c = ctx->c;
+        require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
+        const int64_t n = c.N();
+        require(m >= 0, "m must be >= 0");
+        h1w::noalloc_require_fits(m, n);
+        if (m > 0) {
+            need_ptr(J, 8, "J");
+            require(ldj >= n, "ldj must be >= N");
+        }
+        require(std::isfinite(alpha), "alpha must be finite");
+        need_ptr(x, 8, "x");
+        need_ptr(y, 8, "y");
+        require(!overlap(x, n, y, n, 1, n, 8), "x and y overlap");
+        if (m > 0) {  // J (m rows of pitch ldj) against y (one row of N)
+            const char* j0 = reinterpret_cast<const char*>(J);
+            const char* j1 = j0 + ((int64_t)(m - 1) * ldj + n) * 8;
+            const char* y0 = reinterpret_cast<const char*>(y);
+            require(!(j0 < y0 + n * 8 && y0 < j1), "J and y overlap");
+        }
+        c.gn_apply_noalloc(m, J, ldj, alpha, x, y);
     });
 }
 

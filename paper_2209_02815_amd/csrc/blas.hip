@@ -171,12 +171,12 @@ __global__ __launch_bounds__(kBlock) void k_jt_u_t(int m, int64_t N, const doubl
     }
 }
 
-// out = J^T v + add_coef * add   (add may be null)
+// out = J^T v + add_coef * add   (add may be null, or equal to out: each
+// thread reads add[n] before it writes out[n], so out and add carry no
+// __restrict__)
 __global__ __launch_bounds__(kBlock) void k_jt_plain(int m, int64_t N, const double* __restrict__ J,
                                                      int64_t ldj, const double* __restrict__ v,
-                                                     double* __restrict__ out,
-                                                     const double* __restrict__ add,
-                                                     double add_coef) {
+                                                     double* out, const double* add, double add_coef) {
     __shared__ double sv[kTile];
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double acc = 0.0;

@@ -163,6 +163,9 @@ struct Ctx {
     void precond_one(const double* r, double* z, int zmode);
     void precond_apply(int k, const double* R, int64_t ldr, double* Zout, int64_t ldz, int zmode);
     void gn_apply(int m, const double* J, int64_t ldj, double alpha, const double* x, double* y);
+    // the same product with its scratch in the library's static device array
+    // (no allocation; noalloc.hip)
+    void gn_apply_noalloc(int m, const double* J, int64_t ldj, double alpha, const double* x, double* y);
     void gn_solve(int m, const double* J, int64_t ldj, double alpha, const double* b, const double* d,
                   const double* res, double* x, const h1w_solve_opts& o, h1w_info* info);
 

@@ -184,6 +184,11 @@ void launch_reduce_parts(hipStream_t s, int nvec, int nparts, const double* part
 int launch_rows_dot_partial(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm,
                             const double* v, double* partial);  // returns #chunks
 size_t rows_dot_partial_elems(int m, int64_t N);
+// noalloc.hip: the static device scratch of h1w_gn_apply_noalloc (its
+// address taken once per device; elements it needs for m rows on N nodes)
+void noalloc_init_device();
+size_t noalloc_scratch_elems(int m, int64_t N);
+void noalloc_require_fits(int m, int64_t N);  // EINVAL beyond the array's size
 // transpose products, see blas.hip for the epilogue modes
 void launch_jt_u_t(hipStream_t s, int m, int64_t N, const double* J, int64_t ldj,
                    const double* w, const double* jp, const double* r, double inv_alpha,
