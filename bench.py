@@ -53,6 +53,13 @@ def parse():
                     help="skip the comparison solve modes (Laplace-only and exact-B preconditioners)")
     ap.add_argument("--no-ert", action="store_true",
                     help="skip the ERT survey (65^3 forward map, J, GN solve and two Gauss-Newton steps)")
+    ap.add_argument("--batch-profile", action="store_true",
+                    help="only the batch of 256 uneven 2D instances, with one worker, nu = 2, FP64 then mixed, "
+                         "two calls each (the batch's kernels under a tracer without concurrent workers); "
+                         "prints a JSON line of its own")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from the counter CSVs of two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this script with --calibrate-copy on --workload, and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of 1 GiB (a kernel of known size for PMC counter scaling)")
     return ap.parse_args()
@@ -79,7 +86,10 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix
 
 
 # functions whose source text decides the PMC traffic recorded for a class
-TRAFFIC_SOURCES = {"jv": ("blas.hip", ["k_rows_dot", "launch_rows_dot_partial"])}
+TRAFFIC_SOURCES = {"jv": ("blas.hip", ["k_rows_dot", "launch_rows_dot_partial"]),
+                   "gemm": ("gemm.hip", ["k_cap_gemm", "plan", "launch_capacitance_partial"])}
+# kernel symbol (prefix of the demangled name) of each class in a PMC trace
+TRAFFIC_SYMBOLS = {"jv": "k_rows_dot<double>", "gemm": "k_cap_gemm<double>"}
 
 
 def _function_text(src: str, name: str) -> str:
@@ -124,14 +134,69 @@ def roofline(cls: str, st: dict) -> dict:
         peak, unit = PEAK_HBM_GBS, "GB/s"
     traffic = None
     tp = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tp):
-        t = json.load(open(tp))
-        if cls in TRAFFIC_SOURCES and t.get("class") == cls and t.get("source_sha") == source_sha(cls):
+    if os.path.exists(tp) and cls in TRAFFIC_SOURCES:
+        t = json.load(open(tp)).get("classes", {}).get(cls)
+        if t and t.get("source_sha") == source_sha(cls):
             traffic = t.get("traffic_bytes_per_launch")
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": traffic, "kernel": cls, "symbol": KERNELS[cls][1], "launches": st["launches"],
             "avg_launch_us": 1e3 * avg_ms, "algorithmic_bytes_per_launch": st["bytes"] / st["launches"],
             "algorithmic_flops_per_launch": st["flops"] / st["launches"]}
+
+
+def write_traffic(fetch_csv, write_csv, workload):
+    """profiles/traffic.json from two rocprofv3 --pmc runs of bench.py on
+    `workload` with --calibrate-copy (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch): the counters of the 1 GiB device copy give the scale factors,
+    and each class's traffic per launch is the mean over its dispatches in the
+    FP64 solves, next to the algorithmic bytes per launch of those dispatches
+    (the workload's m and N)."""
+    import csv
+    import h1w_inputs as H
+    wl = H.workload(workload)
+
+    def load(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            key = int(r["Dispatch_Id"])
+            name = r["Kernel_Name"].replace("void ", "").replace("h1w::(anonymous namespace)::", "")
+            e = out.setdefault(key, {"name": name, "grid": int(r["Grid_Size"]), "v": 0.0})
+            e["v"] += float(r["Counter_Value"])
+        return out
+
+    fet, wri = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    copy = lambda d: max((e for e in d.values() if e["name"].startswith("__amd_rocclr_copyBuffer")),
+                         key=lambda e: e["v"])
+    gib = float(1 << 30)
+    ff = gib / 1024.0 / copy(fet)["v"]
+    wf = gib / 1024.0 / copy(wri)["v"]
+    classes = {}
+    for cls, sym in TRAFFIC_SYMBOLS.items():
+        fs = [e["v"] for e in fet.values() if e["name"].startswith(sym)]
+        ws = [e["v"] for e in wri.values() if e["name"].startswith(sym)]
+        if not fs or not ws:
+            continue
+        fk, wk = sum(fs) / len(fs), sum(ws) / len(ws)
+        if cls == "jv":
+            alg = 8.0 * wl.m * wl.N + 8.0 * wl.N
+        else:  # the streamed lower-triangle product in row blocks: J rows below the block and the Z block
+            alg = None
+        classes[cls] = {"symbol": sym, "source_sha": source_sha(cls), "dispatches": len(fs),
+                        "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+                        "traffic_bytes_per_launch": 1024.0 * (fk * ff + wk * wf),
+                        "algorithmic_bytes_per_launch": alg}
+    out = {"workload": workload, "copy_calibration": {"fetch_factor": ff, "write_factor": wf,
+                                                      "kernel": "__amd_rocclr_copyBuffer of the 1 GiB device copy"},
+           "classes": classes,
+           "command": (f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmcF "
+                       f"-o run -- python3 <repo>/bench.py --workload {workload} --steps 1 --warmup 1 --profile-steps 1 "
+                       f"--no-mixed --no-batch --no-compare --no-ert --no-cpu-baseline --calibrate-copy ; the same with "
+                       f"--pmc WRITE_SIZE into <out>/pmcW ; python3 <repo>/bench.py --write-traffic "
+                       f"<out>/pmcF/run_counter_collection.csv <out>/pmcW/run_counter_collection.csv")}
+    json.dump(out, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    return out
 
 
 def time_solves(ctx, Jd, alpha, bd, xd, steps, warmup, profile_steps, rtol):
@@ -360,6 +425,35 @@ def batch_bench(args, threads):
     return out
 
 
+def batch_profile(args, threads):
+    """The batch workload with one worker (no overlap between instances), nu = 2
+    fixed, FP64 then mixed, two calls each: the run a kernel tracer records for
+    the batch's kernels."""
+    import torch
+    import h1w_inputs as H
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads()
+    items = []
+    for wl in wls:
+        items.append(dict(shape=wl.shape, beta=wl.beta, alpha=wl.alpha,
+                          J=torch.from_numpy(H.j_rows(wl, threads=threads)).to("cuda:0"),
+                          b=torch.from_numpy(H.rhs_b(wl)).to("cuda:0"),
+                          x=torch.zeros(wl.N, dtype=torch.float64, device="cuda:0")))
+    torch.cuda.synchronize()
+    out = {"workload": f"{len(wls)} 2D instances (batch workload), one worker, nu = 2"}
+    for label, prec in (("fp64", nat.H1W_FP64), ("mixed", nat.H1W_MIXED)):
+        times = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            infos, _, _ = nat.h1w_batch_solve(items, precision=prec, nworkers=1, autotune=0, rtol=args.rtol)
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - t0))
+        out[label] = {"ms_calls": [round(t, 2) for t in times], "iters_total": int(sum(i.iters for i in infos)),
+                      "worst_relres_true": max(i.relres_true for i in infos)}
+        log(f"batch profile {label}: {out[label]}")
+    return out
+
+
 def grid_text(shape) -> str:
     """'3D 129^3' for a cube, '2D 129x65' otherwise."""
     if len(set(shape)) == 1:
@@ -404,6 +498,15 @@ def main():
     import h1w_inputs as H
     import paper_2209_02815_amd as P
 
+    if args.write_traffic:
+        print(json.dumps(write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload)), flush=True)
+        return
+
+    if args.batch_profile:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        print(json.dumps({"batch_profile": batch_profile(args, threads)}), flush=True)
+        return
+
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
@@ -436,9 +539,32 @@ def main():
             "iters": int(np.median([i["iters"] for i in infos])), "relres_true": rr,
             "t_zbuild_ms": med("t_zbuild_ms"), "t_gemm_ms": med("t_gemm_ms"), "t_factor_ms": med("t_factor_ms"),
             "t_cg_ms": med("t_cg_ms"), "t_total_ms": med("t_total_ms"), "factor": infos[-1]["factor_used"],
-            "zmode": infos[-1]["zmode_used"], "roofline": roof, "kernel_time_share": shares,
+            "zmode": infos[-1]["zmode_used"], "restarts": infos[-1]["restarts"],
+            "kappa_S_est": infos[-1]["kappa_S_est"], "s_max_over_alpha": infos[-1]["s_max_over_alpha"],
+            "roofline": roof, "kernel_time_share": shares,
         }
         log(f"{mode}: {results[mode]}")
+    # the opt-in FP32-accumulated capacitance product on the same system: one
+    # solve after one warmup, at most 60 flexible-CG iterations (its Woodbury
+    # correction degrades as max S_ii / alpha grows; the status says whether it
+    # still reached the tolerance)
+    fp32gemm = None
+    if not args.no_mixed:
+        with P.Context(wl.shape, wl.beta, precision="mixed", cap_fp32_gemm=True) as ctx:
+            fp32gemm = {}
+            try:
+                ctx.gn_solve(Jd, wl.alpha, b=bd, x=xd, rtol=args.rtol, maxit=60)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = ctx.gn_solve(Jd, wl.alpha, b=bd, x=xd, rtol=args.rtol, maxit=60)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                fp32gemm = {"status": "ok", "solves_per_s": 1.0 / dt, "iters": info.iters,
+                            "relres_true": info.relres_true, "t_gemm_ms": info.t_gemm_ms,
+                            "t_cg_ms": info.t_cg_ms, "s_max_over_alpha": info.s_max_over_alpha}
+            except P._native.H1WError as e:
+                fp32gemm = {"status": f"failed: {e}"}
+        log(f"mixed with the FP32-accumulated capacitance product: {fp32gemm}")
     del Jd, xd
     torch.cuda.empty_cache()
 
@@ -496,6 +622,7 @@ def main():
         "fp64": r64,
         "mixed": rmx,
         "mixed_over_fp64": (rmx["solves_per_s"] / r64["solves_per_s"]) if rmx else None,
+        "mixed_fp32_gemm": fp32gemm,
         "comparison_modes": compare,
         "batch": batch,
         "ert": ert,

@@ -175,6 +175,11 @@ typedef struct {
     double t_cg_ms;          /* Krylov loop including the final true residual */
     double t_total_ms;       /* whole call */
     double asym_S_over_alpha;/* max |S - S^T| / alpha (full GEMM only, else 0) */
+    double kappa_S_est;      /* estimate of cond(S) from the pivots u_ii of its factor:
+                                (max u_ii / min u_ii)^2 for Cholesky, max |u_ii| / min |u_ii|
+                                for LU (a lower estimate) */
+    double s_max_over_alpha; /* max_i S_ii / alpha: the factor by which rounding errors in S
+                                are amplified in the Woodbury correction */
 } h1w_info;
 
 /* Create a context for one grid: builds the multigrid hierarchy, the dense

@@ -48,7 +48,8 @@ class h1w_info(C.Structure):
                 ("failed_pivot", C.c_int), ("nlevels", C.c_int), ("restarts", C.c_int),
                 ("relres_true", C.c_double), ("relres_rec", C.c_double),
                 ("t_zbuild_ms", C.c_double), ("t_gemm_ms", C.c_double), ("t_factor_ms", C.c_double),
-                ("t_cg_ms", C.c_double), ("t_total_ms", C.c_double), ("asym_S_over_alpha", C.c_double)]
+                ("t_cg_ms", C.c_double), ("t_total_ms", C.c_double), ("asym_S_over_alpha", C.c_double),
+                ("kappa_S_est", C.c_double), ("s_max_over_alpha", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1,6 +1,10 @@
 // C ABI entry points (include/h1w.h): argument validation on the host,
 // translation of internal errors to status codes; no exception crosses the ABI.
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -14,21 +18,43 @@ namespace {
 
 thread_local std::string g_setup_error;
 
+// H1W_TRACE=1 in the environment: one line per entry-point call on stderr
+// (name, context, status, host wall time, and the error message on failure)
+bool trace_on() {
+    static const bool on = [] {
+        const char* v = std::getenv("H1W_TRACE");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+h1w_status traced(const char* name, const h1w_ctx* ctx, h1w_status st,
+                  std::chrono::steady_clock::time_point t0) {
+    if (trace_on()) {
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "[h1w] %s ctx=%p status=%d %.3f ms%s%s\n", name, (const void*)ctx, (int)st, ms,
+                     st != H1W_OK && ctx ? " : " : "", st != H1W_OK && ctx ? ctx->c.err.c_str() : "");
+    }
+    return st;
+}
+
 template <typename Fn>
-h1w_status guarded(h1w_ctx* ctx, Fn&& fn) {
+h1w_status guarded(const char* name, h1w_ctx* ctx, Fn&& fn) {
+    const auto t0 = std::chrono::steady_clock::now();
     try {
         fn();
         if (ctx) ctx->c.err.clear();
-        return H1W_OK;
+        return traced(name, ctx, H1W_OK, t0);
     } catch (const h1w::Error& e) {
         if (ctx) ctx->c.err = e.msg;
-        return e.st;
+        return traced(name, ctx, e.st, t0);
     } catch (const std::bad_alloc&) {
         if (ctx) ctx->c.err = "host allocation failed";
-        return H1W_ENOMEM;
+        return traced(name, ctx, H1W_ENOMEM, t0);
     } catch (const std::exception& e) {
         if (ctx) ctx->c.err = e.what();
-        return H1W_EINVAL;
+        return traced(name, ctx, H1W_EINVAL, t0);
     }
 }
 
@@ -142,7 +168,7 @@ h1w_status h1w_setup(const h1w_grid_desc* desc, void* hip_stream, h1w_ctx** out)
         g_setup_error = "host allocation failed";
         return H1W_ENOMEM;
     }
-    const h1w_status st = guarded(ctx, [&] { ctx->c.init(*desc, static_cast<hipStream_t>(hip_stream)); });
+    const h1w_status st = guarded(__func__, ctx, [&] { ctx->c.init(*desc, static_cast<hipStream_t>(hip_stream)); });
     if (st != H1W_OK) {
         g_setup_error = ctx->c.err;
         delete ctx;
@@ -172,7 +198,7 @@ h1w_status h1w_get_sizes(const h1w_ctx* ctx, int64_t* N, int* nlevels) {
 
 h1w_status h1w_operator_apply(h1w_ctx* ctx, int k, const void* X, int64_t ldx, void* Y, int64_t ldy, int dtype) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         const int64_t n = c.N();
         require(k >= 0, "k must be >= 0");
@@ -209,7 +235,7 @@ h1w_status h1w_poisson_solve_batched(h1w_ctx* ctx, int k, const void* F, int64_t
     if (!ctx) return H1W_EINVAL;
     if (info) *info = h1w_info{};
     if (info) info->failed_pivot = -1;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         const int64_t n = c.N();
         require(k >= 0, "k must be >= 0");
@@ -249,7 +275,7 @@ h1w_status h1w_capacitance_build(h1w_ctx* ctx, int m, const double* J, int64_t l
         *info = h1w_info{};
         info->failed_pivot = -1;
     }
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
@@ -288,7 +314,7 @@ h1w_status h1w_capacitance_build(h1w_ctx* ctx, int m, const double* J, int64_t l
 h1w_status h1w_precond_apply(h1w_ctx* ctx, int k, const double* R, int64_t ldr, double* Zout, int64_t ldz,
                              int zmode) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
@@ -309,7 +335,7 @@ h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
         *info = h1w_info{};
         info->failed_pivot = -1;
     }
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
@@ -335,7 +361,7 @@ h1w_status h1w_gn_solve(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
 h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha, const double* x,
                         double* y) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
@@ -357,7 +383,7 @@ h1w_status h1w_gn_apply(h1w_ctx* ctx, int m, const double* J, int64_t ldj, doubl
 h1w_status h1w_gn_apply_noalloc(h1w_ctx* ctx, int m, const double* J, int64_t ldj, double alpha, const double* x,
                                 double* y) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(!c.ert, "this entry point needs an H1 Gram context (op = H1W_OP_H1GRAM)");
         const int64_t n = c.N();
@@ -383,7 +409,7 @@ h1w_status h1w_gn_apply_noalloc(h1w_ctx* ctx, int m, const double* J, int64_t ld
 
 h1w_status h1w_set_kernel_timing(h1w_ctx* ctx, unsigned mask) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         ctx->c.flush_timing();
         ctx->c.tmask = mask & ((1u << H1W_K_NCLASS) - 1);
     });
@@ -391,7 +417,7 @@ h1w_status h1w_set_kernel_timing(h1w_ctx* ctx, unsigned mask) {
 
 h1w_status h1w_get_kernel_timing(h1w_ctx* ctx, int kclass, h1w_kstat* out) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         require(kclass >= 0 && kclass < H1W_K_NCLASS, "kclass out of range");
         require(out != nullptr, "out is NULL");
         ctx->c.flush_timing();
@@ -401,7 +427,7 @@ h1w_status h1w_get_kernel_timing(h1w_ctx* ctx, int kclass, h1w_kstat* out) {
 
 h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         ctx->c.flush_timing();
         for (auto& s : ctx->c.kst) s = h1w_kstat{};
     });
@@ -447,7 +473,7 @@ h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_bat
 
 h1w_status h1w_ert_set_conductivity(h1w_ctx* ctx, const double* logsig) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(c.ert, "h1w_ert_set_conductivity needs an ERT context (op = H1W_OP_ERT)");
         need_ptr(logsig, 8, "logsig");
@@ -463,7 +489,7 @@ h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double* logsig, int n_src, 
         *info = h1w_info{};
         info->failed_pivot = -1;
     }
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(c.ert, "h1w_ert_sensitivities needs an ERT context (op = H1W_OP_ERT)");
         const int64_t n = c.N();
@@ -520,7 +546,7 @@ h1w_status h1w_ert_sensitivities(h1w_ctx* ctx, const double* logsig, int n_src, 
 h1w_status h1w_ert_vjp(h1w_ctx* ctx, int n_src, const int* src_node, const double* U, int64_t ldu, int n_meas,
                        const int* pair, const double* kgeo, const double* gbar, double* grad) {
     if (!ctx) return H1W_EINVAL;
-    return guarded(ctx, [&] {
+    return guarded(__func__, ctx, [&] {
         auto& c = ctx->c;
         require(c.ert, "h1w_ert_vjp needs an ERT context (op = H1W_OP_ERT)");
         if (!c.ert_ready) throw h1w::Error{H1W_ESTATE, "no conductivity set"};
@@ -561,7 +587,7 @@ h1w_status h1w_ert_gn_step(h1w_ctx* ert, h1w_ctx* h1, double* m, const double* m
         *info = h1w_info{};
         info->failed_pivot = -1;
     }
-    return guarded(h1, [&] {
+    return guarded(__func__, h1, [&] {
         auto& E = ert->c;
         auto& G = h1->c;
         require(E.ert, "the first context must be an ERT context");

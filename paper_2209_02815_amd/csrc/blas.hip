@@ -51,51 +51,50 @@ __global__ __launch_bounds__(kBlock) void k_reduce_parts(int nparts, const doubl
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// partial[i*nchunk + c] = sum over chunk c of M[i, n] v[n], rows i of this block.
-// The block's kRowsPerBlock rows are accumulated back to back (loads of every
-// row in flight, no barrier between rows) and reduced together at the end, in
-// a fixed order (wave sums, then the 4 waves in order).
+// partial[i*nchunk + c] = sum over chunk c of M[i, n] v[n] for every row i.
+// One block per chunk of kRowChunk nodes walks all m rows: each wave takes
+// rows wid, wid + 4, ... and reduces each row's chunk itself (lane l holds
+// nodes c0 + 2 l + 128 e, e < 16, as 16-byte pairs; fixed order: lane sums
+// over e, then the wave sum), so v's slice is read once per chunk and every
+// row piece is a 16 KB (FP64) run.
 template <typename TM>
 __global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const TM* __restrict__ M,
                                                      int64_t ldm, const double* __restrict__ v,
                                                      double* __restrict__ partial) {
-    __shared__ double sh[kRowsPerBlock][kBlock / 64];
+    constexpr int E = kRowChunk / 128;  // node pairs per lane
     const int nchunk = gridDim.x;
     const int64_t base = (int64_t)blockIdx.x * kRowChunk;
-    constexpr int E = kRowChunk / kBlock;
-    double vv[E];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double v0[E], v1[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int64_t n = base + e * kBlock + threadIdx.x;
-        vv[e] = n < N ? v[n] : 0.0;
+        const int64_t n = base + 128 * e + 2 * lane;
+        v0[e] = n < N ? v[n] : 0.0;
+        v1[e] = n + 1 < N ? v[n + 1] : 0.0;
     }
-    const int r0 = blockIdx.y * kRowsPerBlock;
-    double acc[kRowsPerBlock];
+    const bool tail = base + kRowChunk > N;
+    for (int i = wid; i < m; i += kBlock / 64) {
+        const TM* row = M + (int64_t)i * ldm;
+        double acc = 0.0;
+        if (!tail) {
 #pragma unroll
-    for (int rr = 0; rr < kRowsPerBlock; ++rr) {
-        acc[rr] = 0.0;
-        const TM* row = M + (int64_t)min(r0 + rr, m - 1) * ldm;
+            for (int e = 0; e < E; ++e) {
+                const int64_t n = base + 128 * e + 2 * lane;
+                acc = fma(double(row[n]), v0[e], acc);
+                acc = fma(double(row[n + 1]), v1[e], acc);
+            }
+        } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int64_t n = base + e * kBlock + threadIdx.x;
-            if (n < N) acc[rr] += double(row[n]) * vv[e];
+            for (int e = 0; e < E; ++e) {
+                const int64_t n = base + 128 * e + 2 * lane;
+                const double x0 = n < N ? double(row[n]) : 0.0;
+                const double x1 = n + 1 < N ? double(row[n + 1]) : 0.0;
+                acc = fma(x0, v0[e], acc);
+                acc = fma(x1, v1[e], acc);
+            }
         }
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int rr = 0; rr < kRowsPerBlock; ++rr) {
-        const double t = wave_sum(acc[rr]);
-        if (lane == 0) sh[rr][wid] = t;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < kRowsPerBlock) {
-        const int i = r0 + threadIdx.x;
-        if (i < m) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) t += sh[threadIdx.x][w];
-            partial[(int64_t)i * nchunk + blockIdx.x] = t;
-        }
+        acc = wave_sum(acc);
+        if (lane == 0) partial[(int64_t)i * nchunk + blockIdx.x] = acc;
     }
 }
 
@@ -443,8 +442,7 @@ int launch_rows_dot_partial(hipStream_t s, int m, int64_t N, const double* M, in
                             double* partial) {
     const int nchunk = (int)cdiv(N, kRowChunk);
     if (m <= 0) return nchunk;
-    const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
-    hipLaunchKernelGGL((k_rows_dot<double>), grid, dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
+    hipLaunchKernelGGL((k_rows_dot<double>), dim3(nchunk), dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
     H1W_LAUNCHED();
     return nchunk;
 }
@@ -453,8 +451,7 @@ int launch_rows_dot_partial_f32(hipStream_t s, int m, int64_t N, const float* M,
                                 double* partial) {
     const int nchunk = (int)cdiv(N, kRowChunk);
     if (m <= 0) return nchunk;
-    const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
-    hipLaunchKernelGGL((k_rows_dot<float>), grid, dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
+    hipLaunchKernelGGL((k_rows_dot<float>), dim3(nchunk), dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
     H1W_LAUNCHED();
     return nchunk;
 }

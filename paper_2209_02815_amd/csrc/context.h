@@ -64,6 +64,8 @@ struct Ctx {
     bool lu_pivoted = false;         // fallback LU with partial pivoting in use
     int failed_pivot = -1;
     double asym = 0.0;
+    double kappa_est = 0.0;   // pivot-ratio estimate of cond(S) from its factor
+    double s_over_alpha = 0.0;  // max S_ii / alpha: the amplification of rounding in S by 1/alpha
 
     // Krylov workspace
     enum { kR, kP, kQ, kY, kU, kZ, kT, kB, kTmpN, kNVec };

@@ -5,6 +5,7 @@
 #include "context.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -663,91 +664,106 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     if (fp32 && zbytes > avail / 100 * 90)
         throw Error{H1W_ENOMEM, "the FP32 Z of a MIXED context does not fit in device memory"};
     double gflops = 0.0;
-    if (!z_streamed) {
-        Zbuf.reserve(zbytes);
-        ldz = n;
-        if (!fp32) {
-            apply_B(m, J, ldj, Zbuf.as<double>(), ldz);
-        } else {
-            // FP32 V-cycles on J_i - s_i W1; the constant mode s_i v stays exact in FP64
-            ensure_deflation_vectors();
-            sdef.reserve((size_t)m * sizeof(double));
-            jvdef.reserve((size_t)m * sizeof(double));
-            const size_t pe = rows_dot_partial_elems(m, n);
-            dpart.reserve(2 * pe * sizeof(double));
-            const int nch = launch_rows_dot2_partial(stream, m, n, J, ldj, ones.as<double>(), vdef.as<double>(),
-                                                     dpart.as<double>(), dpart.as<double>() + pe);
-            launch_reduce_parts(stream, m, nch, dpart.as<double>(), sdef.as<double>());
-            launch_reduce_parts(stream, m, nch, dpart.as<double>() + pe, jvdef.as<double>());
-            launch_scale(stream, m, 1.0 / wsum, sdef.as<double>(), sdef.as<double>());
-            for (int r0 = 0; r0 < m; r0 += chunk) {
-                const int kk = std::min(chunk, m - r0);
-                stage.reserve((size_t)kk * pitch[0] * sizeof(float));
-                launch_convert_deflate(stream, n, kk, J + (int64_t)r0 * ldj, ldj, sdef.as<double>() + r0,
-                                       wvec.as<double>(), stage.as<float>(), pitch[0]);
-                vcycle_chunk<float>(kk, stage.as<float>(), pitch[0], Zbuf.as<float>() + (int64_t)r0 * ldz, ldz);
-            }
-        }
-        ev_record(1);
-        // S = alpha I + J Z^T (lower triangle only when Z is FP64 and S will be Cholesky-factored)
-        const bool lower = !fp32 && fac == H1W_FACTOR_CHOL;
-        const size_t pe = gemm_partial_elems(m, m, n);
-        gpart.reserve(pe * sizeof(double));
-        int splits = 0;
-        gflops = lower ? (double)m * (m + 1) * n : 2.0 * m * m * n;
-        timed(H1W_K_GEMM, (double)m * n * (8 + zes), gflops, [&] {
-            if (!fp32)
-                splits = launch_capacitance_partial<double>(stream, m, m, n, J, ldj, Zbuf.as<double>(), ldz, lower,
-                                                            gpart.as<double>(), pe);
-            else if (d.flags & H1W_FLAG_CAP_FP32_GEMM)
-                splits = launch_capacitance_partial_f32acc(stream, m, m, n, J, ldj, Zbuf.as<float>(), ldz,
-                                                           gpart.as<double>(), pe);
-            else
-                splits = launch_capacitance_partial<float>(stream, m, m, n, J, ldj, Zbuf.as<float>(), ldz, lower,
-                                                           gpart.as<double>(), pe);
-        });
-        launch_capacitance_reduce(stream, m, m, splits, gpart.as<double>(), lower, alpha, Sbuf.as<double>(), m);
-        if (fp32) {
-            // Z = Z1 - 1 mu^T + v s^T with mu_i the W-mean of the stored row Z1_i:
-            // S += (J v) s^T - (J 1) mu^T, J 1 = wsum * s
-            mudef.reserve((size_t)m * sizeof(double));
-            jneg.reserve((size_t)m * sizeof(double));
-            const int nch = launch_rows_dot_partial_f32(stream, m, n, Zbuf.as<float>(), ldz, wvec.as<double>(),
-                                                        dpart.as<double>());
-            launch_reduce_parts(stream, m, nch, dpart.as<double>(), mudef.as<double>());
-            launch_scale(stream, m, 1.0 / wsum, mudef.as<double>(), mudef.as<double>());
-            launch_scale(stream, m, -wsum, sdef.as<double>(), jneg.as<double>());
-            launch_rank2_add(stream, m, jvdef.as<double>(), sdef.as<double>(), jneg.as<double>(), mudef.as<double>(),
-                             Sbuf.as<double>());
-        }
-    } else {
+    // S = alpha I + J Z^T. FP64 Z with a Cholesky factor (or a streamed Z):
+    // lower triangle only, mirrored at the end; otherwise the full product.
+    const bool lower = !fp32 && (z_streamed || fac == H1W_FACTOR_CHOL);
+    // Z is built and multiplied in blocks of zb rows: one block when Z is
+    // stored, row chunks (multiples of 128) when it is streamed. A lower block
+    // S[r0:m, r0:r1] = J[r0:m] Z_b^T starts on the diagonal; a full block is
+    // the column block S[0:m, r0:r1] = J Z_b^T.
+    int zb = m;
+    if (z_streamed) {
         Zbuf.release();
-        ldz = n;
         // rows of Z per chunk: a multiple of 128 using at most ~30% of the free memory
-        int zc = (int)std::min<size_t>((size_t)m, (avail / 100 * 30) / ((size_t)n * sizeof(double)));
-        zc = std::max(1, zc >= 128 ? zc / 128 * 128 : zc);
-        if (d.flags & H1W_FLAG_STREAM_Z) zc = std::min(zc, 128);  // forced: 128-row chunks
-        zchunk.reserve((size_t)zc * n * sizeof(double));
-        size_t pe = 0;
-        for (int c0 = 0; c0 < m; c0 += zc) pe = std::max(pe, gemm_partial_elems(m - c0, std::min(zc, m - c0), n));
-        gpart.reserve(pe * sizeof(double));
-        for (int c0 = 0; c0 < m; c0 += zc) {
-            const int cc = std::min(zc, m - c0);
-            apply_B(cc, J + (int64_t)c0 * ldj, ldj, zchunk.as<double>(), n);
-            // S[c0:m, c0:c0+cc] = J[c0:m] Zc^T (+ alpha on the diagonal)
-            const int rows = m - c0;
-            int splits = 0;
-            timed(H1W_K_GEMM, (double)(rows + cc) * n * 8, 2.0 * rows * cc * n, [&] {
-                splits = launch_capacitance_partial<double>(stream, rows, cc, n, J + (int64_t)c0 * ldj, ldj,
-                                                            zchunk.as<double>(), n, false, gpart.as<double>(), pe);
-            });
-            launch_capacitance_reduce(stream, rows, cc, splits, gpart.as<double>(), false, alpha,
-                                      Sbuf.as<double>() + (int64_t)c0 * m + c0, m);
-            gflops += 2.0 * rows * cc * n;
-        }
-        launch_mirror_lower(stream, m, Sbuf.as<double>());
-        ev_record(1);
+        zb = (int)std::min<size_t>((size_t)m, (avail / 100 * 30) / ((size_t)n * sizeof(double)));
+        zb = std::max(1, zb >= 128 ? zb / 128 * 128 : zb);
+        if (d.flags & H1W_FLAG_STREAM_Z) zb = std::min(zb, 128);  // forced: 128-row chunks
+        zchunk.reserve((size_t)zb * n * sizeof(double));
+    } else {
+        Zbuf.reserve(zbytes);
     }
+    ldz = n;
+    if (fp32) {
+        // FP32 V-cycles on J_i - s_i W1; the constant mode s_i v stays exact in FP64
+        ensure_deflation_vectors();
+        sdef.reserve((size_t)m * sizeof(double));
+        jvdef.reserve((size_t)m * sizeof(double));
+        const size_t pe = rows_dot_partial_elems(m, n);
+        dpart.reserve(2 * pe * sizeof(double));
+        const int nch = launch_rows_dot2_partial(stream, m, n, J, ldj, ones.as<double>(), vdef.as<double>(),
+                                                 dpart.as<double>(), dpart.as<double>() + pe);
+        launch_reduce_parts(stream, m, nch, dpart.as<double>(), sdef.as<double>());
+        launch_reduce_parts(stream, m, nch, dpart.as<double>() + pe, jvdef.as<double>());
+        launch_scale(stream, m, 1.0 / wsum, sdef.as<double>(), sdef.as<double>());
+    }
+    size_t pe = 0;
+    for (int r0 = 0; r0 < m; r0 += zb) {
+        const int cc = std::min(zb, m - r0);
+        pe = std::max(pe, lower ? gemm_partial_elems(m - r0, cc, n) : gemm_partial_elems(m, cc, n));
+    }
+    gpart.reserve(pe * sizeof(double));
+    const bool one_block = zb >= m;
+    for (int r0 = 0; r0 < m; r0 += zb) {
+        const int cc = std::min(zb, m - r0);
+        double* z64 = nullptr;
+        float* z32 = nullptr;
+        if (fp32) {
+            z32 = Zbuf.as<float>() + (int64_t)r0 * ldz;
+            for (int q0 = r0; q0 < r0 + cc; q0 += chunk) {
+                const int kk = std::min(chunk, r0 + cc - q0);
+                stage.reserve((size_t)kk * pitch[0] * sizeof(float));
+                launch_convert_deflate(stream, n, kk, J + (int64_t)q0 * ldj, ldj, sdef.as<double>() + q0,
+                                       wvec.as<double>(), stage.as<float>(), pitch[0]);
+                vcycle_chunk<float>(kk, stage.as<float>(), pitch[0], Zbuf.as<float>() + (int64_t)q0 * ldz, ldz);
+            }
+        } else {
+            z64 = z_streamed ? zchunk.as<double>() : Zbuf.as<double>() + (int64_t)r0 * ldz;
+            apply_B(cc, J + (int64_t)r0 * ldj, ldj, z64, ldz);
+        }
+        if (one_block) ev_record(1);
+        double* gp = gpart.as<double>();
+        int splits = 0;
+        if (lower) {
+            const int rows = m - r0;
+            const double useful = (double)cc * (cc + 1) * n + 2.0 * (rows - cc) * cc * n;
+            timed(H1W_K_GEMM, (double)(rows + cc) * n * 8, useful, [&] {
+                splits = launch_capacitance_partial<double>(stream, rows, cc, n, J + (int64_t)r0 * ldj, ldj, z64,
+                                                            ldz, true, gp, pe);
+            });
+            launch_capacitance_reduce(stream, rows, cc, splits, gp, true, alpha, 0,
+                                      Sbuf.as<double>() + (int64_t)r0 * m + r0, m);
+            gflops += useful;
+        } else {
+            const double fl = 2.0 * m * cc * n;
+            timed(H1W_K_GEMM, (double)m * n * 8 + (double)cc * n * zes, fl, [&] {
+                if (!fp32)
+                    splits = launch_capacitance_partial<double>(stream, m, cc, n, J, ldj, z64, ldz, false, gp, pe);
+                else if (d.flags & H1W_FLAG_CAP_FP32_GEMM)
+                    splits = launch_capacitance_partial_f32acc(stream, m, cc, n, J, ldj, z32, ldz, gp, pe);
+                else
+                    splits = launch_capacitance_partial<float>(stream, m, cc, n, J, ldj, z32, ldz, false, gp, pe);
+            });
+            launch_capacitance_reduce(stream, m, cc, splits, gp, false, alpha, r0, Sbuf.as<double>() + r0, m);
+            gflops += fl;
+        }
+    }
+    if (lower) launch_mirror_lower(stream, m, Sbuf.as<double>());
+    if (fp32) {
+        // Z = Z1 - 1 mu^T + v s^T with mu_i the W-mean of the stored row Z1_i:
+        // S += (J v) s^T - (J 1) mu^T, J 1 = wsum * s
+        mudef.reserve((size_t)m * sizeof(double));
+        jneg.reserve((size_t)m * sizeof(double));
+        const int nch = launch_rows_dot_partial_f32(stream, m, n, Zbuf.as<float>(), ldz, wvec.as<double>(),
+                                                    dpart.as<double>());
+        launch_reduce_parts(stream, m, nch, dpart.as<double>(), mudef.as<double>());
+        launch_scale(stream, m, 1.0 / wsum, mudef.as<double>(), mudef.as<double>());
+        launch_scale(stream, m, -wsum, sdef.as<double>(), jneg.as<double>());
+        launch_rank2_add(stream, m, jvdef.as<double>(), sdef.as<double>(), jneg.as<double>(), mudef.as<double>(),
+                         Sbuf.as<double>());
+    }
+    // with several blocks the V-cycles and the products interleave: their sum
+    // is reported as the Z build and the GEMM time is 0
+    if (!one_block) ev_record(1);
     ev_record(2);
     asym = 0.0;
     if (fp32 || fac != H1W_FACTOR_CHOL) {
@@ -805,6 +821,15 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
         factor = H1W_FACTOR_LU;
     }
     ev_record(3);
+    // diagonal statistics: a cheap estimate of cond(S) from the pivots (its
+    // square for Cholesky, S = U^T U) and max S_ii / alpha
+    launch_diag_stats(stream, m, Sbuf.as<double>(), F1.as<double>(), scal.as<double>());
+    read_scal(4);
+    {
+        const double pr = hscal[3] > 0.0 ? hscal[2] / hscal[3] : INFINITY;
+        kappa_est = factor == H1W_FACTOR_CHOL ? pr * pr : pr;
+        s_over_alpha = hscal[0] / alpha;
+    }
     have_cap = true;
     sync();
     flush_timing();
@@ -818,6 +843,8 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
         info->factor_used = factor;
         info->failed_pivot = failed_pivot;
         info->asym_S_over_alpha = asym;
+        info->kappa_S_est = kappa_est;
+        info->s_max_over_alpha = s_over_alpha;
         info->nlevels = (int)lv.size();
     }
 }
@@ -1019,14 +1046,21 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
 
     int it = 0, restarts = 0;
     double relres_rec = 0.0, relres_true = 0.0;
-    // Recompute form: the Jz recurrence Jz = (Jy - (S - alpha I) w) / alpha
-    // assumes B (J^T w) = Z^T w, but the two come from separate V-cycles whose
-    // rounding differs; amplified by 1/alpha, the recursive residual drifts
-    // from the true one by an amount that grows with the residual size during
-    // the iteration. One replacement of r by the true residual once the
-    // recursive residual is below sqrt(rtol) bounds the later drift far below
-    // rtol (otherwise the final check fails and forces a late restart).
-    const double replace_tol = (m > 0 && !laplace && zm == H1W_Z_RECOMPUTE) ? std::sqrt(rtol) : 0.0;
+    // Residual replacement. The Jz recurrence Jz = (Jy - (S - alpha I) w) / alpha
+    // carries the rounding of S and of the J-space products amplified by
+    // ||S|| / alpha, and in the recompute form also the difference between the
+    // two V-cycles B (J^T w) and Z^T w; so the recursive residual drifts from
+    // the true one by an amount that grows with the residual size during the
+    // iteration (measured at 129^3: 4.5e-8 ||b|| in the recompute form, 5.5e-9
+    // in the stored form, about 100 u max S_ii / alpha). Once the recursive
+    // residual is below sqrt(rtol), r is replaced by the true residual, keeping
+    // the search direction, which bounds the later drift far below rtol
+    // (otherwise the final check can fail and force a late restart). Always in
+    // the recompute form; in the stored form when the predicted drift reaches
+    // a tenth of rtol.
+    const bool drifts = 100.0 * 0.5 * DBL_EPSILON * s_over_alpha >= 0.1 * rtol;
+    const double replace_tol =
+        (m > 0 && !laplace && (zm == H1W_Z_RECOMPUTE || drifts)) ? std::sqrt(rtol) : 0.0;
     bool replaced = false;
     h1w_status status = H1W_OK;
 
@@ -1154,7 +1188,7 @@ void Ctx::gn_solve(int m_, const double* J_, int64_t ldj_, double alpha_, const 
                 if (relres_true <= rtol) break;
                 ++restarts;
                 H1W_HIP(hipMemcpyAsync(r, u, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
-                precond_step(true);
+                precond_step(false);  // the direction is kept
                 continue;
             }
             if (it >= maxit) {

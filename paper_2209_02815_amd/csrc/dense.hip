@@ -180,7 +180,49 @@ __global__ __launch_bounds__(kDense) void k_asym(int m, const double* __restrict
     }
 }
 
+// out[0..3] = max S_ii, min S_ii, max |F_ii|, min |F_ii| (S and its factor,
+// whose diagonal holds the pivots u_ii of S = U^T U or S = L U)
+__global__ __launch_bounds__(kDense) void k_diag_stats(int m, const double* __restrict__ S,
+                                                       const double* __restrict__ F, double* __restrict__ out) {
+    __shared__ double sh[4][kDense / 64];
+    double smax = -INFINITY, smin = INFINITY, fmax_ = 0.0, fmin_ = INFINITY;
+    for (int i = threadIdx.x; i < m; i += kDense) {
+        const double sv = S[(int64_t)i * m + i], fv = fabs(F[(int64_t)i * m + i]);
+        smax = fmax(smax, sv);
+        smin = fmin(smin, sv);
+        fmax_ = fmax(fmax_, fv);
+        fmin_ = fmin(fmin_, fv);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        smax = fmax(smax, __shfl_down(smax, off, 64));
+        smin = fmin(smin, __shfl_down(smin, off, 64));
+        fmax_ = fmax(fmax_, __shfl_down(fmax_, off, 64));
+        fmin_ = fmin(fmin_, __shfl_down(fmin_, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = smax;
+        sh[1][threadIdx.x >> 6] = smin;
+        sh[2][threadIdx.x >> 6] = fmax_;
+        sh[3][threadIdx.x >> 6] = fmin_;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kDense / 64; ++w) {
+            sh[0][0] = fmax(sh[0][0], sh[0][w]);
+            sh[1][0] = fmin(sh[1][0], sh[1][w]);
+            sh[2][0] = fmax(sh[2][0], sh[2][w]);
+            sh[3][0] = fmin(sh[3][0], sh[3][w]);
+        }
+        for (int k = 0; k < 4; ++k) out[k] = sh[k][0];
+    }
+}
+
 }  // namespace
+
+void launch_diag_stats(hipStream_t s, int m, const double* S, const double* F, double* out) {
+    hipLaunchKernelGGL(k_diag_stats, dim3(1), dim3(kDense), 0, s, m, S, F, out);
+    H1W_LAUNCHED();
+}
 
 void launch_lu(hipStream_t s, int m, double* A, int* piv, int* info) {
     hipLaunchKernelGGL(k_lu, dim3(1), dim3(kDense), 0, s, m, A, piv, info);

@@ -9,8 +9,10 @@
 // order (deterministic) and adds alpha on the diagonal. When S is known to be
 // symmetric (FP64 Z), only tiles on or below the diagonal are computed and
 // the upper triangle is mirrored. The product is general rectangular
-// (m rows of J against m2 rows of Z), which also serves a capacitance built
-// from Z in row chunks when Z does not fit next to J.
+// (m rows of J against m2 <= m rows of Z), which also serves a capacitance
+// built from Z in row chunks when Z does not fit next to J: there the block
+// S[c0:, c0:c0+m2] starts on the diagonal, and its lower mode skips the tiles
+// (and 64 x 64 wave quadrants) strictly above it in the same way.
 //
 // Each wave owns a 64 x 64 sub-tile = 4 x 4 blocks of v_mfma_f64_16x16x4_f64
 // whose operands come from LDS copies of the work-group's 128-row tiles of J
@@ -36,7 +38,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kTileMN = 128;
 constexpr int kGemmThreads = 256;
 constexpr int kResidentWG = 512;  // 256 CUs x 2 work-groups
-constexpr size_t kMaxPartialBytes = size_t(256) << 20;
+constexpr size_t kMaxPartialBytes = size_t(1) << 30;
 
 // K is consumed in chunks of KB = 16: the 256 threads copy the 128 x KB
 // tiles of J and Z into LDS (double-buffered; rows padded to an odd stride so
@@ -64,9 +66,17 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
     const int tile = u - split * ntile;
     int tr, tc;
     if (lower) {
-        tr = 0;
-        while ((tr + 1) * (tr + 2) / 2 <= tile) ++tr;
-        tc = tile - tr * (tr + 1) / 2;
+        // row tile r holds min(r + 1, T2) tiles: a triangle of T2 (T2 + 1) / 2
+        // tiles, then full rows of T2
+        const int tri = T2 * (T2 + 1) / 2;
+        if (tile < tri) {
+            tr = 0;
+            while ((tr + 1) * (tr + 2) / 2 <= tile) ++tr;
+            tc = tile - tr * (tr + 1) / 2;
+        } else {
+            tr = T2 + (tile - tri) / T2;
+            tc = (tile - tri) - (tr - T2) * T2;
+        }
     } else {
         tr = tile / T2;
         tc = tile - tr * T2;
@@ -285,7 +295,8 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm32(int m, int m2, i
 }
 
 // S[i][j] (block of m x m2 at S, leading dimension lds) = sum over splits of
-// the partials (+ alpha on the block diagonal i == j). lower: the square
+// the partials (+ alpha where i == j + diag_off: the global diagonal of a
+// block that starts diag_off columns right of it). lower: the square
 // product was computed on and below the diagonal only; S[i][j] for i < j is
 // taken from the partial at (j, i). A work-group takes kRedOut consecutive
 // outputs; its kRedGroups thread groups sum the splits g, g + kRedGroups, ...
@@ -295,7 +306,7 @@ constexpr int kRedGroups = 8;
 constexpr int kRedOut = kBlock / kRedGroups;
 
 __global__ __launch_bounds__(kBlock) void k_cap_reduce(int m, int m2, int splits, const double* __restrict__ partial,
-                                                       int lower, double alpha, double* __restrict__ S,
+                                                       int lower, double alpha, int diag_off, double* __restrict__ S,
                                                        int64_t lds) {
     __shared__ double sh[kRedGroups][kRedOut];
     const int g = threadIdx.x / kRedOut, q = threadIdx.x % kRedOut;
@@ -315,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_cap_reduce(int m, int m2, int splits
         double t = sh[0][q];
 #pragma unroll
         for (int h = 1; h < kRedGroups; ++h) t += sh[h][q];
-        if (i == j) t += alpha;
+        if (i == j + diag_off) t += alpha;
         S[(int64_t)i * lds + j] = t;
     }
 }
@@ -337,11 +348,25 @@ GemmPlan plan(int m, int m2, int64_t N, bool lower) {
     GemmPlan p;
     p.T = (int)cdiv(m, kTileMN);
     p.T2 = (int)cdiv(m2, kTileMN);
-    p.ntile = lower ? p.T * (p.T + 1) / 2 : p.T * p.T2;
+    p.ntile = lower ? p.T2 * (p.T2 + 1) / 2 + (p.T - p.T2) * p.T2 : p.T * p.T2;
+    // splits: about four rounds of resident work-groups, the count in
+    // [s0, 4 s0] whose last round is the fullest (fewest idle slots while the
+    // slowest groups finish); bounded by the partial buffer and by K
     const size_t per_split = (size_t)m * m2 * sizeof(double);
-    int splits = std::max(1, kResidentWG / p.ntile);
-    splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, cdiv(N, 256)));
-    splits = (int)std::max<size_t>(1, std::min<size_t>(splits, kMaxPartialBytes / per_split));
+    const int smax_mem = (int)std::max<size_t>(1, kMaxPartialBytes / per_split);
+    const int smax_k = (int)std::max<int64_t>(1, cdiv(N, 256));
+    const int s0 = std::max(1, (int)cdiv(4 * kResidentWG, p.ntile) / 2);
+    int splits = 1;
+    double best = 1e30;
+    for (int sp = s0; sp <= 4 * s0; ++sp) {
+        const int spc = std::min({sp, smax_mem, smax_k});
+        const double tot = (double)p.ntile * spc;
+        const double waste = std::ceil(tot / kResidentWG) * kResidentWG / tot;
+        if (waste < best - 1e-9) {
+            best = waste;
+            splits = spc;
+        }
+    }
     p.kper = cdiv(cdiv(N, splits), KB) * KB;
     p.splits = (int)cdiv(N, p.kper);
     return p;
@@ -352,7 +377,7 @@ GemmPlan plan(int m, int m2, int64_t N, bool lower) {
 size_t gemm_partial_elems(int m, int m2, int64_t N) {
     const GemmPlan p = plan(m, m2, N, false);
     size_t e = (size_t)p.splits * m * m2;
-    if (m == m2) e = std::max(e, (size_t)plan(m, m, N, true).splits * m * m);
+    if (m >= m2) e = std::max(e, (size_t)plan(m, m2, N, true).splits * m * m2);
     return e;
 }
 
@@ -360,7 +385,7 @@ template <typename TZ>
 int launch_capacitance_partial(hipStream_t s, int m, int m2, int64_t N, const double* J, int64_t ldj, const TZ* Z,
                                int64_t ldz, bool lower_only, double* partial, size_t partial_elems) {
     if (m <= 0 || m2 <= 0) return 0;
-    if (lower_only && m != m2) throw Error{H1W_EINVAL, "internal: lower-triangle GEMM needs a square output"};
+    if (lower_only && m < m2) throw Error{H1W_EINVAL, "internal: lower-triangle GEMM needs m >= m2"};
     const GemmPlan p = plan(m, m2, N, lower_only);
     if ((size_t)p.splits * m * m2 > partial_elems) throw Error{H1W_EINVAL, "internal: GEMM partial buffer too small"};
     const int total = p.ntile * p.splits;
@@ -385,10 +410,10 @@ int launch_capacitance_partial_f32acc(hipStream_t s, int m, int m2, int64_t N, c
 }
 
 void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const double* partial, bool lower_only,
-                               double alpha, double* S, int64_t lds) {
+                               double alpha, int diag_off, double* S, int64_t lds) {
     if (m <= 0 || m2 <= 0) return;
     hipLaunchKernelGGL(k_cap_reduce, dim3((unsigned)cdiv((int64_t)m * m2, kRedOut)), dim3(kBlock), 0, s, m, m2,
-                       splits, partial, (int)lower_only, alpha, S, lds);
+                       splits, partial, (int)lower_only, alpha, diag_off, S, lds);
     H1W_LAUNCHED();
 }
 

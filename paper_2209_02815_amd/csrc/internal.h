@@ -275,7 +275,7 @@ int launch_capacitance_partial(hipStream_t s, int m, int m2, int64_t N, const do
 int launch_capacitance_partial_f32acc(hipStream_t s, int m, int m2, int64_t N, const double* J, int64_t ldj,
                                       const float* Z, int64_t ldz, double* partial, size_t partial_elems);
 void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const double* partial, bool lower_only,
-                               double alpha, double* S, int64_t lds);
+                               double alpha, int diag_off, double* S, int64_t lds);
 void launch_mirror_lower(hipStream_t s, int m, double* S);
 size_t gemm_partial_elems(int m, int m2, int64_t N);
 
@@ -287,6 +287,8 @@ void launch_lu_solve(hipStream_t s, int m, const double* LUt, const double* LU, 
 void launch_jz_update_dev(hipStream_t s, int m, const double* S, double alpha, const double* Jy, const double* w,
                           const double* bdev, double* Jz, double* Jp);
 void launch_asym(hipStream_t s, int m, const double* S, double* out);
+// out[0..3] = max S_ii, min S_ii, max |F_ii|, min |F_ii| of S and its factor F
+void launch_diag_stats(hipStream_t s, int m, const double* S, const double* F, double* out);
 // blocked.hip: right-looking blocked Cholesky (mode 0, upper) or LU without
 // pivoting (mode 1) in place, with diagonal-block inverses; triangular solves
 size_t blocked_inv_elems(int m);

@@ -61,7 +61,8 @@ def test_cube257_solve(P, system, prec):
         x, info = ctx.gn_solve(Jd, wl.alpha, b=bd, rtol=RTOL)
         torch.cuda.synchronize()
     _log(f"{prec}: iters={info.iters} restarts={info.restarts} relres(GPU)={info.relres_true:.3e} "
-         f"zmode={info.zmode_used} factor={info.factor_used} total={info.t_total_ms:.0f} ms")
+         f"relres(recursive)={info.relres_rec:.3e} zmode={info.zmode_used} factor={info.factor_used} "
+         f"total={info.t_total_ms:.0f} ms kappa(S)~{info.kappa_S_est:.2e} max S_ii/alpha={info.s_max_over_alpha:.2e}")
     # FP64: the 139 GB J leaves no room for an FP64 Z, so it is streamed and the
     # CG uses the recompute form; mixed stores the FP32 Z and factors S by LU
     assert info.zmode_used == (2 if prec == "fp64" else 1)

@@ -614,11 +614,40 @@ def test_full_size_cube129(P, prec, rtol):
         x = host(x)
         del Jd
     rr, fl = gn.relres_streamed(wl.shape, wl.beta, [J], wl.alpha, b, x)
-    print(f"cube129 {prec} rtol={rtol:g}: iters={info.iters} relres(oracle)={rr:.3e} "
-          f"relres(GPU)={info.relres_true:.3e} FP64 floor={fl:.2e}")
+    print(f"cube129 {prec} rtol={rtol:g}: iters={info.iters} restarts={info.restarts} relres(oracle)={rr:.3e} "
+          f"relres(GPU)={info.relres_true:.3e} relres(recursive)={info.relres_rec:.3e} FP64 floor={fl:.2e} "
+          f"kappa(S)~{info.kappa_S_est:.2e} max S_ii/alpha={info.s_max_over_alpha:.2e}")
     assert rr <= rtol * 1.01
     assert abs(rr - info.relres_true) <= 1e-3 * rtol + 4.0 * np.sqrt(wl.N) * fl
     # the tolerance stays well above the componentwise FP64 rounding bound of
     # one product G x (1.5e-12 at 129^3, a worst-case bound)
     assert fl <= 0.05 * rtol
     assert info.iters <= (12 if rtol >= 1e-8 else 16)
+
+
+def test_trace_log_lines():
+    # H1W_TRACE=1: one stderr line per entry-point call, with its status and,
+    # for a failed call, the error message (run in a fresh process so the
+    # variable is read at library load)
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, torch\n"
+        "import paper_2209_02815_amd as P\n"
+        "from paper_2209_02815_amd import _native as nat\n"
+        "with P.Context((17, 17), 1e-2) as ctx:\n"
+        "    b = torch.ones(289, dtype=torch.float64, device='cuda:0')\n"
+        "    J = torch.ones((3, 289), dtype=torch.float64, device='cuda:0')\n"
+        "    ctx.gn_solve(J, 1e-3, b=b, rtol=1e-8)\n"
+        "    try:\n"
+        "        ctx.gn_solve(J, -1.0, b=b)\n"
+        "    except nat.H1WError:\n"
+        "        pass\n")
+    env = dict(__import__("os").environ, H1W_TRACE="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120,
+                       cwd=__import__("os").path.dirname(__import__("os").path.dirname(__file__)))
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[h1w] ")]
+    assert any(l.startswith("[h1w] h1w_setup ") and "status=0" in l for l in lines), lines
+    assert any(l.startswith("[h1w] h1w_gn_solve ") and "status=0" in l for l in lines), lines
+    assert any(l.startswith("[h1w] h1w_gn_solve ") and "status=-1" in l and "alpha" in l for l in lines), lines
