@@ -27,18 +27,6 @@ import scipy.sparse as sp
 
 from . import operator as op
 
-DEFAULT_NU = 2
-DEFAULT_LO = 0.3
-DEFAULT_HI = 2.0
-
-
-def default_coarse_max(dim: int) -> int:
-    # The coarsest level is a parameter of the multigrid Poisson solver, which
-    # Section 3 leaves open: 9^3 nodes in 3D and 9^2 in 2D (the default of
-    # the GPU contexts too, so that both build the same hierarchy).
-    return 729 if dim == 3 else 81
-
-
 def level_shapes(shape, coarse_max: int):
     """Grid shapes from fine to coarsest."""
     shapes = [tuple(shape)]
@@ -79,12 +67,15 @@ def interpolation(coarse_shape) -> sp.csr_matrix:
 
 
 class VCycle:
-    """B f for the symmetric V(nu, nu) cycle described in the module docstring."""
+    """B f for the symmetric V(nu, nu) cycle described in the module docstring.
 
-    def __init__(self, shape, beta, nu=DEFAULT_NU, lo=DEFAULT_LO, hi=DEFAULT_HI,
-                 coarse_max=None):
+    Every parameter of B is given by the caller (Section 3.2 leaves the
+    Laplace solver open, so none has a value of its own here): nu smoothing
+    steps per side, the Chebyshev interval [lo, hi] for eig(D^-1 A), and
+    coarse_max, the node count at or below which a level is the coarsest."""
+
+    def __init__(self, shape, beta, *, nu, lo, hi, coarse_max):
         dim = len(shape)
-        coarse_max = default_coarse_max(dim) if coarse_max is None else coarse_max
         self.shapes = level_shapes(shape, coarse_max)
         self.dim = dim
         self.weights = chebyshev_weights(nu, lo, hi)

@@ -22,6 +22,8 @@ import pytest
 import h1w_inputs as H
 from oracle import gn, multigrid as mg, operator as op, poisson
 
+import mgparams as mgp
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -93,14 +95,14 @@ def test_vcycle_fp64_matches_oracle(P, shape, cmax, nu):
     beta = 1e-2
     N = int(np.prod(shape))
     F = rng(1).standard_normal((5, N))
-    with P.Context(shape, beta, nu=nu, coarse_max=cmax, rhs_chunk=2) as ctx:
+    with P.Context(shape, beta, rhs_chunk=2, **mgp.ctx_kw(len(shape), nu=nu, coarse_max=cmax)) as ctx:
         Fd = padded(5, N)
         Fd.copy_(dev(F))
         Xd = padded(5, N, pad=11)
         ctx.vcycle(Fd, Xd)
         X = host(Xd)
         nl = ctx.nlevels
-    V = mg.VCycle(shape, beta, nu=nu, coarse_max=cmax)
+    V = mgp.vcycle(shape, beta, nu=nu, coarse_max=cmax)
     assert nl == V.nlevels
     Xref = V.apply(F)
     assert rel_rows(X, Xref).max() < 100 * EPS64 * np.linalg.cond(V.Acoarse)
@@ -111,10 +113,10 @@ def test_vcycle_fp32_matches_oracle(P, shape, cmax, nu):
     beta = 1e-2
     N = int(np.prod(shape))
     F = rng(2).standard_normal((4, N)).astype(np.float32)
-    with P.Context(shape, beta, precision="mixed", nu=nu, coarse_max=cmax) as ctx:
+    with P.Context(shape, beta, precision="mixed", **mgp.ctx_kw(len(shape), nu=nu, coarse_max=cmax)) as ctx:
         Fd = dev(F, torch.float32)
         X = host(ctx.vcycle(Fd))
-    Xref = mg.VCycle(shape, beta, nu=nu, coarse_max=cmax).apply(F.astype(np.float64))
+    Xref = mgp.vcycle(shape, beta, nu=nu, coarse_max=cmax).apply(F.astype(np.float64))
     assert rel_rows(X, Xref).max() < 2e-5
 
 
@@ -138,8 +140,8 @@ def test_vcycle_fused_matches_unfused(P, shape, cmax, k, chunk, prec):
     F = rng(12).standard_normal((k, N))
     out = []
     for fused in (True, False):
-        with P.Context(shape, beta, precision="fp64" if prec == "fp64" else "mixed", coarse_max=cmax,
-                       rhs_chunk=chunk, fused_vcycle=fused) as ctx:
+        with P.Context(shape, beta, precision="fp64" if prec == "fp64" else "mixed", rhs_chunk=chunk,
+                       fused_vcycle=fused, **mgp.ctx_kw(len(shape), coarse_max=cmax or None)) as ctx:
             Fd = padded(k, N, dtype=tdt)
             Fd.copy_(dev(F, tdt))
             Xd = padded(k, N, pad=5, dtype=tdt)
@@ -150,7 +152,7 @@ def test_vcycle_fused_matches_unfused(P, shape, cmax, k, chunk, prec):
             out.append(host(Xd))
             nfused = kt["vdown"]["launches"] + kt["vtail"]["launches"]
             assert (nfused > 0) == fused and (kt["smooth"]["launches"] > 0) == (not fused)
-    V = mg.VCycle(shape, beta, coarse_max=cmax or 729)
+    V = mgp.vcycle(shape, beta, coarse_max=cmax or None)
     tol = 100 * EPS64 * np.linalg.cond(V.Acoarse) if prec == "fp64" else 2e-5
     assert rel_rows(out[0], out[1]).max() < tol
     if N <= 40000:  # and both against the oracle
@@ -177,8 +179,8 @@ def test_vcycle_tail_matches_per_level(P, shape, cmax, k, chunk, tail, prec):
     F = rng(14).standard_normal((k, N))
     out = []
     for vt in (True, False):
-        with P.Context(shape, beta, precision="fp64" if prec == "fp64" else "mixed", coarse_max=cmax,
-                       rhs_chunk=chunk, vtail=vt) as ctx:
+        with P.Context(shape, beta, precision="fp64" if prec == "fp64" else "mixed", rhs_chunk=chunk,
+                       vtail=vt, **mgp.ctx_kw(len(shape), coarse_max=cmax or None)) as ctx:
             Fd = padded(k, N, dtype=tdt)
             Fd.copy_(dev(F, tdt))
             Xd = padded(k, N, pad=3, dtype=tdt)
@@ -190,7 +192,7 @@ def test_vcycle_tail_matches_per_level(P, shape, cmax, k, chunk, tail, prec):
             assert (kt["vtail"]["launches"] > 0) == (vt and tail)
             assert (kt["coarse"]["launches"] == 0) == (vt and tail)
     assert np.array_equal(out[0], out[1])
-    V = mg.VCycle(shape, beta, coarse_max=cmax or 81)
+    V = mgp.vcycle(shape, beta, coarse_max=cmax or None)
     tol = 100 * EPS64 * np.linalg.cond(V.Acoarse) if prec == "fp64" else 2e-5
     if N <= 40000:
         Xref = V.apply(F if prec == "fp64" else F.astype(np.float32).astype(np.float64))
@@ -263,10 +265,10 @@ def _bump_problem(name, m=None):
                                          ("cube17", 3, 0)])
 def test_capacitance_fp64(P, name, m, cmax):
     wl, J, _ = _bump_problem(name, m)
-    with P.Context(wl.shape, wl.beta, coarse_max=cmax) as ctx:
+    with P.Context(wl.shape, wl.beta, **mgp.ctx_kw(wl.dim, coarse_max=cmax or None)) as ctx:
         S, Z, info = ctx.capacitance_build(dev(J), wl.alpha, want_S=True, want_Z=True)
         S, Z = host(S), host(Z)
-    V = mg.VCycle(wl.shape, wl.beta, coarse_max=cmax or None)
+    V = mgp.vcycle(wl.shape, wl.beta, coarse_max=cmax or None)
     Zref = V.apply(J)
     Sref = wl.alpha * np.eye(J.shape[0]) + J @ Zref.T
     tol = 100 * EPS64 * np.linalg.cond(V.Acoarse)   # Z inherits the coarsest-solve rounding
@@ -279,14 +281,14 @@ def test_capacitance_fp64(P, name, m, cmax):
 @pytest.mark.parametrize("name,m", [("square33", 130), ("cube17", None)])
 def test_capacitance_mixed(P, name, m):
     wl, J, _ = _bump_problem(name, m)
-    with P.Context(wl.shape, wl.beta, precision="mixed") as ctx:
+    with P.Context(wl.shape, wl.beta, precision="mixed", **mgp.ctx_kw(wl.dim)) as ctx:
         S, Z, info = ctx.capacitance_build(dev(J), wl.alpha, want_S=True, want_Z=True)
         S, Z = host(S), host(Z)
     # Z_out is the full Z rounded to FP32 (its constant mode is kept in FP64
     # inside the library): S - alpha I = J Z^T up to that rounding
     Sref = wl.alpha * np.eye(J.shape[0]) + J @ Z.T
     assert np.abs(S - Sref).max() <= 1e-6 * np.abs(Sref).max()
-    Zref = mg.VCycle(wl.shape, wl.beta).apply(J)
+    Zref = mgp.vcycle(wl.shape, wl.beta).apply(J)
     assert rel_rows(Z, Zref).max() < 2e-5
     S64 = wl.alpha * np.eye(J.shape[0]) + J @ Zref.T
     assert np.abs(S - S64).max() <= 2e-5 * np.abs(S64).max()
@@ -299,10 +301,10 @@ def test_capacitance_mixed(P, name, m):
 def test_precond_apply_fp64(P, zmode):
     wl, J, _ = _bump_problem("cube17")
     R = rng(5).standard_normal((2, wl.N))
-    with P.Context(wl.shape, wl.beta) as ctx:
+    with P.Context(wl.shape, wl.beta, **mgp.ctx_kw(wl.dim)) as ctx:
         ctx.capacitance_build(dev(J), wl.alpha)
         Zp = host(ctx.precond_apply(dev(R), zmode=zmode))
-    V = mg.VCycle(wl.shape, wl.beta)
+    V = mgp.vcycle(wl.shape, wl.beta)
     ref = gn.woodbury_precond(V.apply, J, wl.alpha, R)
     assert rel_rows(Zp, ref).max() < 1e-8
     # (alpha B^-1 + J^T J) z = r  <=>  alpha z + B J^T J z = B r
@@ -313,13 +315,13 @@ def test_precond_apply_fp64(P, zmode):
 def test_precond_apply_mixed_consistency(P):
     wl, J, _ = _bump_problem("cube17")
     R = rng(6).standard_normal((1, wl.N))
-    with P.Context(wl.shape, wl.beta, precision="mixed") as ctx:
+    with P.Context(wl.shape, wl.beta, precision="mixed", **mgp.ctx_kw(wl.dim)) as ctx:
         _, Z, _ = ctx.capacitance_build(dev(J), wl.alpha, want_Z=True)
         Zp = host(ctx.precond_apply(dev(R)))
         Z = host(Z)
     # with S~ consistent with Z~: J z = w and y~ = alpha z + Z~^T w, y~ ~ B r (FP32 V-cycle)
     ytil = wl.alpha * Zp[0] + Z.T @ (J @ Zp[0])
-    yref = mg.VCycle(wl.shape, wl.beta).apply(R[0])
+    yref = mgp.vcycle(wl.shape, wl.beta).apply(R[0])
     assert np.linalg.norm(ytil - yref) <= 1e-4 * np.linalg.norm(yref)
 
 
@@ -544,14 +546,14 @@ def test_blocked_factor_fp64(P, m, factor):
     # blocks with a ragged last one
     wl, J, b = _bump_problem("square33", m)
     R = rng(9).standard_normal((1, wl.N))
-    with P.Context(wl.shape, wl.beta) as ctx:
+    with P.Context(wl.shape, wl.beta, **mgp.ctx_kw(wl.dim)) as ctx:
         Jd = dev(J)
         _, _, info = ctx.capacitance_build(Jd, wl.alpha, factor=factor)
         assert info.factor_used == factor
         Zp = host(ctx.precond_apply(dev(R), zmode=1))
         x, info = ctx.gn_solve(Jd, wl.alpha, b=dev(b), rtol=1e-10, factor=factor)
         x = host(x)
-    V = mg.VCycle(wl.shape, wl.beta)
+    V = mgp.vcycle(wl.shape, wl.beta)
     ref = gn.woodbury_precond(V.apply, J, wl.alpha, R)
     assert rel_rows(Zp, ref).max() < 1e-8
     assert gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, x) <= 1.01e-10
@@ -580,7 +582,7 @@ def test_streamed_z_capacitance_and_solve(P):
     # J too large to hold an FP64 Z next to it); m = 130 crosses a chunk edge
     wl, J, b = _bump_problem("square33", 130)
     R = rng(10).standard_normal((1, wl.N))
-    with P.Context(wl.shape, wl.beta, stream_z=True) as ctx:
+    with P.Context(wl.shape, wl.beta, stream_z=True, **mgp.ctx_kw(wl.dim)) as ctx:
         Jd = dev(J)
         S, _, info = ctx.capacitance_build(Jd, wl.alpha, want_S=True)
         assert info.zmode_used == 2 and info.factor_used == 1
@@ -590,7 +592,7 @@ def test_streamed_z_capacitance_and_solve(P):
             ctx.precond_apply(dev(R), zmode=1)
         x, info = ctx.gn_solve(Jd, wl.alpha, b=dev(b), rtol=1e-10)
         x = host(x)
-    V = mg.VCycle(wl.shape, wl.beta)
+    V = mgp.vcycle(wl.shape, wl.beta)
     Sref = wl.alpha * np.eye(130) + J @ V.apply(J).T
     tol = 100 * EPS64 * np.linalg.cond(V.Acoarse)
     assert np.abs(S - Sref).max() <= tol * np.abs(Sref).max()

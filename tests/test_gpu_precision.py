@@ -21,12 +21,13 @@ import numpy as np
 import pytest
 
 import h1w_inputs as H
-from oracle import gn, krylov, multigrid as mg
+from oracle import gn, krylov
+
+import mgparams as mgp
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-MG = {2: dict(nu=2, lo=0.3, hi=2.0, coarse_max=81), 3: dict(nu=2, lo=0.3, hi=2.0, coarse_max=729)}
 
 
 @pytest.fixture(scope="module")
@@ -45,13 +46,11 @@ def host(t):
 
 
 def context(P, wl, prec="fp64", **kw):
-    p = MG[wl.dim]
-    return P.Context(wl.shape, wl.beta, precision=prec, nu=p["nu"], cheb=(p["lo"], p["hi"]),
-                     coarse_max=p["coarse_max"], **kw)
+    return P.Context(wl.shape, wl.beta, precision=prec, **mgp.ctx_kw(wl.dim), **kw)
 
 
 def oracle_vcycle(wl):
-    return mg.VCycle(wl.shape, wl.beta, **MG[wl.dim])
+    return mgp.vcycle(wl.shape, wl.beta)
 
 
 class OracleSystem:

@@ -90,7 +90,7 @@ def test_woodbury_precond_identity_with_vcycle():
     # alpha z + B J^T J z = B r  for z = (alpha B^{-1} + J^T J)^{-1} r
     shape = (33, 33)
     J, b, al, be = _small(shape, 7, alpha=1e-3)
-    V = multigrid.VCycle(shape, be, coarse_max=9)
+    V = multigrid.VCycle(shape, be, nu=2, lo=0.3, hi=2.0, coarse_max=9)
     r = np.random.default_rng(4).standard_normal(int(np.prod(shape)))
     z = gn.woodbury_precond(V.apply, J, al, r)
     lhs = al * z + V.apply(J.T @ (J @ z))

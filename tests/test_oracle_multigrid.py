@@ -44,7 +44,7 @@ def test_interpolation_exact_on_affine(cshape):
 
 def test_no_coarsening_is_exact_inverse():
     shape = (9, 9)
-    V = mg.VCycle(shape, 1e-2, coarse_max=10**6)
+    V = mg.VCycle(shape, 1e-2, nu=2, lo=0.3, hi=2.0, coarse_max=10**6)
     assert V.nlevels == 1
     f = np.random.default_rng(0).standard_normal(81)
     assert np.allclose(V.apply(f), poisson.dct_solve(shape, 1e-2, f), rtol=1e-11, atol=1e-11)
@@ -52,7 +52,7 @@ def test_no_coarsening_is_exact_inverse():
 
 @pytest.mark.parametrize("shape,cmax", [((33, 33), 9), ((17, 17, 17), 27), ((9, 17, 5), 1)])
 def test_symmetric_positive(shape, cmax):
-    V = mg.VCycle(shape, 1e-2, coarse_max=cmax)
+    V = mg.VCycle(shape, 1e-2, nu=2, lo=0.3, hi=2.0, coarse_max=cmax)
     rng = np.random.default_rng(2)
     N = int(np.prod(shape))
     for _ in range(4):
@@ -65,7 +65,7 @@ def test_symmetric_positive(shape, cmax):
 @pytest.mark.parametrize("shape,cmax,bound", [((65, 65), 9, 0.2), ((33, 33, 33), 27, 0.22)])
 def test_vcycle_contraction(shape, cmax, bound):
     beta = 1e-2
-    V = mg.VCycle(shape, beta, coarse_max=cmax)
+    V = mg.VCycle(shape, beta, nu=2, lo=0.3, hi=2.0, coarse_max=cmax)
     A = op.gram_operator(shape, beta)
     f = np.random.default_rng(7).standard_normal(int(np.prod(shape)))
     xs = poisson.dct_solve(shape, beta, f)
