@@ -265,8 +265,16 @@ def cpu_baseline(wl, J, b, threads, full=False):
     t_gemm_blk = time.perf_counter() - t0
     log(f"cpu baseline: 64 x 64 capacitance block {t_gemm_blk:.2f} s")
     t_full = t_sample + (wl.m - ms) * t_poisson + (wl.m / 64) ** 2 * t_gemm_blk
+    cpu_model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     out = {
-        "value": 1.0 / t_full, "unit": "solves/s", "cores": threads, "kind": "oracle",
+        "value": 1.0 / t_full, "unit": "solves/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model,
         "sample": (f"oracle Woodbury solve on the {'x'.join(map(str, wl.shape))} grid with {ms} of {wl.m} rows "
                    f"({t_sample:.2f} s) + 1 DCT Poisson solve ({t_poisson:.3f} s) + 64x64 block of the "
                    f"capacitance product ({t_gemm_blk:.3f} s), scaled to one full solve: {t_full:.1f} s"),

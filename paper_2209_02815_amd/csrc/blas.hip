@@ -52,13 +52,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce_parts(int nparts, const doubl
 }
 
 // partial[i*nchunk + c] = sum over chunk c of M[i, n] v[n] for every row i.
-// One block per chunk of kRowChunk nodes walks all m rows: each wave takes
-// rows wid, wid + 4, ... and reduces each row's chunk itself (lane l holds
-// nodes c0 + 2 l + 128 e, e < 16, as 16-byte pairs; fixed order: lane sums
-// over e, then the wave sum), so v's slice is read once per chunk and every
-// row piece is a 16 KB (FP64) run.
+// Block (c, g) takes chunk c of kRowChunk nodes and the rows of group g
+// (rows_per consecutive rows; one group of all m rows on large grids, where
+// the chunks alone fill the GPU): each wave takes rows wid, wid + 4, ... of
+// the group and reduces each row's chunk itself (lane l holds nodes
+// c0 + 2 l + 128 e, e < 16, as 16-byte pairs; fixed order: lane sums over e,
+// then the wave sum), so v's slice is read once per block and every row
+// piece is a 16 KB (FP64) run.
 template <typename TM>
-__global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const TM* __restrict__ M,
+__global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int rows_per, int64_t N, const TM* __restrict__ M,
                                                      int64_t ldm, const double* __restrict__ v,
                                                      double* __restrict__ partial) {
     constexpr int E = kRowChunk / 128;  // node pairs per lane
@@ -73,7 +75,8 @@ __global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int64_t N, const TM*
         v1[e] = n + 1 < N ? v[n + 1] : 0.0;
     }
     const bool tail = base + kRowChunk > N;
-    for (int i = wid; i < m; i += kBlock / 64) {
+    const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
+    for (int i = i0 + wid; i < i1; i += kBlock / 64) {
         const TM* row = M + (int64_t)i * ldm;
         double acc = 0.0;
         if (!tail) {
@@ -438,11 +441,20 @@ void launch_reduce_parts(hipStream_t s, int nvec, int nparts, const double* part
 
 size_t rows_dot_partial_elems(int m, int64_t N) { return (size_t)m * (size_t)cdiv(N, kRowChunk); }
 
+// row groups of the J v pass: enough blocks for about 2048 in all (8 per CU),
+// at least 4 rows (one per wave) per group
+static int rows_dot_rows_per(int m, int nchunk) {
+    const int groups = (int)std::clamp<int64_t>(cdiv(2048, nchunk), 1, cdiv(m, 4));
+    return (int)(cdiv(cdiv(m, groups), 4) * 4);
+}
+
 int launch_rows_dot_partial(hipStream_t s, int m, int64_t N, const double* M, int64_t ldm, const double* v,
                             double* partial) {
     const int nchunk = (int)cdiv(N, kRowChunk);
     if (m <= 0) return nchunk;
-    hipLaunchKernelGGL((k_rows_dot<double>), dim3(nchunk), dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
+    const int rp = rows_dot_rows_per(m, nchunk);
+    hipLaunchKernelGGL((k_rows_dot<double>), dim3(nchunk, (unsigned)cdiv(m, rp)), dim3(kBlock), 0, s, m, rp, N, M,
+                       ldm, v, partial);
     H1W_LAUNCHED();
     return nchunk;
 }
@@ -451,7 +463,9 @@ int launch_rows_dot_partial_f32(hipStream_t s, int m, int64_t N, const float* M,
                                 double* partial) {
     const int nchunk = (int)cdiv(N, kRowChunk);
     if (m <= 0) return nchunk;
-    hipLaunchKernelGGL((k_rows_dot<float>), dim3(nchunk), dim3(kBlock), 0, s, m, N, M, ldm, v, partial);
+    const int rp = rows_dot_rows_per(m, nchunk);
+    hipLaunchKernelGGL((k_rows_dot<float>), dim3(nchunk, (unsigned)cdiv(m, rp)), dim3(kBlock), 0, s, m, rp, N, M,
+                       ldm, v, partial);
     H1W_LAUNCHED();
     return nchunk;
 }
