@@ -333,7 +333,7 @@ h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx);
  * a HIP stream (default priority) and one context per (grid, precision,
  * smoothing steps, beta, graph replay) it meets, reused by later items of
  * that key. Workers are kept for the process and reused by later batches
- * (at most 12 contexts each, the least recently used dropped beyond that; a
+ * (at most 24 contexts each, the least recently used dropped beyond that; a
  * context whose item failed is dropped), so their device memory stays
  * allocated until the process ends; a batch on grids met before allocates
  * no device memory. With opts.autotune, the first item of

@@ -29,13 +29,21 @@ CFLAGS = [
 ]
 
 
+# host-code AddressSanitizer build (device code is built as usual): for CPU
+# tests of the host paths (argument validation, error handling) under ASan
+ASAN_LIB = os.path.join(PKG, "libh1w_asan.so")
+ASAN_FLAGS = ["-O1", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+def _compile(src: str, asan: bool = False) -> str:
+    out = os.path.join(BUILD, "asan") if asan else BUILD
+    obj = os.path.join(out, os.path.basename(src) + ".o")
+    flags = [f for f in CFLAGS if f != "-O3"] + ASAN_FLAGS if asan else CFLAGS
+    cmd = [HIPCC, *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -45,20 +53,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, asan: bool = False) -> str:
+    """Compile and link libh1w.so (or, with asan, libh1w_asan.so: host code
+    instrumented by AddressSanitizer, whose runtime the loading process must
+    preload)."""
+    os.makedirs(os.path.join(BUILD, "asan") if asan else BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, asan), srcs))
+    lib = ASAN_LIB if asan else LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(asan="--asan" in sys.argv[1:]))

@@ -72,7 +72,7 @@ struct ShapeKey {
     }
 };
 
-constexpr int kMaxCtxPerWorker = 12;
+constexpr int kMaxCtxPerWorker = 24;
 
 struct TuneKey {
     int dim, n0, n1, n2, precision, bucket;

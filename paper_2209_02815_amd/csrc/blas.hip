@@ -12,7 +12,6 @@ namespace h1w {
 namespace {
 
 constexpr int kDotBlocks = 1024;   // max blocks of a dot-product pass
-constexpr int kRowsPerBlock = 8;   // rows of J per block in J v
 constexpr int kRowChunk = kBlock * 8;   // nodes per block in J v
 constexpr int kTile = 256;         // rows of J staged in LDS per sweep in J^T v
 
@@ -101,41 +100,46 @@ __global__ __launch_bounds__(kBlock) void k_rows_dot(int m, int rows_per, int64_
     }
 }
 
-// Two products in one pass over M: partial sums of M[i,:].v1 and M[i,:].v2.
-__global__ __launch_bounds__(kBlock) void k_rows_dot2(int m, int64_t N, const double* __restrict__ M, int64_t ldm,
-                                                      const double* __restrict__ v1, const double* __restrict__ v2,
-                                                      double* __restrict__ part1, double* __restrict__ part2) {
-    __shared__ double sh[kBlock / 64];
+// Two products in one pass over M: partial sums of M[i,:].v1 and M[i,:].v2,
+// in the layout and order of k_rows_dot (block (chunk, row group), a wave per
+// row, lane pairs of nodes).
+__global__ __launch_bounds__(kBlock) void k_rows_dot2(int m, int rows_per, int64_t N, const double* __restrict__ M,
+                                                      int64_t ldm, const double* __restrict__ v1,
+                                                      const double* __restrict__ v2, double* __restrict__ part1,
+                                                      double* __restrict__ part2) {
+    constexpr int E = kRowChunk / 128;
     const int nchunk = gridDim.x;
     const int64_t base = (int64_t)blockIdx.x * kRowChunk;
-    constexpr int E = kRowChunk / kBlock;
-    double a1[E], a2[E];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double a0[E], a1[E], b0[E], b1[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int64_t n = base + e * kBlock + threadIdx.x;
-        a1[e] = n < N ? v1[n] : 0.0;
-        a2[e] = n < N ? v2[n] : 0.0;
+        const int64_t n = base + 128 * e + 2 * lane;
+        a0[e] = n < N ? v1[n] : 0.0;
+        a1[e] = n + 1 < N ? v1[n + 1] : 0.0;
+        b0[e] = n < N ? v2[n] : 0.0;
+        b1[e] = n + 1 < N ? v2[n + 1] : 0.0;
     }
-    const int r0 = blockIdx.y * kRowsPerBlock;
-    for (int rr = 0; rr < kRowsPerBlock; ++rr) {
-        const int i = r0 + rr;
-        if (i >= m) break;
+    const bool tail = base + kRowChunk > N;
+    const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
+    for (int i = i0 + wid; i < i1; i += kBlock / 64) {
         const double* row = M + (int64_t)i * ldm;
         double s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int64_t n = base + e * kBlock + threadIdx.x;
-            if (n < N) {
-                const double x = row[n];
-                s1 += x * a1[e];
-                s2 += x * a2[e];
-            }
+            const int64_t n = base + 128 * e + 2 * lane;
+            const double x0 = (!tail || n < N) ? row[n] : 0.0;
+            const double x1 = (!tail || n + 1 < N) ? row[n + 1] : 0.0;
+            s1 = fma(x0, a0[e], s1);
+            s1 = fma(x1, a1[e], s1);
+            s2 = fma(x0, b0[e], s2);
+            s2 = fma(x1, b1[e], s2);
         }
-        const double t1 = block_sum<kBlock>(s1, sh);
-        const double t2 = block_sum<kBlock>(s2, sh);
-        if (threadIdx.x == 0) {
-            part1[(int64_t)i * nchunk + blockIdx.x] = t1;
-            part2[(int64_t)i * nchunk + blockIdx.x] = t2;
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        if (lane == 0) {
+            part1[(int64_t)i * nchunk + blockIdx.x] = s1;
+            part2[(int64_t)i * nchunk + blockIdx.x] = s2;
         }
     }
 }
@@ -498,8 +502,9 @@ int launch_rows_dot2_partial(hipStream_t s, int m, int64_t N, const double* M, i
                              const double* v2, double* part1, double* part2) {
     const int nchunk = (int)cdiv(N, kRowChunk);
     if (m <= 0) return nchunk;
-    const dim3 grid(nchunk, (unsigned)cdiv(m, kRowsPerBlock));
-    hipLaunchKernelGGL(k_rows_dot2, grid, dim3(kBlock), 0, s, m, N, M, ldm, v1, v2, part1, part2);
+    const int rp = rows_dot_rows_per(m, nchunk);
+    hipLaunchKernelGGL(k_rows_dot2, dim3(nchunk, (unsigned)cdiv(m, rp)), dim3(kBlock), 0, s, m, rp, N, M, ldm, v1,
+                       v2, part1, part2);
     H1W_LAUNCHED();
     return nchunk;
 }

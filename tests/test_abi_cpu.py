@@ -44,7 +44,7 @@ def test_status_strings_and_notimpl():
 
 @pytest.mark.parametrize("bad", [
     dict(dim=4), dict(n=(1, 9, 9)), dict(beta=0.0), dict(beta=float("nan")), dict(precision=7),
-    dict(nu=-1), dict(cheb=(2.0, 1.0)), dict(flags=16), dict(rhs_chunk=-3),
+    dict(nu=-1), dict(cheb=(2.0, 1.0)), dict(flags=64), dict(flags=16), dict(rhs_chunk=-3),
 ])
 def test_setup_rejects_invalid_arguments_on_host(bad):
     from paper_2209_02815_amd import _native as nat
