@@ -637,7 +637,9 @@ void launch_node_weights(hipStream_t s, int dim, const Geom& g, double* out) {
 void launch_convert_deflate(hipStream_t s, int64_t N, int k, const double* X, int64_t ldx, const double* sv,
                             const double* wv, float* Y, int64_t ldy) {
     if (k <= 0) return;
-    hipLaunchKernelGGL(k_convert_deflate, grid_for(N, k), dim3(kBlock), 0, s, N, k, X, ldx, sv, wv, Y, ldy);
+    // one thread per node walks the k rows: the weight w(p) is read once, not once per row
+    hipLaunchKernelGGL(k_convert_deflate, dim3((unsigned)cdiv(N, kBlock), 1), dim3(kBlock), 0, s, N, k, X, ldx, sv,
+                       wv, Y, ldy);
     H1W_LAUNCHED();
 }
 
