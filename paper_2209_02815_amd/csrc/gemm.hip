@@ -92,41 +92,43 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
     // group but skips its MFMAs (its SIMD time goes to the co-resident group)
     const bool idle = lower && tr == tc && wr < wc;
 
-    // loader: column lk of rows lr + 16 q, q = 0..7
+    // loader: column lk of rows lr + 16 q, q = 0..7. Rows past the end of J
+    // or Z read row 0 instead: they only feed output rows (columns) that are
+    // never stored. Columns past the K range are zeroed, at the LDS store:
+    // the loaded registers are first used there, after the chunk's MFMAs,
+    // so the loads stay in flight during the compute (a select right after
+    // the load would make the wave wait for them at once).
     const int lk = tid & 15, lr = tid >> 4;
     const double* pa[8];
     const TZ* pb[8];
-    bool va[8], vb[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int r = arow0 + lr + 16 * q;
-        va[q] = r < m;
-        pa[q] = J + (int64_t)(va[q] ? r : 0) * ldj;
+        pa[q] = J + (int64_t)(r < m ? r : 0) * ldj;
         const int c = brow0 + lr + 16 * q;
-        vb[q] = c < m2;
-        pb[q] = Z + (int64_t)(vb[q] ? c : 0) * ldz;
+        pb[q] = Z + (int64_t)(c < m2 ? c : 0) * ldz;
     }
     const int64_t k0 = (int64_t)split * kper;
     const int64_t k1 = std::min<int64_t>(N, k0 + kper);
     const int nchunk = (int)((k1 - k0 + KB - 1) / KB);
-    double ra[8], rb[8];
+    double ra[8];
+    TZ rb[8];
+    bool kin = false;
     auto gload = [&](int c) {
         const int64_t k = k0 + (int64_t)c * KB + lk;
-        const bool in = k < k1;
-        const int64_t kc = in ? k : k0;
+        kin = k < k1;
+        const int64_t kc = kin ? k : k0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const double x = pa[q][kc];
-            ra[q] = (va[q] && in) ? x : 0.0;
-            const double y = double(pb[q][kc]);
-            rb[q] = (vb[q] && in) ? y : 0.0;
+            ra[q] = pa[q][kc];
+            rb[q] = pb[q][kc];
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            sA[buf][(lr + 16 * q) * LDT + lk] = ra[q];
-            sB[buf][(lr + 16 * q) * LDT + lk] = rb[q];
+            sA[buf][(lr + 16 * q) * LDT + lk] = kin ? ra[q] : 0.0;
+            sB[buf][(lr + 16 * q) * LDT + lk] = kin ? double(rb[q]) : 0.0;
         }
     };
     d4 acc[4][4];
@@ -212,40 +214,39 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm32(int m, int m2, i
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int arow0 = tr * kTileMN, brow0 = tc * kTileMN;
 
+    // rows past the ends read row 0 and K columns past the range are zeroed
+    // at the LDS store, as in k_cap_gemm (loads stay in flight over the MFMAs)
     const int lk = tid & 31, lr = tid >> 5;
     const double* pa[16];
     const float* pb[16];
-    bool va[16], vb[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int r = arow0 + lr + 8 * q;
-        va[q] = r < m;
-        pa[q] = J + (int64_t)(va[q] ? r : 0) * ldj;
+        pa[q] = J + (int64_t)(r < m ? r : 0) * ldj;
         const int c = brow0 + lr + 8 * q;
-        vb[q] = c < m2;
-        pb[q] = Z + (int64_t)(vb[q] ? c : 0) * ldz;
+        pb[q] = Z + (int64_t)(c < m2 ? c : 0) * ldz;
     }
     const int64_t k0 = (int64_t)split * kper;
     const int64_t k1 = std::min<int64_t>(N, k0 + kper);
     const int nchunk = (int)((k1 - k0 + KB32 - 1) / KB32);
-    float ra[16], rb[16];
+    double ra[16];
+    float rb[16];
+    bool kin = false;
     auto gload = [&](int c) {
         const int64_t k = k0 + (int64_t)c * KB32 + lk;
-        const bool in = k < k1;
-        const int64_t kc = in ? k : k0;
+        kin = k < k1;
+        const int64_t kc = kin ? k : k0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const float x = (float)pa[q][kc];
-            ra[q] = (va[q] && in) ? x : 0.0f;
-            const float y = pb[q][kc];
-            rb[q] = (vb[q] && in) ? y : 0.0f;
+            ra[q] = pa[q][kc];
+            rb[q] = pb[q][kc];
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            sA[buf][(lr + 8 * q) * LDT32 + lk] = ra[q];
-            sB[buf][(lr + 8 * q) * LDT32 + lk] = rb[q];
+            sA[buf][(lr + 8 * q) * LDT32 + lk] = kin ? (float)ra[q] : 0.0f;
+            sB[buf][(lr + 8 * q) * LDT32 + lk] = kin ? rb[q] : 0.0f;
         }
     };
     f4 acc[4][4];
