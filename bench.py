@@ -306,7 +306,7 @@ def ert_bench(args):
     out = {"workload": f"ERT {sv.shape[0]}^3, {sv.n_src} pole sources, {sv.n_meas} pole-pole pairs, "
                        f"log10 sigma GRF (mean -2, std 0.5, corr 0.2)", "N": sv.N, "n_meas": sv.n_meas}
     with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec, P.Context(sv.shape, 1e-2) as hc:
-        J = torch.empty(sv.n_meas, sv.N, dtype=torch.float64, device="cuda:0")
+        J = ec.empty_jacobian()
         ec.set_kernel_timing(["ert_sens", "ert_stencil"])
         g, _, _, info = ec.forward(m, J_out=J)
         ec.reset_kernel_timing()

@@ -436,7 +436,10 @@ h1w_status h1w_ert_set_conductivity(h1w_ctx* ctx, const double* logsig);
  * kgeo        n_meas geometric factors, or NULL for 2 pi |x_a - x_b|
  * g_out       n_meas voltages g_i (may be NULL)
  * J_out       n_meas x N sensitivities, row-major with leading dimension
- *             ldj >= N (may be NULL)
+ *             ldj >= N (may be NULL). The kernel writes each row in runs of
+ *             64 values; with ldj a multiple of 16 (rows on 128-byte
+ *             boundaries) those runs do not straddle cache lines and J is
+ *             written about twice as fast as with an odd ldj
  * U_out       n_src x N pole fields u_a, leading dimension ldu >= N (may be
  *             NULL: the context keeps them for h1w_ert_vjp with U = NULL)
  * opts        rtol (0 -> 1e-12) and maxit (0 -> 500) of the batched

@@ -246,12 +246,19 @@ __global__ __launch_bounds__(kBlock) void k_ert_march(EG g, ErtLevel c, int k, M
     }
 }
 
-// Fc = P^T R on the coarse nodes that are not on a Dirichlet face (0 there)
-__global__ __launch_bounds__(kBlock) void k_ert_restrict(EG gf, EG gc, const double* __restrict__ R, int64_t ldr,
+// Fc = P^T R on the coarse nodes that are not on a Dirichlet face (0 there).
+// Work items (block of coarse nodes, row of R) go to the 8 XCDs in
+// contiguous ranges (block ids go round-robin over the XCDs): the fine plane
+// that two neighbouring coarse planes share is then read into one L2.
+__global__ __launch_bounds__(kBlock) void k_ert_restrict(EG gf, EG gc, int nblk, int total,
+                                                         const double* __restrict__ R, int64_t ldr,
                                                          double* __restrict__ Fc, int64_t ldc) {
-    const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int per = (total + 7) / 8;
+    const int u = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (u >= total) return;
+    const int64_t r = u / nblk;
+    const int64_t P = (u - r * nblk) * (int64_t)kBlock + threadIdx.x;
     if (P >= gc.N) return;
-    const int64_t r = blockIdx.y;
     int I, J, L;
     split(gc, P, I, J, L);
     double acc = 0.0;
@@ -365,8 +372,9 @@ __global__ __launch_bounds__(kBlock) void k_ert_meas(int n_meas, const int* __re
     gout[t] = k[t] * U[(int64_t)a * ldu + src[b]];
 }
 
-// Pairwise-gradient sensitivities. TN nodes per work-group, NS sources at most
-// (NS * TN = 1024); the 6 x n_src x TN edge differences sit in LDS.
+// Pairwise-gradient sensitivities, narrow form (33..64 sources). TN nodes per
+// work-group, NS sources at most (NS * TN = 1024); the 6 x n_src x TN edge
+// differences sit in LDS.
 constexpr int kSensThreads = 256;
 template <int TN, bool VJP>
 __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* __restrict__ sig, int n_src,
@@ -479,6 +487,116 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
         if (tid < TN && p < g.N) {
             double s = 0.0;
             for (int q = 0; q < G; ++q) s += red[q * TN + tid];
+            grad[p] = -s;
+        }
+    }
+}
+
+// Pairwise-gradient sensitivities, wide form (n_src <= NS, NS = 16 or 32):
+// a work-group of kSensWaves waves owns 64 consecutive nodes, one per lane,
+// and the 6 x NS x 64 edge differences of its nodes sit in LDS. Every wave
+// takes a contiguous range of measurements, so the measurement index, the
+// electrode pair and k_i are wave-uniform (scalar loads, no divergent
+// branches), and each store of J writes one 512-byte run of a row.
+constexpr int kSensWaves = 16;
+constexpr int kSensBatch = 8;  // measurements whose pair, k_i (and gbar_i) are loaded together
+template <int NS, bool VJP>
+__global__ __launch_bounds__(64 * kSensWaves) void k_ert_sens_wide(EG g, const double* __restrict__ sig, int n_src,
+                                                                   const double* __restrict__ U, int64_t ldu,
+                                                                   int n_meas, const int* __restrict__ pair,
+                                                                   const double* __restrict__ k,
+                                                                   double* __restrict__ J, int64_t ldj,
+                                                                   const double* __restrict__ gbar,
+                                                                   double* __restrict__ grad) {
+    __shared__ double dl[6 * NS * 64];
+    __shared__ double red[VJP ? kSensWaves * 64 : 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // node tiles in contiguous ranges per XCD (block ids go round-robin over
+    // the 8 XCDs): the neighbour rows and planes of a tile were mostly
+    // brought into the same L2 by the tiles next to it
+    const int ntile = (int)((g.N + 63) / 64);
+    const int per = (ntile + 7) >> 3;
+    const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (tile >= ntile) return;
+    const int64_t p = (int64_t)tile * 64 + lane;
+    const bool live = p < g.N;
+    const int64_t PY = g.nx, PZ = (int64_t)g.nx * g.ny;
+    int i = 0, j = 0, l = 0;
+    if (live) split(g, p, i, j, l);
+
+    // edge differences of the fields at the lane's node: wave w takes
+    // sources w, w + kSensWaves, ...
+    for (int s = wave; s < n_src; s += kSensWaves) {
+        double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (live) {
+            const double* u = U + (int64_t)s * ldu;
+            const double u0 = u[p];
+            if (i < g.nx - 1) d[0] = u0 - u[p + 1];
+            if (i > 0) d[1] = u0 - u[p - 1];
+            if (j < g.ny - 1) d[2] = u0 - u[p + PY];
+            if (j > 0) d[3] = u0 - u[p - PY];
+            if (l < g.nz - 1) d[4] = u0 - u[p + PZ];
+            if (l > 0) d[5] = u0 - u[p - PZ];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) dl[(e * NS + s) * 64 + lane] = d[e];
+    }
+    // edge weights of the lane's node (half its conductivity times the
+    // face-over-length factor of each incident edge)
+    double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        const double hs = 0.5 * sig[p];
+        const double gx = hs * geom_x(g, j, l), gy = hs * geom_y(g, i, l), gz = hs * geom_z(g, i, j);
+        if (i < g.nx - 1) w[0] = gx;
+        if (i > 0) w[1] = gx;
+        if (j < g.ny - 1) w[2] = gy;
+        if (j > 0) w[3] = gy;
+        if (l < g.nz - 1) w[4] = gz;
+        if (l > 0) w[5] = gz;
+    }
+    __syncthreads();
+
+    const int mper = (n_meas + kSensWaves - 1) / kSensWaves;
+    const int i0 = wave * mper, i1 = min(n_meas, i0 + mper);
+    int a_cur = -1;
+    double wa[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc_all = 0.0;
+    for (int ib = i0; ib < i1; ib += kSensBatch) {
+        int qa[kSensBatch], qb[kSensBatch];
+        double qk[kSensBatch], qg[kSensBatch];
+#pragma unroll
+        for (int u = 0; u < kSensBatch; ++u) {
+            const int ii = min(ib + u, i1 - 1);
+            qa[u] = pair[2 * ii];
+            qb[u] = pair[2 * ii + 1];
+            qk[u] = k[ii];
+            qg[u] = VJP ? gbar[ii] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSensBatch; ++u) {
+            if (ib + u >= i1) break;
+            const int a = qa[u], b = qb[u];
+            if (a != a_cur) {  // wave-uniform
+#pragma unroll
+                for (int e = 0; e < 6; ++e) wa[e] = w[e] * dl[(e * NS + a) * 64 + lane];
+                a_cur = a;
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) acc += wa[e] * dl[(e * NS + b) * 64 + lane];
+            if (VJP)
+                acc_all += qg[u] * qk[u] * acc;
+            else if (live)
+                J[(int64_t)(ib + u) * ldj + p] = -qk[u] * acc;
+        }
+    }
+    if (VJP) {
+        red[wave * 64 + lane] = acc_all;
+        __syncthreads();
+        if (wave == 0 && live) {
+            double s = 0.0;
+            for (int q = 0; q < kSensWaves; ++q) s += red[q * 64 + lane];
             grad[p] = -s;
         }
     }
@@ -655,8 +773,11 @@ void Ctx::ert_vcycle_chunk(int k, const double* F, int64_t ldf, double* X, int64
         {
             const EG gf = make_eg(lv[l], dmask), gc = make_eg(lv[l + 1], dmask);
             timed(H1W_K_ERT_STENCIL, ces * (gf.N + gc.N), 0.0, [&] {
-                hipLaunchKernelGGL(k_ert_restrict, dim3((unsigned)cdiv(gc.N, kBlock), (unsigned)k), dim3(kBlock), 0,
-                                   stream, gf, gc, (const double*)b, lb, fb[l + 1], pitch[l + 1]);
+                const int nblk = (int)cdiv(gc.N, kBlock);
+                require((int64_t)nblk * k < (int64_t(1) << 31), "ERT restriction launch too large");
+                const int total = nblk * k;
+                hipLaunchKernelGGL(k_ert_restrict, dim3((unsigned)(8 * cdiv(total, 8))), dim3(kBlock), 0, stream, gf,
+                                   gc, nblk, total, (const double*)b, lb, fb[l + 1], pitch[l + 1]);
                 H1W_LAUNCHED();
             });
         }
@@ -714,19 +835,29 @@ void Ctx::ert_sens(int n_src, const double* U, int64_t ldu, int n_meas, const in
     const EG g = make_eg(lv[0], dmask);
     const double* sig = ert_level(0).sig;
     const bool vjp = gbar != nullptr;
-    const int tn = n_src <= 32 ? 32 : 16;
-    const unsigned blocks = (unsigned)(8 * cdiv(cdiv(g.N, tn), 8));
     const double nn = (double)g.N;
     const double bytes = vjp ? 8.0 * nn * (n_src + 2.0) : 8.0 * nn * (n_src + 1.0 + n_meas);
     timed(H1W_K_ERT_SENS, bytes, 12.0 * n_meas * nn, [&] {
-        if (tn == 32) {
-            if (vjp)
-                hipLaunchKernelGGL((k_ert_sens<32, true>), dim3(blocks), dim3(kSensThreads), 0, stream, g, sig, n_src,
-                                   U, ldu, n_meas, pair, k, J, ldj, gbar, grad);
-            else
-                hipLaunchKernelGGL((k_ert_sens<32, false>), dim3(blocks), dim3(kSensThreads), 0, stream, g, sig, n_src,
-                                   U, ldu, n_meas, pair, k, J, ldj, gbar, grad);
+        if (n_src <= 32) {
+            const unsigned blocks = (unsigned)(8 * cdiv(cdiv(g.N, 64), 8));
+            const dim3 block(64 * kSensWaves);
+#define H1W_SENS_WIDE(NS, V)                                                                                      \
+    hipLaunchKernelGGL((k_ert_sens_wide<NS, V>), dim3(blocks), block, 0, stream, g, sig, n_src, U, ldu, n_meas, pair, \
+                       k, J, ldj, gbar, grad)
+            if (n_src <= 16) {
+                if (vjp)
+                    H1W_SENS_WIDE(16, true);
+                else
+                    H1W_SENS_WIDE(16, false);
+            } else {
+                if (vjp)
+                    H1W_SENS_WIDE(32, true);
+                else
+                    H1W_SENS_WIDE(32, false);
+            }
+#undef H1W_SENS_WIDE
         } else {
+            const unsigned blocks = (unsigned)(8 * cdiv(cdiv(g.N, 16), 8));
             if (vjp)
                 hipLaunchKernelGGL((k_ert_sens<16, true>), dim3(blocks), dim3(kSensThreads), 0, stream, g, sig, n_src,
                                    U, ldu, n_meas, pair, k, J, ldj, gbar, grad);

@@ -70,15 +70,24 @@ class ErtContext:
     def set_conductivity(self, logsig):
         nat.h1w_ert_set_conductivity(self.handle, logsig)
 
+    def empty_jacobian(self):
+        """An uninitialised n_meas x N FP64 J on the context's device whose rows
+        start on 128-byte boundaries (row pitch N rounded up to 16 values): the
+        sensitivity kernel writes each row in 512-byte runs, and runs that
+        straddle cache lines write J at about half the rate."""
+        import torch
+        ld = -(-self.N // 16) * 16
+        return torch.empty(self.n_meas, ld, dtype=torch.float64, device=self.src.device)[:, :self.N]
+
     def forward(self, logsig=None, jacobian: bool = False, fields: bool = False, rtol: float = 0.0,
                 maxit: int = 0, J_out=None, U_out=None):
         """(g, J or None, U or None, info) for log-conductivity logsig (None:
-        the conductivity already set)."""
+        the conductivity already set). A J allocated here has the row pitch of
+        empty_jacobian()."""
         import torch
         dev = self.src.device
         g = torch.empty(self.n_meas, dtype=torch.float64, device=dev)
-        J = J_out if J_out is not None else (
-            torch.empty(self.n_meas, self.N, dtype=torch.float64, device=dev) if jacobian else None)
+        J = J_out if J_out is not None else (self.empty_jacobian() if jacobian else None)
         U = U_out if U_out is not None else (
             torch.empty(self.n_src, self.N, dtype=torch.float64, device=dev) if fields else None)
         info = nat.h1w_ert_sensitivities(self.handle, self.src, self.pair, logsig, self.kgeo, g, J, U,
@@ -153,7 +162,7 @@ def ert_gauss_newton(ert: ErtContext, h1, m0, m_ref, g_obs, alpha: float, steps:
     import torch
     m = m0.clone()
     dev = m.device
-    J = torch.empty(ert.n_meas, ert.N, dtype=torch.float64, device=dev)
+    J = ert.empty_jacobian()
     dm = torch.empty_like(m)
     g = torch.empty(ert.n_meas, dtype=torch.float64, device=dev)
     hist = []
