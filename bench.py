@@ -23,6 +23,7 @@ Prints one JSON line (see the keys below).
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -404,11 +405,12 @@ def batch_bench(args, threads):
     # autotune 2: the timed call tunes every key again (tuning cost included)
     for label, prec, nw, tune, gr in (("fp64", nat.H1W_FP64, 8, 1, False),
                                       ("mixed", nat.H1W_MIXED, 8, 1, False),
-                                      ("fp64_fixed_nu", nat.H1W_FP64, 8, 0, False),
-                                      ("mixed_fixed_nu", nat.H1W_MIXED, 8, 0, False),
+                                      ("fp64_untuned", nat.H1W_FP64, 8, 0, False),
+                                      ("mixed_untuned", nat.H1W_MIXED, 8, 0, False),
                                       ("fp64_tuning_in_timed_call", nat.H1W_FP64, 8, 2, False),
                                       ("fp64_graphs", nat.H1W_FP64, 8, 1, True),
-                                      ("fp64_one_worker", nat.H1W_FP64, 1, 0, False)):
+                                      ("fp64_one_worker", nat.H1W_FP64, 1, 0, False),
+                                      ("fp64_one_worker_autotuned", nat.H1W_FP64, 1, 1, False)):
         torch.cuda.synchronize()
         tw = time.perf_counter()
         nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol, graphs=gr)
@@ -428,7 +430,9 @@ def batch_bench(args, threads):
                       "worst_relres_true": worst, "ms_warmup_call": 1e3 * dt_warm,
                       "ms_timed_calls": [round(1e3 * t, 2) for t in times],
                       "contexts": "kept from the warmup call",
-                      "nu_chosen": sorted({rep.tuned[k].nu for k in range(rep.ntuned)}) if tune else None}
+                      "cheb_lo_chosen": (dict(sorted(collections.Counter(
+                          round(rep.tuned[k].cheb_lo, 2) for k in range(rep.ntuned)).items()))
+                          if tune else None)}
         log(f"batch {label}: {out[label]}")
     return out
 

@@ -331,16 +331,19 @@ h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx);
  * The items are ordered by decreasing work N * (m + 1) and pulled from one
  * queue by opts.nworkers host threads; each thread drives a worker that owns
  * a HIP stream (default priority) and one context per (grid, precision,
- * smoothing steps, beta, graph replay) it meets, reused by later items of
+ * smoother schedule, beta, graph replay) it meets, reused by later items of
  * that key. Workers are kept for the process and reused by later batches
  * (at most 24 contexts each, the least recently used dropped beyond that; a
  * context whose item failed is dropped), so their device memory stays
  * allocated until the process ends; a batch on grids met before allocates
- * no device memory. With opts.autotune, the first item of
- * each (grid, precision, ceil(log2 m)) key is solved with nu = 1, 3 and 2
- * smoothing steps per side back to back by one worker, and the later items
- * of the key use the nu with the shortest wall time (the nu = 2 solve is the
- * item's result; until a key is tuned its items use nu = 2, or opts.nu).
+ * no device memory. With opts.autotune, the smoother schedule is tuned per
+ * (grid, precision) key: the first item of a key is solved by one worker,
+ * back to back, with the Chebyshev intervals [0.4, 2] and [0.5, 2] for
+ * eig(D^-1 A) and then the default [0.3, 2] (opts.nu smoothing steps per side
+ * in each; the same kernels per iteration), and the later items of the key
+ * use the interval with the fewest CG iterations, the default on a tie (the
+ * default solve is the item's result; until a key is tuned its items use the
+ * default).
  * Items of one grid must share beta. All pointers are device
  * pointers owned by the caller; J, b, x follow h1w_gn_solve (J m x N with
  * leading dimension ldj, x receives the solution). infos and status (count
@@ -363,7 +366,7 @@ typedef struct {
 typedef struct {
     int precision;       /* H1W_FP64 or H1W_MIXED, for every item */
     int nworkers;        /* host threads / streams (0 -> 8, at most 16) */
-    int autotune;        /* 1: choose the smoothing steps per key as described above,
+    int autotune;        /* 1: choose the smoother schedule per grid as described above,
                             reusing the keys tuned by earlier batches of the process;
                             2: tune every key again (and keep the new choice); 0: off */
     int nu;              /* smoothing steps when not tuned (0 -> 2) */
@@ -377,10 +380,13 @@ typedef struct {
 typedef struct {
     int dim;
     int n[3];
-    int m_bucket;        /* ceil(log2 m) */
-    int nu;              /* chosen smoothing steps */
-    double ms_per_unit;  /* its wall time per N * (m + 1), in ms */
+    int m_bucket;        /* ceil(log2 m) of the item the key was tuned on */
+    int nu;              /* smoothing steps per side (opts.nu) */
+    double ms_per_unit;  /* the chosen schedule's wall time per N * (m + 1), in ms */
     int reused;          /* 1: the choice of an earlier batch */
+    double cheb_lo;      /* chosen lower end of the Chebyshev interval (upper end 2) */
+    int iters;           /* CG iterations of the tuning item with the chosen schedule */
+    int iters_default;   /* ... and with the default one */
 } h1w_batch_tuned;
 
 typedef struct {

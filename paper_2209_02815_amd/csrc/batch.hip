@@ -5,7 +5,7 @@
 // Executor: the instances are sorted by decreasing work (N * (m + 1)) and
 // pulled from a shared queue by nworkers host threads. Each thread drives one
 // worker: a HIP stream (default priority) and one context per (grid,
-// precision, smoother steps, beta, graph replay) it has met, so the
+// precision, smoother schedule, beta, graph replay) it has met, so the
 // hierarchy, the coarsest inverse and the device workspace are set up once
 // per key and reused by later instances. Workers are kept for the process
 // (per device, at most kMaxCtxPerWorker contexts each, the least recently
@@ -18,21 +18,25 @@
 // streams let the small kernels and host round trips of different instances
 // overlap.
 //
-// Autotuner: for each (grid, precision, row bucket ceil(log2 m)) key, the
-// worker that meets the key first solves that instance with nu = 1, 3 and
-// then 2 smoothing steps per side, back to back on its own stream, twice over
-// (the faster of each candidate's two runs counts), and the later instances
-// of the key use nu = 1 or 3 only if its wall time is below 0.75 times that
-// of the default; the losing candidates' contexts are dropped at once, so
-// that they do not push the contexts later batches use out of the worker's
-// cache (the candidates are compared on the same
-// system, so differences in m, alpha and iteration count between instances
-// do not enter; the margin covers the launches that a single solve's wall
-// time undercounts and the batch pays for). The last tuning solve
-// (nu = 2) is the instance's result; while a key is being tuned, other
-// workers solve its instances with the default nu. Tuned keys are kept for
-// the process: a later batch reuses them (autotune = 1) or tunes them again
-// (autotune = 2).
+// Autotuner: it picks the smoother schedule of the V-cycle, i.e. the lower
+// end of the Chebyshev interval for eig(D^-1 A) at the batch's number of
+// smoothing steps (the upper end stays 2, a bound of that spectrum), per
+// (grid, precision) key: the schedule changes B, not J, so the rows and alpha
+// of an instance do not enter, and one context per grid serves every instance
+// of it. The worker that meets a key first solves that instance with each
+// candidate interval and then the default, back to back on its own stream.
+// The candidates differ only in the smoother's Chebyshev weights (the same
+// kernels and launches per CG iteration), so the one with the fewest CG
+// iterations has the shortest time to solution; the tuner compares iteration
+// counts, which, unlike the wall time of one small solve while other workers
+// share the GPU, do not depend on timing; a tie keeps the default. On the 2D
+// grids of the batch workload [0.4, 2] and [0.5, 2] need 6 iterations where
+// the default [0.3, 2] needs 7; on 3D grids all three need 7. The losing
+// candidates' contexts are dropped at once, so that they do not push the
+// contexts later batches use out of the worker's cache. The default's solve
+// is the instance's result; while a key is being tuned, other workers solve
+// its instances with the default. Tuned keys are kept for the process: a
+// later batch reuses them (autotune = 1) or tunes them again (autotune = 2).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -49,18 +53,20 @@ namespace h1w {
 
 namespace {
 
-constexpr int kTuneCandidates[] = {1, 3, 2};  // the default last: its solution is kept
+// smoother schedules tried by the tuner (lower Chebyshev bound with the
+// upper bound kChebHiDefault; 0 = the default interval, last: its solution
+// is kept)
+constexpr double kTuneLo[] = {0.4, 0.5, 0.0};
 constexpr int kNumCandidates = 3;
-constexpr double kTuneMargin = 0.75;  // another nu is kept only below 0.75 x the default's time
-constexpr int kTuneReps = 2;         // timed solves per candidate (the faster counts)
 
 struct GridKey {
     int dim, n0, n1, n2, precision, nu;
+    double cheb_lo;  // 0: the default interval
     double beta;
     bool graphs;
     bool operator<(const GridKey& o) const {
-        return std::tie(dim, n0, n1, n2, precision, nu, beta, graphs) <
-               std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu, o.beta, o.graphs);
+        return std::tie(dim, n0, n1, n2, precision, nu, cheb_lo, beta, graphs) <
+               std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu, o.cheb_lo, o.beta, o.graphs);
     }
 };
 
@@ -75,10 +81,9 @@ struct ShapeKey {
 constexpr int kMaxCtxPerWorker = 24;
 
 struct TuneKey {
-    int dim, n0, n1, n2, precision, bucket;
+    int dim, n0, n1, n2, precision;
     bool operator<(const TuneKey& o) const {
-        return std::tie(dim, n0, n1, n2, precision, bucket) <
-               std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.bucket);
+        return std::tie(dim, n0, n1, n2, precision) < std::tie(o.dim, o.n0, o.n1, o.n2, o.precision);
     }
 };
 
@@ -93,8 +98,10 @@ struct TuneState {
     bool claimed = false;                    // a worker is tuning (or has tuned) the key
     bool done = false;
     bool reused = false;                     // taken from an earlier batch of the process
-    double best = -1.0;                      // wall time per N (m + 1) of the best candidate
-    int best_nu = 2;
+    double best = -1.0;                      // wall time per N (m + 1) of the chosen candidate
+    double best_lo = 0.0;                    // its lower Chebyshev bound (0: the default)
+    int best_iters = 0, def_iters = 0;       // CG iterations of the chosen candidate and the default
+    int bucket = 0;                          // ceil(log2 m) of the instance it was tuned on
 };
 
 // tuning results of earlier batches in this process
@@ -167,10 +174,11 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     std::vector<std::string> worker_err(nworkers);
     std::vector<std::string> item_err(count);
 
-    // nu for an instance of key tk; tuning = this worker tunes the key now
-    auto choose_nu = [&](const TuneKey& tk, bool& tuning) -> int {
+    // schedule (lower Chebyshev bound, 0 = default) for an instance of key tk;
+    // tuning = this worker tunes the key now
+    auto choose_lo = [&](const TuneKey& tk, bool& tuning) -> double {
         tuning = false;
-        if (!o.autotune) return nu_fixed;
+        if (!o.autotune) return 0.0;
         std::lock_guard<std::mutex> lk(tune_mu);
         TuneState& ts = tune[tk];
         if (!ts.claimed && o.autotune == 1) {  // a choice of an earlier batch
@@ -184,15 +192,18 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
         if (!ts.claimed) {
             ts.claimed = true;
             tuning = true;
-            return nu_fixed;
+            return 0.0;
         }
-        return ts.done ? ts.best_nu : nu_fixed;
+        return ts.done ? ts.best_lo : 0.0;
     };
-    auto finish_tuning = [&](const TuneKey& tk, int nu, double t_norm) {
+    auto finish_tuning = [&](const TuneKey& tk, double lo, double t_norm, int its, int its_def, int bucket) {
         std::lock_guard<std::mutex> lk(tune_mu);
         TuneState& ts = tune[tk];
         ts.best = t_norm;
-        ts.best_nu = nu;
+        ts.best_lo = lo;
+        ts.best_iters = its;
+        ts.def_iters = its_def;
+        ts.bucket = bucket;
         ts.done = true;
     };
 
@@ -230,13 +241,16 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 require(it.b != nullptr && it.x != nullptr && (it.m == 0 || it.J != nullptr),
                         "item b, x (and J when m > 0) must not be NULL");
                 const int n2 = it.dim == 3 ? it.n[2] : 1;
-                TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision, row_bucket(it.m)};
+                TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision};
                 bool tuning = false;
-                const int nu = choose_nu(tk, tuning);
+                const double lo = choose_lo(tk, tuning);
                 require(std::isfinite(it.beta) && it.beta == grid_beta[ShapeKey{it.dim, it.n[0], it.n[1], n2}],
                         "items of one grid must share beta within a batch");
-                auto ctx_for = [&](int nu_c) -> Ctx& {
-                    GridKey gk{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c, it.beta, o.graphs != 0};
+                auto gkey = [&](double lo_c) {
+                    return GridKey{it.dim, it.n[0], it.n[1], n2, o.precision, nu_fixed, lo_c, it.beta, o.graphs != 0};
+                };
+                auto ctx_for = [&](double lo_c) -> Ctx& {
+                    const GridKey gk = gkey(lo_c);
                     me.last_use[gk] = ++me.clock;
                     used.push_back(gk);
                     auto& slot = me.ctxs[gk];
@@ -261,7 +275,11 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                         d.n[2] = n2;
                         d.beta = it.beta;
                         d.precision = o.precision;
-                        d.nu = nu_c;
+                        d.nu = nu_fixed;
+                        if (lo_c > 0.0) {
+                            d.cheb_lo = lo_c;
+                            d.cheb_hi = kChebHiDefault;
+                        }
                         d.flags = o.graphs ? H1W_FLAG_GRAPH_VCYCLE : 0u;
                         auto c = std::make_unique<Ctx>();
                         c->init(d, me.stream);
@@ -274,69 +292,58 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                     return *me.ctxs[gk];
                 };
                 require(std::isfinite(it.alpha) && it.alpha > 0.0, "item alpha must be finite and > 0");
-                require(it.m == 0 || it.ldj >= ctx_for(nu).N(), "item ldj must be >= N");
+                require(it.m == 0 || it.ldj >= ctx_for(lo).N(), "item ldj must be >= N");
                 h1w_solve_opts so{};
                 so.rtol = o.rtol;
                 so.maxit = o.maxit;
                 if (!tuning) {
-                    ctx_for(nu).gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
+                    ctx_for(lo).gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
                 } else {
                     // the candidates on this instance, the default last (its x is the result)
-                    int best_nu = nu_fixed;
-                    double best = -1.0, t_alt = -1.0, t_def = -1.0;
-                    int alt_nu = nu_fixed;
-                    bool failed[kNumCandidates] = {};
-                    // every candidate twice (the faster run counts: the first run
-                    // of a new context also sets it up); the default solves last
-                    for (int cc = 0; cc < kTuneReps * kNumCandidates; ++cc) {
-                        const int c = cc % kNumCandidates;
-                        const int nu_c = c + 1 == kNumCandidates ? nu_fixed : kTuneCandidates[c];
-                        if ((c + 1 < kNumCandidates && nu_c == nu_fixed) || failed[c]) continue;
-                        Ctx& cx = ctx_for(nu_c);
+                    double t_def = -1.0, t_best = -1.0, best_lo = 0.0;
+                    int it_def = -1, it_best = -1;
+                    for (int c = 0; c < kNumCandidates; ++c) {
+                        const double lo_c = kTuneLo[c];
+                        Ctx& cx = ctx_for(lo_c);
                         cx.sync();
                         const auto t0 = std::chrono::steady_clock::now();
-                        if (nu_c == nu_fixed) {
+                        if (lo_c == 0.0) {
                             cx.gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
                         } else {
                             try {  // a candidate that fails (e.g. no convergence) is skipped
                                 cx.gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
                             } catch (const Error&) {
-                                failed[c] = true;
                                 used.pop_back();
-                                drop(GridKey{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c, it.beta,
-                                             o.graphs != 0});
+                                drop(gkey(lo_c));
                                 continue;
                             }
                         }
                         const double ms =
                             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                        if (nu_c == nu_fixed) {
-                            t_def = t_def < 0.0 ? ms : std::min(t_def, ms);
-                        } else if (t_alt < 0.0 || ms < t_alt) {
-                            t_alt = ms;
-                            alt_nu = nu_c;
+                        if (lo_c == 0.0) {
+                            t_def = ms;
+                            it_def = inf.iters;
+                        } else if (it_best < 0 || inf.iters < it_best) {
+                            t_best = ms;
+                            it_best = inf.iters;
+                            best_lo = lo_c;
                         }
                     }
-                    // another nu must beat the default by kTuneMargin: one solve's
-                    // wall time undercounts what the batch pays for the extra
-                    // launches of the unfused candidates (the default nu = 2 has
-                    // the fused passes)
-                    best_nu = nu_fixed;
-                    best = t_def;
-                    if (t_alt >= 0.0 && (t_def < 0.0 || t_alt < kTuneMargin * t_def)) {
-                        best_nu = alt_nu;
-                        best = t_alt;
+                    // a candidate replaces the default only with fewer iterations
+                    double best = t_def;
+                    if (it_best >= 0 && it_best < it_def) {
+                        best = t_best;
+                    } else {
+                        best_lo = 0.0;
+                        it_best = it_def;
                     }
-                    finish_tuning(tk, best_nu, best / work(i));
+                    finish_tuning(tk, best_lo, best / work(i), it_best, it_def, row_bucket(it.m));
                     // the losing candidates' contexts are not used again by
                     // this key: dropped now (in the tuning call) rather than
                     // by the LRU cap later, when a timed batch would pay for
                     // re-creating what they pushed out
-                    for (int c = 0; c + 1 < kNumCandidates; ++c) {
-                        const int nu_c = kTuneCandidates[c];
-                        if (nu_c != best_nu && nu_c != nu_fixed)
-                            drop(GridKey{it.dim, it.n[0], it.n[1], n2, o.precision, nu_c, it.beta, o.graphs != 0});
-                    }
+                    for (int c = 0; c < kNumCandidates; ++c)
+                        if (kTuneLo[c] != best_lo && kTuneLo[c] != 0.0) drop(gkey(kTuneLo[c]));
                 }
             } catch (const Error& e) {
                 st = e.st;
@@ -393,8 +400,11 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
             r.n[0] = tk.n0;
             r.n[1] = tk.n1;
             r.n[2] = tk.n2;
-            r.m_bucket = tk.bucket;
-            r.nu = ts.best_nu;
+            r.m_bucket = ts.bucket;
+            r.nu = nu_fixed;
+            r.cheb_lo = ts.best_lo > 0.0 ? ts.best_lo : kChebLoDefault;
+            r.iters = ts.best_iters;
+            r.iters_default = ts.def_iters;
             r.ms_per_unit = ts.best;
             r.reused = ts.reused ? 1 : 0;
         }

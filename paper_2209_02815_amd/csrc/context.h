@@ -11,6 +11,10 @@
 
 namespace h1w {
 
+// default Chebyshev interval for the eigenvalues of D^-1 A (grid_desc cheb_lo,
+// cheb_hi both 0): 2 bounds that spectrum for the 5- and 7-point operators
+constexpr double kChebLoDefault = 0.3, kChebHiDefault = 2.0;
+
 // coefficient arrays of one ERT level (each N_l long, pitch-aligned)
 struct ErtLevel {
     double *sig, *D, *cx, *cy, *cz;

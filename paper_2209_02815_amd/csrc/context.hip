@@ -141,8 +141,8 @@ void Ctx::init(const h1w_grid_desc& desc, hipStream_t s) {
     require(d.rhs_chunk >= 0 && d.rhs_chunk <= 65535, "rhs_chunk must be in [0, 65535]");
     if (d.nu == 0) d.nu = 2;
     if (d.cheb_lo == 0.0 && d.cheb_hi == 0.0) {
-        d.cheb_lo = 0.3;
-        d.cheb_hi = 2.0;
+        d.cheb_lo = kChebLoDefault;
+        d.cheb_hi = kChebHiDefault;
     }
     require(d.cheb_lo > 0.0 && d.cheb_hi > d.cheb_lo && std::isfinite(d.cheb_hi), "need 0 < cheb_lo < cheb_hi");
     if (d.coarse_max == 0) d.coarse_max = ert ? 125 : (dim == 3 ? 729 : 81);

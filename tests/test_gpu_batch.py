@@ -80,16 +80,22 @@ def test_batch_autotune_reports_choices(P):
     items, host = make_items(wls)
     infos, stats, rep = nat.h1w_batch_solve(items, nworkers=2, autotune=2, rtol=1e-10)   # tune every key
     assert all(s == 0 for s in stats)
-    keys = {(rep.tuned[k].n[0], rep.tuned[k].m_bucket) for k in range(rep.ntuned)}
-    assert keys == {(wl.shape[0], int(np.ceil(np.log2(wl.m)))) for wl in wls}
-    assert all(rep.tuned[k].nu in (1, 2, 3) and rep.tuned[k].ms_per_unit > 0 for k in range(rep.ntuned))
-    assert all(rep.tuned[k].reused == 0 for k in range(rep.ntuned))
-    chosen = {(rep.tuned[k].n[0], rep.tuned[k].m_bucket): rep.tuned[k].nu for k in range(rep.ntuned)}
+    # one key per grid (the smoother schedule changes B, not J)
+    tuned = [rep.tuned[k] for k in range(rep.ntuned)]
+    assert {t.n[0] for t in tuned} == {wl.shape[0] for wl in wls} and len(tuned) == 2
+    assert all(t.nu == 2 and t.ms_per_unit > 0 and t.reused == 0 for t in tuned)
+    # an interval other than the default is chosen only with fewer CG iterations
+    for t in tuned:
+        assert t.cheb_lo in (0.3, 0.4, 0.5)
+        assert 0 < t.iters <= t.iters_default
+        assert (t.cheb_lo == 0.3) == (t.iters == t.iters_default), (t.cheb_lo, t.iters, t.iters_default)
+    chosen = {t.n[0]: t.cheb_lo for t in tuned}
+    print("tuned lower Chebyshev bounds:", chosen, [(t.iters, t.iters_default) for t in tuned], flush=True)
     # a second batch of the process reuses the choices (autotune = 1)
     _, stats2, rep2 = nat.h1w_batch_solve(items, nworkers=2, autotune=1, rtol=1e-10)
     assert all(s == 0 for s in stats2)
     assert all(rep2.tuned[k].reused == 1 for k in range(rep2.ntuned))
-    assert {(rep2.tuned[k].n[0], rep2.tuned[k].m_bucket): rep2.tuned[k].nu for k in range(rep2.ntuned)} == chosen
+    assert {rep2.tuned[k].n[0]: rep2.tuned[k].cheb_lo for k in range(rep2.ntuned)} == chosen
     for wl, it, (J, b) in zip(wls, items, host):
         rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy())
         assert rr <= 1.01e-10
