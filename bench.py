@@ -308,9 +308,9 @@ def ert_bench(args):
                        f"log10 sigma GRF (mean -2, std 0.5, corr 0.2)", "N": sv.N, "n_meas": sv.n_meas}
     with P.ErtContext(sv.shape, sv.electrodes, sv.pairs) as ec, P.Context(sv.shape, 1e-2) as hc:
         J = ec.empty_jacobian()
-        ec.set_kernel_timing(["ert_sens", "ert_stencil"])
         g, _, _, info = ec.forward(m, J_out=J)
-        ec.reset_kernel_timing()
+        # timed forwards without per-kernel events; then two profiled ones
+        # for the kernel classes' rooflines
         reps = 5
         infos = []
         torch.cuda.synchronize()
@@ -320,6 +320,10 @@ def ert_bench(args):
             infos.append(info)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
+        prof = 2
+        ec.set_kernel_timing(["ert_sens", "ert_stencil"])
+        for _ in range(prof):
+            ec.forward(m, J_out=J)
         kt = ec.kernel_timing()
         ec.set_kernel_timing([])
         st = kt["ert_sens"]
@@ -329,7 +333,7 @@ def ert_bench(args):
             "t_fields_ms": float(np.median([i.t_cg_ms for i in infos])),
             "t_voltages_and_J_ms": float(np.median([i.t_gemm_ms for i in infos])),
             "sens_kernel": roofline("ert_sens", st),
-            "stencil_ms_per_forward": kt["ert_stencil"]["ms"] / reps,
+            "stencil_ms_per_forward": kt["ert_stencil"]["ms"] / prof,
         }
         log(f"ert forward: {out['forward_with_J']}")
         m_ref = torch.full_like(m, float(np.log(1e-2)))
