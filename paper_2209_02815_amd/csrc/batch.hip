@@ -81,9 +81,9 @@ struct ShapeKey {
 constexpr int kMaxCtxPerWorker = 24;
 
 struct TuneKey {
-    int dim, n0, n1, n2, precision;
+    int dim, n0, n1, n2, precision, nu;  // nu: the batch's smoothing steps, which the interval goes with
     bool operator<(const TuneKey& o) const {
-        return std::tie(dim, n0, n1, n2, precision) < std::tie(o.dim, o.n0, o.n1, o.n2, o.precision);
+        return std::tie(dim, n0, n1, n2, precision, nu) < std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu);
     }
 };
 
@@ -241,7 +241,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 require(it.b != nullptr && it.x != nullptr && (it.m == 0 || it.J != nullptr),
                         "item b, x (and J when m > 0) must not be NULL");
                 const int n2 = it.dim == 3 ? it.n[2] : 1;
-                TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision};
+                TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision, nu_fixed};
                 bool tuning = false;
                 const double lo = choose_lo(tk, tuning);
                 require(std::isfinite(it.beta) && it.beta == grid_beta[ShapeKey{it.dim, it.n[0], it.n[1], n2}],
@@ -401,7 +401,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
             r.n[1] = tk.n1;
             r.n[2] = tk.n2;
             r.m_bucket = ts.bucket;
-            r.nu = nu_fixed;
+            r.nu = tk.nu;
             r.cheb_lo = ts.best_lo > 0.0 ? ts.best_lo : kChebLoDefault;
             r.iters = ts.best_iters;
             r.iters_default = ts.def_iters;

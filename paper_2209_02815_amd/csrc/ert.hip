@@ -399,25 +399,26 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
     const int64_t j0 = (int64_t)tile * TN;
     const int64_t PY = g.nx, PZ = (int64_t)g.nx * g.ny;
 
-    // edge differences of every field at the TN nodes
+    // edge differences of every field at the TN nodes (the seven loads of an
+    // item issued together, as in the wide form)
     for (int q = tid; q < n_src * TN; q += kSensThreads) {
         const int s = q / TN, t = q - s * TN;
         const int64_t p = j0 + t;
-        double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (p < g.N) {
-            int i, j, l;
-            split(g, p, i, j, l);
-            const double* u = U + (int64_t)s * ldu;
-            const double u0 = u[p];
-            if (i < g.nx - 1) d[0] = u0 - u[p + 1];
-            if (i > 0) d[1] = u0 - u[p - 1];
-            if (j < g.ny - 1) d[2] = u0 - u[p + PY];
-            if (j > 0) d[3] = u0 - u[p - PY];
-            if (l < g.nz - 1) d[4] = u0 - u[p + PZ];
-            if (l > 0) d[5] = u0 - u[p - PZ];
-        }
+        const bool live = p < g.N;
+        int i = 0, j = 0, l = 0;
+        if (live) split(g, p, i, j, l);
+        const bool has[6] = {live && i < g.nx - 1, live && i > 0, live && j < g.ny - 1,
+                             live && j > 0,        live && l < g.nz - 1, live && l > 0};
+        const int64_t pc = live ? p : 0;
+        const int64_t nb[6] = {has[0] ? p + 1 : pc,  has[1] ? p - 1 : pc,  has[2] ? p + PY : pc,
+                               has[3] ? p - PY : pc, has[4] ? p + PZ : pc, has[5] ? p - PZ : pc};
+        const double* u = U + (int64_t)s * ldu;
+        double un[6];
+        const double u0 = u[pc];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) dl[(e * NS + s) * TN + t] = d[e];
+        for (int e = 0; e < 6; ++e) un[e] = u[nb[e]];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) dl[(e * NS + s) * TN + t] = has[e] ? u0 - un[e] : 0.0;
     }
     if (tid < TN) {
         const int64_t p = j0 + tid;
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(kSensThreads) void k_ert_sens(EG g, const double* _
 // electrode pair and k_i are wave-uniform (scalar loads, no divergent
 // branches), and each store of J writes one 512-byte run of a row.
 constexpr int kSensWaves = 16;
-constexpr int kSensBatch = 8;  // measurements whose pair, k_i (and gbar_i) are loaded together
+constexpr int kSensBatch = 4;  // measurements whose sums are formed before their stores
 template <int NS, bool VJP>
 __global__ __launch_bounds__(64 * kSensWaves) void k_ert_sens_wide(EG g, const double* __restrict__ sig, int n_src,
                                                                    const double* __restrict__ U, int64_t ldu,
@@ -526,34 +527,31 @@ __global__ __launch_bounds__(64 * kSensWaves) void k_ert_sens_wide(EG g, const d
     if (live) split(g, p, i, j, l);
 
     // edge differences of the fields at the lane's node: wave w takes
-    // sources w, w + kSensWaves, ...
+    // sources w, w + kSensWaves, ... The seven loads of a source are issued
+    // together (an absent neighbour's address falls back to the node itself,
+    // and its difference is set to 0), not one conditional load at a time.
+    const bool has[6] = {live && i < g.nx - 1, live && i > 0, live && j < g.ny - 1,
+                         live && j > 0,        live && l < g.nz - 1, live && l > 0};
+    const int64_t pc = live ? p : 0;
+    const int64_t nb[6] = {has[0] ? p + 1 : pc,  has[1] ? p - 1 : pc,  has[2] ? p + PY : pc,
+                           has[3] ? p - PY : pc, has[4] ? p + PZ : pc, has[5] ? p - PZ : pc};
     for (int s = wave; s < n_src; s += kSensWaves) {
-        double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (live) {
-            const double* u = U + (int64_t)s * ldu;
-            const double u0 = u[p];
-            if (i < g.nx - 1) d[0] = u0 - u[p + 1];
-            if (i > 0) d[1] = u0 - u[p - 1];
-            if (j < g.ny - 1) d[2] = u0 - u[p + PY];
-            if (j > 0) d[3] = u0 - u[p - PY];
-            if (l < g.nz - 1) d[4] = u0 - u[p + PZ];
-            if (l > 0) d[5] = u0 - u[p - PZ];
-        }
+        const double* u = U + (int64_t)s * ldu;
+        double un[6];
+        const double u0 = u[pc];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) dl[(e * NS + s) * 64 + lane] = d[e];
+        for (int e = 0; e < 6; ++e) un[e] = u[nb[e]];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) dl[(e * NS + s) * 64 + lane] = has[e] ? u0 - un[e] : 0.0;
     }
     // edge weights of the lane's node (half its conductivity times the
     // face-over-length factor of each incident edge)
-    double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (live) {
-        const double hs = 0.5 * sig[p];
+    double w[6];
+    {
+        const double hs = 0.5 * sig[pc];
         const double gx = hs * geom_x(g, j, l), gy = hs * geom_y(g, i, l), gz = hs * geom_z(g, i, j);
-        if (i < g.nx - 1) w[0] = gx;
-        if (i > 0) w[1] = gx;
-        if (j < g.ny - 1) w[2] = gy;
-        if (j > 0) w[3] = gy;
-        if (l < g.nz - 1) w[4] = gz;
-        if (l > 0) w[5] = gz;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) w[e] = has[e] ? (e < 2 ? gx : (e < 4 ? gy : gz)) : 0.0;
     }
     __syncthreads();
 
@@ -562,34 +560,47 @@ __global__ __launch_bounds__(64 * kSensWaves) void k_ert_sens_wide(EG g, const d
     int a_cur = -1;
     double wa[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double acc_all = 0.0;
-    for (int ib = i0; ib < i1; ib += kSensBatch) {
+    // sum over the edges of w_e (u_a(p) - u_a(q)) (u_b(p) - u_b(q)) for
+    // measurement (a, b); w_e (u_a(p) - u_a(q)) is kept while a repeats
+    auto meas = [&](int a, int b) {
+        if (a != a_cur) {  // wave-uniform
+#pragma unroll
+            for (int e = 0; e < 6; ++e) wa[e] = w[e] * dl[(e * NS + a) * 64 + lane];
+            a_cur = a;
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) acc += wa[e] * dl[(e * NS + b) * 64 + lane];
+        return acc;
+    };
+    int ib = i0;
+    // whole batches: the sums first, then their stores back to back, so that
+    // several 512-byte runs of J are in flight per wave
+    for (; ib + kSensBatch <= i1; ib += kSensBatch) {
         int qa[kSensBatch], qb[kSensBatch];
-        double qk[kSensBatch], qg[kSensBatch];
+        double qk[kSensBatch], acc[kSensBatch];
 #pragma unroll
         for (int u = 0; u < kSensBatch; ++u) {
-            const int ii = min(ib + u, i1 - 1);
-            qa[u] = pair[2 * ii];
-            qb[u] = pair[2 * ii + 1];
-            qk[u] = k[ii];
-            qg[u] = VJP ? gbar[ii] : 0.0;
+            qa[u] = pair[2 * (ib + u)];
+            qb[u] = pair[2 * (ib + u) + 1];
+            qk[u] = k[ib + u];
         }
 #pragma unroll
-        for (int u = 0; u < kSensBatch; ++u) {
-            if (ib + u >= i1) break;
-            const int a = qa[u], b = qb[u];
-            if (a != a_cur) {  // wave-uniform
+        for (int u = 0; u < kSensBatch; ++u) acc[u] = meas(qa[u], qb[u]);
+        if (VJP) {
 #pragma unroll
-                for (int e = 0; e < 6; ++e) wa[e] = w[e] * dl[(e * NS + a) * 64 + lane];
-                a_cur = a;
-            }
-            double acc = 0.0;
+            for (int u = 0; u < kSensBatch; ++u) acc_all += gbar[ib + u] * qk[u] * acc[u];
+        } else if (live) {
 #pragma unroll
-            for (int e = 0; e < 6; ++e) acc += wa[e] * dl[(e * NS + b) * 64 + lane];
-            if (VJP)
-                acc_all += qg[u] * qk[u] * acc;
-            else if (live)
-                J[(int64_t)(ib + u) * ldj + p] = -qk[u] * acc;
+            for (int u = 0; u < kSensBatch; ++u) J[(int64_t)(ib + u) * ldj + p] = -qk[u] * acc[u];
         }
+    }
+    for (; ib < i1; ++ib) {
+        const double acc = meas(pair[2 * ib], pair[2 * ib + 1]);
+        if (VJP)
+            acc_all += gbar[ib] * k[ib] * acc;
+        else if (live)
+            J[(int64_t)ib * ldj + p] = -k[ib] * acc;
     }
     if (VJP) {
         red[wave * 64 + lane] = acc_all;
