@@ -504,7 +504,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
+        print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding is a design note "
                                    "(z-slab domain decomposition), not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
