@@ -101,6 +101,27 @@ def test_batch_autotune_reports_choices(P):
         assert rr <= 1.01e-10
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_autotune_departs_where_iterations_drop(P, prec):
+    # on 129^2 grids at rtol 1e-8 the Chebyshev interval [0.4, 2] or [0.5, 2]
+    # needs one CG iteration fewer than the default [0.3, 2]: the tuner must
+    # take it (its choice rests on iteration counts, so it is deterministic),
+    # and every instance solved with it must still meet the tolerance
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads(count=6, batch_id=9, sides=(129,), m_lo=40, m_hi=60)
+    items, host = make_items(wls)
+    precision = {"fp64": nat.H1W_FP64, "mixed": nat.H1W_MIXED}[prec]
+    infos, stats, rep = nat.h1w_batch_solve(items, precision=precision, nworkers=2, autotune=2, rtol=1e-8)
+    assert all(s == 0 for s in stats)
+    assert rep.ntuned == 1
+    t = rep.tuned[0]
+    print(f"{prec}: chosen lower bound {t.cheb_lo}, iterations {t.iters} against {t.iters_default}", flush=True)
+    assert t.cheb_lo in (0.4, 0.5) and t.iters < t.iters_default
+    for wl, it, (J, b) in zip(wls, items, host):
+        rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy())
+        assert rr <= 1.01e-8
+
+
 def test_batch_bad_item_fails_alone(P):
     from paper_2209_02815_amd import _native as nat
     wls = small_batch()[:4]
