@@ -88,7 +88,7 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix
 
 # functions whose source text decides the PMC traffic recorded for a class
 TRAFFIC_SOURCES = {"jv": ("blas.hip", ["k_rows_dot", "launch_rows_dot_partial"]),
-                   "gemm": ("gemm.hip", ["k_cap_gemm", "plan", "launch_capacitance_partial"])}
+                   "gemm": ("gemm.hip", ["cap_tile", "k_cap_gemm", "plan", "launch_capacitance_partial"])}
 # kernel symbol (prefix of the demangled name) of each class in a PMC trace
 TRAFFIC_SYMBOLS = {"jv": "k_rows_dot<double>", "gemm": "k_cap_gemm<double>"}
 
@@ -372,11 +372,12 @@ BATCH_REPS = 3
 
 def batch_bench(args, threads):
     """256 independent 2D instances of uneven size (sides {65,129,193,257}, m in
-    [16,128], log-uniform alpha in [1e-5,1e-2]) solved by h1w_batch_solve: FP64
-    and mixed with 8 workers, with the autotuner (choices made in the warmup
-    call, or again inside the timed call) and with nu = 2 fixed, FP64 with the
-    V-cycles replayed from HIP graphs, and FP64 with one worker (no overlap)
-    for reference. Before the first line, two untimed passes in each precision
+    [16,128], log-uniform alpha in [1e-5,1e-2]) solved by h1w_batch_solve:
+    FP64 and mixed in the grouped (lock-step) mode, one worker per grid; then
+    one solve per instance with 8 workers, with the autotuner (choices made in
+    the warmup call, or again inside the timed call) and with the default
+    smoother, FP64 with the V-cycles replayed from HIP graphs, and FP64 with
+    one worker (no overlap) for reference. Before the first line, two untimed passes in each precision
     (nu = 2 fixed) warm the process: the first calls of a process run slower
     for a while (about 150 against 120 ms), which would otherwise favour the
     lines timed later. Each line then has one warmup pass, and the batch is
@@ -407,30 +408,33 @@ def batch_bench(args, threads):
     torch.cuda.synchronize()
     # autotune 1: keys tuned by the warmup call are reused by the timed one;
     # autotune 2: the timed call tunes every key again (tuning cost included)
-    for label, prec, nw, tune, gr in (("fp64", nat.H1W_FP64, 8, 1, False),
-                                      ("mixed", nat.H1W_MIXED, 8, 1, False),
-                                      ("fp64_untuned", nat.H1W_FP64, 8, 0, False),
-                                      ("mixed_untuned", nat.H1W_MIXED, 8, 0, False),
-                                      ("fp64_tuning_in_timed_call", nat.H1W_FP64, 8, 2, False),
-                                      ("fp64_graphs", nat.H1W_FP64, 8, 1, True),
-                                      ("fp64_one_worker", nat.H1W_FP64, 1, 0, False),
-                                      ("fp64_one_worker_autotuned", nat.H1W_FP64, 1, 1, False)):
+    for label, prec, nw, tune, gr, grp in (("fp64_grouped", nat.H1W_FP64, 8, 0, False, True),
+                                           ("mixed_grouped", nat.H1W_MIXED, 8, 0, False, True),
+                                           ("fp64", nat.H1W_FP64, 8, 1, False, False),
+                                           ("mixed", nat.H1W_MIXED, 8, 1, False, False),
+                                           ("fp64_untuned", nat.H1W_FP64, 8, 0, False, False),
+                                           ("mixed_untuned", nat.H1W_MIXED, 8, 0, False, False),
+                                           ("fp64_tuning_in_timed_call", nat.H1W_FP64, 8, 2, False, False),
+                                           ("fp64_graphs", nat.H1W_FP64, 8, 1, True, False),
+                                           ("fp64_one_worker", nat.H1W_FP64, 1, 0, False, False),
+                                           ("fp64_one_worker_autotuned", nat.H1W_FP64, 1, 1, False, False)):
         torch.cuda.synchronize()
         tw = time.perf_counter()
-        nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol, graphs=gr)
+        nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune, rtol=args.rtol, graphs=gr,
+                            grouped=grp)
         torch.cuda.synchronize()
         dt_warm = time.perf_counter() - tw
         times, worst = [], 0.0
         for _ in range(BATCH_REPS):
             t0 = time.perf_counter()
             infos, stats, rep = nat.h1w_batch_solve(items, precision=prec, nworkers=nw, autotune=tune,
-                                                    rtol=args.rtol, graphs=gr)
+                                                    rtol=args.rtol, graphs=gr, grouped=grp)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             worst = max(worst, max(i.relres_true for i in infos))
         dt = sorted(times)[len(times) // 2]
         out[label] = {"instances_per_s": len(items) / dt, "ms": 1e3 * dt, "workers": rep.nworkers,
-                      "autotune": tune, "graphs": gr, "iters_total": int(sum(i.iters for i in infos)),
+                      "autotune": tune, "graphs": gr, "grouped": grp, "iters_total": int(sum(i.iters for i in infos)),
                       "worst_relres_true": worst, "ms_warmup_call": 1e3 * dt_warm,
                       "ms_timed_calls": [round(1e3 * t, 2) for t in times],
                       "contexts": "kept from the warmup call",

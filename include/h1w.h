@@ -374,6 +374,20 @@ typedef struct {
     int maxit;           /* as h1w_solve_opts.maxit (0 -> 500) */
     int graphs;          /* 1: contexts replay their V-cycles from HIP graphs
                             (H1W_FLAG_GRAPH_VCYCLE) */
+    int grouped;         /* 1: lock-step mode. The items of one grid (same dim, n,
+                            beta) are solved together by one worker: their vectors
+                            stacked, so that each step of the iteration is one launch
+                            for the whole group (V-cycles, operator, J and J^T passes
+                            over the stacked rows, dot products, updates with
+                            per-item step lengths and activity masks); each item's
+                            S = alpha I + J Z^T is one tile of a grouped MFMA product
+                            and is inverted in one work-group. Needs m <= 128 for every
+                            item (EINVAL for the others); autotune and graphs are
+                            ignored. The preconditioned CG (stored-Z Woodbury apply,
+                            flexible direction coefficient) stops each item on its
+                            recursive residual and checks its true residual (up to two
+                            restarts); a group that fails gives its status to all of
+                            its items. 0: one solve per item (above). */
 } h1w_batch_opts;
 
 #define H1W_BATCH_MAX_KEYS 64

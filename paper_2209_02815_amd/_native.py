@@ -62,7 +62,7 @@ class h1w_batch_item(C.Structure):
 
 class h1w_batch_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("nworkers", C.c_int), ("autotune", C.c_int), ("nu", C.c_int),
-                ("rtol", C.c_double), ("maxit", C.c_int), ("graphs", C.c_int)]
+                ("rtol", C.c_double), ("maxit", C.c_int), ("graphs", C.c_int), ("grouped", C.c_int)]
 
 
 H1W_BATCH_MAX_KEYS = 64
@@ -351,7 +351,8 @@ def h1w_reset_kernel_timing(ctx):
 
 
 def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotune: int = 0, nu: int = 0,
-                    rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True, graphs: bool = False):
+                    rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True, graphs: bool = False,
+                    grouped: bool = False):
     """items: list of dicts with shape, beta, alpha, J (CUDA (m, N) float64 or None), b, x.
     Returns (infos, statuses, report); raises on the first failing item unless raise_on_error is False."""
     arr = (h1w_batch_item * max(1, len(items)))()
@@ -375,7 +376,7 @@ def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotun
                 raise ValueError(f"item {i}: {name} must be a contiguous float64 CUDA vector of N entries")
         e.b, e.x = it["b"].data_ptr(), it["x"].data_ptr()
     opts = h1w_batch_opts(int(precision), int(nworkers), int(autotune), int(nu), float(rtol), int(maxit),
-                          int(bool(graphs)))
+                          int(bool(graphs)), int(bool(grouped)))
     infos = (h1w_info * max(1, len(items)))()
     stats = (C.c_int * max(1, len(items)))()
     rep = h1w_batch_report()

@@ -447,6 +447,7 @@ h1w_status h1w_batch_solve(int count, const h1w_batch_item* items, const h1w_bat
                 "nworkers, nu and maxit must be >= 0 (nu <= 16)");
         require(std::isfinite(opts->rtol) && opts->rtol >= 0.0, "rtol must be >= 0");
         require(opts->graphs == 0 || opts->graphs == 1, "graphs must be 0 or 1");
+        require(opts->grouped == 0 || opts->grouped == 1, "grouped must be 0 or 1");
         require(opts->autotune >= 0 && opts->autotune <= 2, "autotune must be 0, 1 or 2");
         std::vector<h1w_status> own;
         h1w_status* stp = status;

@@ -40,6 +40,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -130,10 +131,188 @@ WorkerPool& worker_pool() {
 
 }  // namespace
 
+namespace {
+
+// Grouped (lock-step) mode: the items of one grid form a group solved by
+// Ctx::gn_group_solve on one worker; the groups are spread over the workers.
+void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
+                         h1w_status* status, h1w_batch_report* report, std::string* first_err, int device) {
+    constexpr int kMaxGroup = 256;  // items per lock-step group (larger grids' groups are cut)
+    const int nu_fixed = o.nu > 0 ? o.nu : 2;
+    std::vector<std::string> item_err(count);
+    // groups of item indices per grid, in first-seen order, cut at kMaxGroup
+    std::map<std::tuple<int, int, int, int, double>, std::vector<int>> by_grid;
+    std::vector<std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) {
+        const h1w_batch_item& it = items[i];
+        if (status) status[i] = H1W_OK;
+        if (infos) infos[i] = h1w_info{};
+        if ((it.dim != 2 && it.dim != 3) || it.m < 0 || it.m > Ctx::kGroupMaxRows || !std::isfinite(it.beta)) {
+            if (status) status[i] = H1W_EINVAL;
+            item_err[i] = "grouped items need dim 2 or 3, 0 <= m <= 128 and a finite beta";
+            continue;
+        }
+        const int n2 = it.dim == 3 ? it.n[2] : 1;
+        auto& v = by_grid[{it.dim, it.n[0], it.n[1], n2, it.beta}];
+        v.push_back(i);
+        if ((int)v.size() == kMaxGroup) {
+            groups.push_back(std::move(v));
+            v.clear();
+        }
+    }
+    for (auto& [key, v] : by_grid)
+        if (!v.empty()) groups.push_back(std::move(v));
+    // larger groups (by work) first
+    auto gwork = [&](const std::vector<int>& v) {
+        double w = 0.0;
+        for (int i : v) {
+            double nn = 1.0;
+            for (int a = 0; a < items[i].dim; ++a) nn *= items[i].n[a];
+            w += nn * (items[i].m + 1);
+        }
+        return w;
+    };
+    std::stable_sort(groups.begin(), groups.end(),
+                     [&](const std::vector<int>& a, const std::vector<int>& b) { return gwork(a) > gwork(b); });
+
+    const int nworkers = std::clamp(o.nworkers > 0 ? o.nworkers : 8, 1, 16);
+    const int nw = std::max(1, std::min(nworkers, (int)groups.size()));
+    std::vector<Worker*> workers(nw, nullptr);
+    {
+        std::lock_guard<std::mutex> lk(worker_pool().mu);
+        auto& idle = worker_pool().idle[device];
+        for (int w = 0; w < nw; ++w) {
+            if (!idle.empty()) {
+                workers[w] = idle.back();
+                idle.pop_back();
+            } else {
+                workers[w] = new Worker();
+            }
+        }
+    }
+    std::atomic<int> next{0};
+    std::vector<std::string> worker_err(nw);
+    auto run = [&](int w) {
+        Worker& me = *workers[w];
+        try {
+            H1W_HIP(hipSetDevice(device));
+            if (!me.stream) {
+                std::lock_guard<std::recursive_mutex> lk(capture_lock());
+                H1W_HIP(hipStreamCreateWithFlags(&me.stream, hipStreamNonBlocking));
+            }
+        } catch (const Error& e) {
+            worker_err[w] = e.msg;
+            return;
+        }
+        for (;;) {
+            const int q = next.fetch_add(1);
+            if (q >= (int)groups.size()) break;
+            const std::vector<int>& grp = groups[q];
+            const h1w_batch_item& i0 = items[grp[0]];
+            const int n2 = i0.dim == 3 ? i0.n[2] : 1;
+            const GridKey gk{i0.dim, i0.n[0], i0.n[1], n2, o.precision, nu_fixed, 0.0, i0.beta, false};
+            std::vector<h1w_info> ginf(grp.size(), h1w_info{});
+            h1w_status st = H1W_OK;
+            std::string msg;
+            try {
+                me.last_use[gk] = ++me.clock;
+                auto& slot = me.ctxs[gk];
+                if (!slot) {
+                    while ((int)me.ctxs.size() > kMaxCtxPerWorker) {
+                        auto victim = me.ctxs.end();
+                        uint64_t oldest = UINT64_MAX;
+                        for (auto c = me.ctxs.begin(); c != me.ctxs.end(); ++c)
+                            if (c->second && me.last_use[c->first] < oldest) {
+                                oldest = me.last_use[c->first];
+                                victim = c;
+                            }
+                        if (victim == me.ctxs.end()) break;
+                        me.last_use.erase(victim->first);
+                        me.ctxs.erase(victim);
+                    }
+                    h1w_grid_desc d{};
+                    d.dim = i0.dim;
+                    d.n[0] = i0.n[0];
+                    d.n[1] = i0.n[1];
+                    d.n[2] = n2;
+                    d.beta = i0.beta;
+                    d.precision = o.precision;
+                    d.nu = nu_fixed;
+                    auto c = std::make_unique<Ctx>();
+                    c->init(d, me.stream);
+                    me.ctxs[gk] = std::move(c);
+                }
+                Ctx& cx = *me.ctxs[gk];
+                std::vector<Ctx::GroupItem> gi(grp.size());
+                for (size_t k = 0; k < grp.size(); ++k) {
+                    const h1w_batch_item& it = items[grp[k]];
+                    gi[k] = Ctx::GroupItem{it.m, it.J, it.ldj, it.alpha, it.b, it.x};
+                }
+                h1w_solve_opts so{};
+                so.rtol = o.rtol;
+                so.maxit = o.maxit;
+                const auto t0 = std::chrono::steady_clock::now();
+                cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data());
+                const double ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                for (auto& f : ginf) f.t_total_ms = ms;
+            } catch (const Error& e) {
+                st = e.st;
+                msg = e.msg;
+            } catch (const std::bad_alloc&) {
+                st = H1W_ENOMEM;
+                msg = "host allocation failed";
+            } catch (const std::exception& e) {
+                st = H1W_EINVAL;
+                msg = e.what();
+            }
+            if (st != H1W_OK) {  // a context left by a failed group is not reused
+                me.ctxs.erase(gk);
+                me.last_use.erase(gk);
+            }
+            for (size_t k = 0; k < grp.size(); ++k) {
+                if (infos) infos[grp[k]] = ginf[k];
+                if (status) status[grp[k]] = st;
+                if (st != H1W_OK) item_err[grp[k]] = msg;
+            }
+        }
+    };
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::thread> threads;
+    threads.reserve(nw);
+    for (int w = 0; w < nw; ++w) threads.emplace_back(run, w);
+    for (auto& t : threads) t.join();
+    const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    {
+        std::lock_guard<std::mutex> lk(worker_pool().mu);
+        auto& idle = worker_pool().idle[device];
+        for (Worker* w : workers) idle.push_back(w);
+    }
+    for (const auto& e : worker_err)
+        if (!e.empty()) throw Error{H1W_EHIP, "batch worker setup failed: " + e};
+    if (first_err) {
+        first_err->clear();
+        for (int i = 0; i < count && first_err->empty(); ++i)
+            if (!item_err[i].empty()) *first_err = "item " + std::to_string(i) + ": " + item_err[i];
+    }
+    if (report) {
+        *report = h1w_batch_report{};
+        report->t_total_ms = total_ms;
+        report->nworkers = nw;
+        report->ntuned = 0;
+    }
+}
+
+}  // namespace
+
 void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
                  h1w_status* status, h1w_batch_report* report, std::string* first_err) {
     int device = 0;
     H1W_HIP(hipGetDevice(&device));
+    if (o.grouped) {
+        batch_solve_grouped(count, items, o, infos, status, report, first_err, device);
+        return;
+    }
     const int nworkers = std::clamp(o.nworkers > 0 ? o.nworkers : 8, 1, 16);
     const int nu_fixed = o.nu > 0 ? o.nu : 2;
 

@@ -133,6 +133,21 @@ struct Ctx {
     // Y = A X with the context's operator (FP64; the H1 Gram operator or the ERT one)
     void apply_A(int k, const double* X, int64_t ldx, double* Y, int64_t ldy);
 
+    // lock-step solve of G GN systems on this grid (grouped.hip): item g has
+    // m_g <= 128 rows J_g (leading dimension ldj_g), weight alpha_g, b_g, x_g
+    struct GroupItem {
+        int m;
+        const double* J;
+        int64_t ldj;
+        double alpha;
+        const double* b;
+        double* x;
+    };
+    static constexpr int kGroupMaxRows = 128;
+    DevBuf grpJ, grpZ, grpVec, grpS, grpSinv, grpPart, grpTab, grpScal, grpDefl;
+    void vcycle_group(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
+    void gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so, h1w_info* infos);
+
     // ERT context (op = H1W_OP_ERT): conductivity operator, see ert.hip
     bool ert = false;
     unsigned dmask = 0;              // Dirichlet faces

@@ -51,36 +51,16 @@ constexpr size_t kMaxPartialBytes = size_t(1) << 30;
 constexpr int KB = 16;
 constexpr int LDT = KB + 1;  // LDS row stride (doubles)
 
+// One work item of the product: the 128 x 128 output tile (tr, tc) of
+// J (m rows) times Z^T (m2 rows) over the K range [k0, k1), stored into P
+// (m x m2, row-major). lower: the product is the lower triangle of a
+// symmetric one (the wave quadrant strictly above a diagonal tile idles).
 template <typename TZ>
-__global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int64_t N, const double* __restrict__ J,
-                                                              int64_t ldj, const TZ* __restrict__ Z, int64_t ldz,
-                                                              int T, int T2, int ntile, int lower, int total,
-                                                              int64_t kper, double* __restrict__ partial) {
+__device__ __forceinline__ void cap_tile(int m, int m2, const double* __restrict__ J, int64_t ldj,
+                                         const TZ* __restrict__ Z, int64_t ldz, int tr, int tc, bool lower,
+                                         int64_t k0, int64_t k1, double* __restrict__ P) {
     __shared__ double sA[2][kTileMN * LDT];
     __shared__ double sB[2][kTileMN * LDT];
-    const int bid = blockIdx.x;
-    const int per = (total + 7) / 8;
-    const int u = (bid & 7) * per + (bid >> 3);
-    if (u >= total) return;
-    const int split = u / ntile;
-    const int tile = u - split * ntile;
-    int tr, tc;
-    if (lower) {
-        // row tile r holds min(r + 1, T2) tiles: a triangle of T2 (T2 + 1) / 2
-        // tiles, then full rows of T2
-        const int tri = T2 * (T2 + 1) / 2;
-        if (tile < tri) {
-            tr = 0;
-            while ((tr + 1) * (tr + 2) / 2 <= tile) ++tr;
-            tc = tile - tr * (tr + 1) / 2;
-        } else {
-            tr = T2 + (tile - tri) / T2;
-            tc = (tile - tri) - (tr - T2) * T2;
-        }
-    } else {
-        tr = tile / T2;
-        tc = tile - tr * T2;
-    }
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int l16 = lane & 15, g = lane >> 4;
@@ -108,8 +88,6 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
         const int c = brow0 + lr + 16 * q;
         pb[q] = Z + (int64_t)(c < m2 ? c : 0) * ldz;
     }
-    const int64_t k0 = (int64_t)split * kper;
-    const int64_t k1 = std::min<int64_t>(N, k0 + kper);
     const int nchunk = (int)((k1 - k0 + KB - 1) / KB);
     double ra[8];
     TZ rb[8];
@@ -165,7 +143,6 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
         __syncthreads();
     }
     if (idle) return;
-    double* P = partial + (int64_t)split * m * m2;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -176,6 +153,77 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int
                 const int col = brow0 + wc + c * 16 + l16;
                 if (row < m && col < m2) P[(int64_t)row * m2 + col] = acc[r][c][v];
             }
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(kGemmThreads, 2) void k_cap_gemm(int m, int m2, int64_t N, const double* __restrict__ J,
+                                                              int64_t ldj, const TZ* __restrict__ Z, int64_t ldz,
+                                                              int T, int T2, int ntile, int lower, int total,
+                                                              int64_t kper, double* __restrict__ partial) {
+    const int bid = blockIdx.x;
+    const int per = (total + 7) / 8;
+    const int u = (bid & 7) * per + (bid >> 3);
+    if (u >= total) return;
+    const int split = u / ntile;
+    const int tile = u - split * ntile;
+    int tr, tc;
+    if (lower) {
+        // row tile r holds min(r + 1, T2) tiles: a triangle of T2 (T2 + 1) / 2
+        // tiles, then full rows of T2
+        const int tri = T2 * (T2 + 1) / 2;
+        if (tile < tri) {
+            tr = 0;
+            while ((tr + 1) * (tr + 2) / 2 <= tile) ++tr;
+            tc = tile - tr * (tr + 1) / 2;
+        } else {
+            tr = T2 + (tile - tri) / T2;
+            tc = (tile - tri) - (tr - T2) * T2;
+        }
+    } else {
+        tr = tile / T2;
+        tc = tile - tr * T2;
+    }
+    const int64_t k0 = (int64_t)split * kper;
+    cap_tile<TZ>(m, m2, J, ldj, Z, ldz, tr, tc, lower != 0, k0, std::min<int64_t>(N, k0 + kper),
+                 partial + (int64_t)split * m * m2);
+}
+
+// Grouped products of a lock-step batch: work item u is split u - io[g] of
+// instance g (m[g] <= 128 rows, one 128 x 128 tile), found by bisection over
+// io; the items go to the 8 XCDs in contiguous ranges as above.
+__global__ __launch_bounds__(kGemmThreads, 2) void k_grp_gemm(GrpGemm t, int64_t N, const double* __restrict__ J,
+                                                              int64_t ldj, const double* __restrict__ Z,
+                                                              int64_t ldz, double* __restrict__ partial) {
+    const int bid = blockIdx.x;
+    const int per = (t.total + 7) / 8;
+    const int u = (bid & 7) * per + (bid >> 3);
+    if (u >= t.total) return;
+    int lo = 0, hi = t.G - 1;  // the last g with io[g] <= u
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.io[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    const int g = lo, m = t.m[g];
+    const int64_t kp = t.kper[g];
+    const int64_t k0 = (int64_t)(u - t.io[g]) * kp;
+    cap_tile<double>(m, m, J + (int64_t)t.ro[g] * ldj, ldj, Z + (int64_t)t.ro[g] * ldz, ldz, 0, 0, false, k0,
+                     std::min<int64_t>(N, k0 + kp), partial + t.poff[g] + (int64_t)(u - t.io[g]) * m * m);
+}
+
+// S_g = alpha_g I + the sum of instance g's partials in item order
+__global__ __launch_bounds__(kBlock) void k_grp_reduce(GrpGemm t, const double* __restrict__ partial,
+                                                       double* __restrict__ S) {
+    const int g = blockIdx.y, m = t.m[g];
+    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= m * m) return;
+    const int ns = t.io[g + 1] - t.io[g];
+    const double* p = partial + t.poff[g] + idx;
+    double acc = 0.0;
+    for (int sp = 0; sp < ns; ++sp) acc += p[(int64_t)sp * m * m];
+    const int i = idx / m, j = idx - i * m;
+    if (i == j) acc += t.alpha[g];
+    S[t.soff[g] + idx] = acc;
 }
 
 // FP32-accumulated variant (opt-in, MIXED contexts): the same work items and
@@ -415,6 +463,21 @@ void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const d
     if (m <= 0 || m2 <= 0) return;
     hipLaunchKernelGGL(k_cap_reduce, dim3((unsigned)cdiv((int64_t)m * m2, kRedOut)), dim3(kBlock), 0, s, m, m2,
                        splits, partial, (int)lower_only, alpha, diag_off, S, lds);
+    H1W_LAUNCHED();
+}
+
+void launch_grp_gemm_partial(hipStream_t s, const GrpGemm& t, int64_t N, const double* J, int64_t ldj,
+                             const double* Z, int64_t ldz, double* partial) {
+    if (t.total <= 0) return;
+    hipLaunchKernelGGL(k_grp_gemm, dim3((unsigned)(8 * cdiv(t.total, 8))), dim3(kGemmThreads), 0, s, t, N, J, ldj, Z,
+                       ldz, partial);
+    H1W_LAUNCHED();
+}
+
+void launch_grp_gemm_reduce(hipStream_t s, const GrpGemm& t, const double* partial, double* S) {
+    if (t.G <= 0) return;
+    hipLaunchKernelGGL(k_grp_reduce, dim3((unsigned)cdiv(128 * 128, kBlock), (unsigned)t.G), dim3(kBlock), 0, s, t,
+                       partial, S);
     H1W_LAUNCHED();
 }
 

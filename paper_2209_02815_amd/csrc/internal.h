@@ -278,6 +278,25 @@ void launch_capacitance_reduce(hipStream_t s, int m, int m2, int splits, const d
                                double alpha, int diag_off, double* S, int64_t lds);
 void launch_mirror_lower(hipStream_t s, int m, double* S);
 size_t gemm_partial_elems(int m, int m2, int64_t N);
+// grouped products of a lock-step batch: instance g has m[g] <= 128 rows at
+// row ro[g] of the stacked J and Z (leading dimensions ldj, ldz); its K range
+// is cut into the work items io[g] .. io[g+1]-1 of kper[g] values each, whose
+// partial m x m products go to partial + poff[g] + (item - io[g]) m^2;
+// reduce: S_g (at soff[g], m x m row-major) = alpha[g] I + the sum of the
+// partials in item order
+struct GrpGemm {
+    int G, total;
+    const int* m;
+    const int* ro;
+    const int* io;
+    const int64_t* kper;
+    const int64_t* poff;
+    const int64_t* soff;
+    const double* alpha;
+};
+void launch_grp_gemm_partial(hipStream_t s, const GrpGemm& t, int64_t N, const double* J, int64_t ldj,
+                             const double* Z, int64_t ldz, double* partial);
+void launch_grp_gemm_reduce(hipStream_t s, const GrpGemm& t, const double* partial, double* S);
 
 // dense.hip (single-workgroup factorisations for m <= a few thousand)
 void launch_lu(hipStream_t s, int m, double* A, int* piv, int* info);

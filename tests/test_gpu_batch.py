@@ -122,6 +122,41 @@ def test_batch_autotune_departs_where_iterations_drop(P, prec):
         assert rr <= 1.01e-8
 
 
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-10), ("fp64", 1e-8), ("mixed", 1e-8)])
+def test_grouped_batch_matches_oracle(P, prec, rtol):
+    # lock-step mode: every instance of a grid advanced together; each x must
+    # meet rtol on the oracle's FP64 true residual, as the reported one says
+    from paper_2209_02815_amd import _native as nat
+    wls = small_batch() + H.batch_workloads(count=6, batch_id=11, sides=(65,), m_lo=100, m_hi=128)
+    items, host = make_items(wls)
+    precision = {"fp64": nat.H1W_FP64, "mixed": nat.H1W_MIXED}[prec]
+    infos, stats, rep = nat.h1w_batch_solve(items, precision=precision, nworkers=3, rtol=rtol, grouped=True)
+    assert all(s == 0 for s in stats)
+    worst = 0.0
+    for wl, it, (J, b), inf in zip(wls, items, host, infos):
+        x = it["x"].cpu().numpy()
+        Jm = J if J is not None else np.zeros((0, wl.N))
+        rr = gn.true_relres(wl.shape, wl.beta, Jm, wl.alpha, b, x)
+        floor = gn.residual_rounding_floor(wl.shape, wl.beta, Jm, wl.alpha, b, x)
+        assert rr <= 1.01 * rtol, (wl.name, rr)
+        assert abs(rr - inf.relres_true) <= 1e-3 * rtol + floor, (wl.name, rr, inf.relres_true)
+        worst = max(worst, rr)
+    print(f"grouped {prec} rtol {rtol}: worst true residual {worst:.2e}, iterations "
+          f"{sorted(i.iters for i in infos)}", flush=True)
+
+
+def test_grouped_batch_rejects_more_than_128_rows(P):
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads(count=2, batch_id=12, sides=(17,), m_lo=129, m_hi=140) + \
+        H.batch_workloads(count=2, batch_id=13, sides=(17,), m_lo=5, m_hi=10)
+    items, host = make_items(wls)
+    infos, stats, rep = nat.h1w_batch_solve(items, nworkers=2, rtol=1e-10, grouped=True, raise_on_error=False)
+    assert stats[0] == nat.H1W_EINVAL and stats[1] == nat.H1W_EINVAL
+    assert stats[2] == 0 and stats[3] == 0
+    for wl, it, (J, b) in list(zip(wls, items, host))[2:]:
+        assert gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy()) <= 1.01e-10
+
+
 def test_batch_bad_item_fails_alone(P):
     from paper_2209_02815_amd import _native as nat
     wls = small_batch()[:4]
