@@ -54,10 +54,10 @@ def parse():
                     help="skip the comparison solve modes (Laplace-only and exact-B preconditioners)")
     ap.add_argument("--no-ert", action="store_true",
                     help="skip the ERT survey (65^3 forward map, J, GN solve and two Gauss-Newton steps)")
-    ap.add_argument("--batch-profile", action="store_true",
+    ap.add_argument("--batch-profile", nargs="?", const="per-instance", choices=("per-instance", "grouped"),
                     help="only the batch of 256 uneven 2D instances, with one worker, nu = 2, FP64 then mixed, "
-                         "two calls each (the batch's kernels under a tracer without concurrent workers); "
-                         "prints a JSON line of its own")
+                         "two calls each, one solve per instance or in the grouped mode (the batch's kernels "
+                         "under a tracer without concurrent workers); prints a JSON line of its own")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from the counter CSVs of two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this script with --calibrate-copy on --workload, and exit")
@@ -373,20 +373,23 @@ BATCH_REPS = 3
 def batch_bench(args, threads):
     """256 independent 2D instances of uneven size (sides {65,129,193,257}, m in
     [16,128], log-uniform alpha in [1e-5,1e-2]) solved by h1w_batch_solve:
-    FP64 and mixed in the grouped (lock-step) mode, one worker per grid; then
-    one solve per instance with 8 workers, with the autotuner (choices made in
-    the warmup call, or again inside the timed call) and with the default
-    smoother, FP64 with the V-cycles replayed from HIP graphs, and FP64 with
-    one worker (no overlap) for reference. Before the first line, two untimed passes in each precision
-    (nu = 2 fixed) warm the process: the first calls of a process run slower
-    for a while (about 150 against 120 ms), which would otherwise favour the
-    lines timed later. Each line then has one warmup pass, and the batch is
-    timed three times (BATCH_REPS); the median is reported (every time is
-    listed). The executor
-    keeps its workers' contexts for the process, so the timed call reuses the
-    per-grid setup (hierarchy, coarsest inverse, workspace) of the warmup
-    call; every instance's Z, S, factorisation and CG are computed in the
-    timed call. The warmup call's time is reported beside it."""
+    - FP64 and mixed in the grouped (lock-step) mode, one worker per grid,
+      with the autotuner (choices made in the warmup call) and with the
+      default smoother;
+    - one solve per instance with 8 workers, FP64 and mixed, with the
+      autotuner (choices made in the warmup call, or again inside the timed
+      call) and with the default smoother;
+    - FP64 with the V-cycles replayed from HIP graphs, and FP64 with one
+      worker (no overlap) for reference.
+    Before the first line, two untimed passes in each precision (nu = 2
+    fixed) warm the process: the first calls of a process run slower for a
+    while (about 150 against 120 ms), which would otherwise favour the lines
+    timed later. Each line then has one warmup pass, and the batch is timed
+    three times (BATCH_REPS); the median is reported (every time is listed).
+    The executor keeps its workers' contexts for the process, so the timed
+    call reuses the per-grid setup (hierarchy, coarsest inverse, workspace) of
+    the warmup call; every instance's Z, S, factorisation and CG are computed
+    in the timed call. The warmup call's time is reported beside it."""
     import torch
     import h1w_inputs as H
     from paper_2209_02815_amd import _native as nat
@@ -408,8 +411,10 @@ def batch_bench(args, threads):
     torch.cuda.synchronize()
     # autotune 1: keys tuned by the warmup call are reused by the timed one;
     # autotune 2: the timed call tunes every key again (tuning cost included)
-    for label, prec, nw, tune, gr, grp in (("fp64_grouped", nat.H1W_FP64, 8, 0, False, True),
-                                           ("mixed_grouped", nat.H1W_MIXED, 8, 0, False, True),
+    for label, prec, nw, tune, gr, grp in (("fp64_grouped", nat.H1W_FP64, 8, 1, False, True),
+                                           ("mixed_grouped", nat.H1W_MIXED, 8, 1, False, True),
+                                           ("fp64_grouped_untuned", nat.H1W_FP64, 8, 0, False, True),
+                                           ("mixed_grouped_untuned", nat.H1W_MIXED, 8, 0, False, True),
                                            ("fp64", nat.H1W_FP64, 8, 1, False, False),
                                            ("mixed", nat.H1W_MIXED, 8, 1, False, False),
                                            ("fp64_untuned", nat.H1W_FP64, 8, 0, False, False),
@@ -446,9 +451,10 @@ def batch_bench(args, threads):
 
 
 def batch_profile(args, threads):
-    """The batch workload with one worker (no overlap between instances), nu = 2
-    fixed, FP64 then mixed, two calls each: the run a kernel tracer records for
-    the batch's kernels."""
+    """The batch workload with one worker (no overlap between instances or
+    grids), nu = 2 fixed, FP64 then mixed, two calls each, one solve per
+    instance or in the grouped mode: the run a kernel tracer records for the
+    batch's kernels."""
     import torch
     import h1w_inputs as H
     from paper_2209_02815_amd import _native as nat
@@ -460,12 +466,15 @@ def batch_profile(args, threads):
                           b=torch.from_numpy(H.rhs_b(wl)).to("cuda:0"),
                           x=torch.zeros(wl.N, dtype=torch.float64, device="cuda:0")))
     torch.cuda.synchronize()
-    out = {"workload": f"{len(wls)} 2D instances (batch workload), one worker, nu = 2"}
+    grouped = args.batch_profile == "grouped"
+    out = {"workload": f"{len(wls)} 2D instances (batch workload), one worker, nu = 2",
+           "mode": args.batch_profile}
     for label, prec in (("fp64", nat.H1W_FP64), ("mixed", nat.H1W_MIXED)):
         times = []
         for _ in range(2):
             t0 = time.perf_counter()
-            infos, _, _ = nat.h1w_batch_solve(items, precision=prec, nworkers=1, autotune=0, rtol=args.rtol)
+            infos, _, _ = nat.h1w_batch_solve(items, precision=prec, nworkers=1, autotune=0, rtol=args.rtol,
+                                              grouped=grouped)
             torch.cuda.synchronize()
             times.append(1e3 * (time.perf_counter() - t0))
         out[label] = {"ms_calls": [round(t, 2) for t in times], "iters_total": int(sum(i.iters for i in infos)),

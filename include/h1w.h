@@ -382,8 +382,14 @@ typedef struct {
                             per-item step lengths and activity masks); each item's
                             S = alpha I + J Z^T is one tile of a grouped MFMA product
                             and is inverted in one work-group. Needs m <= 128 for every
-                            item (EINVAL for the others); autotune and graphs are
-                            ignored. The preconditioned CG (stored-Z Woodbury apply,
+                            item (EINVAL for the others); graphs is ignored. With
+                            autotune, a group whose key is untuned is solved whole with
+                            each interval and then the default, and keeps the interval
+                            with the least work (its items' CG iterations weighted by
+                            m + 1; the default on a tie), solving once more with it
+                            unless that is the default. Grouped keys are kept apart
+                            from those of the per-item mode, which choose on one
+                            item's iterations. The preconditioned CG (stored-Z Woodbury apply,
                             flexible direction coefficient) stops each item on its
                             recursive residual and checks its true residual (up to two
                             restarts); a group that fails gives its status to all of
@@ -394,13 +400,17 @@ typedef struct {
 typedef struct {
     int dim;
     int n[3];
-    int m_bucket;        /* ceil(log2 m) of the item the key was tuned on */
+    int m_bucket;        /* ceil(log2 m) of the item the key was tuned on (grouped:
+                            of the group's first item) */
     int nu;              /* smoothing steps per side (opts.nu) */
-    double ms_per_unit;  /* the chosen schedule's wall time per N * (m + 1), in ms */
+    double ms_per_unit;  /* the chosen schedule's wall time per N * (m + 1), in ms
+                            (grouped: per the group's sum of N * (m + 1)) */
     int reused;          /* 1: the choice of an earlier batch */
     double cheb_lo;      /* chosen lower end of the Chebyshev interval (upper end 2) */
-    int iters;           /* CG iterations of the tuning item with the chosen schedule */
-    int iters_default;   /* ... and with the default one */
+    int iters;           /* CG iterations of the tuning item with the chosen schedule
+                            (grouped: summed over the tuning group's items) */
+    int iters_default;   /* ... and with the default one (-1: the default failed) */
+    int grouped;         /* 1: a key of the grouped mode */
 } h1w_batch_tuned;
 
 typedef struct {

@@ -71,7 +71,7 @@ H1W_BATCH_MAX_KEYS = 64
 class h1w_batch_tuned(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("m_bucket", C.c_int), ("nu", C.c_int),
                 ("ms_per_unit", C.c_double), ("reused", C.c_int), ("cheb_lo", C.c_double),
-                ("iters", C.c_int), ("iters_default", C.c_int)]
+                ("iters", C.c_int), ("iters_default", C.c_int), ("grouped", C.c_int)]
 
 
 class h1w_batch_report(C.Structure):

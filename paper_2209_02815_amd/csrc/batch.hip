@@ -37,6 +37,10 @@
 // is the instance's result; while a key is being tuned, other workers solve
 // its instances with the default. Tuned keys are kept for the process: a
 // later batch reuses them (autotune = 1) or tunes them again (autotune = 2).
+// In the grouped mode the tuning worker solves the whole group with each
+// candidate and the default, and keeps the schedule with the least work (the
+// instances' iterations weighted by m + 1): one instance's iterations need
+// not show what a schedule does to the rest of its group.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -83,8 +87,10 @@ constexpr int kMaxCtxPerWorker = 24;
 
 struct TuneKey {
     int dim, n0, n1, n2, precision, nu;  // nu: the batch's smoothing steps, which the interval goes with
+    bool grouped;                        // chosen for the grouped mode (by a whole group's steps)
     bool operator<(const TuneKey& o) const {
-        return std::tie(dim, n0, n1, n2, precision, nu) < std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu);
+        return std::tie(dim, n0, n1, n2, precision, nu, grouped) <
+               std::tie(o.dim, o.n0, o.n1, o.n2, o.precision, o.nu, o.grouped);
     }
 };
 
@@ -108,6 +114,95 @@ struct TuneState {
 // tuning results of earlier batches in this process
 std::mutex g_tuned_mu;
 std::map<TuneKey, TuneState> g_tuned;
+
+// The tuning keys met by one batch call, shared by its workers.
+struct BatchTuner {
+    int autotune = 0;
+    std::mutex mu;
+    std::map<TuneKey, TuneState> keys;
+
+    // schedule (lower Chebyshev bound, 0 = the default) for key tk; tuning:
+    // the caller tunes the key now (and runs the default meanwhile)
+    double choose(const TuneKey& tk, bool& tuning) {
+        tuning = false;
+        if (!autotune) return 0.0;
+        std::lock_guard<std::mutex> lk(mu);
+        TuneState& ts = keys[tk];
+        if (!ts.claimed && autotune == 1) {  // a choice of an earlier batch
+            std::lock_guard<std::mutex> lg(g_tuned_mu);
+            auto f = g_tuned.find(tk);
+            if (f != g_tuned.end()) {
+                ts = f->second;
+                ts.reused = true;
+            }
+        }
+        if (!ts.claimed) {
+            ts.claimed = true;
+            tuning = true;
+            return 0.0;
+        }
+        return ts.done ? ts.best_lo : 0.0;
+    }
+
+    void finish(const TuneKey& tk, double lo, double t_norm, int its, int its_def, int bucket) {
+        std::lock_guard<std::mutex> lk(mu);
+        TuneState& ts = keys[tk];
+        ts.best = t_norm;
+        ts.best_lo = lo;
+        ts.best_iters = its;
+        ts.def_iters = its_def;
+        ts.bucket = bucket;
+        ts.done = true;
+    }
+
+    // keeps the choices made by this batch for later ones and lists the
+    // batch's keys in the report
+    void publish(h1w_batch_report* report) {
+        if (autotune) {
+            std::lock_guard<std::mutex> lk(g_tuned_mu);
+            for (const auto& [tk, ts] : keys)
+                if (ts.done && !ts.reused) g_tuned[tk] = ts;
+        }
+        if (!report) return;
+        int k = 0;
+        for (const auto& [tk, ts] : keys) {
+            if (k >= H1W_BATCH_MAX_KEYS) break;
+            h1w_batch_tuned& r = report->tuned[k++];
+            r.dim = tk.dim;
+            r.n[0] = tk.n0;
+            r.n[1] = tk.n1;
+            r.n[2] = tk.n2;
+            r.m_bucket = ts.bucket;
+            r.nu = tk.nu;
+            r.cheb_lo = ts.best_lo > 0.0 ? ts.best_lo : kChebLoDefault;
+            r.iters = ts.best_iters;
+            r.iters_default = ts.def_iters;
+            r.ms_per_unit = ts.best;
+            r.reused = ts.reused ? 1 : 0;
+            r.grouped = tk.grouped ? 1 : 0;
+        }
+        report->ntuned = k;
+    }
+};
+
+// the default schedule is the last candidate: in the per-instance mode its
+// solve is the instance's result
+constexpr int kDefaultCandidate = kNumCandidates - 1;
+static_assert(kTuneLo[kDefaultCandidate] == 0.0, "the default schedule is tried last");
+
+// The schedule to keep, from a cost per candidate (CG iterations, or a
+// weighted sum of them; negative: the candidate failed): another candidate
+// replaces the default only with a lower cost (or when the default failed).
+// Returns its index into kTuneLo, or -1 when every candidate failed.
+template <typename T>
+int pick_candidate(const T* cost) {
+    int best = -1;
+    for (int c = 0; c < kDefaultCandidate; ++c)
+        if (cost[c] >= 0 && (best < 0 || cost[c] < cost[best])) best = c;
+    if (cost[kDefaultCandidate] >= 0 && (best < 0 || cost[best] >= cost[kDefaultCandidate]))
+        return kDefaultCandidate;
+    return best;
+}
 
 struct Worker {
     hipStream_t stream = nullptr;
@@ -190,6 +285,8 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
             }
         }
     }
+    BatchTuner tuner;
+    tuner.autotune = o.autotune;
     std::atomic<int> next{0};
     std::vector<std::string> worker_err(nw);
     auto run = [&](int w) {
@@ -210,12 +307,21 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
             const std::vector<int>& grp = groups[q];
             const h1w_batch_item& i0 = items[grp[0]];
             const int n2 = i0.dim == 3 ? i0.n[2] : 1;
-            const GridKey gk{i0.dim, i0.n[0], i0.n[1], n2, o.precision, nu_fixed, 0.0, i0.beta, false};
-            std::vector<h1w_info> ginf(grp.size(), h1w_info{});
-            h1w_status st = H1W_OK;
-            std::string msg;
-            try {
+            const TuneKey tk{i0.dim, i0.n[0], i0.n[1], n2, o.precision, nu_fixed, true};
+            bool tuning = false;
+            const double lo0 = tuner.choose(tk, tuning);
+            auto gkey = [&](double lo_c) {
+                return GridKey{i0.dim, i0.n[0], i0.n[1], n2, o.precision, nu_fixed, lo_c, i0.beta, false};
+            };
+            std::vector<GridKey> used;  // contexts this group ran on (dropped if it fails)
+            auto drop = [&](const GridKey& gk) {
+                me.ctxs.erase(gk);
+                me.last_use.erase(gk);
+            };
+            auto ctx_for = [&](double lo_c) -> Ctx& {
+                const GridKey gk = gkey(lo_c);
                 me.last_use[gk] = ++me.clock;
+                used.push_back(gk);
                 auto& slot = me.ctxs[gk];
                 if (!slot) {
                     while ((int)me.ctxs.size() > kMaxCtxPerWorker) {
@@ -238,11 +344,20 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                     d.beta = i0.beta;
                     d.precision = o.precision;
                     d.nu = nu_fixed;
+                    if (lo_c > 0.0) {
+                        d.cheb_lo = lo_c;
+                        d.cheb_hi = kChebHiDefault;
+                    }
                     auto c = std::make_unique<Ctx>();
                     c->init(d, me.stream);
                     me.ctxs[gk] = std::move(c);
                 }
-                Ctx& cx = *me.ctxs[gk];
+                return *me.ctxs[gk];
+            };
+            std::vector<h1w_info> ginf(grp.size(), h1w_info{});
+            h1w_status st = H1W_OK;
+            std::string msg;
+            try {
                 std::vector<Ctx::GroupItem> gi(grp.size());
                 for (size_t k = 0; k < grp.size(); ++k) {
                     const h1w_batch_item& it = items[grp[k]];
@@ -251,10 +366,62 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                 h1w_solve_opts so{};
                 so.rtol = o.rtol;
                 so.maxit = o.maxit;
-                const auto t0 = std::chrono::steady_clock::now();
-                cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data());
-                const double ms =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                double lo = lo0;
+                bool have_result = false;  // ginf and the items' x hold the chosen schedule's solve
+                double ms = 0.0;
+                if (tuning) {
+                    // the whole group with each candidate and then the default
+                    // (its solve stays the result if it is kept); the choice
+                    // is the schedule with the least work: the items' CG
+                    // iterations weighted by m + 1 (a converged item drops out
+                    // of the group's passes)
+                    double cost[kNumCandidates], tms[kNumCandidates];
+                    int sum_it[kNumCandidates];
+                    Error def_err{H1W_OK, ""};
+                    for (int c = 0; c < kNumCandidates; ++c) {
+                        cost[c] = -1.0;
+                        Ctx& cx = ctx_for(kTuneLo[c]);
+                        cx.sync();
+                        const auto t0 = std::chrono::steady_clock::now();
+                        try {  // a candidate that fails (e.g. no convergence) is skipped
+                            cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data());
+                        } catch (const Error& e) {
+                            used.pop_back();
+                            drop(gkey(kTuneLo[c]));
+                            if (c == kDefaultCandidate) def_err = e;
+                            continue;
+                        }
+                        tms[c] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                        cost[c] = 0.0;
+                        sum_it[c] = 0;
+                        for (size_t k = 0; k < gi.size(); ++k) {
+                            cost[c] += (double)ginf[k].iters * (gi[k].m + 1);
+                            sum_it[c] += ginf[k].iters;
+                        }
+                    }
+                    const int pick = pick_candidate(cost);
+                    if (pick < 0) throw def_err;  // every schedule failed: the default's error
+                    double nn = 1.0, work = 0.0;
+                    for (int a = 0; a < i0.dim; ++a) nn *= i0.n[a];
+                    for (const auto& g : gi) work += nn * (g.m + 1);
+                    lo = kTuneLo[pick];
+                    tuner.finish(tk, lo, tms[pick] / work, sum_it[pick],
+                                 cost[kDefaultCandidate] >= 0.0 ? sum_it[kDefaultCandidate] : -1, row_bucket(i0.m));
+                    for (int c = 0; c < kDefaultCandidate; ++c)
+                        if (c != pick && cost[c] >= 0.0) drop(gkey(kTuneLo[c]));
+                    if (pick == kDefaultCandidate) {
+                        have_result = true;
+                        ms = tms[pick];
+                    } else {
+                        drop(gkey(0.0));
+                    }
+                }
+                if (!have_result) {
+                    Ctx& cx = ctx_for(lo);
+                    const auto t0 = std::chrono::steady_clock::now();
+                    cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data());
+                    ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                }
                 for (auto& f : ginf) f.t_total_ms = ms;
             } catch (const Error& e) {
                 st = e.st;
@@ -266,10 +433,8 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                 st = H1W_EINVAL;
                 msg = e.what();
             }
-            if (st != H1W_OK) {  // a context left by a failed group is not reused
-                me.ctxs.erase(gk);
-                me.last_use.erase(gk);
-            }
+            if (st != H1W_OK)  // a context left by a failed group is not reused
+                for (const GridKey& gk : used) drop(gk);
             for (size_t k = 0; k < grp.size(); ++k) {
                 if (infos) infos[grp[k]] = ginf[k];
                 if (status) status[grp[k]] = st;
@@ -299,8 +464,8 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
         *report = h1w_batch_report{};
         report->t_total_ms = total_ms;
         report->nworkers = nw;
-        report->ntuned = 0;
     }
+    tuner.publish(report);
 }
 
 }  // namespace
@@ -327,8 +492,8 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
 
-    std::mutex tune_mu;
-    std::map<TuneKey, TuneState> tune;  // the keys met by this batch
+    BatchTuner tuner;
+    tuner.autotune = o.autotune;
     std::atomic<int> next{0};
     std::vector<Worker*> workers(nworkers, nullptr);
     {
@@ -352,39 +517,6 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     }
     std::vector<std::string> worker_err(nworkers);
     std::vector<std::string> item_err(count);
-
-    // schedule (lower Chebyshev bound, 0 = default) for an instance of key tk;
-    // tuning = this worker tunes the key now
-    auto choose_lo = [&](const TuneKey& tk, bool& tuning) -> double {
-        tuning = false;
-        if (!o.autotune) return 0.0;
-        std::lock_guard<std::mutex> lk(tune_mu);
-        TuneState& ts = tune[tk];
-        if (!ts.claimed && o.autotune == 1) {  // a choice of an earlier batch
-            std::lock_guard<std::mutex> lg(g_tuned_mu);
-            auto f = g_tuned.find(tk);
-            if (f != g_tuned.end()) {
-                ts = f->second;
-                ts.reused = true;
-            }
-        }
-        if (!ts.claimed) {
-            ts.claimed = true;
-            tuning = true;
-            return 0.0;
-        }
-        return ts.done ? ts.best_lo : 0.0;
-    };
-    auto finish_tuning = [&](const TuneKey& tk, double lo, double t_norm, int its, int its_def, int bucket) {
-        std::lock_guard<std::mutex> lk(tune_mu);
-        TuneState& ts = tune[tk];
-        ts.best = t_norm;
-        ts.best_lo = lo;
-        ts.best_iters = its;
-        ts.def_iters = its_def;
-        ts.bucket = bucket;
-        ts.done = true;
-    };
 
     auto run = [&](int w) {
         Worker& me = *workers[w];
@@ -420,9 +552,9 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                 require(it.b != nullptr && it.x != nullptr && (it.m == 0 || it.J != nullptr),
                         "item b, x (and J when m > 0) must not be NULL");
                 const int n2 = it.dim == 3 ? it.n[2] : 1;
-                TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision, nu_fixed};
+                TuneKey tk{it.dim, it.n[0], it.n[1], n2, o.precision, nu_fixed, false};
                 bool tuning = false;
-                const double lo = choose_lo(tk, tuning);
+                const double lo = tuner.choose(tk, tuning);
                 require(std::isfinite(it.beta) && it.beta == grid_beta[ShapeKey{it.dim, it.n[0], it.n[1], n2}],
                         "items of one grid must share beta within a batch");
                 auto gkey = [&](double lo_c) {
@@ -479,14 +611,15 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                     ctx_for(lo).gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
                 } else {
                     // the candidates on this instance, the default last (its x is the result)
-                    double t_def = -1.0, t_best = -1.0, best_lo = 0.0;
-                    int it_def = -1, it_best = -1;
+                    int its[kNumCandidates];
+                    double tms[kNumCandidates];
                     for (int c = 0; c < kNumCandidates; ++c) {
+                        its[c] = -1;
                         const double lo_c = kTuneLo[c];
                         Ctx& cx = ctx_for(lo_c);
                         cx.sync();
                         const auto t0 = std::chrono::steady_clock::now();
-                        if (lo_c == 0.0) {
+                        if (c == kDefaultCandidate) {
                             cx.gn_solve(it.m, it.J, it.ldj, it.alpha, it.b, nullptr, nullptr, it.x, so, &inf);
                         } else {
                             try {  // a candidate that fails (e.g. no convergence) is skipped
@@ -497,32 +630,18 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
                                 continue;
                             }
                         }
-                        const double ms =
-                            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                        if (lo_c == 0.0) {
-                            t_def = ms;
-                            it_def = inf.iters;
-                        } else if (it_best < 0 || inf.iters < it_best) {
-                            t_best = ms;
-                            it_best = inf.iters;
-                            best_lo = lo_c;
-                        }
+                        tms[c] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                        its[c] = inf.iters;
                     }
-                    // a candidate replaces the default only with fewer iterations
-                    double best = t_def;
-                    if (it_best >= 0 && it_best < it_def) {
-                        best = t_best;
-                    } else {
-                        best_lo = 0.0;
-                        it_best = it_def;
-                    }
-                    finish_tuning(tk, best_lo, best / work(i), it_best, it_def, row_bucket(it.m));
+                    const int pick = pick_candidate(its);  // the default ran, so pick >= 0
+                    tuner.finish(tk, kTuneLo[pick], tms[pick] / work(i), its[pick], its[kDefaultCandidate],
+                                 row_bucket(it.m));
                     // the losing candidates' contexts are not used again by
                     // this key: dropped now (in the tuning call) rather than
                     // by the LRU cap later, when a timed batch would pay for
                     // re-creating what they pushed out
-                    for (int c = 0; c < kNumCandidates; ++c)
-                        if (kTuneLo[c] != best_lo && kTuneLo[c] != 0.0) drop(gkey(kTuneLo[c]));
+                    for (int c = 0; c < kDefaultCandidate; ++c)
+                        if (c != pick && its[c] >= 0) drop(gkey(kTuneLo[c]));
                 }
             } catch (const Error& e) {
                 st = e.st;
@@ -562,33 +681,12 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
             if (!item_err[order[q]].empty())
                 *first_err = "item " + std::to_string(order[q]) + ": " + item_err[order[q]];
     }
-    if (o.autotune) {
-        std::lock_guard<std::mutex> lk(g_tuned_mu);
-        for (const auto& [tk, ts] : tune)
-            if (ts.done && !ts.reused) g_tuned[tk] = ts;
-    }
     if (report) {
         *report = h1w_batch_report{};
         report->t_total_ms = total_ms;
         report->nworkers = nworkers;
-        int k = 0;
-        for (const auto& [tk, ts] : tune) {
-            if (k >= H1W_BATCH_MAX_KEYS) break;
-            h1w_batch_tuned& r = report->tuned[k++];
-            r.dim = tk.dim;
-            r.n[0] = tk.n0;
-            r.n[1] = tk.n1;
-            r.n[2] = tk.n2;
-            r.m_bucket = ts.bucket;
-            r.nu = tk.nu;
-            r.cheb_lo = ts.best_lo > 0.0 ? ts.best_lo : kChebLoDefault;
-            r.iters = ts.best_iters;
-            r.iters_default = ts.def_iters;
-            r.ms_per_unit = ts.best;
-            r.reused = ts.reused ? 1 : 0;
-        }
-        report->ntuned = k;
     }
+    tuner.publish(report);
 }
 
 }  // namespace h1w

@@ -663,7 +663,6 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
     z_streamed = !fp32 && ((d.flags & H1W_FLAG_STREAM_Z) || zbytes > avail / 100 * 45);
     if (fp32 && zbytes > avail / 100 * 90)
         throw Error{H1W_ENOMEM, "the FP32 Z of a MIXED context does not fit in device memory"};
-    double gflops = 0.0;
     // S = alpha I + J Z^T. FP64 Z with a Cholesky factor (or a streamed Z):
     // lower triangle only, mirrored at the end; otherwise the full product.
     const bool lower = !fp32 && (z_streamed || fac == H1W_FACTOR_CHOL);
@@ -732,7 +731,6 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
             });
             launch_capacitance_reduce(stream, rows, cc, splits, gp, true, alpha, 0,
                                       Sbuf.as<double>() + (int64_t)r0 * m + r0, m);
-            gflops += useful;
         } else {
             const double fl = 2.0 * m * cc * n;
             timed(H1W_K_GEMM, (double)m * n * 8 + (double)cc * n * zes, fl, [&] {
@@ -744,7 +742,6 @@ void Ctx::capacitance_build(int m_, const double* J_, int64_t ldj_, double alpha
                     splits = launch_capacitance_partial<float>(stream, m, cc, n, J, ldj, z32, ldz, false, gp, pe);
             });
             launch_capacitance_reduce(stream, m, cc, splits, gp, false, alpha, r0, Sbuf.as<double>() + r0, m);
-            gflops += fl;
         }
     }
     if (lower) launch_mirror_lower(stream, m, Sbuf.as<double>());

@@ -23,7 +23,11 @@
 // handled in FP64, S is formed in FP64 from the same Z, and everything else
 // is FP64). An instance stops when its
 // recursive residual reaches rtol; the true residual b - G x is then checked
-// and an instance that misses rtol restarts from its x.
+// and an instance that misses rtol restarts from its x. Converged instances
+// drop out of the passes over J (masked work-groups) and, once a quarter of
+// the group has converged, out of the V-cycles (the active right-hand sides
+// are compacted), so the group's slowest instances do not make every
+// instance pay for their extra iterations.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -37,12 +41,17 @@ namespace {
 constexpr int kGrpRows = Ctx::kGroupMaxRows;
 constexpr int kGJThreadsG = 1024;
 
+// Activity masks: act[g] = 0 marks an instance that has converged; the
+// kernels below skip its rows and vectors (act == nullptr: every instance),
+// so a step costs about what its active instances need.
+
 // out[i] = J_i . v_g for the M stacked rows (g the instance of row i, found by
 // bisection over the row offsets): one work-group per row, four independent
 // partial sums per thread (four loads in flight), fixed order
 __global__ __launch_bounds__(kBlock) void k_grp_rows_dot(int64_t N, const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ V, int64_t ldv,
-                                                          const int* __restrict__ ro, int G, double* __restrict__ out) {
+                                                          const int* __restrict__ ro, int G,
+                                                          const int* __restrict__ act, double* __restrict__ out) {
     __shared__ double sh[kBlock / 64];
     const int64_t i = blockIdx.x;
     int lo = 0, hi = G - 1;
@@ -51,6 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_grp_rows_dot(int64_t N, const double
         if (ro[mid] <= i) lo = mid;
         else hi = mid - 1;
     }
+    if (act && !act[lo]) return;
     const double* a = A + i * lda;
     const double* v = V + (int64_t)lo * ldv;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -82,6 +92,19 @@ __global__ __launch_bounds__(kBlock) void k_grp_scatter(int64_t N, const double*
     dst[g][n] = X[g * ldx + n];
 }
 
+// compaction of the active vectors (idx: the active instances in order):
+// Dst[r] = Src[idx[r]] (TO_COMPACT) or Dst[idx[r]] = Src[r], r < the grid's y
+template <bool TO_COMPACT>
+__global__ __launch_bounds__(kBlock) void k_grp_compact(int64_t N, const double* __restrict__ Src, int64_t lds,
+                                                        const int* __restrict__ idx, double* __restrict__ Dst,
+                                                        int64_t ldd) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    const int r = blockIdx.y;
+    const int64_t s = TO_COMPACT ? idx[r] : r, d = TO_COMPACT ? r : idx[r];
+    Dst[d * ldd + n] = Src[s * lds + n];
+}
+
 // sum over instance g's rows of A[i, n] c[i], combined per MODE:
 //   0: Out[g, n] = alpha_g Out[g, n] + sum     (G p, with Out holding A p)
 //   1: Out[g, n] = (Y[g, n] - sum) / alpha_g   (the Woodbury apply)
@@ -89,9 +112,11 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_grp_jt(int64_t N, const double* __restrict__ A, int64_t lda,
                                                    const int* __restrict__ ro, const double* __restrict__ c,
                                                    const double* __restrict__ alpha, const double* __restrict__ Y,
-                                                   int64_t ldy, double* __restrict__ Out, int64_t ldo) {
+                                                   int64_t ldy, const int* __restrict__ act, double* __restrict__ Out,
+                                                   int64_t ldo) {
     __shared__ double cs[kGrpRows];
     const int g = blockIdx.y;
+    if (act && !act[g]) return;
     const int r0 = ro[g], m = ro[g + 1] - r0;
     for (int t = threadIdx.x; t < m; t += kBlock) cs[t] = c[r0 + t];
     __syncthreads();
@@ -154,9 +179,11 @@ __global__ __launch_bounds__(kGJThreadsG) void k_grp_inverse(const int* __restri
 // w[ro_g + i] = sum_j S_g^{-1}[i][j] t[ro_g + j], one work-group per instance
 __global__ __launch_bounds__(kGrpRows) void k_grp_matvec(const int* __restrict__ ro, const int64_t* __restrict__ soff,
                                                          const double* __restrict__ SinvT,
-                                                         const double* __restrict__ t, double* __restrict__ w) {
+                                                         const double* __restrict__ t, const int* __restrict__ act,
+                                                         double* __restrict__ w) {
     __shared__ double ts[kGrpRows];
     const int g = blockIdx.x;
+    if (!act[g]) return;
     const int r0 = ro[g], m = ro[g + 1] - r0;
     const int i = threadIdx.x;
     if (i < m) ts[i] = t[r0 + i];
@@ -347,9 +374,9 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     launch_grp_gemm_partial(stream, t, n, Jall, P, Zall, P, grpPart.as<double>());
     launch_grp_gemm_reduce(stream, t, grpPart.as<double>(), grpS.as<double>());
 
-    // vectors: B, X, R, Z, P, Q, Y (G x P each); M-vectors t (J y or J p) and
-    // w = S^{-1} t; scalars
-    grpVec.reserve((size_t)7 * G * P * sizeof(double) + (size_t)2 * rows * sizeof(double));
+    // vectors: B, X, R, Z, P, Q, Y and the compacted Rc, Yc (G x P each);
+    // M-vectors t (J y or J p) and w = S^{-1} t; scalars
+    grpVec.reserve((size_t)9 * G * P * sizeof(double) + (size_t)2 * rows * sizeof(double));
     double* Bv = grpVec.as<double>();
     double* X = Bv + (size_t)G * P;
     double* R = X + (size_t)G * P;
@@ -357,9 +384,11 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     double* Pv = Zv + (size_t)G * P;
     double* Q = Pv + (size_t)G * P;
     double* Y = Q + (size_t)G * P;
-    double* tv = Y + (size_t)G * P;
+    double* Rc = Y + (size_t)G * P;
+    double* Yc = Rc + (size_t)G * P;
+    double* tv = Yc + (size_t)G * P;
     double* wv = tv + rows;
-    grpScal.reserve((size_t)(7 * G + 64 * G) * sizeof(double) + (size_t)(G + 8) * sizeof(int));
+    grpScal.reserve((size_t)(7 * G + 64 * G) * sizeof(double) + (size_t)(2 * G + 8) * sizeof(int));
     double* dnrm = grpScal.as<double>();
     double* drz = dnrm + G;
     double* dpq = drz + G;
@@ -369,7 +398,8 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     double* drzn = dzq + G;
     double* pp = drzn + G;  // 64 G dot-product partials
     int* dact = (int*)(pp + 64 * G);
-    int* dflag = dact + G;
+    int* didx = dact + G;  // the active instances, in order
+    int* dflag = didx + G;
     H1W_HIP(hipMemsetAsync(dflag, 0, 8 * sizeof(int), stream));
     if (M > 0)
         hipLaunchKernelGGL(k_grp_inverse, dim3((unsigned)G), dim3(kGJThreadsG), 0, stream, d_ro, d_soff,
@@ -380,47 +410,67 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
                        Bv, P);
     H1W_LAUNCHED();
     H1W_HIP(hipMemset2DAsync(X, P * sizeof(double), 0, n * sizeof(double), G, stream));
+    // Z, P, Q, Y start at zero: the rows of an instance that never runs (b = 0)
+    // are then read as zeros by the unmasked kernels
+    H1W_HIP(hipMemsetAsync(Zv, 0, (size_t)4 * G * P * sizeof(double), stream));
 
     const dim3 gridNG((unsigned)cdiv(n, kBlock), (unsigned)G);
-    // out[i] = J_i . V[instance of i] for the M stacked rows
-    auto rows_dot = [&](const double* V, double* out) {
+    // host copies of the activity mask and of the active instances' indices
+    std::vector<double> rr(G), nb(G), hsc(G);
+    std::vector<int> act(G, 0), iters(G, 0), hidx(G, 0);
+    int nact = 0;
+    // out[i] = J_i . V[instance of i] for the M stacked rows (mask: nullptr or dact)
+    auto rows_dot = [&](const double* V, double* out, const int* mask) {
         hipLaunchKernelGGL(k_grp_rows_dot, dim3((unsigned)M), dim3(kBlock), 0, stream, n, (const double*)Jall, P, V,
-                           P, d_ro, G, out);
+                           P, d_ro, G, mask, out);
         H1W_LAUNCHED();
     };
-    // z = P^{-1} r
+    // z = P^{-1} r for the active instances. With a quarter or more of the
+    // group converged, their right-hand sides are compacted first, so the
+    // V-cycles run on the active ones only (two extra vector copies each).
     auto precond = [&](const double* Rin, double* Zout) {
-        vcycle_group(G, Rin, P, Y, P);
+        if (nact * 4 > G * 3) {
+            vcycle_group(G, Rin, P, Y, P);
+        } else if (nact > 0) {
+            const dim3 gc((unsigned)cdiv(n, kBlock), (unsigned)nact);
+            hipLaunchKernelGGL(k_grp_compact<true>, gc, dim3(kBlock), 0, stream, n, Rin, P, (const int*)didx, Rc, P);
+            H1W_LAUNCHED();
+            vcycle_group(nact, Rc, P, Yc, P);
+            hipLaunchKernelGGL(k_grp_compact<false>, gc, dim3(kBlock), 0, stream, n, (const double*)Yc, P,
+                               (const int*)didx, Y, P);
+            H1W_LAUNCHED();
+        }
         if (M > 0) {
-            rows_dot(Y, tv);
+            rows_dot(Y, tv, dact);
             hipLaunchKernelGGL(k_grp_matvec, dim3((unsigned)G), dim3(kGrpRows), 0, stream, d_ro, d_soff,
-                               (const double*)grpSinv.p, (const double*)tv, wv);
+                               (const double*)grpSinv.p, (const double*)tv, (const int*)dact, wv);
         }
         hipLaunchKernelGGL(k_grp_jt<1>, gridNG, dim3(kBlock), 0, stream, n, (const double*)Zall, P, d_ro,
-                           (const double*)wv, d_alpha, (const double*)Y, P, Zout, P);
+                           (const double*)wv, d_alpha, (const double*)Y, P, (const int*)dact, Zout, P);
         H1W_LAUNCHED();
     };
-    // Q = G X = alpha A X + J^T (J X); jx: J X (nullptr: one pass over J forms it)
-    auto applyG = [&](const double* Pin, double* Qout, const double* jx) {
+    // Q = G X = alpha A X + J^T (J X) (mask: nullptr, every instance, or dact)
+    auto applyG = [&](const double* Pin, double* Qout, const int* mask) {
         launch_apply<double>(stream, dim, lv[0], G, Pin, P, Qout, P, 1.0);
-        if (M > 0 && !jx) {
-            rows_dot(Pin, tv);
-            jx = tv;
-        }
+        if (M > 0) rows_dot(Pin, tv, mask);
         hipLaunchKernelGGL(k_grp_jt<0>, gridNG, dim3(kBlock), 0, stream, n, (const double*)Jall, P, d_ro,
-                           M > 0 ? jx : (const double*)tv, d_alpha, (const double*)nullptr, 0, Qout, P);
+                           (const double*)tv, d_alpha, (const double*)nullptr, 0, mask, Qout, P);
         H1W_LAUNCHED();
     };
-    std::vector<double> rr(G), nb(G), hsc(G);
-    std::vector<int> act(G, 0), iters(G, 0);
     int hflag[2] = {0, 0};
     auto fetch = [&](const double* d, std::vector<double>& h) {
         H1W_HIP(hipMemcpyAsync(h.data(), d, G * sizeof(double), hipMemcpyDeviceToHost, stream));
         H1W_HIP(hipMemcpyAsync(hflag, dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
         sync();
     };
+    // uploads the mask and the active list (the host copies change only after
+    // the next fetch has synchronised the stream)
     auto put_act = [&]() {
+        nact = 0;
+        for (int g = 0; g < G; ++g)
+            if (act[g]) hidx[nact++] = g;
         H1W_HIP(hipMemcpyAsync(dact, act.data(), G * sizeof(int), hipMemcpyHostToDevice, stream));
+        H1W_HIP(hipMemcpyAsync(didx, hidx.data(), G * sizeof(int), hipMemcpyHostToDevice, stream));
     };
 
     // ||b||, and r = b (x = 0)
@@ -452,7 +502,7 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
                 }
                 throw Error{H1W_ENOCONV, "grouped GN-CG did not reach rtol within maxit iterations"};
             }
-            applyG(Pv, Q, nullptr);
+            applyG(Pv, Q, dact);
             launch_batched_dots(stream, G, n, Pv, P, Q, P, pp, dpq);
             launch_pcg_alpha(stream, G, drz, dpq, dact, da, dflag + 1);
             launch_batched_cg_xr(stream, G, n, da, Pv, P, Q, P, X, P, R, P, dact);
@@ -476,7 +526,8 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
             launch_pcg_beta(stream, G, drzn, drz, dzq, da, dact, db);
             launch_batched_p(stream, G, n, db, Zv, P, Pv, P, dact);
         }
-        // true residuals r = b - G x; an instance that misses rtol restarts from x
+        // true residuals r = b - G x (every instance); one that misses rtol
+        // restarts from x
         applyG(X, Q, nullptr);
         hipLaunchKernelGGL(k_grp_sub, gridNG, dim3(kBlock), 0, stream, n, (const double*)Bv, (const double*)Q, R, P);
         H1W_LAUNCHED();

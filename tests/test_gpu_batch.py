@@ -145,6 +145,44 @@ def test_grouped_batch_matches_oracle(P, prec, rtol):
           f"{sorted(i.iters for i in infos)}", flush=True)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_grouped_batch_autotune_departs_where_iterations_drop(P, prec):
+    # the grouped mode solves the whole group with each schedule and keeps
+    # the one with the least work (iterations weighted by m + 1): on 129^2
+    # grids at rtol 1e-8 that is [0.4, 2] or [0.5, 2], one CG iteration fewer
+    # than the default for every instance of the group, each of which must
+    # still meet the tolerance on the oracle's true residual
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads(count=6, batch_id=9, sides=(129,), m_lo=40, m_hi=60)
+    items, host = make_items(wls)
+    precision = {"fp64": nat.H1W_FP64, "mixed": nat.H1W_MIXED}[prec]
+    infos0, stats0, _ = nat.h1w_batch_solve(items, precision=precision, nworkers=1, autotune=0, rtol=1e-8,
+                                            grouped=True)
+    assert all(s == 0 for s in stats0)
+    iters0 = [i.iters for i in infos0]
+    infos, stats, rep = nat.h1w_batch_solve(items, precision=precision, nworkers=1, autotune=2, rtol=1e-8,
+                                            grouped=True)
+    assert all(s == 0 for s in stats)
+    assert rep.ntuned == 1
+    t = rep.tuned[0]
+    iters = [i.iters for i in infos]
+    print(f"grouped {prec}: chosen lower bound {t.cheb_lo}, group iterations {t.iters} against "
+          f"{t.iters_default}; per instance {iters} against {iters0}", flush=True)
+    assert t.grouped == 1
+    assert t.cheb_lo in (0.4, 0.5) and t.iters < t.iters_default
+    assert t.iters == sum(iters) and t.iters_default == sum(iters0)
+    assert sum(iters) < sum(iters0)
+    for wl, it, (J, b) in zip(wls, items, host):
+        rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy())
+        assert rr <= 1.01e-8
+    # a later batch reuses the choice (autotune = 1) without tuning again
+    infos2, stats2, rep2 = nat.h1w_batch_solve(items, precision=precision, nworkers=1, autotune=1, rtol=1e-8,
+                                               grouped=True)
+    assert all(s == 0 for s in stats2)
+    assert rep2.ntuned == 1 and rep2.tuned[0].reused == 1 and rep2.tuned[0].cheb_lo == t.cheb_lo
+    assert [i.iters for i in infos2] == iters
+
+
 def test_grouped_batch_rejects_more_than_128_rows(P):
     from paper_2209_02815_amd import _native as nat
     wls = H.batch_workloads(count=2, batch_id=12, sides=(17,), m_lo=129, m_hi=140) + \
