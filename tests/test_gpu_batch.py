@@ -183,6 +183,27 @@ def test_grouped_batch_autotune_departs_where_iterations_drop(P, prec):
     assert [i.iters for i in infos2] == iters
 
 
+def test_grouped_batch_cut_groups_and_zero_rhs(P):
+    # 300 instances on one grid are cut into groups of at most 256 (two
+    # groups, so two workers solve the same grid at once); an instance with
+    # b = 0 never becomes active and returns x = 0 exactly
+    from paper_2209_02815_amd import _native as nat
+    wls = H.batch_workloads(count=300, batch_id=14, sides=(17,), m_lo=1, m_hi=8)
+    items, host = make_items(wls)
+    zero = 7
+    items[zero]["b"].zero_()
+    infos, stats, rep = nat.h1w_batch_solve(items, nworkers=2, rtol=1e-10, grouped=True)
+    assert all(s == 0 for s in stats)
+    assert rep.nworkers == 2
+    assert torch.count_nonzero(items[zero]["x"]).item() == 0
+    assert infos[zero].iters == 0 and infos[zero].relres_true == 0.0
+    for k, (wl, it, (J, b)) in enumerate(zip(wls, items, host)):
+        if k == zero:
+            continue
+        rr = gn.true_relres(wl.shape, wl.beta, J, wl.alpha, b, it["x"].cpu().numpy())
+        assert rr <= 1.01e-10, (k, rr)
+
+
 def test_grouped_batch_rejects_more_than_128_rows(P):
     from paper_2209_02815_amd import _native as nat
     wls = H.batch_workloads(count=2, batch_id=12, sides=(17,), m_lo=129, m_hi=140) + \
