@@ -348,8 +348,8 @@ h1w_status h1w_reset_kernel_timing(h1w_ctx* ctx);
  * pointers owned by the caller; J, b, x follow h1w_gn_solve (J m x N with
  * leading dimension ldj, x receives the solution). infos and status (count
  * entries each, may be NULL) receive each item's diagnostics and status;
- * the call returns H1W_OK when every item succeeded, else the first failing
- * item's status (in the queue order), and blocks until all items are done.
+ * the call returns H1W_OK when every item succeeded, else the status of the
+ * failing item with the lowest index, and blocks until all items are done.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int dim;             /* 2 or 3 */
@@ -381,8 +381,10 @@ typedef struct {
                             over the stacked rows, dot products, updates with
                             per-item step lengths and activity masks); each item's
                             S = alpha I + J Z^T is one tile of a grouped MFMA product
-                            and is inverted in one work-group. Needs m <= 128 for every
-                            item (EINVAL for the others); graphs is ignored. With
+                            and is inverted in one work-group. Items with m > 128 are
+                            solved after the groups, one solve per item as with
+                            grouped = 0 (same options); graphs is ignored by the
+                            groups. With
                             autotune, a group whose key is untuned is solved whole with
                             each interval and then the default, and keeps the interval
                             with the least work (its items' CG iterations weighted by

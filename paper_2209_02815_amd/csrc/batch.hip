@@ -231,10 +231,11 @@ namespace {
 // Grouped (lock-step) mode: the items of one grid form a group solved by
 // Ctx::gn_group_solve on one worker; the groups are spread over the workers.
 void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
-                         h1w_status* status, h1w_batch_report* report, std::string* first_err, int device) {
+                         h1w_status* status, h1w_batch_report* report, std::vector<std::string>& item_err,
+                         int device) {
     constexpr int kMaxGroup = 256;  // items per lock-step group (larger grids' groups are cut)
     const int nu_fixed = o.nu > 0 ? o.nu : 2;
-    std::vector<std::string> item_err(count);
+    item_err.assign(count, std::string());
     // groups of item indices per grid, in first-seen order, cut at kMaxGroup
     std::map<std::tuple<int, int, int, int, double>, std::vector<int>> by_grid;
     std::vector<std::vector<int>> groups;
@@ -455,11 +456,6 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
     }
     for (const auto& e : worker_err)
         if (!e.empty()) throw Error{H1W_EHIP, "batch worker setup failed: " + e};
-    if (first_err) {
-        first_err->clear();
-        for (int i = 0; i < count && first_err->empty(); ++i)
-            if (!item_err[i].empty()) *first_err = "item " + std::to_string(i) + ": " + item_err[i];
-    }
     if (report) {
         *report = h1w_batch_report{};
         report->t_total_ms = total_ms;
@@ -468,16 +464,10 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
     tuner.publish(report);
 }
 
-}  // namespace
-
-void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
-                 h1w_status* status, h1w_batch_report* report, std::string* first_err) {
-    int device = 0;
-    H1W_HIP(hipGetDevice(&device));
-    if (o.grouped) {
-        batch_solve_grouped(count, items, o, infos, status, report, first_err, device);
-        return;
-    }
+// One solve per item on the workers' streams.
+void batch_solve_each(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
+                      h1w_status* status, h1w_batch_report* report, std::vector<std::string>& item_err,
+                      int device) {
     const int nworkers = std::clamp(o.nworkers > 0 ? o.nworkers : 8, 1, 16);
     const int nu_fixed = o.nu > 0 ? o.nu : 2;
 
@@ -516,7 +506,7 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
         grid_beta.emplace(ShapeKey{it.dim, it.n[0], it.n[1], it.dim == 3 ? it.n[2] : 1}, it.beta);
     }
     std::vector<std::string> worker_err(nworkers);
-    std::vector<std::string> item_err(count);
+    item_err.assign(count, std::string());
 
     auto run = [&](int w) {
         Worker& me = *workers[w];
@@ -675,18 +665,77 @@ void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o
     }
     for (const auto& e : worker_err)
         if (!e.empty()) throw Error{H1W_EHIP, "batch worker setup failed: " + e};
-    if (first_err) {
-        first_err->clear();
-        for (int q = 0; q < count && first_err->empty(); ++q)
-            if (!item_err[order[q]].empty())
-                *first_err = "item " + std::to_string(order[q]) + ": " + item_err[order[q]];
-    }
     if (report) {
         *report = h1w_batch_report{};
         report->t_total_ms = total_ms;
         report->nworkers = nworkers;
     }
     tuner.publish(report);
+}
+
+}  // namespace
+
+void batch_solve(int count, const h1w_batch_item* items, const h1w_batch_opts& o, h1w_info* infos,
+                 h1w_status* status, h1w_batch_report* report, std::string* first_err) {
+    int device = 0;
+    H1W_HIP(hipGetDevice(&device));
+    std::vector<std::string> item_err;
+    // grouped mode: items with more rows than a group's instance may hold are
+    // solved one at a time after the groups
+    std::vector<int> big;
+    if (o.grouped)
+        for (int i = 0; i < count; ++i)
+            if (items[i].m > Ctx::kGroupMaxRows) big.push_back(i);
+    if (!o.grouped) {
+        batch_solve_each(count, items, o, infos, status, report, item_err, device);
+    } else if (big.empty()) {
+        batch_solve_grouped(count, items, o, infos, status, report, item_err, device);
+    } else {
+        std::vector<int> small;
+        for (int i = 0, b = 0; i < count; ++i) {
+            if (b < (int)big.size() && big[b] == i) ++b;
+            else small.push_back(i);
+        }
+        item_err.assign(count, std::string());
+        h1w_batch_report reps[2];
+        int nrep = 0;
+        auto run = [&](const std::vector<int>& idx, bool grouped) {
+            if (idx.empty()) return;
+            const int n = (int)idx.size();
+            std::vector<h1w_batch_item> sub(n);
+            for (int k = 0; k < n; ++k) sub[k] = items[idx[k]];
+            std::vector<h1w_info> sinf(n);
+            std::vector<h1w_status> sst(n, H1W_OK);
+            std::vector<std::string> serr;
+            h1w_batch_report& rep = reps[nrep++];
+            rep = h1w_batch_report{};
+            h1w_batch_opts so = o;
+            so.grouped = grouped ? 1 : 0;
+            if (grouped) batch_solve_grouped(n, sub.data(), so, sinf.data(), sst.data(), &rep, serr, device);
+            else batch_solve_each(n, sub.data(), so, sinf.data(), sst.data(), &rep, serr, device);
+            for (int k = 0; k < n; ++k) {
+                if (infos) infos[idx[k]] = sinf[k];
+                if (status) status[idx[k]] = sst[k];
+                item_err[idx[k]] = serr[k];
+            }
+        };
+        run(small, true);
+        run(big, false);
+        if (report) {
+            *report = h1w_batch_report{};
+            for (int r = 0; r < nrep; ++r) {
+                report->t_total_ms += reps[r].t_total_ms;
+                report->nworkers = std::max(report->nworkers, reps[r].nworkers);
+                for (int k = 0; k < reps[r].ntuned && report->ntuned < H1W_BATCH_MAX_KEYS; ++k)
+                    report->tuned[report->ntuned++] = reps[r].tuned[k];
+            }
+        }
+    }
+    if (first_err) {
+        first_err->clear();
+        for (int i = 0; i < count && first_err->empty(); ++i)
+            if (!item_err[i].empty()) *first_err = "item " + std::to_string(i) + ": " + item_err[i];
+    }
 }
 
 }  // namespace h1w
