@@ -73,9 +73,11 @@ __device__ __forceinline__ void cap_tile(int m, int m2, const double* __restrict
     const int arow0 = tr * kTileMN, brow0 = tc * kTileMN;
     // on a diagonal tile of the lower-triangle product the wave at rows 0-63,
     // columns 64-127 lies strictly above the diagonal, whose entries the
-    // reduction never reads: it keeps loading and synchronising with the
-    // group but skips its MFMAs (its SIMD time goes to the co-resident group)
-    const bool idle = lower && tr == tc && wr < wc;
+    // reduction never reads; on a ragged tile a wave's quadrant can lie past
+    // the last row or column. Such a wave keeps loading and synchronising
+    // with the group but skips its MFMAs (its SIMD time goes to the
+    // co-resident group)
+    const bool idle = (lower && tr == tc && wr < wc) || arow0 + wr >= m || brow0 + wc >= m2;
 
     // loader: column lk of rows lr + 16 q, q = 0..7. Rows past the end of J
     // or Z read row 0 instead: they only feed output rows (columns) that are
