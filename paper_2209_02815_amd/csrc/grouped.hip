@@ -416,7 +416,7 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
 
     const dim3 gridNG((unsigned)cdiv(n, kBlock), (unsigned)G);
     // host copies of the activity mask and of the active instances' indices
-    std::vector<double> rr(G), nb(G), hsc(G);
+    std::vector<double> rr(G), nb(G);
     std::vector<int> act(G, 0), iters(G, 0), hidx(G, 0);
     int nact = 0;
     // out[i] = J_i . V[instance of i] for the M stacked rows (mask: nullptr or dact)
