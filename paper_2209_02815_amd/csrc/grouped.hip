@@ -45,21 +45,16 @@ constexpr int kGJThreadsG = 1024;
 // kernels below skip its rows and vectors (act == nullptr: every instance),
 // so a step costs about what its active instances need.
 
-// out[i] = J_i . v_g for the M stacked rows (g the instance of row i, found by
-// bisection over the row offsets): one work-group per row, four independent
-// partial sums per thread (four loads in flight), fixed order
+// out[i] = J_i . v_g for the M stacked rows (g = rowg[i], the instance of row
+// i): one work-group per row, four independent partial sums per thread (four
+// loads in flight), fixed order
 __global__ __launch_bounds__(kBlock) void k_grp_rows_dot(int64_t N, const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ V, int64_t ldv,
-                                                          const int* __restrict__ ro, int G,
+                                                          const int* __restrict__ rowg,
                                                           const int* __restrict__ act, double* __restrict__ out) {
     __shared__ double sh[kBlock / 64];
     const int64_t i = blockIdx.x;
-    int lo = 0, hi = G - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ro[mid] <= i) lo = mid;
-        else hi = mid - 1;
-    }
+    const int lo = rowg[i];
     if (act && !act[lo]) return;
     const double* a = A + i * lda;
     const double* v = V + (int64_t)lo * ldv;
@@ -319,9 +314,10 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     const size_t rows = (size_t)std::max(M, 1);
 
     // device tables: int64 block (soff, poff, kper, then the row, b and x
-    // pointers), int block (ro, io, m), alpha
+    // pointers), int block (ro, io, m, the instance of each row; padded to an
+    // even count so that alpha stays 8-byte aligned), alpha
     const size_t nptr = rows + 2 * (size_t)G;
-    const size_t n64 = (size_t)(G + 1) * 2 + G + nptr, nint = (size_t)(G + 1) * 2 + G;
+    const size_t n64 = (size_t)(G + 1) * 2 + G + nptr, nint = ((size_t)(G + 1) * 2 + G + rows + 1) / 2 * 2;
     std::vector<char> host(n64 * 8 + nint * 4 + (size_t)G * 8);
     {
         const void** hp = (const void**)(host.data() + ((size_t)(G + 1) * 2 + G) * 8);
@@ -339,6 +335,10 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
         std::copy(ro.begin(), ro.end(), hi);
         std::copy(io.begin(), io.end(), hi + (G + 1));
         std::copy(mm.begin(), mm.end(), hi + 2 * (G + 1));
+        int* hrow = hi + 2 * (G + 1) + G;
+        hrow[0] = 0;
+        for (int g = 0; g < G; ++g)
+            for (int r = ro[g]; r < ro[g + 1]; ++r) hrow[r] = g;
         std::copy(alph.begin(), alph.end(), (double*)(host.data() + n64 * 8 + nint * 4));
     }
     grpTab.reserve(host.size());
@@ -349,6 +349,7 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     const int* d_ro = (const int*)((const char*)grpTab.p + n64 * 8);
     const int* d_io = d_ro + (G + 1);
     const int* d_m = d_io + (G + 1);
+    const int* d_rowg = d_m + G;
     const double* d_alpha = (const double*)((const char*)grpTab.p + n64 * 8 + nint * 4);
     const double* const* d_rowp = (const double* const*)(d_soff + (G + 1) * 2 + G);
     const double* const* d_bp = d_rowp + rows;
@@ -422,7 +423,7 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     // out[i] = J_i . V[instance of i] for the M stacked rows (mask: nullptr or dact)
     auto rows_dot = [&](const double* V, double* out, const int* mask) {
         hipLaunchKernelGGL(k_grp_rows_dot, dim3((unsigned)M), dim3(kBlock), 0, stream, n, (const double*)Jall, P, V,
-                           P, d_ro, G, mask, out);
+                           P, d_rowg, mask, out);
         H1W_LAUNCHED();
     };
     // z = P^{-1} r for the active instances. With a quarter or more of the
