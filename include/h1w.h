@@ -394,8 +394,12 @@ typedef struct {
                             item's iterations. The preconditioned CG (stored-Z Woodbury apply,
                             flexible direction coefficient) stops each item on its
                             recursive residual and checks its true residual (up to two
-                            restarts); a group that fails gives its status to all of
-                            its items. 0: one solve per item (above). */
+                            restarts; maxit counts the group's iterations). Each item
+                            gets its own status: ENOCONV if it misses rtol, ENUMERIC
+                            if its values turn non-finite or its CG breaks down, the
+                            other items unaffected; a failure of the whole group (its
+                            set-up, a zero capacitance pivot) gives its status to all
+                            of its items. 0: one solve per item (above). */
 } h1w_batch_opts;
 
 #define H1W_BATCH_MAX_KEYS 64

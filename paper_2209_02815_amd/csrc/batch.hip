@@ -356,7 +356,8 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                 return *me.ctxs[gk];
             };
             std::vector<h1w_info> ginf(grp.size(), h1w_info{});
-            h1w_status st = H1W_OK;
+            std::vector<h1w_status> gst(grp.size(), H1W_OK);  // each item's own outcome
+            h1w_status st = H1W_OK;                            // a failure of the whole group
             std::string msg;
             try {
                 std::vector<Ctx::GroupItem> gi(grp.size());
@@ -375,17 +376,20 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                     // (its solve stays the result if it is kept); the choice
                     // is the schedule with the least work: the items' CG
                     // iterations weighted by m + 1 (a converged item drops out
-                    // of the group's passes)
+                    // of the group's passes). A candidate counts only if it
+                    // solved every item.
                     double cost[kNumCandidates], tms[kNumCandidates];
                     int sum_it[kNumCandidates];
                     Error def_err{H1W_OK, ""};
+                    bool def_ran = false;
+                    std::vector<h1w_status> cst(grp.size());
                     for (int c = 0; c < kNumCandidates; ++c) {
                         cost[c] = -1.0;
                         Ctx& cx = ctx_for(kTuneLo[c]);
                         cx.sync();
                         const auto t0 = std::chrono::steady_clock::now();
                         try {  // a candidate that fails (e.g. no convergence) is skipped
-                            cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data());
+                            cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data(), cst.data());
                         } catch (const Error& e) {
                             used.pop_back();
                             drop(gkey(kTuneLo[c]));
@@ -393,6 +397,11 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                             continue;
                         }
                         tms[c] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                        if (c == kDefaultCandidate) {
+                            def_ran = true;
+                            gst = cst;
+                        }
+                        if (std::any_of(cst.begin(), cst.end(), [](h1w_status v) { return v != H1W_OK; })) continue;
                         cost[c] = 0.0;
                         sum_it[c] = 0;
                         for (size_t k = 0; k < gi.size(); ++k) {
@@ -400,8 +409,14 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                             sum_it[c] += ginf[k].iters;
                         }
                     }
-                    const int pick = pick_candidate(cost);
-                    if (pick < 0) throw def_err;  // every schedule failed: the default's error
+                    int pick = pick_candidate(cost);
+                    if (pick < 0) {
+                        // no schedule solved every item: the default's solve
+                        // (the last one) is the result, its failures the items'
+                        if (!def_ran) throw def_err;
+                        pick = kDefaultCandidate;
+                        sum_it[pick] = -1;
+                    }
                     double nn = 1.0, work = 0.0;
                     for (int a = 0; a < i0.dim; ++a) nn *= i0.n[a];
                     for (const auto& g : gi) work += nn * (g.m + 1);
@@ -420,7 +435,7 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
                 if (!have_result) {
                     Ctx& cx = ctx_for(lo);
                     const auto t0 = std::chrono::steady_clock::now();
-                    cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data());
+                    cx.gn_group_solve((int)grp.size(), gi.data(), so, ginf.data(), gst.data());
                     ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 }
                 for (auto& f : ginf) f.t_total_ms = ms;
@@ -437,9 +452,15 @@ void batch_solve_grouped(int count, const h1w_batch_item* items, const h1w_batch
             if (st != H1W_OK)  // a context left by a failed group is not reused
                 for (const GridKey& gk : used) drop(gk);
             for (size_t k = 0; k < grp.size(); ++k) {
+                const h1w_status sk = st != H1W_OK ? st : gst[k];
                 if (infos) infos[grp[k]] = ginf[k];
-                if (status) status[grp[k]] = st;
-                if (st != H1W_OK) item_err[grp[k]] = msg;
+                if (status) status[grp[k]] = sk;
+                if (st != H1W_OK)
+                    item_err[grp[k]] = msg;
+                else if (sk == H1W_ENOCONV)
+                    item_err[grp[k]] = "grouped GN-CG: missed rtol on its true residual within maxit iterations";
+                else if (sk != H1W_OK)
+                    item_err[grp[k]] = "grouped GN-CG: non-finite values or a breakdown in this instance";
             }
         }
     };

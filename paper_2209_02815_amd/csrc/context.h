@@ -146,7 +146,10 @@ struct Ctx {
     static constexpr int kGroupMaxRows = 128;
     DevBuf grpJ, grpZ, grpVec, grpS, grpSinv, grpPart, grpTab, grpScal, grpDefl;
     void vcycle_group(int k, const double* F, int64_t ldf, double* X, int64_t ldx);
-    void gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so, h1w_info* infos);
+    // status[g]: H1W_OK, or ENOCONV / ENUMERIC for an instance that failed
+    // alone; failures of the whole group (set-up, a capacitance pivot) throw
+    void gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so, h1w_info* infos,
+                        h1w_status* status);
 
     // ERT context (op = H1W_OP_ERT): conductivity operator, see ert.hip
     bool ert = false;

@@ -27,7 +27,8 @@
 // drop out of the passes over J (masked work-groups) and, once a quarter of
 // the group has converged, out of the V-cycles (the active right-hand sides
 // are compacted), so the group's slowest instances do not make every
-// instance pay for their extra iterations.
+// instance pay for their extra iterations. Each instance ends with a status
+// of its own: non-finite values or a breakdown stop only that instance.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -279,7 +280,8 @@ void Ctx::vcycle_group(int k, const double* F, int64_t ldf, double* X, int64_t l
     }
 }
 
-void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so, h1w_info* infos) {
+void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so, h1w_info* infos,
+                         h1w_status* status) {
     require(!ert, "grouped solves need an H1 context");
     require(G >= 1, "internal: empty group");
     const int64_t n = N(), P = pitch[0];
@@ -480,14 +482,19 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     launch_batched_dots(stream, G, n, R, P, R, P, pp, dnrm);
     fetch(dnrm, rr);
     if (hflag[0]) throw Error{H1W_ENUMERIC, "capacitance matrix of a grouped instance has a zero or non-finite pivot"};
+    // per-instance outcome: an instance with non-finite values or a CG
+    // breakdown stops alone (ENUMERIC), one that misses rtol within maxit
+    // iterations and the restarts is ENOCONV; the others are unaffected
+    for (int g = 0; g < G; ++g) status[g] = H1W_OK;
     for (int g = 0; g < G; ++g) {
-        if (!std::isfinite(rr[g])) throw Error{H1W_ENUMERIC, "non-finite right-hand side in a grouped instance"};
         nb[g] = std::sqrt(rr[g]);
-        act[g] = nb[g] > 0.0;
+        if (!std::isfinite(rr[g])) status[g] = H1W_ENUMERIC;
+        act[g] = status[g] == H1W_OK && nb[g] > 0.0;
     }
-    std::vector<double> relres(G, 0.0);
+    std::vector<double> relres(G, 0.0), hpq(G);
     int total_it = 0;
-    for (int cycle = 0; cycle < 3; ++cycle) {
+    bool out_of_iters = false;
+    for (int cycle = 0; cycle < 3 && !out_of_iters; ++cycle) {
         if (std::none_of(act.begin(), act.end(), [](int v) { return v; })) break;
         put_act();
         // z = P^{-1} r, p = z, rz = r.z
@@ -497,11 +504,8 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
         launch_batched_dots(stream, G, n, R, P, Zv, P, pp, drz);
         for (;;) {
             if (total_it >= maxit) {
-                for (int g = 0; g < G; ++g) {
-                    infos[g].iters = iters[g];
-                    infos[g].relres_rec = nb[g] > 0.0 ? std::sqrt(rr[g]) / nb[g] : 0.0;
-                }
-                throw Error{H1W_ENOCONV, "grouped GN-CG did not reach rtol within maxit iterations"};
+                out_of_iters = true;
+                break;
             }
             applyG(Pv, Q, dact);
             launch_batched_dots(stream, G, n, Pv, P, Q, P, pp, dpq);
@@ -509,12 +513,27 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
             launch_batched_cg_xr(stream, G, n, da, Pv, P, Q, P, X, P, R, P, dact);
             launch_batched_dots(stream, G, n, R, P, R, P, pp, dnrm);
             fetch(dnrm, rr);
-            if (hflag[1]) throw Error{H1W_ENUMERIC, "grouped GN-CG breakdown (p.Gp <= 0 or NaN)"};
+            if (hflag[1]) {
+                // p.Gp <= 0 or not finite for some active instance (its step
+                // was 0): find it, stop it, clear the flag
+                fetch(dpq, hpq);
+                for (int g = 0; g < G; ++g)
+                    if (act[g] && !(hpq[g] > 0.0 && hpq[g] <= 1.79e308)) {
+                        status[g] = H1W_ENUMERIC;
+                        act[g] = 0;
+                    }
+                H1W_HIP(hipMemsetAsync(dflag + 1, 0, sizeof(int), stream));
+                hflag[1] = 0;
+            }
             ++total_it;
             bool any = false;
             for (int g = 0; g < G; ++g) {
                 if (!act[g]) continue;
-                if (!std::isfinite(rr[g])) throw Error{H1W_ENUMERIC, "non-finite residual in a grouped instance"};
+                if (!std::isfinite(rr[g])) {
+                    status[g] = H1W_ENUMERIC;
+                    act[g] = 0;
+                    continue;
+                }
                 ++iters[g];
                 if (std::sqrt(rr[g]) <= rtol * nb[g]) act[g] = 0;
                 any = any || act[g];
@@ -536,7 +555,7 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
         fetch(dnrm, rr);
         for (int g = 0; g < G; ++g) {
             relres[g] = nb[g] > 0.0 ? std::sqrt(rr[g]) / nb[g] : 0.0;
-            act[g] = relres[g] > rtol;
+            act[g] = status[g] == H1W_OK && !(relres[g] <= rtol);
         }
     }
     hipLaunchKernelGGL(k_grp_scatter, dim3((unsigned)cdiv(n, kBlock), (unsigned)G), dim3(kBlock), 0, stream, n,
@@ -549,8 +568,8 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
         infos[g].nlevels = (int)lv.size();
     }
     sync();
-    if (std::any_of(relres.begin(), relres.end(), [&](double v) { return !(v <= rtol); }))
-        throw Error{H1W_ENOCONV, "a grouped instance missed rtol on its true residual after restarts"};
+    for (int g = 0; g < G; ++g)
+        if (status[g] == H1W_OK && !(relres[g] <= rtol)) status[g] = H1W_ENOCONV;
 }
 
 }  // namespace h1w

@@ -204,6 +204,40 @@ def test_grouped_batch_cut_groups_and_zero_rhs(P):
         assert rr <= 1.01e-10, (k, rr)
 
 
+def test_grouped_batch_failures_stay_with_their_items(P):
+    # with maxit below what some instances need, those instances end ENOCONV
+    # and the rest of their group is solved as usual; an instance whose b holds
+    # a NaN ends ENUMERIC without touching the others
+    from paper_2209_02815_amd import _native as nat
+    wls = small_batch() + H.batch_workloads(count=6, batch_id=11, sides=(65,), m_lo=100, m_hi=128)
+    items, host = make_items(wls)
+    ref, _, _ = nat.h1w_batch_solve(items, nworkers=2, rtol=1e-8, grouped=True)
+    need = [i.iters for i in ref]
+    cap = sorted(need)[len(need) // 2]
+    assert max(need) > cap
+    bad = 3
+    items[bad]["b"][5] = float("nan")
+    for it in items:
+        it["x"].zero_()
+    infos, stats, rep = nat.h1w_batch_solve(items, nworkers=2, rtol=1e-8, maxit=cap, grouped=True,
+                                            raise_on_error=False)
+    assert stats[bad] == nat.H1W_ENUMERIC
+    n_ok = n_fail = 0
+    for k, (wl, it, (J, b), inf, st) in enumerate(zip(wls, items, host, infos, stats)):
+        if k == bad:
+            continue
+        if need[k] <= cap and st == 0:
+            Jm = J if J is not None else np.zeros((0, wl.N))
+            rr = gn.true_relres(wl.shape, wl.beta, Jm, wl.alpha, b, it["x"].cpu().numpy())
+            assert rr <= 1.01e-8, (k, rr)
+            n_ok += 1
+        elif need[k] > cap:
+            assert st == nat.H1W_ENOCONV, (k, st, need[k], cap)
+            n_fail += 1
+    print(f"maxit {cap}: {n_ok} instances solved, {n_fail} ENOCONV, instance {bad} ENUMERIC", flush=True)
+    assert n_ok > 0 and n_fail > 0
+
+
 def test_grouped_batch_solves_larger_items_one_at_a_time(P):
     # items with more than 128 rows do not fit a group's capacitance tile:
     # the grouped call solves them after the groups, one solve per item
