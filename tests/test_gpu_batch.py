@@ -320,19 +320,22 @@ def test_batch_workers_reused_across_batches(P):
             assert rr <= 1.01e-10, (wl.name, beta, rr)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_full_batch_workload(P, prec):
+@pytest.mark.parametrize("prec,grouped", [("fp64", False), ("mixed", False), ("fp64", True), ("mixed", True)])
+def test_full_batch_workload(P, prec, grouped):
     # the benchmark's batch at its real size: 256 2D instances, sides drawn
     # from {65, 129, 193, 257}, m in [16, 128], alpha log-uniform in
-    # [1e-5, 1e-2], in the launch configuration bench.py times (8 workers,
-    # autotuned); every instance's FP64 true residual recomputed by the oracle
+    # [1e-5, 1e-2], in the launch configurations bench.py times (one solve
+    # per instance on 8 workers, or the grouped mode with one worker per
+    # grid; autotuned); every instance's FP64 true residual recomputed by the
+    # oracle
     from paper_2209_02815_amd import _native as nat
     rtol = 1e-8
     wls = H.batch_workloads()
     items, host = make_items(wls)
     precision = nat.H1W_FP64 if prec == "fp64" else nat.H1W_MIXED
-    infos, stats, rep = nat.h1w_batch_solve(items, precision=precision, nworkers=8, autotune=1, rtol=rtol)
-    assert all(s == 0 for s in stats) and rep.nworkers == 8
+    infos, stats, rep = nat.h1w_batch_solve(items, precision=precision, nworkers=8, autotune=1, rtol=rtol,
+                                            grouped=grouped)
+    assert all(s == 0 for s in stats) and rep.nworkers == (4 if grouped else 8)
     worst = 0.0
     for wl, it, (J, b), info in zip(wls, items, host, infos):
         x = it["x"].cpu().numpy()
@@ -341,5 +344,5 @@ def test_full_batch_workload(P, prec):
         floor = gn.residual_rounding_floor(wl.shape, wl.beta, J, wl.alpha, b, x)
         assert abs(rr - info.relres_true) <= 1e-3 * rtol + floor, (wl.name, rr, info.relres_true, floor)
         worst = max(worst, rr)
-    print(f"batch {prec}: 256 instances, worst oracle relres {worst:.2e}, "
+    print(f"batch {prec} grouped={grouped}: 256 instances, worst oracle relres {worst:.2e}, "
           f"{sum(i.iters for i in infos)} iterations in total")
