@@ -354,7 +354,10 @@ def h1w_batch_solve(items, precision: int = H1W_FP64, nworkers: int = 0, autotun
                     rtol: float = 0.0, maxit: int = 0, raise_on_error: bool = True, graphs: bool = False,
                     grouped: bool = False):
     """items: list of dicts with shape, beta, alpha, J (CUDA (m, N) float64 or None), b, x.
-    Returns (infos, statuses, report); raises on the first failing item unless raise_on_error is False."""
+    grouped: solve the items of one grid in lock step (items with more than 128
+    rows one at a time after the groups); otherwise one solve per item on
+    nworkers streams. Returns (infos, statuses, report); raises for the failing
+    item with the lowest index unless raise_on_error is False."""
     arr = (h1w_batch_item * max(1, len(items)))()
     for i, it in enumerate(items):
         shape = tuple(it["shape"])
