@@ -63,6 +63,30 @@ for name, nargs in [("h1w_gn_solve", 11), ("h1w_gn_apply", 7), ("h1w_gn_apply_no
     f = getattr(lib, name)
     f.argtypes = [P] * nargs
     assert f(*([None] * nargs)) == -1, name
+# batch options are validated before any device work
+class BatchOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("nworkers", C.c_int), ("autotune", C.c_int), ("nu", C.c_int),
+                ("rtol", C.c_double), ("maxit", C.c_int), ("graphs", C.c_int), ("grouped", C.c_int)]
+
+lib.h1w_batch_solve.argtypes = [I, P, P, P, P, P]
+item = (C.c_char * 256)()
+for b in [dict(grouped=2), dict(graphs=3), dict(precision=7), dict(autotune=5), dict(rtol=float("nan")),
+          dict(nworkers=-1), dict(nu=17), dict(maxit=-2)]:
+    o = BatchOpts()
+    o.precision = b.get("precision", 0)
+    o.nworkers = b.get("nworkers", 0)
+    o.autotune = b.get("autotune", 0)
+    o.nu = b.get("nu", 0)
+    o.rtol = b.get("rtol", 1e-8)
+    o.maxit = b.get("maxit", 0)
+    o.graphs = b.get("graphs", 0)
+    o.grouped = b.get("grouped", 0)
+    st = lib.h1w_batch_solve(1, C.cast(item, P), C.cast(C.byref(o), P), None, None, None)
+    assert st == -1 and lib.h1w_last_error(None), (b, st)
+o = BatchOpts()
+assert lib.h1w_batch_solve(-1, None, C.cast(C.byref(o), P), None, None, None) == -1
+assert lib.h1w_batch_solve(1, None, C.cast(C.byref(o), P), None, None, None) == -1
+assert lib.h1w_batch_solve(1, C.cast(item, P), None, None, None, None) == -1
 print("ASAN-CHILD-OK")
 '''
 
