@@ -47,8 +47,8 @@ constexpr int kGJThreadsG = 1024;
 // so a step costs about what its active instances need.
 
 // out[i] = J_i . v_g for the M stacked rows (g = rowg[i], the instance of row
-// i): one work-group per row, four independent partial sums per thread (four
-// loads in flight), fixed order
+// i): one work-group per row, eight independent partial sums per thread,
+// combined in a fixed tree order
 __global__ __launch_bounds__(kBlock) void k_grp_rows_dot(int64_t N, const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ V, int64_t ldv,
                                                           const int* __restrict__ rowg,
@@ -59,14 +59,21 @@ __global__ __launch_bounds__(kBlock) void k_grp_rows_dot(int64_t N, const double
     if (act && !act[lo]) return;
     const double* a = A + i * lda;
     const double* v = V + (int64_t)lo * ldv;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t n = threadIdx.x;
-    for (; n + 3 * kBlock < N; n += 4 * kBlock) {
+    constexpr int U = 8;  // independent partial sums: eight loads of the row in flight per thread
+    double acc[U];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = fma(a[n + q * kBlock], v[n + q * kBlock], acc[q]);
+    for (int q = 0; q < U; ++q) acc[q] = 0.0;
+    int64_t n = threadIdx.x;
+    for (; n + (U - 1) * kBlock < N; n += U * kBlock) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) acc[q] = fma(a[n + q * kBlock], v[n + q * kBlock], acc[q]);
     }
     for (int q = 0; n < N; n += kBlock, ++q) acc[q] = fma(a[n], v[n], acc[q]);
-    const double s = block_sum<kBlock>((acc[0] + acc[1]) + (acc[2] + acc[3]), sh);
+#pragma unroll
+    for (int w = U / 2; w > 0; w /= 2)
+#pragma unroll
+        for (int q = 0; q < w; ++q) acc[q] += acc[q + w];
+    const double s = block_sum<kBlock>(acc[0], sh);
     if (threadIdx.x == 0) out[i] = s;
 }
 
@@ -424,8 +431,8 @@ void Ctx::gn_group_solve(int G, const GroupItem* items, const h1w_solve_opts& so
     int nact = 0;
     // out[i] = J_i . V[instance of i] for the M stacked rows (mask: nullptr or dact)
     auto rows_dot = [&](const double* V, double* out, const int* mask) {
-        hipLaunchKernelGGL(k_grp_rows_dot, dim3((unsigned)M), dim3(kBlock), 0, stream, n, (const double*)Jall, P, V,
-                           P, d_rowg, mask, out);
+        hipLaunchKernelGGL(k_grp_rows_dot, dim3((unsigned)M), dim3(kBlock), 0, stream, n, (const double*)Jall, P, V, P,
+                           d_rowg, mask, out);
         H1W_LAUNCHED();
     };
     // z = P^{-1} r for the active instances. With a quarter or more of the
